@@ -1,0 +1,8 @@
+"""FP64 CPU oracle of the npFEM time step. Test infrastructure only: imported by the tests,
+the smoke check and the benchmark's CPU-baseline leg, never by the GPU library."""
+from .npfem_oracle import (CellType, step, step_batch, predict, gradient, pd_rhs, energy,
+                           solve, volume, volume_gradient, surface_area, area_root,
+                           triangle_projections, triangle_rest_frames, bending_stencils,
+                           bending_vectors, bending_projection, volume_projection,
+                           deformation_gradients, interior_edges, system_matrix,
+                           cell_volume_area)

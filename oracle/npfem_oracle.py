@@ -1,0 +1,428 @@
+"""Plain FP64 CPU oracle of the npFEM projective-dynamics time step.
+
+TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's CPU-baseline
+leg may import this module. The GPU library shares no code with it: it has its own setup
+(in C++) and its own kernels (HIP), and neither side imports the other.
+
+What it computes (supplementary material, "Nodal Projective FEM (npFEM)" subsection):
+  * implicit Euler, v_{n+1} = (x_{n+1} - x_n)/h  (first displayed equation) and
+    F_int(x_{n+1}) + F_ext(x_n) - C v_{n+1} = M (v_{n+1} - v_n)/h (second), with C = 0;
+  * the equivalent minimisation of g(x) = 1/(2h^2) ||M^(1/2)(x - y_n)||_F^2 + sum_i E_i(x),
+    y_n = x_n + h v_n + h^2 M^-1 F_ext (third displayed equation, C = 0);
+  * the quasi-Newton iteration x^{k+1} = x^k - H~ grad g(x^k) with a constant Hessian
+    approximation H~ (fourth displayed equation), here H~ = L^-1 where L is the Hessian of the
+    quadratic part of g; with projective-dynamics energies this is the local/global iteration.
+
+The paper does not write out the elemental energies E_i (it defers to the npFEM journal
+paper). They are read here as projective-dynamics constraint energies
+w/2 ||A x - p(x)||^2 with exact projections p:
+  * per triangle: strain (singular values clamped to [s_min, s_max]; [1, 1] = polar factor)
+    and area (singular values (d, 1/d) nearest to (s1, s2)), weights shear_B * A_t and
+    area_C * A_t (Skalak B and C of the parameter table);
+  * per interior edge: isometric quadratic bending (cotangent stencil, Bergou et al. 2006 /
+    Wardetzky et al. 2007) projected onto its rest norm, weight k_bending;
+  * per cell: volume, projected by one linearised step onto V = V0, weight k_volume per vertex;
+  * uniform lumped mass m = density * V0 / n (the mass matrix is the lumped total mass,
+    interior fluid included, npFEM subsection).
+Everything is float64, vectorised over the cells of one type (arrays [N][n][3]).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+# ----------------------------------------------------------------------------------------
+# Cell-type setup: rest frames, bending stencils, mass and the constant system matrix L.
+# ----------------------------------------------------------------------------------------
+
+
+class CellType:
+    """Per-type constants of the step (all float64).
+
+    Attributes
+    ----------
+    n, m, e : vertices, triangles, interior edges (hinges)
+    tri     : int [m][3]
+    G       : [m][3][2]  gradient vectors g_a, g_b, g_c of the linear triangle (F = sum_j x_j g_j^T)
+    area    : [m]        rest triangle areas A_t
+    hinge   : int [e][4] (i, j, k, l): edge (i, j), opposite vertices k and l
+    coef    : [e][4]     bending stencil a_e
+    rest_norm : [e]      ||sum_q a_e,q X_q|| at rest
+    V0, mass, h         rest volume, per-vertex lumped mass, time step
+    w_s, w_a, w_b, w_v  constraint weights (shear, area, bending, volume)
+    L       : [n][n]     constant system matrix (Hessian of the quadratic part of g)
+    """
+
+    def __init__(self, rest_xyz, tri, material, h: float):
+        X = np.asarray(rest_xyz, dtype=np.float64)
+        tri = np.asarray(tri, dtype=np.int64)
+        self.X, self.tri = X, tri
+        self.n, self.m = X.shape[0], tri.shape[0]
+        self.h = float(h)
+        self.w_s = float(material.shear_B)
+        self.w_a = float(material.area_C)
+        self.w_b = float(material.k_bend)
+        self.w_v = float(material.k_vol)
+        self.s_min = float(material.strain_min)
+        self.s_max = float(material.strain_max)
+
+        self.G, self.area = triangle_rest_frames(X, tri)
+        self.hinge, self.coef, self.rest_norm = bending_stencils(X, tri)
+        self.e = self.hinge.shape[0]
+        self.V0 = float(volume(X[None], tri)[0])
+        self.mass = float(material.density) * self.V0 / self.n
+        self.L = system_matrix(self)
+        self.cho = scipy.linalg.cho_factor(self.L, lower=True)
+
+
+def triangle_rest_frames(X, tri):
+    """Rest 2D frame per triangle t = (a, b, c).
+
+    e1 = X_b - X_a, e2 = X_c - X_a, t1 = e1/|e1|, t2 = normalise(e2 - (e2.t1) t1);
+    D_m = [[|e1|, e2.t1], [0, e2.t2]] holds the rest edges in that frame, and
+    F = [x_b - x_a, x_c - x_a] D_m^-1, i.e. g_b = row 0 of D_m^-1, g_c = row 1,
+    g_a = -g_b - g_c. Returns G [m][3][2] and rest areas A_t = |e1 x e2|/2.
+    """
+    a, b, c = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+    e1, e2 = b - a, c - a
+    l1 = np.linalg.norm(e1, axis=1)
+    t1 = e1 / l1[:, None]
+    d12 = np.einsum("ij,ij->i", e2, t1)
+    perp = e2 - d12[:, None] * t1
+    l2 = np.linalg.norm(perp, axis=1)
+    Dm = np.zeros((len(tri), 2, 2))
+    Dm[:, 0, 0] = l1
+    Dm[:, 0, 1] = d12
+    Dm[:, 1, 1] = l2
+    Bm = np.linalg.inv(Dm)
+    G = np.empty((len(tri), 3, 2))
+    G[:, 1, :] = Bm[:, 0, :]
+    G[:, 2, :] = Bm[:, 1, :]
+    G[:, 0, :] = -G[:, 1, :] - G[:, 2, :]
+    area = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1)
+    return G, area
+
+
+def _cot(u, v):
+    return np.einsum("ij,ij->i", u, v) / np.linalg.norm(np.cross(u, v), axis=1)
+
+
+def interior_edges(tri):
+    """Hinges (i, j, k, l): (i, j, k) and (j, i, l) are the two triangles of edge {i, j},
+    each in its own counter-clockwise order. One hinge per edge of a closed mesh."""
+    opp = {}
+    for t in tri:
+        for r in range(3):
+            p, q, o = int(t[r]), int(t[(r + 1) % 3]), int(t[(r + 2) % 3])
+            opp[(p, q)] = o
+    hinges = []
+    for (p, q), o in opp.items():
+        if p < q:
+            hinges.append((p, q, o, opp[(q, p)]))
+    return np.asarray(sorted(hinges), dtype=np.int64)
+
+
+def bending_stencils(X, tri):
+    """Isometric quadratic bending stencil a_e over (i, j, k, l) and its rest norm.
+
+    With e0 = X_j - X_i, e1 = X_k - X_i, e2 = X_l - X_i, e3 = X_k - X_j, e4 = X_l - X_j and
+    c_pq = cot of the angle between e_p and e_q (angles at j taken against -e0):
+    a_e = sqrt(3/(A0 + A1)) (c03 + c04, c01 + c02, -c01 - c03, -c02 - c04), where A0, A1
+    are the areas of triangles (i, j, k) and (j, i, l).
+    """
+    H = interior_edges(tri)
+    i, j, k, l = (X[H[:, q]] for q in range(4))
+    e0, e1, e2, e3, e4 = j - i, k - i, l - i, k - j, l - j
+    c01, c02 = _cot(e0, e1), _cot(e0, e2)
+    c03, c04 = _cot(-e0, e3), _cot(-e0, e4)
+    A0 = 0.5 * np.linalg.norm(np.cross(e0, e1), axis=1)
+    A1 = 0.5 * np.linalg.norm(np.cross(e0, e2), axis=1)
+    s = np.sqrt(3.0 / (A0 + A1))
+    coef = s[:, None] * np.stack([c03 + c04, c01 + c02, -c01 - c03, -c02 - c04], axis=1)
+    u = np.einsum("eq,eqd->ed", coef, X[H])
+    return H, coef, np.linalg.norm(u, axis=1)
+
+
+def system_matrix(ct: CellType) -> np.ndarray:
+    """L = (m/h^2 + w_v) I + sum_t (w_s + w_a) A_t G_t^T G_t + sum_e w_b a_e a_e^T.
+
+    It is the Hessian of the quadratic part of g, shared by the three coordinates and by
+    every cell of the type.
+    """
+    n = ct.n
+    L = np.eye(n) * (ct.mass / ct.h ** 2 + ct.w_v)
+    wt = (ct.w_s + ct.w_a) * ct.area
+    for p in range(3):
+        for q in range(3):
+            np.add.at(L, (ct.tri[:, p], ct.tri[:, q]),
+                      wt * np.einsum("tk,tk->t", ct.G[:, p, :], ct.G[:, q, :]))
+    for p in range(4):
+        for q in range(4):
+            np.add.at(L, (ct.hinge[:, p], ct.hinge[:, q]), ct.w_b * ct.coef[:, p] * ct.coef[:, q])
+    return L
+
+
+# ----------------------------------------------------------------------------------------
+# Geometry of a deformed state x [N][n][3].
+# ----------------------------------------------------------------------------------------
+
+
+def deformation_gradients(x, ct):
+    """F [N][m][3][2] = sum_j x_j g_j^T over the triangle's vertices."""
+    return np.einsum("nmjd,mjk->nmdk", x[:, ct.tri], ct.G)
+
+
+def bending_vectors(x, ct):
+    """u [N][e][3] = sum_q a_e,q x_h(q)."""
+    return np.einsum("eq,neqd->ned", ct.coef, x[:, ct.hinge])
+
+
+def volume(x, tri=None):
+    """Enclosed volume V = 1/6 sum_t x_a . (x_b x x_c), per cell [N]."""
+    if tri is None:
+        raise ValueError("tri required")
+    a, b, c = x[:, tri[:, 0]], x[:, tri[:, 1]], x[:, tri[:, 2]]
+    return np.einsum("nmd,nmd->n", a, np.cross(b, c)) / 6.0
+
+
+def volume_gradient(x, tri):
+    """dV/dx_i [N][n][3] = 1/6 sum over triangles containing i of (cyclic) x_b x x_c."""
+    a, b, c = x[:, tri[:, 0]], x[:, tri[:, 1]], x[:, tri[:, 2]]
+    g = np.zeros_like(x)
+    np.add.at(g, (slice(None), tri[:, 0]), np.cross(b, c) / 6.0)
+    np.add.at(g, (slice(None), tri[:, 1]), np.cross(c, a) / 6.0)
+    np.add.at(g, (slice(None), tri[:, 2]), np.cross(a, b) / 6.0)
+    return g
+
+
+def surface_area(x, tri):
+    a, b, c = x[:, tri[:, 0]], x[:, tri[:, 1]], x[:, tri[:, 2]]
+    return 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=-1).sum(axis=1)
+
+
+# ----------------------------------------------------------------------------------------
+# Local step: projections.
+# ----------------------------------------------------------------------------------------
+
+
+def area_root(s1, s2):
+    """Singular value d of the nearest area-preserving stretch (d, 1/d) to (s1, s2).
+
+    Stationary points of (t - s1)^2 + (1/t - s2)^2 over t > 0 are the positive roots of
+    t^4 - s1 t^3 + s2 t - 1 = 0. All roots come from the companion-matrix eigenvalues
+    (as numpy.roots does), the positive real ones are polished by Newton in float64 and the
+    one with the smallest objective is returned.
+    """
+    s1 = np.asarray(s1, dtype=np.float64)
+    s2 = np.asarray(s2, dtype=np.float64)
+    shape = s1.shape
+    s1f, s2f = s1.ravel(), s2.ravel()
+    P = s1f.size
+    C = np.zeros((P, 4, 4))
+    C[:, 0, 0] = s1f
+    C[:, 0, 2] = -s2f
+    C[:, 0, 3] = 1.0
+    C[:, 1, 0] = C[:, 2, 1] = C[:, 3, 2] = 1.0
+    r = np.linalg.eigvals(C)
+    re = r.real
+    ok = (np.abs(r.imag) <= 1e-6 * np.maximum(1.0, np.abs(re))) & (re > 0)
+    t = np.where(ok, re, 1.0)
+    for _ in range(4):
+        f = ((t - s1f[:, None]) * t) * t * t + s2f[:, None] * t - 1.0
+        fp = (4.0 * t - 3.0 * s1f[:, None]) * t * t + s2f[:, None]
+        t = np.where(ok & (fp != 0), t - f / np.where(fp != 0, fp, 1.0), t)
+    obj = (t - s1f[:, None]) ** 2 + (1.0 / t - s2f[:, None]) ** 2
+    obj = np.where(ok & (t > 0), obj, np.inf)
+    best = np.argmin(obj, axis=1)
+    d = t[np.arange(P), best]
+    if not np.all(np.isfinite(obj[np.arange(P), best])):
+        raise FloatingPointError("area projection found no positive real root")
+    return d.reshape(shape)
+
+
+def triangle_projections(F, ct):
+    """(p_strain, p_area), each [N][m][3][2], from the thin SVD F = U diag(s) V^T."""
+    U, s, Vh = np.linalg.svd(F, full_matrices=False)
+    ss = np.clip(s, ct.s_min, ct.s_max)
+    p_s = U @ (ss[..., :, None] * Vh)
+    d = area_root(s[..., 0], s[..., 1])
+    sa = np.stack([d, 1.0 / d], axis=-1)
+    p_a = U @ (sa[..., :, None] * Vh)
+    return p_s, p_a
+
+
+def bending_projection(u, ct):
+    """p = r_e u/||u||; when u = 0 the constraint contributes nothing (p = u)."""
+    nrm = np.linalg.norm(u, axis=-1, keepdims=True)
+    safe = np.where(nrm > 0, nrm, 1.0)
+    return np.where(nrm > 0, ct.rest_norm[None, :, None] * u / safe, u)
+
+
+def volume_projection(x, ct):
+    """One linearised step onto V = V0: p = x + lambda grad V, lambda = (V0 - V)/||grad V||^2.
+
+    Returns (p [N][n][3], lambda [N], V [N]).
+    """
+    V = volume(x, ct.tri)
+    gV = volume_gradient(x, ct.tri)
+    G2 = np.einsum("nid,nid->n", gV, gV)
+    lam = np.where(G2 > 0, (ct.V0 - V) / np.where(G2 > 0, G2, 1.0), 0.0)
+    return x + lam[:, None, None] * gV, lam, V
+
+
+# ----------------------------------------------------------------------------------------
+# Objective, gradient, global step.
+# ----------------------------------------------------------------------------------------
+
+
+def _scatter_triangles(ct, M, N):
+    """Sum over triangles of M_t g_j into vertex j: M [N][m][3][2] -> [N][n][3]."""
+    out = np.zeros((N, ct.n, 3))
+    for j in range(3):
+        np.add.at(out, (slice(None), ct.tri[:, j]), np.einsum("nmdk,mk->nmd", M, ct.G[:, j, :]))
+    return out
+
+
+def _scatter_hinges(ct, W, N):
+    """Sum over hinges of a_e,q W_e into vertex h(q): W [N][e][3] -> [N][n][3]."""
+    out = np.zeros((N, ct.n, 3))
+    for q in range(4):
+        np.add.at(out, (slice(None), ct.hinge[:, q]), ct.coef[None, :, q, None] * W)
+    return out
+
+
+def gradient(x, y, ct):
+    """grad g(x) [N][n][3] with projections recomputed at x (local step of the iteration)."""
+    N = x.shape[0]
+    F = deformation_gradients(x, ct)
+    p_s, p_a = triangle_projections(F, ct)
+    M = ct.area[None, :, None, None] * (ct.w_s * (F - p_s) + ct.w_a * (F - p_a))
+    u = bending_vectors(x, ct)
+    p_b = bending_projection(u, ct)
+    p_v, _, _ = volume_projection(x, ct)
+    g = (ct.mass / ct.h ** 2) * (x - y)
+    g += _scatter_triangles(ct, M, N)
+    g += _scatter_hinges(ct, ct.w_b * (u - p_b), N)
+    g += ct.w_v * (x - p_v)
+    return g
+
+
+def pd_rhs(x, y, ct):
+    """Projective-dynamics global right-hand side (M/h^2) y + sum_c w_c A_c^T p_c(x)."""
+    N = x.shape[0]
+    F = deformation_gradients(x, ct)
+    p_s, p_a = triangle_projections(F, ct)
+    M = ct.area[None, :, None, None] * (ct.w_s * p_s + ct.w_a * p_a)
+    u = bending_vectors(x, ct)
+    p_b = bending_projection(u, ct)
+    p_v, _, _ = volume_projection(x, ct)
+    b = (ct.mass / ct.h ** 2) * y
+    b += _scatter_triangles(ct, M, N)
+    b += _scatter_hinges(ct, ct.w_b * p_b, N)
+    b += ct.w_v * p_v
+    return b
+
+
+def energy(x, y, ct):
+    """g(x) per cell [N] with projections at x."""
+    F = deformation_gradients(x, ct)
+    p_s, p_a = triangle_projections(F, ct)
+    u = bending_vectors(x, ct)
+    p_b = bending_projection(u, ct)
+    p_v, _, _ = volume_projection(x, ct)
+    e = 0.5 * ct.mass / ct.h ** 2 * np.einsum("nid,nid->n", x - y, x - y)
+    e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_s, (F - p_s) ** 2)
+    e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_a, (F - p_a) ** 2)
+    e += 0.5 * ct.w_b * np.einsum("ned,ned->n", u - p_b, u - p_b)
+    e += 0.5 * ct.w_v * np.einsum("nid,nid->n", x - p_v, x - p_v)
+    return e
+
+
+def solve(ct, b, method: str = "cholesky"):
+    """L^-1 b for b [N][n][3]: the three coordinates of every cell share L."""
+    N = b.shape[0]
+    B = np.transpose(b, (1, 0, 2)).reshape(ct.n, N * 3)
+    if method == "cholesky":
+        X = scipy.linalg.cho_solve(ct.cho, B)
+    elif method == "dense":
+        X = np.linalg.solve(ct.L, B)
+    else:
+        raise ValueError(method)
+    return np.transpose(X.reshape(ct.n, N, 3), (1, 0, 2))
+
+
+def predict(x, v, f, ct):
+    """y = x_n + h v_n + h^2 F_ext / m (third displayed equation, C = 0)."""
+    return x + ct.h * v + (ct.h ** 2 / ct.mass) * f
+
+
+def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
+         history: list | None = None):
+    """One implicit-Euler step for N cells of one type; x, v, f are [N][n][3] float64.
+
+    The iteration starts at x^0 = y and performs ``n_iters`` quasi-Newton updates
+    x^{k+1} = x^k - L^-1 grad g(x^k) (form "qn") or the algebraically identical
+    projective-dynamics updates x^{k+1} = L^-1 rhs(x^k) (form "pd"). n_iters = 0 returns
+    the prediction. Returns (x_{n+1}, v_{n+1}) with v_{n+1} = (x_{n+1} - x_n)/h.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = predict(x, v, f, ct)
+    xk = y.copy()
+    if history is not None:
+        history.append(xk.copy())
+    for _ in range(n_iters):
+        if form == "qn":
+            xk = xk - solve(ct, gradient(xk, y, ct), method)
+        elif form == "pd":
+            xk = solve(ct, pd_rhs(xk, y, ct), method)
+        else:
+            raise ValueError(form)
+        if history is not None:
+            history.append(xk.copy())
+    return xk, (xk - x) / ct.h
+
+
+# ----------------------------------------------------------------------------------------
+# Batch helpers: SoA [3][V_total] arrays with cells of mixed types.
+# ----------------------------------------------------------------------------------------
+
+
+def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=None):
+    """Advance the listed cells (default: all) of a SoA batch; returns new (x, v) copies.
+
+    cell_types maps type id -> CellType; x, v, f are float64 [3][V_total].
+    Cells of the same type are stepped together (they are independent).
+    """
+    types = np.asarray(types)
+    offsets = np.asarray(offsets)
+    cells = np.arange(len(types)) if cells is None else np.asarray(cells)
+    xo, vo = x.copy(), v.copy()
+    for t, ct in cell_types.items():
+        sel = cells[types[cells] == t]
+        if sel.size == 0:
+            continue
+        idx = offsets[sel][:, None] + np.arange(ct.n)[None, :]          # [N][n]
+        xs = np.transpose(x[:, idx], (1, 2, 0))
+        vs = np.transpose(v[:, idx], (1, 2, 0))
+        fs = np.transpose(f[:, idx], (1, 2, 0))
+        xn, vn = step(ct, xs, vs, fs, n_iters)
+        xo[:, idx] = np.transpose(xn, (2, 0, 1))
+        vo[:, idx] = np.transpose(vn, (2, 0, 1))
+    return xo, vo
+
+
+def cell_volume_area(cell_types: dict, types, offsets, x, cells=None):
+    """[n_cells][2] float64 (V, S) of the listed cells at positions x [3][V_total]."""
+    types = np.asarray(types)
+    offsets = np.asarray(offsets)
+    cells = np.arange(len(types)) if cells is None else np.asarray(cells)
+    out = np.zeros((len(cells), 2))
+    for t, ct in cell_types.items():
+        pos = np.nonzero(types[cells] == t)[0]
+        if pos.size == 0:
+            continue
+        idx = offsets[cells[pos]][:, None] + np.arange(ct.n)[None, :]
+        xs = np.transpose(x[:, idx], (1, 2, 0))
+        out[pos, 0] = volume(xs, ct.tri)
+        out[pos, 1] = surface_area(xs, ct.tri)
+    return out
