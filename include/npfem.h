@@ -1,0 +1,149 @@
+/*
+ * npfem.h - C ABI of the MI355X npFEM solver library (libnpfem.so).
+ *
+ * The library advances deformable blood cells (surface meshes) by one implicit-Euler time
+ * step (arXiv 1911.03062, supplementary material, npFEM subsection: the velocity update,
+ * Newton's second law with implicit Euler, its minimisation form g(x) and the quasi-Newton
+ * iteration x^{k+1} = x^k - H~ grad g(x^k)). The elemental energies are projective-dynamics
+ * constraints (triangle strain and area, edge bending, cell volume) and H~ is the inverse
+ * of the constant matrix L (Hessian of the quadratic part of g), so one iteration is one
+ * local (projection) step plus one global (linear solve) step.
+ *
+ * Units: um, us, fg, pN. Arrays of vertex data are structure-of-arrays [3][V_total]
+ * (x coordinates of every vertex of the batch, then y, then z); the vertices of one cell
+ * are contiguous and cells follow each other in batch order.
+ *
+ * Errors: every call returns an npfem_status; no exception crosses the ABI. Validation
+ * errors are reported synchronously. npfem_last_error() returns a thread-local message for
+ * the last non-OK status of the calling thread.
+ *
+ * Threads: cell types are immutable after creation and may be shared by batches and
+ * threads. A batch must not be stepped from two threads at once.
+ */
+#ifndef NPFEM_H
+#define NPFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NPFEM_OK = 0,
+  NPFEM_E_INVALID = -1,    /* bad argument (null pointer, size, precision, form)            */
+  NPFEM_E_MESH = -2,       /* mesh not closed/manifold/consistently oriented, degenerate
+                              triangle, unused vertex, or rest volume <= 0                  */
+  NPFEM_E_NOT_SPD = -3,    /* the system matrix failed to factorise                          */
+  NPFEM_E_DT = -4,         /* step dt differs from the cell type's factorised dt             */
+  NPFEM_E_NOMEM = -5,      /* host or device allocation failed                               */
+  NPFEM_E_HIP = -6,        /* a HIP runtime call failed (message names it)                   */
+  NPFEM_E_NONFINITE = -7,  /* a step produced a non-finite position or velocity              */
+  NPFEM_E_UNSUPPORTED = -8 /* the requested form/precision/type size is not available        */
+} npfem_status;
+
+/* Surface mesh of one cell type (host memory, borrowed for the duration of the call). */
+typedef struct {
+  int32_t n_vertices;
+  int32_t n_triangles;
+  const double* rest_xyz;  /* [n_vertices][3], um: the stress-free shape                   */
+  const int32_t* tri;      /* [n_triangles][3], counter-clockwise seen from outside        */
+} npfem_mesh;
+
+/* Material constants (parameter table of the supplementary material). */
+typedef struct {
+  double density;       /* fg/um^3: lumped mass m = density * V0 / n per vertex            */
+  double shear_B;       /* pN/um: strain-constraint weight per unit rest area              */
+  double area_C;        /* pN/um: area-constraint weight per unit rest area                */
+  double skalak_D;      /* pN/um: stored; no role in the projective-dynamics energies      */
+  double k_bend;        /* pN um: bending-constraint weight                                */
+  double k_vol;         /* pN/um: volume-constraint weight per vertex                      */
+  double strain_min;    /* singular-value clamp of the strain projection (1, 1 = polar)    */
+  double strain_max;
+} npfem_material;
+
+typedef struct npfem_celltype npfem_celltype;   /* opaque, library-owned */
+typedef struct npfem_batch npfem_batch;         /* opaque, library-owned */
+
+/* Read-only description of a cell type (host-side setup results). */
+typedef struct {
+  int32_t n_vertices, n_triangles, n_hinges;
+  int32_t bandwidth;        /* max |i - j| over the nonzeros of L                           */
+  double rest_volume;       /* V0, um^3                                                      */
+  double rest_area;         /* um^2                                                          */
+  double vertex_mass;       /* fg                                                            */
+  double dt;                /* us, the dt L was factorised for                               */
+  int32_t tri_rounds;       /* rounds of the per-wave triangle schedule (fused form)         */
+  int32_t hinge_rounds;     /* rounds of the per-wave hinge schedule (fused form)            */
+} npfem_celltype_info;
+
+/* Solver forms (npfem_batch_create `form`). */
+enum {
+  NPFEM_FORM_PLAIN = 0,  /* one cell at a time: predict, K x (local, global), finalise are
+                            separate kernel launches per cell; FP64 or FP32                 */
+  NPFEM_FORM_FUSED = 1   /* every cell of the batch in one launch per step: local + global
+                            iterations fused in LDS, global step as a dense-inverse FP32
+                            MFMA product; FP32 state, FP64 volume/area reductions           */
+};
+
+/*
+ * Build a cell type on the host (no GPU call): validate the mesh, compute the rest frames
+ * of the triangles, the bending stencils of the interior edges, the rest volume V0, the
+ * uniform lumped mass, assemble L = (m/h^2 + k_vol) I + sum_t (B + C) A_t G_t^T G_t
+ * + sum_e k_bend a_e a_e^T, factorise it (Cholesky, FP64) and form its inverse.
+ * `dt` (us) is fixed for the type: stepping with another dt is an error.
+ * Errors: NPFEM_E_INVALID, NPFEM_E_MESH, NPFEM_E_NOT_SPD, NPFEM_E_NOMEM.
+ */
+npfem_status npfem_create_celltype(const npfem_mesh* mesh, const npfem_material* material,
+                                   double dt, npfem_celltype** out);
+void npfem_celltype_destroy(npfem_celltype* type);
+npfem_status npfem_celltype_get_info(const npfem_celltype* type, npfem_celltype_info* out);
+/* Copy the assembled FP64 system matrix L into host memory [n][n] (row-major). */
+npfem_status npfem_celltype_get_matrix(const npfem_celltype* type, double* L_out);
+
+/*
+ * Create a batch of n_cells cells; cell c has type type_of_cell[c] (host array of handles,
+ * borrowed). precision is 32 or 64 (64 only with NPFEM_FORM_PLAIN). vertex_offsets, if not
+ * NULL, receives [n_cells + 1] int64 offsets of each cell in the vertex axis (host memory).
+ * Allocates the batch's device work list and workspace on the current HIP device.
+ * Errors: NPFEM_E_INVALID, NPFEM_E_UNSUPPORTED, NPFEM_E_NOMEM, NPFEM_E_HIP.
+ */
+npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_cell,
+                                int32_t precision, int32_t form, npfem_batch** out,
+                                int64_t* vertex_offsets);
+void npfem_batch_destroy(npfem_batch* batch);
+int64_t npfem_batch_vertex_count(const npfem_batch* batch);
+
+/*
+ * Advance every cell of the batch by one time step of length dt with n_pd_iters
+ * quasi-Newton (local/global) iterations, asynchronously on `stream` (a hipStream_t;
+ * NULL = default stream).
+ *   x, v        device, in/out, [3][V_total] float (precision 32) or double (64):
+ *               positions (um) and velocities (um/us), overwritten with x_{n+1}, v_{n+1};
+ *   ext_forces  device, in, [3][V_total], external force per vertex (pN), same precision;
+ *   cell_volume_area  optional device double [n_cells][2]: enclosed volume and surface
+ *               area of each cell at x_{n+1} (FP64 reductions), or NULL.
+ * Buffers are caller-owned and borrowed for the duration of the enqueued work.
+ * n_pd_iters = 0 returns the prediction x_n + h v_n + h^2 F/m (free flight).
+ * Errors: NPFEM_E_INVALID (null buffer, n_pd_iters < 0), NPFEM_E_DT, NPFEM_E_HIP.
+ * A non-finite result is flagged on the device; npfem_batch_check reports it.
+ */
+npfem_status npfem_step(npfem_batch* batch, void* x, void* v, const void* ext_forces,
+                        double dt, int32_t n_pd_iters, void* stream,
+                        double* cell_volume_area);
+
+/*
+ * Synchronise `stream` and report NPFEM_E_NONFINITE if any step since the last check
+ * produced a non-finite position or velocity (the flag is then cleared), NPFEM_E_HIP on a
+ * device error, NPFEM_OK otherwise.
+ */
+npfem_status npfem_batch_check(npfem_batch* batch, void* stream);
+
+/* Thread-local message of the calling thread's last non-OK status ("" if none). */
+const char* npfem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NPFEM_H */

@@ -1,0 +1,370 @@
+// C ABI of libnpfem: cell types, batches, the step entry point and error reporting.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "npfem_internal.h"
+
+namespace npfem {
+
+namespace {
+thread_local std::string g_last_error;
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(NPFEM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+template <typename D, typename S>
+npfem_status upload(D** dst, const std::vector<S>& src) {
+  std::vector<D> tmp(src.begin(), src.end());
+  if (tmp.empty()) tmp.resize(1);
+  HIP_TRY(hipMalloc((void**)dst, tmp.size() * sizeof(D)));
+  HIP_TRY(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(D), hipMemcpyHostToDevice));
+  return NPFEM_OK;
+}
+
+template <typename D>
+npfem_status upload_raw(D** dst, const D* src, size_t count) {
+  HIP_TRY(hipMalloc((void**)dst, std::max<size_t>(count, 1) * sizeof(D)));
+  if (count) HIP_TRY(hipMemcpy(*dst, src, count * sizeof(D), hipMemcpyHostToDevice));
+  return NPFEM_OK;
+}
+
+#define NP_TRY(expr)                      \
+  do {                                    \
+    npfem_status s_ = (expr);             \
+    if (s_ != NPFEM_OK) return s_;        \
+  } while (0)
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+npfem_status fail(npfem_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+void free_devtype(DevType* d) {
+  if (!d) return;
+  void* ptrs[] = {d->tri_sched, d->hinge_sched, d->ring_info, d->ring_pairs, d->linv_tiles,
+                  d->tri,       d->hinge,       d->vt_off,    d->vt_list,    d->vh_off,
+                  d->vh_list,   d->G64,         d->G32,       d->A64,        d->A32,
+                  d->coef64,    d->coef32,      d->rest64,    d->rest32,     d->cband64,
+                  d->cband32};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete d;
+}
+
+// Device copy of a cell type for the current device (created once, then shared).
+npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(ct->mu);
+  auto it = ct->dev.find(dev);
+  if (it != ct->dev.end()) {
+    *out = it->second;
+    return NPFEM_OK;
+  }
+  DevType* d = new (std::nothrow) DevType();
+  if (!d) return fail(NPFEM_E_NOMEM, "host allocation");
+  TypeParams& p = d->p;
+  p.n = ct->n; p.m = ct->m; p.e = ct->e; p.bw = ct->bw;
+  p.npad = ct->npad; p.gw = ct->gw; p.slots = ct->slots;
+  p.tri_rounds = ct->tri_rounds; p.hinge_rounds = ct->hinge_rounds;
+  p.row_tiles = (ct->n + 15) / 16;
+  p.k_steps = ct->npad / 4;
+  p.pad0 = 0;
+  p.h = ct->h; p.mass = ct->mass; p.inv_h2m = ct->mass / (ct->h * ct->h);
+  p.h2_over_m = ct->h * ct->h / ct->mass;
+  p.w_s = ct->w_s; p.w_a = ct->w_a; p.w_b = ct->w_b; p.w_v = ct->w_v;
+  p.s_min = ct->s_min; p.s_max = ct->s_max; p.V0 = ct->V0;
+
+  npfem_status st = NPFEM_OK;
+  auto chk = [&](npfem_status s) { if (st == NPFEM_OK) st = s; };
+  chk(upload(&d->tri, ct->tri));
+  chk(upload(&d->hinge, ct->hinge));
+  chk(upload(&d->vt_off, ct->vt_off));
+  chk(upload(&d->vt_list, ct->vt_list));
+  chk(upload(&d->vh_off, ct->vh_off));
+  chk(upload(&d->vh_list, ct->vh_list));
+  chk(upload(&d->G64, ct->G));   chk(upload(&d->G32, ct->G));
+  chk(upload(&d->A64, ct->A));   chk(upload(&d->A32, ct->A));
+  chk(upload(&d->coef64, ct->coef)); chk(upload(&d->coef32, ct->coef));
+  chk(upload(&d->rest64, ct->rest_norm)); chk(upload(&d->rest32, ct->rest_norm));
+  chk(upload(&d->cband64, ct->cband)); chk(upload(&d->cband32, ct->cband));
+  if (ct->fused_ok) {
+    chk(upload_raw(&d->tri_sched, ct->tri_sched.data(), ct->tri_sched.size()));
+    chk(upload_raw(&d->hinge_sched, ct->hinge_sched.data(), ct->hinge_sched.size()));
+    chk(upload(&d->ring_info, ct->ring_info));
+    chk(upload(&d->ring_pairs, ct->ring_pairs));
+    // L^-1 in MFMA A-operand order: tile rt, k step s, lane l -> (row rt*16 + l%16, col 4s + l/16)
+    const int RT = p.row_tiles, KS = p.k_steps, n = ct->n;
+    std::vector<float> lt((size_t)RT * KS * 64, 0.0f);
+    for (int rt = 0; rt < RT; ++rt)
+      for (int s = 0; s < KS; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int row = rt * 16 + (l & 15), col = 4 * s + (l >> 4);
+          if (row < n && col < n)
+            lt[((size_t)rt * KS + s) * 64 + l] = (float)ct->Linv[(size_t)row * n + col];
+        }
+    chk(upload(&d->linv_tiles, lt));
+  }
+  if (st != NPFEM_OK) {
+    free_devtype(d);
+    return st;
+  }
+  ct->dev[dev] = d;
+  *out = d;
+  return NPFEM_OK;
+}
+
+}  // namespace npfem
+
+using namespace npfem;
+
+npfem_celltype::~npfem_celltype() {
+  for (auto& kv : dev) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first);
+    free_devtype(kv.second);
+    (void)hipSetDevice(cur);
+  }
+}
+
+struct npfem_batch {
+  int n_cells = 0, precision = 32, form = NPFEM_FORM_FUSED, device = 0;
+  double dt = 0;
+  std::vector<npfem_celltype*> cell_type;
+  std::vector<int64_t> offsets;
+  std::vector<npfem_celltype*> types;
+  std::vector<int> type_of;                 // per cell, index into types
+  std::vector<DevType*> dev_types;          // host pointers to per-type device copies
+  DevType* d_types = nullptr;               // device array of DevType (by value)
+  DevType** d_type_ptrs = nullptr;          // device pointers to each type's device DevType
+  std::vector<DevType*> type_dev_structs;   // device DevType per type (plain form)
+  FusedGroup* d_groups = nullptr;
+  int n_groups = 0;
+  int64_t* d_offsets = nullptr;
+  size_t lds_bytes = 0;
+  void* work = nullptr;                     // plain-form workspace
+  int* d_flag = nullptr;
+  ~npfem_batch() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    if (d_types) (void)hipFree(d_types);
+    for (DevType* p : type_dev_structs)
+      if (p) (void)hipFree(p);
+    if (d_groups) (void)hipFree(d_groups);
+    if (d_offsets) (void)hipFree(d_offsets);
+    if (work) (void)hipFree(work);
+    if (d_flag) (void)hipFree(d_flag);
+    (void)hipSetDevice(cur);
+  }
+};
+
+extern "C" {
+
+const char* npfem_last_error(void) { return g_last_error.c_str(); }
+
+npfem_status npfem_create_celltype(const npfem_mesh* mesh, const npfem_material* material,
+                                   double dt, npfem_celltype** out) {
+  if (!out) return fail(NPFEM_E_INVALID, "out is null");
+  *out = nullptr;
+  npfem_celltype* ct = new (std::nothrow) npfem_celltype();
+  if (!ct) return fail(NPFEM_E_NOMEM, "host allocation");
+  npfem_status s;
+  try {
+    s = build_celltype(mesh, material, dt, ct);
+  } catch (const std::bad_alloc&) {
+    s = fail(NPFEM_E_NOMEM, "host allocation during setup");
+  }
+  if (s != NPFEM_OK) {
+    delete ct;
+    return s;
+  }
+  *out = ct;
+  g_last_error.clear();
+  return NPFEM_OK;
+}
+
+void npfem_celltype_destroy(npfem_celltype* type) { delete type; }
+
+npfem_status npfem_celltype_get_info(const npfem_celltype* t, npfem_celltype_info* out) {
+  if (!t || !out) return fail(NPFEM_E_INVALID, "null argument");
+  out->n_vertices = t->n;
+  out->n_triangles = t->m;
+  out->n_hinges = t->e;
+  out->bandwidth = t->bw;
+  out->rest_volume = t->V0;
+  out->rest_area = t->area0;
+  out->vertex_mass = t->mass;
+  out->dt = t->h;
+  out->tri_rounds = t->tri_rounds;
+  out->hinge_rounds = t->hinge_rounds;
+  return NPFEM_OK;
+}
+
+npfem_status npfem_celltype_get_matrix(const npfem_celltype* t, double* L_out) {
+  if (!t || !L_out) return fail(NPFEM_E_INVALID, "null argument");
+  std::memcpy(L_out, t->L.data(), t->L.size() * sizeof(double));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_cell,
+                                int32_t precision, int32_t form, npfem_batch** out,
+                                int64_t* vertex_offsets) {
+  if (!out) return fail(NPFEM_E_INVALID, "out is null");
+  *out = nullptr;
+  if (n_cells < 0 || (n_cells > 0 && !type_of_cell)) return fail(NPFEM_E_INVALID, "bad cell list");
+  if (precision != 32 && precision != 64) return fail(NPFEM_E_INVALID, "precision must be 32 or 64");
+  if (form != NPFEM_FORM_PLAIN && form != NPFEM_FORM_FUSED) return fail(NPFEM_E_INVALID, "unknown form");
+  if (form == NPFEM_FORM_FUSED && precision != 32)
+    return fail(NPFEM_E_UNSUPPORTED, "the fused form computes in FP32");
+  npfem_batch* b = new (std::nothrow) npfem_batch();
+  if (!b) return fail(NPFEM_E_NOMEM, "host allocation");
+  b->n_cells = n_cells;
+  b->precision = precision;
+  b->form = form;
+  auto bail = [&](npfem_status s) { delete b; return s; };
+  if (hipGetDevice(&b->device) != hipSuccess) return bail(fail(NPFEM_E_HIP, "hipGetDevice failed"));
+  b->offsets.assign(n_cells + 1, 0);
+  b->type_of.resize(n_cells);
+  for (int c = 0; c < n_cells; ++c) {
+    npfem_celltype* t = type_of_cell[c];
+    if (!t) return bail(fail(NPFEM_E_INVALID, "null cell type"));
+    auto it = std::find(b->types.begin(), b->types.end(), t);
+    if (it == b->types.end()) {
+      b->types.push_back(t);
+      b->type_of[c] = (int)b->types.size() - 1;
+    } else {
+      b->type_of[c] = (int)(it - b->types.begin());
+    }
+    b->offsets[c + 1] = b->offsets[c] + t->n;
+  }
+  for (npfem_celltype* t : b->types) {
+    if (b->dt == 0) b->dt = t->h;
+    if (std::fabs(t->h - b->dt) > 1e-12 * b->dt)
+      return bail(fail(NPFEM_E_DT, "cell types of one batch must share dt"));
+    if (form == NPFEM_FORM_FUSED && !t->fused_ok)
+      return bail(fail(NPFEM_E_UNSUPPORTED, t->fused_reason));
+    if (form == NPFEM_FORM_PLAIN && !plain_supported(t->n, t->bw))
+      return bail(fail(NPFEM_E_UNSUPPORTED, "plain form supports n <= 1024"));
+    DevType* d = nullptr;
+    npfem_status s = upload_celltype(t, &d);
+    if (s != NPFEM_OK) return bail(s);
+    b->dev_types.push_back(d);
+  }
+  if (vertex_offsets) std::memcpy(vertex_offsets, b->offsets.data(), (n_cells + 1) * sizeof(int64_t));
+
+  const int nt = (int)b->types.size();
+  if (hipMalloc((void**)&b->d_flag, sizeof(int)) != hipSuccess ||
+      hipMemset(b->d_flag, 0, sizeof(int)) != hipSuccess)
+    return bail(fail(NPFEM_E_NOMEM, "device flag"));
+  if (nt > 0) {
+    if (hipMalloc((void**)&b->d_types, nt * sizeof(DevType)) != hipSuccess)
+      return bail(fail(NPFEM_E_NOMEM, "device type table"));
+    for (int i = 0; i < nt; ++i)
+      if (hipMemcpy(b->d_types + i, b->dev_types[i], sizeof(DevType), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(NPFEM_E_HIP, "type table copy"));
+  }
+  if (form == NPFEM_FORM_PLAIN) {
+    size_t wb = 0;
+    for (npfem_celltype* t : b->types) wb = std::max(wb, plain_work_bytes(precision, t->n, t->m, t->e));
+    if (wb && hipMalloc(&b->work, wb) != hipSuccess) return bail(fail(NPFEM_E_NOMEM, "plain workspace"));
+  } else {
+    // groups of up to 4*gw same-type cells, in batch order within each type
+    std::vector<FusedGroup> groups;
+    for (int ti = 0; ti < nt; ++ti) {
+      const int cap = kFusedWaves * b->types[ti]->gw;
+      FusedGroup gcur{};
+      gcur.type = ti;
+      gcur.count = 0;
+      for (int c = 0; c < n_cells; ++c) {
+        if (b->type_of[c] != ti) continue;
+        gcur.cells[gcur.count++] = c;
+        if (gcur.count == cap) {
+          groups.push_back(gcur);
+          gcur.count = 0;
+        }
+      }
+      if (gcur.count) groups.push_back(gcur);
+      const npfem_celltype* t = b->types[ti];
+      b->lds_bytes = std::max(b->lds_bytes, (size_t)2 * cap * 3 * t->npad * sizeof(float));
+    }
+    b->n_groups = (int)groups.size();
+    if (b->n_groups) {
+      if (hipMalloc((void**)&b->d_groups, groups.size() * sizeof(FusedGroup)) != hipSuccess ||
+          hipMemcpy(b->d_groups, groups.data(), groups.size() * sizeof(FusedGroup),
+                    hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(NPFEM_E_NOMEM, "device work list"));
+    }
+    if (hipMalloc((void**)&b->d_offsets, (n_cells + 1) * sizeof(int64_t)) != hipSuccess ||
+        hipMemcpy(b->d_offsets, b->offsets.data(), (n_cells + 1) * sizeof(int64_t),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(NPFEM_E_NOMEM, "device offsets"));
+  }
+  *out = b;
+  g_last_error.clear();
+  return NPFEM_OK;
+}
+
+void npfem_batch_destroy(npfem_batch* batch) { delete batch; }
+
+int64_t npfem_batch_vertex_count(const npfem_batch* b) { return b ? b->offsets.back() : -1; }
+
+npfem_status npfem_step(npfem_batch* b, void* x, void* v, const void* f, double dt,
+                        int32_t n_pd_iters, void* stream, double* cell_volume_area) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  if (b->n_cells == 0) return NPFEM_OK;
+  if (!x || !v || !f) return fail(NPFEM_E_INVALID, "null state or force buffer");
+  if (n_pd_iters < 0) return fail(NPFEM_E_INVALID, "n_pd_iters < 0");
+  if (!(std::fabs(dt - b->dt) <= 1e-12 * b->dt))
+    return fail(NPFEM_E_DT, "dt differs from the cell types' factorised dt");
+  const int64_t vtot = b->offsets.back();
+  if (b->form == NPFEM_FORM_PLAIN) {
+    const size_t el = b->precision == 64 ? 8 : 4;
+    (void)el;
+    for (int c = 0; c < b->n_cells; ++c) {
+      const int ti = b->type_of[c];
+      hipError_t e = launch_plain_cell(b->precision, b->d_types + ti, b->dev_types[ti]->p, x, v, f,
+                                       vtot, b->offsets[c], n_pd_iters, b->work,
+                                       cell_volume_area ? cell_volume_area + 2 * (int64_t)c : nullptr,
+                                       b->d_flag, stream);
+      if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("plain launch: ") + hipGetErrorString(e));
+    }
+    return NPFEM_OK;
+  }
+  hipError_t e = launch_fused_step(b->d_types, (int)b->types.size(), b->d_groups, b->n_groups,
+                                   b->d_offsets, vtot, (float*)x, (float*)v, (const float*)f,
+                                   n_pd_iters, cell_volume_area, b->d_flag, b->lds_bytes,
+                                   b->n_groups, stream);
+  if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_check(npfem_batch* b, void* stream) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(s));
+  int flag = 0;
+  HIP_TRY(hipMemcpy(&flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    HIP_TRY(hipMemset(b->d_flag, 0, sizeof(int)));
+    return fail(NPFEM_E_NONFINITE, "a step produced a non-finite position or velocity");
+  }
+  return NPFEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,356 @@
+// Fused batched form of the npFEM step: every cell of the batch advanced by one launch.
+//
+// One workgroup (4 waves) takes a group of up to 4*gw cells of one type. Per cell, LDS holds
+// the current positions X and the gradient/update column R (FP32, [cell][coord][npad]).
+// Each wave owns gw cells for everything except the global step:
+//   prediction      delta^0 = h v + h^2 F/m, kept with delta and the cell-local rest of x_n
+//                   in the owning lanes' registers (supplementary material, npFEM
+//                   subsection: y_n with C = 0);
+//   volume          grad_i V = 1/6 sum over incident triangles of their doubled area vector,
+//                   V = 1/3 sum_i x_i . grad_i V and |grad V|^2 reduced per cell in FP64;
+//   local step      R = (m/h^2)(delta - delta^0) - k_vol lambda grad V, then every triangle
+//                   and hinge adds its constraint residual; the schedule packs vertex-disjoint
+//                   elements into rounds, so one wave updates R without atomics or barriers
+//                   and the summation order is fixed (bitwise reproducible);
+//   global step     D = -L^-1 R for all 3 * cells columns of the group at once as an FP32
+//                   MFMA product (v_mfma_f32_16x16x4_f32), A = L^-1 tiles streamed from L2,
+//                   B = R from LDS; the 4 waves split the output tiles;
+//   update          delta += D (quasi-Newton step of the fourth displayed equation).
+// Three workgroup barriers per iteration; everything else is wave-local.
+#include <hip/hip_runtime.h>
+
+#include "npfem_internal.h"
+#include "projections.h"
+
+namespace npfem {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool finite_f(float v) { return v == v && v - v == 0.0f; }
+
+// Makes the packed owner-item codes opaque to the optimiser so that the per-item LDS
+// addresses derived from them are recomputed where used instead of being hoisted out of the
+// iteration loop and kept live in registers.
+template <int NQ>
+__device__ __forceinline__ void refresh_items(int (&item)[NQ]) {
+#pragma unroll
+  for (int it = 0; it < NQ; ++it) asm volatile("" : "+v"(item[it]));
+}
+
+// Volume gradient of vertex vi of the cell whose X columns start at Xc, from its one ring.
+// Also returns the vertex's third of the incident triangles' area (sum |N_t| / 6).
+__device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const float* Xc,
+                                                        int npad, int vi, Vec3<float> pi,
+                                                        float& area_third) {
+  const uint32_t info = T.ring_info[vi];
+  const int off = (int)(info >> 8), deg = (int)(info & 255u);
+  Vec3<float> g = v3<float>(0.f, 0.f, 0.f);
+  float ar = 0.f;
+  for (int s = 0; s < deg; ++s) {
+    const uint32_t pr = T.ring_pairs[off + s];
+    const int b = (int)(pr & 0xffffu), c = (int)(pr >> 16);
+    const Vec3<float> pb = v3<float>(Xc[b], Xc[npad + b], Xc[2 * npad + b]) - pi;
+    const Vec3<float> pc = v3<float>(Xc[c], Xc[npad + c], Xc[2 * npad + c]) - pi;
+    const Vec3<float> nt = cross3(pb, pc);
+    g = g + nt;
+    ar += dsqrt(dot3(nt, nt));
+  }
+  area_third = ar * (1.0f / 6.0f);
+  return g * (1.0f / 6.0f);
+}
+
+template <int NQ>
+__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
+             int n_groups, const int64_t* __restrict__ offsets, int64_t vt,
+             float* __restrict__ x, float* __restrict__ v, const float* __restrict__ f, int K,
+             double* __restrict__ vol_area, int* __restrict__ flag) {
+  extern __shared__ float lds[];
+  __shared__ float lam_lds[kMaxGroupCells];
+  __shared__ int64_t off_lds[kMaxGroupCells];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    const FusedGroup& grp = groups[g];
+    const int count = grp.count;
+    const DevType& T = types[grp.type];
+    const int n = T.p.n, npad = T.p.npad, gw = T.p.gw, S = T.p.slots;
+    const int G4 = kFusedWaves * gw;
+    float* X = lds;
+    float* R = lds + G4 * 3 * npad;
+
+    __syncthreads();   // the previous group's last reads of LDS are done
+    for (int i = tid; i < G4 * 3 * npad; i += kFusedThreads) R[i] = 0.0f;
+
+    // ---- owner items: (cell gc of this wave, vertex vi), q = lane + 64 * it, packed as
+    //      vi | gc << 16; gc >= G4 marks an empty item
+    int item[NQ];
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+      const int q = lane + 64 * it;
+      const int cw = q / n;
+      const int gc = wave * gw + cw;
+      item[it] = (cw < gw && gc < count) ? ((q - cw * n) | (gc << 16)) : (G4 << 16);
+    }
+#define ITEM_OK(it) ((item[it] >> 16) < G4)
+#define ITEM_V(it) (item[it] & 0xffff)
+#define ITEM_C(it) (item[it] >> 16)
+    const float h = (float)T.p.h, h2m = (float)T.p.h2_over_m, ih2m = (float)T.p.inv_h2m;
+    const float w_v = (float)T.p.w_v, ih = (float)(1.0 / T.p.h);
+    if (tid < count) off_lds[tid] = offsets[grp.cells[tid]];
+    __syncthreads();
+    // e = delta - delta^0 is the only per-vertex state kept in registers; delta^0 is
+    // recomputed from v and F when the step is written back
+    float e[NQ][3];
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[it][c] = 0.0f;
+      if (ITEM_OK(it)) {
+        const int64_t off = off_lds[ITEM_C(it)];
+        const int vi = ITEM_V(it);
+        float* Xc = X + ITEM_C(it) * 3 * npad;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float dd = h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi];
+          // cell-local coordinates: positions relative to the cell's first vertex
+          Xc[c * npad + vi] = (x[c * vt + off + vi] - x[c * vt + off]) + dd;
+        }
+      }
+    }
+    __syncthreads();   // R zeroed, X written
+
+    // element-phase lane mapping: cell cw = lane / S, slot s = lane % S
+    const int e_cw = lane / S, e_s = lane - e_cw * S;
+    const int e_gc = wave * gw + e_cw;
+    const bool e_ok = e_gc < count;
+    const float* Xe = X + e_gc * 3 * npad;
+    float* Re = R + e_gc * 3 * npad;
+    const float w_s = (float)T.p.w_s, w_a = (float)T.p.w_a, w_b = (float)T.p.w_b;
+    const float s_min = (float)T.p.s_min, s_max = (float)T.p.s_max;
+
+    // MFMA tiling of this wave
+    const int RT = T.p.row_tiles, KS = T.p.k_steps;
+    const int ncols = 3 * count, CT = (ncols + 15) / 16, ntiles = RT * CT;
+    const int t0 = (ntiles * wave) / kFusedWaves, t1 = (ntiles * (wave + 1)) / kFusedWaves;
+
+    for (int k = 0; k < K; ++k) {
+      refresh_items(item);
+      // ---- volume constraint: grad V per vertex (staged in R), V and |grad V|^2 per cell
+      float vpart[NQ], gpart[NQ];
+#pragma unroll
+      for (int it = 0; it < NQ; ++it) {
+        vpart[it] = 0.0f;
+        gpart[it] = 0.0f;
+        if (ITEM_OK(it)) {
+          const float* Xc = X + ITEM_C(it) * 3 * npad;
+          float* Rc = R + ITEM_C(it) * 3 * npad;
+          const int vi = ITEM_V(it);
+          const Vec3<float> pi = v3<float>(Xc[vi], Xc[npad + vi], Xc[2 * npad + vi]);
+          float at;
+          const Vec3<float> gg = ring_volume_grad(T, Xc, npad, vi, pi, at);
+          Rc[vi] = gg.x; Rc[npad + vi] = gg.y; Rc[2 * npad + vi] = gg.z;
+          vpart[it] = dot3(pi, gg);
+          gpart[it] = dot3(gg, gg);
+        }
+      }
+      for (int cw = 0; cw < gw; ++cw) {
+        const int gc = wave * gw + cw;
+        double vs = 0.0, gs = 0.0;
+#pragma unroll
+        for (int it = 0; it < NQ; ++it)
+          if (ITEM_C(it) == gc) {
+            vs += (double)vpart[it];
+            gs += (double)gpart[it];
+          }
+        vs = wave_sum_d(vs);
+        gs = wave_sum_d(gs);
+        if (lane == 0) lam_lds[gc] = (float)(gs > 0.0 ? (T.p.V0 - vs / 3.0) / gs : 0.0);
+      }
+      __builtin_amdgcn_wave_barrier();
+      // ---- gradient of g: inertia + volume terms
+      refresh_items(item);
+#pragma unroll
+      for (int it = 0; it < NQ; ++it)
+        if (ITEM_OK(it)) {
+          float* Rc = R + ITEM_C(it) * 3 * npad;
+          const int vi = ITEM_V(it);
+          const float lw = w_v * lam_lds[ITEM_C(it)];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            Rc[c * npad + vi] = ih2m * e[it][c] - lw * Rc[c * npad + vi];
+        }
+      __builtin_amdgcn_wave_barrier();
+      // ---- triangle strain + area constraints
+      for (int r = 0; r < T.p.tri_rounds; ++r) {
+        const TriRec rec = T.tri_sched[r * S + e_s];
+        if (e_ok && rec.area > 0.0f) {
+          const int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
+          const Vec3<float> pa = v3<float>(Xe[a], Xe[npad + a], Xe[2 * npad + a]);
+          const Vec3<float> pb = v3<float>(Xe[b], Xe[npad + b], Xe[2 * npad + b]);
+          const Vec3<float> pc = v3<float>(Xe[c], Xe[npad + c], Xe[2 * npad + c]);
+          Vec3<float> ra, rb, rc;
+          triangle_residual<float>(pa, pb, pc, rec.gb0, rec.gb1, rec.gc0, rec.gc1, rec.area, w_s,
+                                   w_a, s_min, s_max, ra, rb, rc);
+          Re[a] += ra.x; Re[npad + a] += ra.y; Re[2 * npad + a] += ra.z;
+          Re[b] += rb.x; Re[npad + b] += rb.y; Re[2 * npad + b] += rb.z;
+          Re[c] += rc.x; Re[npad + c] += rc.y; Re[2 * npad + c] += rc.z;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      // ---- edge bending constraints
+      for (int r = 0; r < T.p.hinge_rounds; ++r) {
+        const HingeRec rec = T.hinge_sched[r * S + e_s];
+        if (e_ok && rec.rest >= 0.0f) {
+          const int i = (int)(rec.ij & 0xffffu), j = (int)(rec.ij >> 16);
+          const int kk = (int)(rec.kl & 0xffffu), l = (int)(rec.kl >> 16);
+          Vec3<float> ri, rj, rk, rl;
+          hinge_residual<float>(v3<float>(Xe[i], Xe[npad + i], Xe[2 * npad + i]),
+                                v3<float>(Xe[j], Xe[npad + j], Xe[2 * npad + j]),
+                                v3<float>(Xe[kk], Xe[npad + kk], Xe[2 * npad + kk]),
+                                v3<float>(Xe[l], Xe[npad + l], Xe[2 * npad + l]), rec.a1, rec.a2,
+                                rec.a3, rec.rest, w_b, ri, rj, rk, rl);
+          Re[i] += ri.x; Re[npad + i] += ri.y; Re[2 * npad + i] += ri.z;
+          Re[j] += rj.x; Re[npad + j] += rj.y; Re[2 * npad + j] += rj.z;
+          Re[kk] += rk.x; Re[npad + kk] += rk.y; Re[2 * npad + kk] += rk.z;
+          Re[l] += rl.x; Re[npad + l] += rl.y; Re[2 * npad + l] += rl.z;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      __syncthreads();
+      // ---- global step: D = -L^-1 R on the matrix cores
+      f4 acc[kMaxTilesPerWave];
+      const float* Lt = T.linv_tiles;
+#pragma unroll
+      for (int i = 0; i < kMaxTilesPerWave; ++i) {
+        acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+        const int t = t0 + i;
+        if (t < t1) {
+          const int rt = t / CT, ct = t - rt * CT;
+          const float* La = Lt + (size_t)rt * KS * 64 + lane;
+          int col = ct * 16 + (lane & 15);
+          col = col < ncols ? col : 0;
+          const float* Rb = R + col * npad + (lane >> 4);
+          f4 a4 = f4{0.f, 0.f, 0.f, 0.f};
+          for (int s = 0; s < KS; ++s)
+            a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(La[s * 64], Rb[4 * s], a4, 0, 0, 0);
+          acc[i] = a4;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kMaxTilesPerWave; ++i) {
+        const int t = t0 + i;
+        if (t < t1) {
+          const int rt = t / CT, ct = t - rt * CT;
+          const int col = ct * 16 + (lane & 15);
+          const int row0 = rt * 16 + 4 * (lane >> 4);
+          if (col < ncols) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (row0 + r < n) R[col * npad + row0 + r] = -acc[i][r];
+          }
+        }
+      }
+      __syncthreads();
+      // ---- update: delta += D (registers), x^{k+1} = x^k + D (LDS)
+      refresh_items(item);
+#pragma unroll
+      for (int it = 0; it < NQ; ++it)
+        if (ITEM_OK(it)) {
+          const float* Rc = R + ITEM_C(it) * 3 * npad;
+          float* Xc = X + ITEM_C(it) * 3 * npad;
+          const int vi = ITEM_V(it);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float dd = Rc[c * npad + vi];
+            e[it][c] += dd;
+            Xc[c * npad + vi] += dd;
+          }
+        }
+      __builtin_amdgcn_wave_barrier();
+    }
+
+    // ---- per-cell volume and area at x_{n+1} (FP64 reductions)
+    refresh_items(item);
+    if (vol_area) {
+      float vpart[NQ], apart[NQ];
+#pragma unroll
+      for (int it = 0; it < NQ; ++it) {
+        vpart[it] = 0.0f;
+        apart[it] = 0.0f;
+        if (ITEM_OK(it)) {
+          const float* Xc = X + ITEM_C(it) * 3 * npad;
+          const int vi = ITEM_V(it);
+          const Vec3<float> pi = v3<float>(Xc[vi], Xc[npad + vi], Xc[2 * npad + vi]);
+          float at;
+          const Vec3<float> gg = ring_volume_grad(T, Xc, npad, vi, pi, at);
+          vpart[it] = dot3(pi, gg);
+          apart[it] = at;
+        }
+      }
+      for (int cw = 0; cw < gw; ++cw) {
+        const int gc = wave * gw + cw;
+        double vs = 0.0, as = 0.0;
+#pragma unroll
+        for (int it = 0; it < NQ; ++it)
+          if (ITEM_C(it) == gc) {
+            vs += (double)vpart[it];
+            as += (double)apart[it];
+          }
+        vs = wave_sum_d(vs);
+        as = wave_sum_d(as);
+        if (lane == 0 && gc < count) {
+          vol_area[2 * (int64_t)grp.cells[gc]] = vs / 3.0;
+          vol_area[2 * (int64_t)grp.cells[gc] + 1] = as;
+        }
+      }
+    }
+    // ---- x_{n+1} = x_n + delta, v_{n+1} = delta / h with delta = delta^0 + e
+    refresh_items(item);
+    bool bad = false;
+#pragma unroll
+    for (int it = 0; it < NQ; ++it)
+      if (ITEM_OK(it)) {
+        const int64_t off = off_lds[ITEM_C(it)];
+        const int vi = ITEM_V(it);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float dl = (h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi]) + e[it][c];
+          const float xn = x[c * vt + off + vi] + dl;
+          const float vn = dl * ih;
+          x[c * vt + off + vi] = xn;
+          v[c * vt + off + vi] = vn;
+          bad |= !(finite_f(xn) && finite_f(vn));
+        }
+      }
+    if (bad) atomicOr(flag, 1);
+#undef ITEM_OK
+#undef ITEM_V
+#undef ITEM_C
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
+                             int n_groups, const int64_t* offsets, int64_t vtot, float* x,
+                             float* v, const float* f, int K, double* vol_area, int* flag,
+                             size_t lds_bytes, int grid, void* stream) {
+  (void)n_types;
+  if (n_groups == 0) return hipSuccess;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_fused_step<kMaxItems>, dim3(grid), dim3(kFusedThreads), lds_bytes, s,
+                     types_dev, groups, n_groups, offsets, vtot, x, v, f, K, vol_area, flag);
+  return hipGetLastError();
+}
+
+}  // namespace npfem

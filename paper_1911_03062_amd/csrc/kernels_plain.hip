@@ -1,0 +1,299 @@
+// Plain one-cell-at-a-time form of the npFEM step: for one cell, a prediction kernel, then
+// n_pd_iters pairs of (local, global) kernels, then a finalisation kernel, each a separate
+// launch of one workgroup (2K + 2 launches per cell and step). Templated on precision; the
+// FP64 instance runs the whole path in double.
+//
+// Step (supplementary material, npFEM subsection, implicit Euler and its quasi-Newton
+// iteration, damping C = 0): delta = x - x_n; delta^0 = h v_n + h^2 F/m (prediction y);
+// iterate delta <- delta - L^-1 grad g(x_n + delta); then x_{n+1} = x_n + delta,
+// v_{n+1} = delta / h. Positions inside the kernels are taken relative to the cell's first
+// vertex, which leaves every difference, and the enclosed volume, unchanged.
+#include <hip/hip_runtime.h>
+
+#include "npfem_internal.h"
+#include "projections.h"
+
+namespace npfem {
+
+namespace {
+
+constexpr int kPlainThreads = 256;
+constexpr int kMaxBand = 1024;
+
+template <typename T>
+struct PlainWork {
+  // all arrays live in one device allocation, laid out by plain_layout()
+  T* d0;      // [3][n] delta^0
+  T* d;       // [3][n] delta^k
+  T* r;       // [3][n] gradient of g
+  T* gv;      // [3][n] volume gradient
+  T* tcon;    // [m][3][3] triangle contributions to (a, b, c)
+  T* tn;      // [m][3] twice the triangle area vector
+  T* hcon;    // [e][4][3] hinge contributions
+};
+
+template <typename T>
+__host__ __device__ inline PlainWork<T> plain_layout(void* base, int n, int m, int e) {
+  T* p = reinterpret_cast<T*>(base);
+  PlainWork<T> w;
+  w.d0 = p; p += 3 * n;
+  w.d = p; p += 3 * n;
+  w.r = p; p += 3 * n;
+  w.gv = p; p += 3 * n;
+  w.tcon = p; p += 9 * m;
+  w.tn = p; p += 3 * m;
+  w.hcon = p;
+  return w;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  const int nw = (blockDim.x + 63) / 64;
+  for (int i = 0; i < nw; ++i) s += sh[i];   // same order in every thread
+  return s;
+}
+
+template <typename T>
+__device__ inline Vec3<T> cell_pos(const T* x, int64_t vt, int64_t off, const T* d, int n, int i) {
+  return v3<T>((x[off + i] - x[off]) + d[i], (x[vt + off + i] - x[vt + off]) + d[n + i],
+               (x[2 * vt + off + i] - x[2 * vt + off]) + d[2 * n + i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPlainThreads)
+k_plain_predict(TypeParams p, const T* __restrict__ v, const T* __restrict__ f, int64_t vt,
+                int64_t off, void* work) {
+  PlainWork<T> w = plain_layout<T>(work, p.n, p.m, p.e);
+  const T h = T(p.h), h2m = T(p.h2_over_m);
+  for (int i = threadIdx.x; i < p.n; i += blockDim.x)
+    for (int c = 0; c < 3; ++c) {
+      const T d0 = h * v[c * vt + off + i] + h2m * f[c * vt + off + i];
+      w.d0[c * p.n + i] = d0;
+      w.d[c * p.n + i] = d0;
+    }
+}
+
+template <typename T>
+struct PlainConst;
+template <>
+struct PlainConst<float> {
+  static __device__ const float* G(const DevType& t) { return t.G32; }
+  static __device__ const float* A(const DevType& t) { return t.A32; }
+  static __device__ const float* coef(const DevType& t) { return t.coef32; }
+  static __device__ const float* rest(const DevType& t) { return t.rest32; }
+  static __device__ const float* cband(const DevType& t) { return t.cband32; }
+};
+template <>
+struct PlainConst<double> {
+  static __device__ const double* G(const DevType& t) { return t.G64; }
+  static __device__ const double* A(const DevType& t) { return t.A64; }
+  static __device__ const double* coef(const DevType& t) { return t.coef64; }
+  static __device__ const double* rest(const DevType& t) { return t.rest64; }
+  static __device__ const double* cband(const DevType& t) { return t.cband64; }
+};
+
+// Local step: projections of every constraint at x^k and assembly of grad g(x^k) into r.
+template <typename T>
+__global__ void __launch_bounds__(kPlainThreads)
+k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t vt, int64_t off,
+              void* work) {
+  const DevType& dt = *dtp;
+  const TypeParams& p = dt.p;
+  const int n = p.n, m = p.m, e = p.e;
+  PlainWork<T> w = plain_layout<T>(work, n, m, e);
+  const T* G = PlainConst<T>::G(dt);
+  const T* A = PlainConst<T>::A(dt);
+  const T* coef = PlainConst<T>::coef(dt);
+  const T* rest = PlainConst<T>::rest(dt);
+  __shared__ double sh[8];
+  __shared__ double lam_sh;
+
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    const int a = dt.tri[3 * t], b = dt.tri[3 * t + 1], c = dt.tri[3 * t + 2];
+    const Vec3<T> pa = cell_pos(x, vt, off, w.d, n, a);
+    const Vec3<T> pb = cell_pos(x, vt, off, w.d, n, b);
+    const Vec3<T> pc = cell_pos(x, vt, off, w.d, n, c);
+    Vec3<T> ra, rb, rc;
+    triangle_residual<T>(pa, pb, pc, G[6 * t + 2], G[6 * t + 3], G[6 * t + 4], G[6 * t + 5],
+                         A[t], T(p.w_s), T(p.w_a), T(p.s_min), T(p.s_max), ra, rb, rc);
+    T* tc = w.tcon + 9 * t;
+    tc[0] = ra.x; tc[1] = ra.y; tc[2] = ra.z;
+    tc[3] = rb.x; tc[4] = rb.y; tc[5] = rb.z;
+    tc[6] = rc.x; tc[7] = rc.y; tc[8] = rc.z;
+    const Vec3<T> nt = cross3(pb - pa, pc - pa);
+    w.tn[3 * t] = nt.x; w.tn[3 * t + 1] = nt.y; w.tn[3 * t + 2] = nt.z;
+  }
+  for (int h = threadIdx.x; h < e; h += blockDim.x) {
+    const int* hv = dt.hinge + 4 * h;
+    Vec3<T> ri, rj, rk, rl;
+    hinge_residual<T>(cell_pos(x, vt, off, w.d, n, hv[0]), cell_pos(x, vt, off, w.d, n, hv[1]),
+                      cell_pos(x, vt, off, w.d, n, hv[2]), cell_pos(x, vt, off, w.d, n, hv[3]),
+                      coef[4 * h + 1], coef[4 * h + 2], coef[4 * h + 3], rest[h], T(p.w_b),
+                      ri, rj, rk, rl);
+    T* hc = w.hcon + 12 * h;
+    hc[0] = ri.x; hc[1] = ri.y; hc[2] = ri.z;
+    hc[3] = rj.x; hc[4] = rj.y; hc[5] = rj.z;
+    hc[6] = rk.x; hc[7] = rk.y; hc[8] = rk.z;
+    hc[9] = rl.x; hc[10] = rl.y; hc[11] = rl.z;
+  }
+  __syncthreads();
+  // volume gradient (1/6 of the summed doubled area vectors of the incident triangles),
+  // V = 1/3 sum_i x_i . grad_i V and |grad V|^2, reduced in FP64
+  double vpart = 0, gpart = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T gx = 0, gy = 0, gz = 0;
+    for (int s = dt.vt_off[i]; s < dt.vt_off[i + 1]; ++s) {
+      const int t = dt.vt_list[s] / 3;
+      gx += w.tn[3 * t]; gy += w.tn[3 * t + 1]; gz += w.tn[3 * t + 2];
+    }
+    gx *= T(1.0 / 6.0); gy *= T(1.0 / 6.0); gz *= T(1.0 / 6.0);
+    w.gv[i] = gx; w.gv[n + i] = gy; w.gv[2 * n + i] = gz;
+    const Vec3<T> pi = cell_pos(x, vt, off, w.d, n, i);
+    vpart += (double)pi.x * (double)gx + (double)pi.y * (double)gy + (double)pi.z * (double)gz;
+    gpart += (double)gx * (double)gx + (double)gy * (double)gy + (double)gz * (double)gz;
+  }
+  const double V = block_sum(vpart, sh) / 3.0;
+  const double G2 = block_sum(gpart, sh);
+  if (threadIdx.x == 0) lam_sh = G2 > 0 ? (p.V0 - V) / G2 : 0.0;
+  __syncthreads();
+  const T lam_w = T(lam_sh * p.w_v);
+  const T ih2m = T(p.inv_h2m);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int c = 0; c < 3; ++c) {
+      T acc = ih2m * (w.d[c * n + i] - w.d0[c * n + i]);
+      for (int s = dt.vt_off[i]; s < dt.vt_off[i + 1]; ++s) acc += w.tcon[3 * dt.vt_list[s] + c];
+      for (int s = dt.vh_off[i]; s < dt.vh_off[i + 1]; ++s) acc += w.hcon[3 * dt.vh_list[s] + c];
+      acc -= lam_w * w.gv[c * n + i];
+      w.r[c * n + i] = acc;
+    }
+  }
+}
+
+// Global step: solve L D = r with the banded Cholesky factor (three right-hand sides, one
+// wave per coordinate, band products reduced across the wave), then delta -= D.
+template <typename T>
+__global__ void __launch_bounds__(192)
+k_plain_solve(const DevType* __restrict__ dtp, void* work) {
+  const DevType& dt = *dtp;
+  const int n = dt.p.n, bw = dt.p.bw, bs = bw + 1;
+  PlainWork<T> w = plain_layout<T>(work, n, dt.p.m, dt.p.e);
+  const T* cb = PlainConst<T>::cband(dt);
+  __shared__ T y[3][kMaxBand];
+  const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T* yc = y[c];
+  const T* rc = w.r + c * n;
+  for (int i = 0; i < n; ++i) {
+    T part = 0;
+    const int kmax = bw < i ? bw : i;
+    for (int k = lane + 1; k <= kmax; k += 64) part += cb[i * bs + k] * yc[i - k];
+    const T s = wave_sum(part);
+    const T yi = (rc[i] - s) / cb[i * bs];
+    if (lane == 0) yc[i] = yi;
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    T part = 0;
+    const int kmax = bw < (n - 1 - i) ? bw : (n - 1 - i);
+    for (int k = lane + 1; k <= kmax; k += 64) part += cb[(i + k) * bs + k] * yc[i + k];
+    const T s = wave_sum(part);
+    const T xi = (yc[i] - s) / cb[i * bs];
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) yc[i] = xi;
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int i = lane; i < n; i += 64) w.d[c * n + i] -= yc[i];
+}
+
+template <typename T>
+__device__ inline bool finite_val(T v) { return v == v && v - v == T(0); }
+
+template <typename T>
+__global__ void __launch_bounds__(kPlainThreads)
+k_plain_finalize(const DevType* __restrict__ dtp, T* __restrict__ x, T* __restrict__ v,
+                 int64_t vt, int64_t off, void* work, double* vol_area, int* flag) {
+  const DevType& dt = *dtp;
+  const TypeParams& p = dt.p;
+  const int n = p.n, m = p.m;
+  PlainWork<T> w = plain_layout<T>(work, n, m, p.e);
+  __shared__ double sh[8];
+  if (vol_area) {
+    double vs = 0, as = 0;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+      const Vec3<T> pa = cell_pos(x, vt, off, w.d, n, dt.tri[3 * t]);
+      const Vec3<T> pb = cell_pos(x, vt, off, w.d, n, dt.tri[3 * t + 1]);
+      const Vec3<T> pc = cell_pos(x, vt, off, w.d, n, dt.tri[3 * t + 2]);
+      const Vec3<T> nt = cross3(pb - pa, pc - pa);
+      vs += (double)pa.x * nt.x + (double)pa.y * nt.y + (double)pa.z * nt.z;
+      as += sqrt((double)nt.x * nt.x + (double)nt.y * nt.y + (double)nt.z * nt.z);
+    }
+    const double V = block_sum(vs, sh) / 6.0;
+    const double S = block_sum(as, sh) * 0.5;
+    if (threadIdx.x == 0) {
+      vol_area[0] = V;
+      vol_area[1] = S;
+    }
+  }
+  __syncthreads();
+  const T ih = T(1) / T(p.h);
+  bool bad = false;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int c = 0; c < 3; ++c) {
+      const T d = w.d[c * n + i];
+      const T xn = x[c * vt + off + i] + d;
+      const T vn = d * ih;
+      x[c * vt + off + i] = xn;
+      v[c * vt + off + i] = vn;
+      bad |= !(finite_val(xn) && finite_val(vn));
+    }
+  if (bad) atomicOr(flag, 1);
+}
+
+template <typename T>
+hipError_t plain_step_t(const DevType* dt_dev, const TypeParams& p, T* x, T* v, const T* f,
+                        int64_t vt, int64_t off, int K, void* work, double* vol_area, int* flag,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_plain_predict<T>, dim3(1), dim3(kPlainThreads), 0, s, p, v, f, vt, off,
+                     work);
+  for (int k = 0; k < K; ++k) {
+    hipLaunchKernelGGL(k_plain_local<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt, off,
+                       work);
+    hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work);
+  }
+  hipLaunchKernelGGL(k_plain_finalize<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, v, vt,
+                     off, work, vol_area, flag);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t plain_work_bytes(int precision, int n, int m, int e) {
+  const size_t el = precision == 64 ? 8 : 4;
+  return el * (12 * (size_t)n + 12 * (size_t)m + 12 * (size_t)e) + 256;
+}
+
+bool plain_supported(int n, int bw) { return n <= kMaxBand && bw < kMaxBand; }
+
+hipError_t launch_plain_cell(int precision, const DevType* dt_dev, const TypeParams& p, void* x,
+                             void* v, const void* f, int64_t vtot, int64_t off, int K,
+                             void* work, double* vol_area, int* flag, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (precision == 64)
+    return plain_step_t<double>(dt_dev, p, (double*)x, (double*)v, (const double*)f, vtot, off, K,
+                                work, vol_area, flag, s);
+  return plain_step_t<float>(dt_dev, p, (float*)x, (float*)v, (const float*)f, vtot, off, K,
+                             work, vol_area, flag, s);
+}
+
+}  // namespace npfem

@@ -1,0 +1,154 @@
+// Internal declarations shared by the host setup, the C ABI and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/npfem.h"
+
+namespace npfem {
+
+// ------------------------------------------------------------------------------------------
+// Device-side records (plain structs, identical layout on host and device).
+// ------------------------------------------------------------------------------------------
+
+// One triangle slot of the per-wave round schedule (32 bytes). A slot with area == 0 is
+// empty. g_b, g_c are the rest-frame gradient vectors (g_a = -g_b - g_c).
+struct TriRec {
+  uint32_t ab;        // a | b << 16
+  uint32_t c;         // c
+  float gb0, gb1, gc0, gc1;
+  float area;
+  float pad;
+};
+
+// One hinge slot (32 bytes): edge (i, j), opposite vertices k, l, stencil a_e, rest norm.
+// A slot with rest < 0 is empty.
+struct HingeRec {
+  uint32_t ij;        // i | j << 16
+  uint32_t kl;        // k | l << 16
+  float a0, a1, a2, a3;
+  float rest;
+  float pad;
+};
+
+// Scalar parameters of a cell type as seen by the kernels.
+struct TypeParams {
+  int32_t n, m, e, bw;          // vertices, triangles, hinges, band width of L
+  int32_t npad;                 // LDS row stride of one (cell, coordinate) column (fused)
+  int32_t gw;                   // cells owned by one wave in a fused group
+  int32_t slots;                // element slots per cell in a wave (64 / gw)
+  int32_t tri_rounds, hinge_rounds;
+  int32_t row_tiles;            // ceil(n / 16): MFMA row tiles of L^-1
+  int32_t k_steps;              // npad / 4: MFMA k steps
+  int32_t pad0;
+  double h, mass, inv_h2m;      // h, m, m / h^2
+  double h2_over_m;             // h^2 / m
+  double w_s, w_a, w_b, w_v;
+  double s_min, s_max;
+  double V0;
+};
+
+// Device copy of a cell type's constants. Pointers are device pointers.
+struct DevType {
+  TypeParams p;
+  // fused form
+  TriRec* tri_sched = nullptr;       // [tri_rounds][slots]
+  HingeRec* hinge_sched = nullptr;   // [hinge_rounds][slots]
+  uint32_t* ring_info = nullptr;     // [n]: offset << 8 | degree
+  uint32_t* ring_pairs = nullptr;    // [sum deg]: b | c << 16
+  float* linv_tiles = nullptr;       // [row_tiles][k_steps][64] MFMA A-operand order
+  // plain form (both precisions)
+  int32_t* tri = nullptr;            // [m][3]
+  int32_t* hinge = nullptr;          // [e][4]
+  int32_t* vt_off = nullptr;         // [n+1] vertex -> (t*3 + j)
+  int32_t* vt_list = nullptr;
+  int32_t* vh_off = nullptr;         // [n+1] vertex -> (e*4 + q)
+  int32_t* vh_list = nullptr;
+  double* G64 = nullptr;  float* G32 = nullptr;          // [m][3][2]
+  double* A64 = nullptr;  float* A32 = nullptr;          // [m]
+  double* coef64 = nullptr; float* coef32 = nullptr;     // [e][4]
+  double* rest64 = nullptr; float* rest32 = nullptr;     // [e]
+  double* cband64 = nullptr; float* cband32 = nullptr;   // [n][bw+1]: C[i][i-k]
+};
+
+}  // namespace npfem
+
+// ------------------------------------------------------------------------------------------
+// Host objects behind the opaque C handles.
+// ------------------------------------------------------------------------------------------
+
+struct npfem_celltype {
+  int n = 0, m = 0, e = 0, bw = 0;
+  double h = 0, V0 = 0, area0 = 0, mass = 0;
+  double w_s = 0, w_a = 0, w_b = 0, w_v = 0, s_min = 1, s_max = 1;
+  std::vector<double> X;          // [n][3]
+  std::vector<int32_t> tri;       // [m][3]
+  std::vector<double> G;          // [m][3][2]
+  std::vector<double> A;          // [m]
+  std::vector<int32_t> hinge;     // [e][4]
+  std::vector<double> coef;       // [e][4]
+  std::vector<double> rest_norm;  // [e]
+  std::vector<double> L;          // [n][n]
+  std::vector<double> chol;       // [n][n] lower Cholesky factor
+  std::vector<double> cband;      // [n][bw+1]
+  std::vector<double> Linv;       // [n][n]
+  std::vector<int32_t> vt_off, vt_list, vh_off, vh_list;
+  std::vector<uint32_t> ring_info, ring_pairs;
+  // fused-form schedule
+  int gw = 0, slots = 0, npad = 0, tri_rounds = 0, hinge_rounds = 0;
+  std::vector<npfem::TriRec> tri_sched;
+  std::vector<npfem::HingeRec> hinge_sched;
+  bool fused_ok = false;
+  std::string fused_reason;
+
+  std::mutex mu;
+  std::map<int, npfem::DevType*> dev;   // per HIP device
+  ~npfem_celltype();
+};
+
+namespace npfem {
+
+void set_error(const std::string& msg);
+npfem_status fail(npfem_status s, const std::string& msg);
+
+// Host setup (setup.cpp).
+npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, double dt,
+                            npfem_celltype* ct);
+
+// Device upload of a cell type (device.cpp); returns the device copy for the current device.
+npfem_status upload_celltype(npfem_celltype* ct, DevType** out);
+void free_devtype(DevType* d);
+
+constexpr int kFusedThreads = 256;          // 4 waves per workgroup
+constexpr int kFusedWaves = 4;
+constexpr int kMaxItems = 9;                // owner items per lane (cells x vertices / 64)
+constexpr int kFusedLdsBudget = 52224;      // bytes of LDS per fused workgroup
+constexpr int kMaxGroupCells = 64;
+
+// One group of same-type cells processed by one fused workgroup.
+struct FusedGroup {
+  int32_t type;                  // index into the batch's type table
+  int32_t count;                 // cells in the group (<= 4 * gw)
+  int32_t cells[kMaxGroupCells]; // batch cell ids
+};
+
+constexpr int kMaxTilesPerWave = 9;         // MFMA 16x16 output tiles held per wave
+
+// Kernel launchers and sizes (kernels_plain.hip, kernels_fused.hip).
+size_t plain_work_bytes(int precision, int n, int m, int e);
+bool plain_supported(int n, int bw);
+hipError_t launch_plain_cell(int precision, const DevType* dt_dev, const TypeParams& p, void* x,
+                             void* v, const void* f, int64_t vtot, int64_t off, int K,
+                             void* work, double* vol_area, int* flag, void* stream);
+hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
+                             int n_groups, const int64_t* offsets, int64_t vtot, float* x,
+                             float* v, const float* f, int K, double* vol_area, int* flag,
+                             size_t lds_bytes, int grid, void* stream);
+
+}  // namespace npfem

@@ -1,0 +1,153 @@
+// Device-side local step of the npFEM iteration: per-triangle strain/area and per-hinge
+// bending residuals of the projective-dynamics constraint energies, templated on precision.
+//
+// Triangle (constraint energies A_t w/2 ||F - p||^2, F = sum_j x_j g_j^T, 3x2):
+//   C = F^T F, s = |F0 x F1| = s1 s2, t = sqrt(tr C + 2 s) = s1 + s2,
+//   disc = sqrt((c00 - c11)^2 + 4 c01^2) = s1^2 - s2^2,
+//   polar factor R = F (F^T F)^(-1/2) = F [[c11 + s, -c01], [-c01, c00 + s]] / (s t),
+//   stretch S = R^T F = (C + s I)/t with eigen-frame Q = [[cos 2a, sin 2a], [sin 2a, -cos 2a]]
+//   (cos 2a, sin 2a) = (c00 - c11, 2 c01)/disc.
+// Any symmetric 2x2 V diag(p, q) V^T in that frame equals (p+q)/2 I + (p-q)/2 Q, so the
+// residual of both projections (strain: singular values clamped to [s_min, s_max]; area:
+// (d, 1/d) nearest to (s1, s2)) is  F - p = R (alpha I + beta Q)  and the contribution to
+// vertex j is  A_t R (w_s (S - S_s) + w_a (S - S_a)) g_j.  All "singular value minus target"
+// differences are formed from a = s1 - 1, b = s2 - 1 and eps = d - 1 so that near the rest
+// state no difference of two numbers close to one is taken twice.
+//
+// Area root: d minimises (d - s1)^2 + (1/d - s2)^2, i.e. solves d^4 - s1 d^3 + s2 d - 1 = 0;
+// with d = 1 + eps, a = s1 - 1, b = s2 - 1 the quartic reads
+//   (b - a) + eps (2 - 3a + b) + eps^2 (3 - 3a) + eps^3 (3 - a) + eps^4 = 0,
+// solved by Newton from eps0 = sqrt(s1/s2) - 1 (exact when s1 = s2). The kernels assume the
+// regime of a single positive root near that start (stretches below 2x in both directions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace npfem {
+
+template <typename T>
+struct Vec3 {
+  T x, y, z;
+};
+
+template <typename T>
+__device__ __forceinline__ Vec3<T> v3(T x, T y, T z) { return {x, y, z}; }
+template <typename T>
+__device__ __forceinline__ Vec3<T> operator-(Vec3<T> a, Vec3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T>
+__device__ __forceinline__ Vec3<T> operator+(Vec3<T> a, Vec3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T>
+__device__ __forceinline__ Vec3<T> operator*(Vec3<T> a, T s) { return {a.x * s, a.y * s, a.z * s}; }
+template <typename T>
+__device__ __forceinline__ T dot3(Vec3<T> a, Vec3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T>
+__device__ __forceinline__ Vec3<T> cross3(Vec3<T> a, Vec3<T> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+__device__ __forceinline__ float dsqrt(float v) { return __builtin_sqrtf(v); }
+__device__ __forceinline__ double dsqrt(double v) { return __builtin_sqrt(v); }
+
+template <typename T>
+__device__ __forceinline__ T clamp_dev(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Triangle residual contributions. Inputs: vertex positions pa, pb, pc (any common origin),
+// rest gradients gb, gc (g_a = -g_b - g_c), rest area, weights. Outputs: contributions to
+// the gradient of g at vertices a, b, c.
+template <typename T>
+__device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T> pc, T gb0,
+                                                  T gb1, T gc0, T gc1, T area, T w_s, T w_a,
+                                                  T s_min, T s_max, Vec3<T>& ra, Vec3<T>& rb,
+                                                  Vec3<T>& rc) {
+  const Vec3<T> e1 = pb - pa, e2 = pc - pa;
+  const Vec3<T> F0 = e1 * gb0 + e2 * gc0;
+  const Vec3<T> F1 = e1 * gb1 + e2 * gc1;
+  const T c00 = dot3(F0, F0), c01 = dot3(F0, F1), c11 = dot3(F1, F1);
+  const Vec3<T> nr = cross3(F0, F1);
+  const T s = dsqrt(dot3(nr, nr));                 // s1 s2
+  const T tr = c00 + c11;
+  const T tt = dsqrt(tr + T(2) * s);               // s1 + s2
+  const T dl = c00 - c11, of = T(2) * c01;
+  const T disc = dsqrt(dl * dl + of * of);         // s1^2 - s2^2
+  Vec3<T> R0, R1;
+  T a, b, q_c, q_s;
+  if (s > T(1e-30) * (tr + T(1e-30))) {
+    const T inv = T(1) / (s * tt);
+    R0 = (F0 * (c11 + s) - F1 * c01) * inv;
+    R1 = (F1 * (c00 + s) - F0 * c01) * inv;
+    const T half_diff = disc / (T(2) * tt);        // (s1 - s2)/2
+    // (s1 + s2) - 2 = ((c00 - 1) + (c11 - 1) + 2 (s - 1)) / (s1 + s2 + 2); each bracket is
+    // an exact subtraction for entries within a factor two of one
+    const T tm2 = ((c00 - T(1)) + (c11 - T(1)) + T(2) * (s - T(1))) / (tt + T(2));
+    a = T(0.5) * tm2 + half_diff;
+    b = T(0.5) * tm2 - half_diff;
+  } else {
+    // rank-deficient F: Gram-Schmidt frame of F's columns (any orthonormal completion)
+    T n0 = dsqrt(c00);
+    if (n0 > T(0)) R0 = F0 * (T(1) / n0);
+    else R0 = v3<T>(1, 0, 0);
+    Vec3<T> w = F1 - R0 * dot3(R0, F1);
+    T nw = dsqrt(dot3(w, w));
+    if (nw > T(1e-30)) R1 = w * (T(1) / nw);
+    else {
+      Vec3<T> ax = (R0.x * R0.x < T(0.5)) ? v3<T>(1, 0, 0) : v3<T>(0, 1, 0);
+      w = ax - R0 * dot3(R0, ax);
+      R1 = w * (T(1) / dsqrt(dot3(w, w)));
+    }
+    a = dsqrt(tr) - T(1);
+    b = T(-1);
+  }
+  if (disc > T(0)) {
+    const T id = T(1) / disc;
+    q_c = dl * id;
+    q_s = of * id;
+  } else {
+    q_c = T(1);
+    q_s = T(0);
+  }
+  // strain: s - clamp(s) per singular value
+  const T ds1 = (a > s_max - T(1) ? a - (s_max - T(1)) : T(0)) + (a < s_min - T(1) ? a - (s_min - T(1)) : T(0));
+  const T ds2 = (b > s_max - T(1) ? b - (s_max - T(1)) : T(0)) + (b < s_min - T(1) ? b - (s_min - T(1)) : T(0));
+  // area: eps = d - 1 by Newton on the shifted quartic
+  const T s1 = T(1) + a, s2 = T(1) + b;
+  T eps = (s2 > T(0)) ? dsqrt(s1 / s2) - T(1) : T(0);
+  const T k0 = b - a, k1 = T(2) - T(3) * a + b, k2 = T(3) - T(3) * a, k3 = T(3) - a;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const T fv = k0 + eps * (k1 + eps * (k2 + eps * (k3 + eps)));
+    const T fp = k1 + eps * (T(2) * k2 + eps * (T(3) * k3 + T(4) * eps));
+    eps = (fp != T(0)) ? eps - fv / fp : eps;
+  }
+  const T ip = T(1) / (T(1) + eps);
+  const T sum_a = (a + b) - eps * eps * ip;                    // (s1 + s2) - (d + 1/d)
+  const T dif_a = (a - b) - eps * (T(2) + eps) * ip;           // (s1 - s2) - (d - 1/d)
+  const T alpha = T(0.5) * (w_s * (ds1 + ds2) + w_a * sum_a);
+  const T beta = T(0.5) * (w_s * (ds1 - ds2) + w_a * dif_a);
+  // T = alpha I + beta Q ; M = area R T (columns M0, M1)
+  const T t00 = alpha + beta * q_c, t01 = beta * q_s, t11 = alpha - beta * q_c;
+  const Vec3<T> M0 = (R0 * t00 + R1 * t01) * area;
+  const Vec3<T> M1 = (R0 * t01 + R1 * t11) * area;
+  rb = M0 * gb0 + M1 * gb1;
+  rc = M0 * gc0 + M1 * gc1;
+  ra = v3<T>(-(rb.x + rc.x), -(rb.y + rc.y), -(rb.z + rc.z));
+}
+
+// Hinge residual: u = sum_q a_q x_q (written relative to x_i, since sum_q a_q = 0),
+// p = r u/|u|, contribution w_b a_q (u - p) to vertex q; the contribution to i is minus the
+// sum of the other three so that the four add up to zero.
+template <typename T>
+__device__ __forceinline__ void hinge_residual(Vec3<T> pi, Vec3<T> pj, Vec3<T> pk, Vec3<T> pl,
+                                               T a1, T a2, T a3, T rest, T w_b, Vec3<T>& ri,
+                                               Vec3<T>& rj, Vec3<T>& rk, Vec3<T>& rl) {
+  const Vec3<T> u = (pj - pi) * a1 + (pk - pi) * a2 + (pl - pi) * a3;
+  const T nu2 = dot3(u, u);
+  T fac = T(0);
+  if (nu2 > T(0)) fac = w_b * (T(1) - rest / dsqrt(nu2));
+  const Vec3<T> W = u * fac;
+  rj = W * a1;
+  rk = W * a2;
+  rl = W * a3;
+  ri = v3<T>(-(rj.x + rk.x + rl.x), -(rj.y + rk.y + rl.y), -(rj.z + rk.z + rl.z));
+}
+
+}  // namespace npfem

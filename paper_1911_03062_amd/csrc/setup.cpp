@@ -1,0 +1,372 @@
+// Host-side (FP64) setup of a cell type: mesh validation, triangle rest frames, bending
+// stencils, lumped mass, assembly and factorisation of the constant system matrix L, its
+// inverse, and the per-wave element schedules of the fused kernel.
+//
+// The method is the implicit-Euler step of the supplementary material (npFEM subsection):
+// g(x) = 1/(2h^2) ||M^(1/2)(x - y)||^2 + sum_i E_i(x), minimised by the quasi-Newton
+// iteration with a constant Hessian approximation. With projective-dynamics energies
+// w/2 ||A x - p||^2 that approximation is L = M/h^2 + sum w A^T A, built here once per type.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <set>
+#include <utility>
+
+#include "npfem_internal.h"
+
+namespace npfem {
+
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 scale(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+
+// cot of the angle between u and v
+inline double cot(V3 u, V3 v) { return dot(u, v) / norm(cross(u, v)); }
+
+// Greedy packing of elements (each touching `arity` vertices) into rounds of at most
+// `slots` elements whose vertex sets are pairwise disjoint. Elements touching the busiest
+// vertices are placed first; each goes to the least-filled round it fits in.
+std::vector<std::vector<int>> pack_rounds(const std::vector<std::vector<int>>& elems, int n,
+                                          int slots) {
+  std::vector<int> deg(n, 0);
+  for (auto& el : elems)
+    for (int v : el) deg[v]++;
+  std::vector<int> order(elems.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    int da = 0, db = 0;
+    for (int v : elems[a]) da = std::max(da, deg[v]);
+    for (int v : elems[b]) db = std::max(db, deg[v]);
+    return da > db;
+  });
+  int max_deg = 0;
+  for (int d : deg) max_deg = std::max(max_deg, d);
+  int lower = std::max<int>(max_deg, (int)((elems.size() + slots - 1) / slots));
+  std::vector<std::vector<int>> rounds(lower);
+  std::vector<std::vector<char>> used(lower, std::vector<char>(n, 0));
+  for (int id : order) {
+    int best = -1;
+    size_t best_fill = (size_t)slots;
+    for (int r = 0; r < (int)rounds.size(); ++r) {
+      if (rounds[r].size() >= (size_t)slots) continue;
+      bool ok = true;
+      for (int v : elems[id])
+        if (used[r][v]) { ok = false; break; }
+      if (ok && rounds[r].size() < best_fill) { best = r; best_fill = rounds[r].size(); }
+    }
+    if (best < 0) {
+      rounds.emplace_back();
+      used.emplace_back(n, 0);
+      best = (int)rounds.size() - 1;
+    }
+    rounds[best].push_back(id);
+    for (int v : elems[id]) used[best][v] = 1;
+  }
+  return rounds;
+}
+
+}  // namespace
+
+npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, double dt,
+                            npfem_celltype* ct) {
+  if (!mesh || !mat || !mesh->rest_xyz || !mesh->tri)
+    return fail(NPFEM_E_INVALID, "null mesh or material");
+  const int n = mesh->n_vertices, m = mesh->n_triangles;
+  if (n < 4 || m < 4) return fail(NPFEM_E_MESH, "mesh needs >= 4 vertices and triangles");
+  if (n > 65535) return fail(NPFEM_E_UNSUPPORTED, "meshes above 65535 vertices");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_E_INVALID, "dt must be > 0");
+  if (!(mat->density > 0) || mat->shear_B < 0 || mat->area_C < 0 || mat->k_bend < 0 ||
+      mat->k_vol < 0 || !(mat->strain_min > 0) || mat->strain_max < mat->strain_min)
+    return fail(NPFEM_E_INVALID, "material constants out of range");
+
+  ct->n = n;
+  ct->m = m;
+  ct->h = dt;
+  ct->w_s = mat->shear_B;
+  ct->w_a = mat->area_C;
+  ct->w_b = mat->k_bend;
+  ct->w_v = mat->k_vol;
+  ct->s_min = mat->strain_min;
+  ct->s_max = mat->strain_max;
+  ct->X.assign(mesh->rest_xyz, mesh->rest_xyz + 3 * (size_t)n);
+  ct->tri.assign(mesh->tri, mesh->tri + 3 * (size_t)m);
+  for (double c : ct->X)
+    if (!std::isfinite(c)) return fail(NPFEM_E_MESH, "non-finite rest coordinate");
+
+  auto P = [&](int i) { return V3{ct->X[3 * i], ct->X[3 * i + 1], ct->X[3 * i + 2]}; };
+
+  // ---- topology: closed, edge-manifold, consistently oriented, no unused vertex
+  double ext = 0;
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) ext = std::max(ext, std::fabs(ct->X[3 * i + d] - ct->X[d]));
+  std::map<std::pair<int, int>, int> opp;  // directed edge -> opposite vertex
+  std::vector<int> used(n, 0);
+  for (int t = 0; t < m; ++t) {
+    int v[3] = {ct->tri[3 * t], ct->tri[3 * t + 1], ct->tri[3 * t + 2]};
+    for (int r = 0; r < 3; ++r) {
+      if (v[r] < 0 || v[r] >= n) return fail(NPFEM_E_MESH, "triangle index out of range");
+      used[v[r]] = 1;
+    }
+    if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2])
+      return fail(NPFEM_E_MESH, "triangle with a repeated vertex");
+    double a2 = norm(cross(sub(P(v[1]), P(v[0])), sub(P(v[2]), P(v[0]))));
+    if (!(a2 > 1e-12 * ext * ext)) return fail(NPFEM_E_MESH, "zero-area triangle");
+    for (int r = 0; r < 3; ++r) {
+      auto key = std::make_pair(v[r], v[(r + 1) % 3]);
+      if (opp.count(key)) return fail(NPFEM_E_MESH, "directed edge used twice (non-manifold "
+                                                    "or inconsistent orientation)");
+      opp[key] = v[(r + 2) % 3];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (!used[i]) return fail(NPFEM_E_MESH, "vertex not used by any triangle");
+  for (auto& kv : opp)
+    if (!opp.count({kv.first.second, kv.first.first}))
+      return fail(NPFEM_E_MESH, "open mesh: an edge has only one triangle");
+
+  // ---- rest volume and area
+  double V0 = 0, area0 = 0;
+  for (int t = 0; t < m; ++t) {
+    V3 a = P(ct->tri[3 * t]), b = P(ct->tri[3 * t + 1]), c = P(ct->tri[3 * t + 2]);
+    V0 += dot(a, cross(b, c)) / 6.0;
+    area0 += 0.5 * norm(cross(sub(b, a), sub(c, a)));
+  }
+  if (!(V0 > 0)) return fail(NPFEM_E_MESH, "rest volume <= 0 (triangles must be CCW from outside)");
+  ct->V0 = V0;
+  ct->area0 = area0;
+  ct->mass = mat->density * V0 / n;
+
+  // ---- triangle rest frames: F = [x_b - x_a, x_c - x_a] D_m^-1, D_m upper triangular
+  ct->G.assign((size_t)m * 6, 0.0);
+  ct->A.assign(m, 0.0);
+  for (int t = 0; t < m; ++t) {
+    V3 a = P(ct->tri[3 * t]), b = P(ct->tri[3 * t + 1]), c = P(ct->tri[3 * t + 2]);
+    V3 e1 = sub(b, a), e2 = sub(c, a);
+    double l1 = norm(e1);
+    V3 t1 = scale(e1, 1.0 / l1);
+    double d12 = dot(e2, t1);
+    double l2 = norm(sub(e2, scale(t1, d12)));
+    // D_m = [[l1, d12], [0, l2]],  D_m^-1 = [[1/l1, -d12/(l1 l2)], [0, 1/l2]]
+    double gb0 = 1.0 / l1, gb1 = -d12 / (l1 * l2);
+    double gc0 = 0.0, gc1 = 1.0 / l2;
+    double* g = &ct->G[6 * (size_t)t];
+    g[2] = gb0; g[3] = gb1;
+    g[4] = gc0; g[5] = gc1;
+    g[0] = -gb0 - gc0; g[1] = -gb1 - gc1;
+    ct->A[t] = 0.5 * norm(cross(e1, e2));
+  }
+
+  // ---- hinges: edge (i, j) with i < j in triangle (i, j, k), opposite l in (j, i, l)
+  std::vector<std::array<int, 4>> hv;
+  for (auto& kv : opp) {
+    int i = kv.first.first, j = kv.first.second;
+    if (i < j) hv.push_back({i, j, kv.second, opp[{j, i}]});
+  }
+  std::sort(hv.begin(), hv.end());
+  const int e = (int)hv.size();
+  ct->e = e;
+  ct->hinge.resize(4 * (size_t)e);
+  ct->coef.resize(4 * (size_t)e);
+  ct->rest_norm.resize(e);
+  for (int h = 0; h < e; ++h) {
+    int i = hv[h][0], j = hv[h][1], k = hv[h][2], l = hv[h][3];
+    V3 xi = P(i), xj = P(j), xk = P(k), xl = P(l);
+    V3 e0 = sub(xj, xi), e1 = sub(xk, xi), e2 = sub(xl, xi), e3 = sub(xk, xj), e4 = sub(xl, xj);
+    V3 me0 = scale(e0, -1.0);
+    double c01 = cot(e0, e1), c02 = cot(e0, e2), c03 = cot(me0, e3), c04 = cot(me0, e4);
+    double A0 = 0.5 * norm(cross(e0, e1)), A1 = 0.5 * norm(cross(e0, e2));
+    double s = std::sqrt(3.0 / (A0 + A1));
+    double a[4] = {s * (c03 + c04), s * (c01 + c02), -s * (c01 + c03), -s * (c02 + c04)};
+    int idx[4] = {i, j, k, l};
+    V3 u{0, 0, 0};
+    for (int q = 0; q < 4; ++q) {
+      ct->hinge[4 * h + q] = idx[q];
+      ct->coef[4 * h + q] = a[q];
+      V3 xq = P(idx[q]);
+      u = {u.x + a[q] * xq.x, u.y + a[q] * xq.y, u.z + a[q] * xq.z};
+    }
+    ct->rest_norm[h] = norm(u);
+  }
+
+  // ---- system matrix L (FP64, dense; it is banded under the mesh's vertex order)
+  std::vector<double>& L = ct->L;
+  L.assign((size_t)n * n, 0.0);
+  const double diag = ct->mass / (dt * dt) + ct->w_v;
+  for (int i = 0; i < n; ++i) L[(size_t)i * n + i] = diag;
+  for (int t = 0; t < m; ++t) {
+    const double w = (ct->w_s + ct->w_a) * ct->A[t];
+    const double* g = &ct->G[6 * (size_t)t];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        int vp = ct->tri[3 * t + p], vq = ct->tri[3 * t + q];
+        L[(size_t)vp * n + vq] += w * (g[2 * p] * g[2 * q] + g[2 * p + 1] * g[2 * q + 1]);
+      }
+  }
+  for (int h = 0; h < e; ++h)
+    for (int p = 0; p < 4; ++p)
+      for (int q = 0; q < 4; ++q)
+        L[(size_t)ct->hinge[4 * h + p] * n + ct->hinge[4 * h + q]] +=
+            ct->w_b * ct->coef[4 * h + p] * ct->coef[4 * h + q];
+  int bw = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (L[(size_t)i * n + j] != 0.0) bw = std::max(bw, std::abs(i - j));
+  ct->bw = bw;
+
+  // ---- Cholesky L = C C^T (lower), FP64; zero fill outside the band is preserved
+  std::vector<double>& C = ct->chol;
+  C.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = L[(size_t)j * n + j];
+    int k0 = std::max(0, j - bw);
+    for (int k = k0; k < j; ++k) d -= C[(size_t)j * n + k] * C[(size_t)j * n + k];
+    if (!(d > 0.0) || !std::isfinite(d)) return fail(NPFEM_E_NOT_SPD, "Cholesky pivot <= 0");
+    double cjj = std::sqrt(d);
+    C[(size_t)j * n + j] = cjj;
+    int i1 = std::min(n - 1, j + bw);
+    for (int i = j + 1; i <= i1; ++i) {
+      double s = L[(size_t)i * n + j];
+      int kk = std::max(k0, i - bw);
+      for (int k = kk; k < j; ++k) s -= C[(size_t)i * n + k] * C[(size_t)j * n + k];
+      C[(size_t)i * n + j] = s / cjj;
+    }
+  }
+  ct->cband.assign((size_t)n * (bw + 1), 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k <= bw && k <= i; ++k) ct->cband[(size_t)i * (bw + 1) + k] = C[(size_t)i * n + i - k];
+
+  // ---- dense inverse: column by column through the factor (FP64)
+  ct->Linv.assign((size_t)n * n, 0.0);
+  std::vector<double> col(n);
+  for (int c = 0; c < n; ++c) {
+    std::fill(col.begin(), col.end(), 0.0);
+    col[c] = 1.0;
+    for (int i = 0; i < n; ++i) {
+      double s = col[i];
+      for (int k = std::max(0, i - bw); k < i; ++k) s -= C[(size_t)i * n + k] * col[k];
+      col[i] = s / C[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = col[i];
+      for (int k = i + 1; k <= std::min(n - 1, i + bw); ++k) s -= C[(size_t)k * n + i] * col[k];
+      col[i] = s / C[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) ct->Linv[(size_t)i * n + c] = col[i];
+  }
+
+  // ---- vertex incidence (plain form gathers) and one-ring triangle pairs (fused form)
+  ct->vt_off.assign(n + 1, 0);
+  ct->vh_off.assign(n + 1, 0);
+  for (int t = 0; t < m; ++t)
+    for (int j = 0; j < 3; ++j) ct->vt_off[ct->tri[3 * t + j] + 1]++;
+  for (int h = 0; h < e; ++h)
+    for (int q = 0; q < 4; ++q) ct->vh_off[ct->hinge[4 * h + q] + 1]++;
+  for (int i = 0; i < n; ++i) {
+    ct->vt_off[i + 1] += ct->vt_off[i];
+    ct->vh_off[i + 1] += ct->vh_off[i];
+  }
+  ct->vt_list.assign(ct->vt_off[n], 0);
+  ct->vh_list.assign(ct->vh_off[n], 0);
+  {
+    std::vector<int> ft(ct->vt_off.begin(), ct->vt_off.end() - 1);
+    std::vector<int> fh(ct->vh_off.begin(), ct->vh_off.end() - 1);
+    for (int t = 0; t < m; ++t)
+      for (int j = 0; j < 3; ++j) ct->vt_list[ft[ct->tri[3 * t + j]]++] = 3 * t + j;
+    for (int h = 0; h < e; ++h)
+      for (int q = 0; q < 4; ++q) ct->vh_list[fh[ct->hinge[4 * h + q]]++] = 4 * h + q;
+  }
+  ct->ring_info.assign(n, 0);
+  ct->ring_pairs.assign(ct->vt_off[n], 0);
+  int max_deg = 0;
+  for (int i = 0; i < n; ++i) {
+    int deg = ct->vt_off[i + 1] - ct->vt_off[i];
+    max_deg = std::max(max_deg, deg);
+    for (int s = 0; s < deg; ++s) {
+      int code = ct->vt_list[ct->vt_off[i] + s];
+      int t = code / 3, j = code % 3;
+      int b = ct->tri[3 * t + (j + 1) % 3], c = ct->tri[3 * t + (j + 2) % 3];
+      ct->ring_pairs[ct->vt_off[i] + s] = (uint32_t)b | ((uint32_t)c << 16);
+    }
+  }
+  if (max_deg > 255) return fail(NPFEM_E_UNSUPPORTED, "vertex degree above 255");
+  for (int i = 0; i < n; ++i)
+    ct->ring_info[i] = ((uint32_t)ct->vt_off[i] << 8) | (uint32_t)(ct->vt_off[i + 1] - ct->vt_off[i]);
+
+  // ---- fused-form layout and element schedules
+  // LDS column stride: a multiple of 4 (MFMA k step) whose quarter is odd, so that the 16
+  // columns x 4 rows of an MFMA B tile fall in 64 distinct LDS banks.
+  int npad = (n + 3) / 4 * 4;
+  if ((npad / 4) % 2 == 0) npad += 4;
+  ct->npad = npad;
+  const int per_cell = 2 * 3 * npad * 4;  // X and R columns, FP32
+  int gw = 0;
+  for (int cand : {16, 8, 4, 2, 1}) {
+    if (kFusedWaves * cand * per_cell > kFusedLdsBudget) continue;
+    if ((cand * n + 63) / 64 > kMaxItems) continue;
+    if (kFusedWaves * cand > kMaxGroupCells) continue;
+    const int tiles = ((n + 15) / 16) * ((3 * kFusedWaves * cand + 15) / 16);
+    if ((tiles + kFusedWaves - 1) / kFusedWaves > kMaxTilesPerWave) continue;
+    gw = cand;
+    break;
+  }
+  ct->fused_ok = gw > 0;
+  if (!ct->fused_ok) {
+    ct->fused_reason = "mesh too large for the fused kernel's LDS layout (n <= 576)";
+    return NPFEM_OK;
+  }
+  ct->gw = gw;
+  ct->slots = 64 / gw;
+  {
+    std::vector<std::vector<int>> tel(m), hel(e);
+    for (int t = 0; t < m; ++t) tel[t] = {ct->tri[3 * t], ct->tri[3 * t + 1], ct->tri[3 * t + 2]};
+    for (int h = 0; h < e; ++h)
+      hel[h] = {ct->hinge[4 * h], ct->hinge[4 * h + 1], ct->hinge[4 * h + 2], ct->hinge[4 * h + 3]};
+    auto tr = pack_rounds(tel, n, ct->slots);
+    auto hr = pack_rounds(hel, n, ct->slots);
+    ct->tri_rounds = (int)tr.size();
+    ct->hinge_rounds = (int)hr.size();
+    ct->tri_sched.assign((size_t)ct->tri_rounds * ct->slots, TriRec{0, 0, 0, 0, 0, 0, 0.0f, 0});
+    ct->hinge_sched.assign((size_t)ct->hinge_rounds * ct->slots,
+                           HingeRec{0, 0, 0, 0, 0, 0, -1.0f, 0});
+    for (int r = 0; r < ct->tri_rounds; ++r)
+      for (size_t s = 0; s < tr[r].size(); ++s) {
+        int t = tr[r][s];
+        const double* g = &ct->G[6 * (size_t)t];
+        TriRec rec;
+        rec.ab = (uint32_t)ct->tri[3 * t] | ((uint32_t)ct->tri[3 * t + 1] << 16);
+        rec.c = (uint32_t)ct->tri[3 * t + 2];
+        rec.gb0 = (float)g[2]; rec.gb1 = (float)g[3];
+        rec.gc0 = (float)g[4]; rec.gc1 = (float)g[5];
+        rec.area = (float)ct->A[t];
+        rec.pad = 0;
+        ct->tri_sched[(size_t)r * ct->slots + s] = rec;
+      }
+    for (int r = 0; r < ct->hinge_rounds; ++r)
+      for (size_t s = 0; s < hr[r].size(); ++s) {
+        int h = hr[r][s];
+        HingeRec rec;
+        rec.ij = (uint32_t)ct->hinge[4 * h] | ((uint32_t)ct->hinge[4 * h + 1] << 16);
+        rec.kl = (uint32_t)ct->hinge[4 * h + 2] | ((uint32_t)ct->hinge[4 * h + 3] << 16);
+        rec.a0 = (float)ct->coef[4 * h]; rec.a1 = (float)ct->coef[4 * h + 1];
+        rec.a2 = (float)ct->coef[4 * h + 2]; rec.a3 = (float)ct->coef[4 * h + 3];
+        rec.rest = (float)ct->rest_norm[h];
+        rec.pad = 0;
+        ct->hinge_sched[(size_t)r * ct->slots + s] = rec;
+      }
+  }
+  return NPFEM_OK;
+}
+
+}  // namespace npfem

@@ -1,0 +1,196 @@
+"""Python binding of libnpfem (ctypes, argument marshalling only).
+
+Every step of the solver runs in the library's HIP kernels; PyTorch supplies device memory
+and the current stream. The library must have been built (``build_lib.build()``); importing
+this module on a machine without it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnpfem.so")
+HEADER_PATH = os.path.join(HERE, "..", "include", "npfem.h")
+
+STATUS = {0: "NPFEM_OK", -1: "NPFEM_E_INVALID", -2: "NPFEM_E_MESH", -3: "NPFEM_E_NOT_SPD",
+          -4: "NPFEM_E_DT", -5: "NPFEM_E_NOMEM", -6: "NPFEM_E_HIP", -7: "NPFEM_E_NONFINITE",
+          -8: "NPFEM_E_UNSUPPORTED"}
+FORMS = {"plain": 0, "fused": 1}
+
+
+class NpfemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_vertices", c_int32), ("n_triangles", c_int32),
+                ("rest_xyz", POINTER(c_double)), ("tri", POINTER(c_int32))]
+
+
+class _Material(ctypes.Structure):
+    _fields_ = [("density", c_double), ("shear_B", c_double), ("area_C", c_double),
+                ("skalak_D", c_double), ("k_bend", c_double), ("k_vol", c_double),
+                ("strain_min", c_double), ("strain_max", c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_vertices", c_int32), ("n_triangles", c_int32), ("n_hinges", c_int32),
+                ("bandwidth", c_int32), ("rest_volume", c_double), ("rest_area", c_double),
+                ("vertex_mass", c_double), ("dt", c_double), ("tri_rounds", c_int32),
+                ("hinge_rounds", c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libnpfem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1911_03062_amd.build_lib")
+    L = ctypes.CDLL(LIB_PATH)
+    L.npfem_create_celltype.argtypes = [POINTER(_Mesh), POINTER(_Material), c_double, POINTER(c_void_p)]
+    L.npfem_create_celltype.restype = c_int32
+    L.npfem_celltype_destroy.argtypes = [c_void_p]
+    L.npfem_celltype_destroy.restype = None
+    L.npfem_celltype_get_info.argtypes = [c_void_p, POINTER(_Info)]
+    L.npfem_celltype_get_info.restype = c_int32
+    L.npfem_celltype_get_matrix.argtypes = [c_void_p, POINTER(c_double)]
+    L.npfem_celltype_get_matrix.restype = c_int32
+    L.npfem_batch_create.argtypes = [c_int32, POINTER(c_void_p), c_int32, c_int32,
+                                     POINTER(c_void_p), POINTER(c_int64)]
+    L.npfem_batch_create.restype = c_int32
+    L.npfem_batch_destroy.argtypes = [c_void_p]
+    L.npfem_batch_destroy.restype = None
+    L.npfem_batch_vertex_count.argtypes = [c_void_p]
+    L.npfem_batch_vertex_count.restype = c_int64
+    L.npfem_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
+                             c_void_p, c_void_p]
+    L.npfem_step.restype = c_int32
+    L.npfem_batch_check.argtypes = [c_void_p, c_void_p]
+    L.npfem_batch_check.restype = c_int32
+    L.npfem_last_error.argtypes = []
+    L.npfem_last_error.restype = c_char_p
+    _lib = L
+    return L
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/npfem.h."""
+    src = open(HEADER_PATH).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(npfem_[a-z_0-9]+)\s*\(", src)))
+
+
+def _check(status: int):
+    if status != 0:
+        msg = lib().npfem_last_error().decode(errors="replace")
+        raise NpfemError(status, msg)
+
+
+class CellType:
+    """A cell type built on the host (mesh validation, rest frames, L and its factors)."""
+
+    def __init__(self, rest_xyz, tri, material, dt: float):
+        x = np.ascontiguousarray(rest_xyz, dtype=np.float64)
+        t = np.ascontiguousarray(tri, dtype=np.int32)
+        if x.ndim != 2 or x.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+            raise ValueError("rest_xyz must be [n][3] and tri [m][3]")
+        mesh = _Mesh(x.shape[0], t.shape[0], x.ctypes.data_as(POINTER(c_double)),
+                     t.ctypes.data_as(POINTER(c_int32)))
+        mat = _Material(material.density, material.shear_B, material.area_C, material.skalak_D,
+                        material.k_bend, material.k_vol, material.strain_min, material.strain_max)
+        h = c_void_p()
+        _check(lib().npfem_create_celltype(ctypes.byref(mesh), ctypes.byref(mat), float(dt),
+                                           ctypes.byref(h)))
+        self._h = h
+        self.dt = float(dt)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(lib().npfem_celltype_get_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    def matrix(self) -> np.ndarray:
+        n = self.info()["n_vertices"]
+        L = np.empty((n, n), dtype=np.float64)
+        _check(lib().npfem_celltype_get_matrix(self._h, L.ctypes.data_as(POINTER(c_double))))
+        return L
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.npfem_celltype_destroy(h)
+            self._h = None
+
+
+class Batch:
+    """A batch of cells (one type handle per cell) bound to the current HIP device."""
+
+    def __init__(self, cell_types, precision: int = 32, form: str = "fused"):
+        self._types = list(cell_types)      # keep the handles alive
+        n = len(self._types)
+        arr = (c_void_p * max(n, 1))(*[t.handle.value for t in self._types])
+        off = np.zeros(n + 1, dtype=np.int64)
+        h = c_void_p()
+        _check(lib().npfem_batch_create(n, arr, int(precision), FORMS[form], ctypes.byref(h),
+                                        off.ctypes.data_as(POINTER(c_int64))))
+        self._h = h
+        self.offsets = off
+        self.n_cells = n
+        self.precision = int(precision)
+        self.form = form
+        self.dt = self._types[0].dt if n else 0.0
+
+    @property
+    def vertex_count(self) -> int:
+        return int(self.offsets[-1])
+
+    def step(self, x, v, f, dt: float, n_pd_iters: int, vol_area=None, stream=None):
+        """Advance in place; x, v, f are device tensors [3][V_total] of the batch's dtype."""
+        import torch
+        dtype = torch.float64 if self.precision == 64 else torch.float32
+        for name, t in (("x", x), ("v", v), ("f", f)):
+            if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()
+                    and tuple(t.shape) == (3, self.vertex_count)):
+                raise ValueError(f"{name} must be a contiguous device tensor [3][{self.vertex_count}] of {dtype}")
+        va = 0
+        if vol_area is not None:
+            if not (vol_area.is_cuda and vol_area.dtype == torch.float64 and vol_area.is_contiguous()
+                    and tuple(vol_area.shape) == (self.n_cells, 2)):
+                raise ValueError("vol_area must be a contiguous float64 device tensor [n_cells][2]")
+            va = vol_area.data_ptr()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_step(self._h, x.data_ptr(), v.data_ptr(), f.data_ptr(), float(dt),
+                                int(n_pd_iters), c_void_p(s.cuda_stream), c_void_p(va)))
+
+    def check(self, stream=None):
+        """Synchronise and raise NpfemError(NPFEM_E_NONFINITE) if a step produced NaN/Inf."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_batch_check(self._h, c_void_p(s.cuda_stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.npfem_batch_destroy(h)
+            self._h = None
+
+
+def make_cell_types(type_inputs: dict, dt: float) -> dict:
+    """{type_id: CellType} from {type_id: (rest_xyz, tri, material)}."""
+    return {k: CellType(x, t, m, dt) for k, (x, t, m) in type_inputs.items()}

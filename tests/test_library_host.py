@@ -1,0 +1,84 @@
+"""Host-side checks of libnpfem (no GPU): exported symbols, cell-type setup against the
+oracle's setup, mesh validation and argument errors."""
+import numpy as np
+import pytest
+
+import npfem_inputs as I
+import oracle as O
+from paper_1911_03062_amd import npfem as N
+
+
+def test_library_exports_every_header_symbol():
+    L = N.lib()
+    syms = N.header_symbols()
+    assert "npfem_step" in syms and "npfem_create_celltype" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+@pytest.mark.parametrize("kind", [I.RBC, I.PLT])
+def test_celltype_setup_matches_oracle(kind):
+    x, t, m = I.cell_type_inputs()[kind]
+    ct = N.CellType(x, t, m, I.DT)
+    oc = O.CellType(x, t, m, I.DT)
+    info = ct.info()
+    assert (info["n_vertices"], info["n_triangles"], info["n_hinges"]) == (oc.n, oc.m, oc.e)
+    assert abs(info["rest_volume"] - oc.V0) < 1e-12 * oc.V0
+    assert abs(info["vertex_mass"] - oc.mass) < 1e-12 * oc.mass
+    assert abs(info["rest_area"] - I.mesh_summary(x, t)["area"]) < 1e-12 * info["rest_area"]
+    Lh = ct.matrix()
+    assert np.abs(Lh - oc.L).max() <= 1e-13 * np.abs(oc.L).max()
+    nz = np.nonzero(oc.L)
+    assert info["bandwidth"] == np.max(np.abs(nz[0] - nz[1]))
+    # vertex-disjoint round schedule: at least the busiest vertex's element count
+    assert info["tri_rounds"] >= 16 if kind == I.RBC else info["tri_rounds"] >= 8
+
+
+def _create(x, t, mat=None, dt=I.DT):
+    return N.CellType(x, t, mat or I.RBC_MATERIAL, dt)
+
+
+def _expect(status, fn):
+    with pytest.raises(N.NpfemError) as ei:
+        fn()
+    assert ei.value.name == status, str(ei.value)
+
+
+def test_mesh_validation_errors():
+    x, t = I.icosahedron()
+    _create(x, t)                                              # valid
+    _expect("NPFEM_E_MESH", lambda: _create(x, t[:-1]))       # open mesh
+    _expect("NPFEM_E_MESH", lambda: _create(x, t[:, ::-1]))   # inside-out -> V0 < 0
+    t2 = t.copy()
+    t2[0] = t2[0, [0, 2, 1]]                                   # one flipped triangle
+    _expect("NPFEM_E_MESH", lambda: _create(x, t2))
+    x3 = np.vstack([x, [[5.0, 5.0, 5.0]]])                    # unused vertex
+    _expect("NPFEM_E_MESH", lambda: _create(x3, t))
+    t4 = t.copy()
+    t4[0, 0] = 99                                              # index out of range
+    _expect("NPFEM_E_MESH", lambda: _create(x, t4))
+    x5 = x.copy()
+    a, b, c = t[0]
+    x5[c] = 0.5 * (x5[a] + x5[b])                              # zero-area triangle
+    _expect("NPFEM_E_MESH", lambda: _create(x5, t))
+    x6 = x.copy()
+    x6[0, 0] = np.nan
+    _expect("NPFEM_E_MESH", lambda: _create(x6, t))
+
+
+def test_argument_errors():
+    x, t = I.icosahedron()
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, dt=0.0))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, dt=-1.0))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(density=0.0)))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(area_C=-1.0)))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(strain_min=1.2, strain_max=1.1)))
+    _expect("NPFEM_E_MESH", lambda: _create(x[:3], t[:3]))
+
+
+def test_small_meshes_match_oracle_matrix():
+    for fn in (I.tetrahedron, I.octahedron, I.icosahedron):
+        x, t = fn()
+        ct = _create(x, t)
+        oc = O.CellType(x, t, I.RBC_MATERIAL, I.DT)
+        assert np.abs(ct.matrix() - oc.L).max() <= 1e-13 * np.abs(oc.L).max()
