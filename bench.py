@@ -1,0 +1,260 @@
+"""Throughput benchmark of the fused npFEM step on one MI355X.
+
+Workload (default): 20 000 red blood cells (258 vertices) + 4 000 platelets (66 vertices) in
+a seeded random interleave, 20 projective-dynamics iterations per step, external forces
+N(0, 2 pN) with 5 % of the cells at 10x (seed 3). Inputs are resident in HBM before timing;
+force arrays come from a pool of pre-generated steps that the steps cycle through.
+
+Prints one JSON line: throughput in cell-PD-iterations/s over the timed steps, per-step
+latency percentiles, the plain one-cell-at-a-time form on a subset for comparison, the
+dominant kernel's roofline figures, the accuracy of the run against the FP64 oracle on
+sampled cells, and the oracle's own CPU throughput on that sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-PD-iterations/s at ≤1e-4 diam error; p50/p99 step latency vs plain"
+PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+# Algorithmic FLOP per cell per PD iteration (local projections + FP64 volume reductions +
+# gather + banded-factor solve), and bytes per vertex per step (read x, v, F; write x, v).
+FLOP_PER_ITER = {0: 3.2e5, 1: 6.9e4}
+BYTES_PER_VERTEX_STEP = 60
+FUSED_SRC = os.path.join(ROOT, "paper_1911_03062_amd", "csrc", "kernels_fused.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_large_24000_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels_fused.hip", "projections.h", "npfem_internal.h"):
+        with open(os.path.join(ROOT, "paper_1911_03062_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Per-launch HBM bytes from the committed counter summary, if it matches the source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large_24000")
+    ap.add_argument("--force-pool", type=int, default=4)
+    ap.add_argument("--sample-cells", type=int, default=6)
+    ap.add_argument("--plain-cells", type=int, default=8)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (a known-size "
+                         "kernel to scale HBM counters by)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the Poisson-arrival serving run (0 skips it)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (accuracy check and CPU baseline)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(cells shard statically across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import npfem_inputs as I
+    from paper_1911_03062_amd import npfem as N
+
+    torch.cuda.set_device(0)
+    w = I.WORKLOADS[args.workload]
+    b = w.batch()
+    K = w.n_pd_iters
+    n_steps_total = args.warmup + args.steps
+    pool_n = max(1, min(args.force_pool, n_steps_total))
+    pool_np = list(w.forces(b, n_steps=pool_n))
+
+    types = {k: N.CellType(x, t, m, I.DT) for k, (x, t, m) in I.cell_type_inputs().items()}
+    batch = N.Batch([types[int(t)] for t in b.types], precision=32, form="fused")
+    x = torch.tensor(b.x0, dtype=torch.float32, device="cuda")
+    v = torch.tensor(b.v0, dtype=torch.float32, device="cuda")
+    pool = [torch.tensor(f, dtype=torch.float32, device="cuda") for f in pool_np]
+    stream = torch.cuda.current_stream()
+
+    for s in range(args.warmup):
+        batch.step(x, v, pool[s % pool_n], I.DT, K)
+    batch.check()
+    torch.cuda.synchronize()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(args.steps):
+        batch.step(x, v, pool[(args.warmup + s) % pool_n], I.DT, K)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    batch.check()
+    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])  # ms
+    gpu_ms = float(lat.sum())
+    elapsed_s = max(wall, gpu_ms * 1e-3)
+    n_cells = b.n_cells
+    value = n_cells * K * args.steps / elapsed_s
+
+    # roofline of the fused kernel: one launch per step
+    n_rbc = int(np.sum(b.types == I.RBC))
+    n_plt = n_cells - n_rbc
+    flop_launch = K * (n_rbc * FLOP_PER_ITER[I.RBC] + n_plt * FLOP_PER_ITER[I.PLT])
+    avg_launch_s = float(np.mean(lat)) * 1e-3
+    achieved_tflops = flop_launch / avg_launch_s / 1e12
+    alg_bytes = BYTES_PER_VERTEX_STEP * b.v_total
+    traffic = measured_traffic()
+
+    if args.copy_calibration_mb > 0:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # plain one-cell-at-a-time form on a subset, same state recipe
+    rng = np.random.default_rng(11)
+    pcells = np.sort(rng.choice(n_cells, size=min(args.plain_cells, n_cells), replace=False))
+    idx = np.concatenate([np.arange(b.offsets[c], b.offsets[c + 1]) for c in pcells])
+    pbatch = N.Batch([types[int(b.types[c])] for c in pcells], precision=32, form="plain")
+    px = torch.tensor(b.x0[:, idx], dtype=torch.float32, device="cuda")
+    pv = torch.tensor(b.v0[:, idx], dtype=torch.float32, device="cuda")
+    pf = torch.tensor(pool_np[0][:, idx], dtype=torch.float32, device="cuda")
+    pbatch.step(px, pv, pf, I.DT, K)
+    torch.cuda.synchronize()
+    pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pe0.record(stream)
+    p_steps = 3
+    for _ in range(p_steps):
+        pbatch.step(px, pv, pf, I.DT, K)
+    pe1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = pe0.elapsed_time(pe1) / p_steps
+    plain_value = len(pcells) * K / (plain_ms * 1e-3)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-PD-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {n_rbc} RBC (258 vertices) + {n_plt} platelets (66 vertices), "
+                        f"interleaved, {K} PD iterations/step, forces N(0, {w.sigma} pN), "
+                        f"{int(w.strong_fraction * 100)}% of cells at 10x",
+            "n_cells": n_cells, "n_vertices": b.v_total, "n_pd_iters": K,
+            "form": "fused", "dt_us": I.DT, "force_pool": pool_n,
+            "reductions": "fp64 (volume, area)",
+        },
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(np.mean(lat))},
+        "plain_gpu": {"value": plain_value, "unit": "cell-PD-iterations/s", "cells": len(pcells),
+                      "ms_per_step": plain_ms, "launches_per_cell_step": 2 * K + 2,
+                      "speedup_fused_over_plain": value / plain_value},
+        "roofline": {
+            "bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "hbm_achieved_GBs": alg_bytes / avg_launch_s / 1e9,
+            "hbm_frac": alg_bytes / avg_launch_s / 1e9 / PEAK_HBM_GBS,
+            "kernel": "k_fused_step", "flop_per_launch": flop_launch,
+            "avg_launch_ms": avg_launch_s * 1e3,
+        },
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+    if args.serve_seconds > 0:
+        from paper_1911_03062_amd import serving as S
+        rest = {k: xx for k, (xx, tt, mm) in I.cell_type_inputs().items()}
+        reqs, sessions = S.poisson_workload(args.serve_seconds, rate=200.0, seed=5)
+        spool = S.SlotPool(types, rest, hbm_budget_bytes=2 << 30)
+        srv = S.StepServer(spool, n_pd_iters=10, sigma=1.0)
+        st = srv.run(reqs, sessions)
+        cells = st["cells_stepped"]
+        out["serving"] = {
+            "arrivals": "Poisson 200/s, 50-10000 cells log-uniform, 80/20 RBC/PLT, K=10, "
+                        "sessions of 10 requests (continue probability 0.8)",
+            "requests": len(reqs), "ticks": len(st["ticks"]),
+            "latency": S.latency_summary(reqs),
+            "throughput_cell_PD_iter_per_s": cells * 10 / st["wall_s"],
+            "gpu_busy_frac": st["busy_ms"] * 1e-3 / st["wall_s"],
+            "hbm_budget_bytes": 2 << 30,
+        }
+        del spool, srv
+
+    if not args.no_cpu_baseline:
+        import oracle as O
+        import contextlib
+        try:
+            from threadpoolctl import threadpool_limits
+            limiter = threadpool_limits(limits=1)
+        except Exception:                      # pragma: no cover
+            limiter = contextlib.nullcontext()
+        ot = {k: O.CellType(x_, t_, m_, I.DT) for k, (x_, t_, m_) in I.cell_type_inputs().items()}
+        strong = I.strong_cells(b, w.seed, w.strong_fraction)
+        srng = np.random.default_rng(12)
+        sample = np.unique(np.concatenate([srng.choice(n_cells, args.sample_cells - 2, replace=False),
+                                           strong[:2]])).astype(np.int64)
+        xo, vo = b.x0.copy(), b.v0.copy()
+        with limiter:
+            c0 = time.perf_counter()
+            for s in range(n_steps_total):
+                xo, vo = O.step_batch(ot, b.types, b.offsets, xo, vo, pool_np[s % pool_n], K,
+                                      cells=sample)
+            cpu_s = time.perf_counter() - c0
+        xg = x.double().cpu().numpy()
+        errs = []
+        for c in sample:
+            sl = slice(int(b.offsets[c]), int(b.offsets[c + 1]))
+            errs.append(np.linalg.norm(xg[:, sl] - xo[:, sl], axis=0).max() / I.DIAMETER[int(b.types[c])])
+        disp = max(np.linalg.norm(xo[:, int(b.offsets[c]):int(b.offsets[c + 1])]
+                                  - b.x0[:, int(b.offsets[c]):int(b.offsets[c + 1])], axis=0).max()
+                   for c in sample)
+        out["accuracy"] = {"max_err_over_diam": float(max(errs)), "gate": 1e-4,
+                           "passes": bool(max(errs) <= 1e-4), "sampled_cells": int(len(sample)),
+                           "steps_compared": n_steps_total, "oracle_max_displacement_um": float(disp)}
+        out["cpu_baseline"] = {
+            "value": len(sample) * K * n_steps_total / cpu_s, "unit": "cell-PD-iterations/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} sampled cells of {w.name} (incl. 2 strongly forced) for "
+                      f"{n_steps_total} steps x {K} PD iterations, NumPy FP64, 1 BLAS thread, "
+                      f"{cpu_s:.1f} s",
+        }
+        if not out["accuracy"]["passes"]:
+            out["value_invalid_reason"] = "accuracy gate failed"
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

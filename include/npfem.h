@@ -133,6 +133,21 @@ npfem_status npfem_step(npfem_batch* batch, void* x, void* v, const void* ext_fo
                         double* cell_volume_area);
 
 /*
+ * Restrict the following npfem_step calls of a fused-form batch to a subset of its cells
+ * (continuous batching: the union of the cells of the requests admitted to one tick).
+ * cell_ids: host array of n distinct cell ids of the batch, read during the call; NULL or
+ * n < 0 restores the list of all cells; n = 0 makes steps do nothing. The group work list is
+ * built on the host and copied asynchronously on `stream` into one of two device lists, so a
+ * step enqueued on the same stream after this call uses it while the previous list may still
+ * be in use by an earlier step. Cells outside the subset are not read or written. The group
+ * count lives in device memory, so a step captured into a HIP graph replays with the list
+ * current at replay time. Errors: NPFEM_E_INVALID (id out of range or repeated),
+ * NPFEM_E_UNSUPPORTED (plain form), NPFEM_E_HIP.
+ */
+npfem_status npfem_batch_set_active(npfem_batch* batch, const int32_t* cell_ids, int32_t n,
+                                    void* stream);
+
+/*
  * Synchronise `stream` and report NPFEM_E_NONFINITE if any step since the last check
  * produced a non-finite position or velocity (the flag is then cleared), NPFEM_E_HIP on a
  * device error, NPFEM_OK otherwise.

@@ -153,8 +153,19 @@ struct npfem_batch {
   DevType* d_types = nullptr;               // device array of DevType (by value)
   DevType** d_type_ptrs = nullptr;          // device pointers to each type's device DevType
   std::vector<DevType*> type_dev_structs;   // device DevType per type (plain form)
-  FusedGroup* d_groups = nullptr;
-  int n_groups = 0;
+  // fused-form work lists: the list of all cells, plus a ring of two subset lists that
+  // npfem_batch_set_active fills from pinned host staging; the kernel reads the group count
+  // from device memory, so a captured step replays with whatever list is current
+  FusedGroup* d_groups = nullptr;           // all cells
+  int* d_count_all = nullptr;
+  int n_groups = 0;                         // groups of the all-cells list (grid capacity)
+  FusedGroup* d_ring[2] = {nullptr, nullptr};
+  int* d_ring_count[2] = {nullptr, nullptr};
+  FusedGroup* h_stage[2] = {nullptr, nullptr};
+  int* h_stage_count[2] = {nullptr, nullptr};
+  hipEvent_t ring_ev[2] = {nullptr, nullptr};
+  int ring_cur = -1;                        // -1: the all-cells list is active
+  std::vector<char> mark;
   int64_t* d_offsets = nullptr;
   size_t lds_bytes = 0;
   void* work = nullptr;                     // plain-form workspace
@@ -167,12 +178,49 @@ struct npfem_batch {
     for (DevType* p : type_dev_structs)
       if (p) (void)hipFree(p);
     if (d_groups) (void)hipFree(d_groups);
+    if (d_count_all) (void)hipFree(d_count_all);
+    for (int i = 0; i < 2; ++i) {
+      if (ring_ev[i]) {
+        (void)hipEventSynchronize(ring_ev[i]);
+        (void)hipEventDestroy(ring_ev[i]);
+      }
+      if (d_ring[i]) (void)hipFree(d_ring[i]);
+      if (d_ring_count[i]) (void)hipFree(d_ring_count[i]);
+      if (h_stage[i]) (void)hipHostFree(h_stage[i]);
+      if (h_stage_count[i]) (void)hipHostFree(h_stage_count[i]);
+    }
     if (d_offsets) (void)hipFree(d_offsets);
     if (work) (void)hipFree(work);
     if (d_flag) (void)hipFree(d_flag);
     (void)hipSetDevice(cur);
   }
 };
+
+namespace {
+
+// Groups of up to 4*gw same-type cells, types in order, cells in the given order.
+void build_groups(const npfem_batch* b, const int32_t* ids, int n, std::vector<FusedGroup>& out) {
+  out.clear();
+  const int nt = (int)b->types.size();
+  for (int ti = 0; ti < nt; ++ti) {
+    const int cap = kFusedWaves * b->types[ti]->gw;
+    FusedGroup gcur{};
+    gcur.type = ti;
+    gcur.count = 0;
+    for (int i = 0; i < n; ++i) {
+      const int c = ids ? ids[i] : i;
+      if (b->type_of[c] != ti) continue;
+      gcur.cells[gcur.count++] = c;
+      if (gcur.count == cap) {
+        out.push_back(gcur);
+        gcur.count = 0;
+      }
+    }
+    if (gcur.count) out.push_back(gcur);
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -284,32 +332,31 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
     for (npfem_celltype* t : b->types) wb = std::max(wb, plain_work_bytes(precision, t->n, t->m, t->e));
     if (wb && hipMalloc(&b->work, wb) != hipSuccess) return bail(fail(NPFEM_E_NOMEM, "plain workspace"));
   } else {
-    // groups of up to 4*gw same-type cells, in batch order within each type
     std::vector<FusedGroup> groups;
+    build_groups(b, nullptr, n_cells, groups);
     for (int ti = 0; ti < nt; ++ti) {
-      const int cap = kFusedWaves * b->types[ti]->gw;
-      FusedGroup gcur{};
-      gcur.type = ti;
-      gcur.count = 0;
-      for (int c = 0; c < n_cells; ++c) {
-        if (b->type_of[c] != ti) continue;
-        gcur.cells[gcur.count++] = c;
-        if (gcur.count == cap) {
-          groups.push_back(gcur);
-          gcur.count = 0;
-        }
-      }
-      if (gcur.count) groups.push_back(gcur);
       const npfem_celltype* t = b->types[ti];
+      const int cap = kFusedWaves * t->gw;
       b->lds_bytes = std::max(b->lds_bytes, (size_t)2 * cap * 3 * t->npad * sizeof(float));
     }
     b->n_groups = (int)groups.size();
-    if (b->n_groups) {
-      if (hipMalloc((void**)&b->d_groups, groups.size() * sizeof(FusedGroup)) != hipSuccess ||
-          hipMemcpy(b->d_groups, groups.data(), groups.size() * sizeof(FusedGroup),
-                    hipMemcpyHostToDevice) != hipSuccess)
-        return bail(fail(NPFEM_E_NOMEM, "device work list"));
+    const size_t gbytes = std::max<size_t>(groups.size(), 1) * sizeof(FusedGroup);
+    if (hipMalloc((void**)&b->d_groups, gbytes) != hipSuccess ||
+        hipMalloc((void**)&b->d_count_all, sizeof(int)) != hipSuccess)
+      return bail(fail(NPFEM_E_NOMEM, "device work list"));
+    if ((b->n_groups && hipMemcpy(b->d_groups, groups.data(), groups.size() * sizeof(FusedGroup),
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(b->d_count_all, &b->n_groups, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(NPFEM_E_HIP, "work list upload"));
+    for (int i = 0; i < 2; ++i) {
+      if (hipMalloc((void**)&b->d_ring[i], gbytes) != hipSuccess ||
+          hipMalloc((void**)&b->d_ring_count[i], sizeof(int)) != hipSuccess ||
+          hipHostMalloc((void**)&b->h_stage[i], gbytes, hipHostMallocDefault) != hipSuccess ||
+          hipHostMalloc((void**)&b->h_stage_count[i], sizeof(int), hipHostMallocDefault) != hipSuccess ||
+          hipEventCreateWithFlags(&b->ring_ev[i], hipEventDisableTiming) != hipSuccess)
+        return bail(fail(NPFEM_E_NOMEM, "active-list ring"));
     }
+    b->mark.assign(n_cells, 0);
     if (hipMalloc((void**)&b->d_offsets, (n_cells + 1) * sizeof(int64_t)) != hipSuccess ||
         hipMemcpy(b->d_offsets, b->offsets.data(), (n_cells + 1) * sizeof(int64_t),
                   hipMemcpyHostToDevice) != hipSuccess)
@@ -346,11 +393,48 @@ npfem_status npfem_step(npfem_batch* b, void* x, void* v, const void* f, double 
     }
     return NPFEM_OK;
   }
-  hipError_t e = launch_fused_step(b->d_types, (int)b->types.size(), b->d_groups, b->n_groups,
+  const FusedGroup* groups = b->ring_cur < 0 ? b->d_groups : b->d_ring[b->ring_cur];
+  const int* count = b->ring_cur < 0 ? b->d_count_all : b->d_ring_count[b->ring_cur];
+  hipError_t e = launch_fused_step(b->d_types, (int)b->types.size(), groups, count, b->n_groups,
                                    b->d_offsets, vtot, (float*)x, (float*)v, (const float*)f,
                                    n_pd_iters, cell_volume_area, b->d_flag, b->lds_bytes,
-                                   b->n_groups, stream);
+                                   stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_set_active(npfem_batch* b, const int32_t* cell_ids, int32_t n,
+                                    void* stream) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  if (b->form != NPFEM_FORM_FUSED)
+    return fail(NPFEM_E_UNSUPPORTED, "active-cell lists need the fused form");
+  if (!cell_ids || n < 0) {
+    b->ring_cur = -1;
+    return NPFEM_OK;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int c = cell_ids[i];
+    if (c < 0 || c >= b->n_cells || b->mark[c]) {
+      for (int j = 0; j < i; ++j) b->mark[cell_ids[j]] = 0;
+      return fail(NPFEM_E_INVALID, "cell id out of range or repeated");
+    }
+    b->mark[c] = 1;
+  }
+  for (int i = 0; i < n; ++i) b->mark[cell_ids[i]] = 0;
+  const int slot = b->ring_cur < 0 ? 0 : (b->ring_cur + 1) % 2;
+  HIP_TRY(hipEventSynchronize(b->ring_ev[slot]));   // staging of this slot is free again
+  std::vector<FusedGroup> groups;
+  build_groups(b, cell_ids, n, groups);
+  std::memcpy(b->h_stage[slot], groups.data(), groups.size() * sizeof(FusedGroup));
+  *b->h_stage_count[slot] = (int)groups.size();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!groups.empty())
+    HIP_TRY(hipMemcpyAsync(b->d_ring[slot], b->h_stage[slot], groups.size() * sizeof(FusedGroup),
+                           hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->d_ring_count[slot], b->h_stage_count[slot], sizeof(int),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(b->ring_ev[slot], s));
+  b->ring_cur = slot;
   return NPFEM_OK;
 }
 

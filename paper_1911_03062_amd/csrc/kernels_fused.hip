@@ -36,6 +36,30 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 
 __device__ __forceinline__ bool finite_f(float v) { return v == v && v - v == 0.0f; }
 
+// Per-type constants are read through pointers stored in device memory; marking them as
+// global-address-space pointers lets the compiler use global (not flat) loads.
+template <typename P>
+__device__ __forceinline__ const __attribute__((address_space(1))) P* gptr(const P* p) {
+  return (const __attribute__((address_space(1))) P*)p;
+}
+
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// 32-byte schedule record i as two 16-byte global loads.
+template <typename Rec>
+__device__ __forceinline__ Rec load_rec(const Rec* base, int i) {
+  static_assert(sizeof(Rec) == 32, "schedule records are 32 bytes");
+  const __attribute__((address_space(1))) u4* q =
+      (const __attribute__((address_space(1))) u4*)(base) + 2 * i;
+  union {
+    u4 v[2];
+    Rec r;
+  } u;
+  u.v[0] = q[0];
+  u.v[1] = q[1];
+  return u.r;
+}
+
 // Makes the packed owner-item codes opaque to the optimiser so that the per-item LDS
 // addresses derived from them are recomputed where used instead of being hoisted out of the
 // iteration loop and kept live in registers.
@@ -50,12 +74,12 @@ __device__ __forceinline__ void refresh_items(int (&item)[NQ]) {
 __device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const float* Xc,
                                                         int npad, int vi, Vec3<float> pi,
                                                         float& area_third) {
-  const uint32_t info = T.ring_info[vi];
+  const uint32_t info = gptr(T.ring_info)[vi];
   const int off = (int)(info >> 8), deg = (int)(info & 255u);
   Vec3<float> g = v3<float>(0.f, 0.f, 0.f);
   float ar = 0.f;
   for (int s = 0; s < deg; ++s) {
-    const uint32_t pr = T.ring_pairs[off + s];
+    const uint32_t pr = gptr(T.ring_pairs)[off + s];
     const int b = (int)(pr & 0xffffu), c = (int)(pr >> 16);
     const Vec3<float> pb = v3<float>(Xc[b], Xc[npad + b], Xc[2 * npad + b]) - pi;
     const Vec3<float> pc = v3<float>(Xc[c], Xc[npad + c], Xc[2 * npad + c]) - pi;
@@ -70,7 +94,7 @@ __device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const 
 template <int NQ>
 __global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
-             int n_groups, const int64_t* __restrict__ offsets, int64_t vt,
+             const int* __restrict__ n_groups_dev, const int64_t* __restrict__ offsets, int64_t vt,
              float* __restrict__ x, float* __restrict__ v, const float* __restrict__ f, int K,
              double* __restrict__ vol_area, int* __restrict__ flag) {
   extern __shared__ float lds[];
@@ -78,6 +102,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
   __shared__ int64_t off_lds[kMaxGroupCells];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
+  const int n_groups = *n_groups_dev;
   for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
     const FusedGroup& grp = groups[g];
     const int count = grp.count;
@@ -191,7 +216,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
       for (int r = 0; r < T.p.tri_rounds; ++r) {
-        const TriRec rec = T.tri_sched[r * S + e_s];
+        const TriRec rec = load_rec(T.tri_sched, r * S + e_s);
         if (e_ok && rec.area > 0.0f) {
           const int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
           const Vec3<float> pa = v3<float>(Xe[a], Xe[npad + a], Xe[2 * npad + a]);
@@ -208,7 +233,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       }
       // ---- edge bending constraints
       for (int r = 0; r < T.p.hinge_rounds; ++r) {
-        const HingeRec rec = T.hinge_sched[r * S + e_s];
+        const HingeRec rec = load_rec(T.hinge_sched, r * S + e_s);
         if (e_ok && rec.rest >= 0.0f) {
           const int i = (int)(rec.ij & 0xffffu), j = (int)(rec.ij >> 16);
           const int kk = (int)(rec.kl & 0xffffu), l = (int)(rec.kl >> 16);
@@ -235,7 +260,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         const int t = t0 + i;
         if (t < t1) {
           const int rt = t / CT, ct = t - rt * CT;
-          const float* La = Lt + (size_t)rt * KS * 64 + lane;
+          const __attribute__((address_space(1))) float* La = gptr(Lt) + (size_t)rt * KS * 64 + lane;
           int col = ct * 16 + (lane & 15);
           col = col < ncols ? col : 0;
           const float* Rb = R + col * npad + (lane >> 4);
@@ -342,14 +367,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 }  // namespace
 
 hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
-                             int n_groups, const int64_t* offsets, int64_t vtot, float* x,
-                             float* v, const float* f, int K, double* vol_area, int* flag,
-                             size_t lds_bytes, int grid, void* stream) {
+                             const int* n_groups_dev, int max_groups, const int64_t* offsets,
+                             int64_t vtot, float* x, float* v, const float* f, int K,
+                             double* vol_area, int* flag, size_t lds_bytes, void* stream) {
   (void)n_types;
-  if (n_groups == 0) return hipSuccess;
+  if (max_groups == 0) return hipSuccess;
+  // one workgroup per group up to a few waves of the chip; beyond that workgroups loop
+  const int grid = max_groups < kMaxFusedGrid ? max_groups : kMaxFusedGrid;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_fused_step<kMaxItems>, dim3(grid), dim3(kFusedThreads), lds_bytes, s,
-                     types_dev, groups, n_groups, offsets, vtot, x, v, f, K, vol_area, flag);
+                     types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, K, vol_area, flag);
   return hipGetLastError();
 }
 

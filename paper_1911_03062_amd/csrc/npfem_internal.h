@@ -130,6 +130,7 @@ constexpr int kFusedWaves = 4;
 constexpr int kMaxItems = 9;                // owner items per lane (cells x vertices / 64)
 constexpr int kFusedLdsBudget = 52224;      // bytes of LDS per fused workgroup
 constexpr int kMaxGroupCells = 64;
+constexpr int kMaxFusedGrid = 4096;         // workgroups of one fused launch (then they loop)
 
 // One group of same-type cells processed by one fused workgroup.
 struct FusedGroup {
@@ -147,8 +148,8 @@ hipError_t launch_plain_cell(int precision, const DevType* dt_dev, const TypePar
                              void* v, const void* f, int64_t vtot, int64_t off, int K,
                              void* work, double* vol_area, int* flag, void* stream);
 hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
-                             int n_groups, const int64_t* offsets, int64_t vtot, float* x,
-                             float* v, const float* f, int K, double* vol_area, int* flag,
-                             size_t lds_bytes, int grid, void* stream);
+                             const int* n_groups_dev, int max_groups, const int64_t* offsets,
+                             int64_t vtot, float* x, float* v, const float* f, int K,
+                             double* vol_area, int* flag, size_t lds_bytes, void* stream);
 
 }  // namespace npfem

@@ -17,8 +17,7 @@
 // Area root: d minimises (d - s1)^2 + (1/d - s2)^2, i.e. solves d^4 - s1 d^3 + s2 d - 1 = 0;
 // with d = 1 + eps, a = s1 - 1, b = s2 - 1 the quartic reads
 //   (b - a) + eps (2 - 3a + b) + eps^2 (3 - 3a) + eps^3 (3 - a) + eps^4 = 0,
-// solved by Newton from eps0 = sqrt(s1/s2) - 1 (exact when s1 = s2). The kernels assume the
-// regime of a single positive root near that start (stretches below 2x in both directions).
+// solved by bracketed Newton for its largest root (exact start eps0 = 0 when s1 = s2 <= 2).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,31 +30,51 @@ struct Vec3 {
 };
 
 template <typename T>
-__device__ __forceinline__ Vec3<T> v3(T x, T y, T z) { return {x, y, z}; }
+__host__ __device__ __forceinline__ Vec3<T> v3(T x, T y, T z) { return {x, y, z}; }
 template <typename T>
-__device__ __forceinline__ Vec3<T> operator-(Vec3<T> a, Vec3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__host__ __device__ __forceinline__ Vec3<T> operator-(Vec3<T> a, Vec3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 template <typename T>
-__device__ __forceinline__ Vec3<T> operator+(Vec3<T> a, Vec3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__host__ __device__ __forceinline__ Vec3<T> operator+(Vec3<T> a, Vec3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 template <typename T>
-__device__ __forceinline__ Vec3<T> operator*(Vec3<T> a, T s) { return {a.x * s, a.y * s, a.z * s}; }
+__host__ __device__ __forceinline__ Vec3<T> operator*(Vec3<T> a, T s) { return {a.x * s, a.y * s, a.z * s}; }
 template <typename T>
-__device__ __forceinline__ T dot3(Vec3<T> a, Vec3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ __forceinline__ T dot3(Vec3<T> a, Vec3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 template <typename T>
-__device__ __forceinline__ Vec3<T> cross3(Vec3<T> a, Vec3<T> b) {
+__host__ __device__ __forceinline__ Vec3<T> cross3(Vec3<T> a, Vec3<T> b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
-__device__ __forceinline__ float dsqrt(float v) { return __builtin_sqrtf(v); }
-__device__ __forceinline__ double dsqrt(double v) { return __builtin_sqrt(v); }
+// FP32 uses the hardware square root and reciprocal (v_sqrt_f32, v_rcp_f32, about 1 ulp)
+// instead of the correctly rounded expansions; FP64 keeps IEEE sqrt and division. The host
+// versions exist so that the same element math can be checked on the CPU.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ float dsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ float drcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ float drsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+#else
+inline float dsqrt(float v) { return __builtin_sqrtf(v); }
+inline float drcp(float v) { return 1.0f / v; }
+inline float drsqrt(float v) { return 1.0f / __builtin_sqrtf(v); }
+#endif
+__host__ __device__ __forceinline__ double dsqrt(double v) { return __builtin_sqrt(v); }
+__host__ __device__ __forceinline__ double drcp(double v) { return 1.0 / v; }
+__host__ __device__ __forceinline__ double drsqrt(double v) { return 1.0 / __builtin_sqrt(v); }
 
 template <typename T>
-__device__ __forceinline__ T clamp_dev(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__host__ __device__ __forceinline__ T kRootTol();
+template <>
+__host__ __device__ __forceinline__ float kRootTol<float>() { return 2e-7f; }
+template <>
+__host__ __device__ __forceinline__ double kRootTol<double>() { return 4e-16; }
+
+template <typename T>
+__host__ __device__ __forceinline__ T clamp_dev(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Triangle residual contributions. Inputs: vertex positions pa, pb, pc (any common origin),
 // rest gradients gb, gc (g_a = -g_b - g_c), rest area, weights. Outputs: contributions to
 // the gradient of g at vertices a, b, c.
 template <typename T>
-__device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T> pc, T gb0,
+__host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T> pc, T gb0,
                                                   T gb1, T gc0, T gc1, T area, T w_s, T w_a,
                                                   T s_min, T s_max, Vec3<T>& ra, Vec3<T>& rb,
                                                   Vec3<T>& rc) {
@@ -72,33 +91,34 @@ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T
   Vec3<T> R0, R1;
   T a, b, q_c, q_s;
   if (s > T(1e-30) * (tr + T(1e-30))) {
-    const T inv = T(1) / (s * tt);
+    const T inv = drcp(s * tt);
     R0 = (F0 * (c11 + s) - F1 * c01) * inv;
     R1 = (F1 * (c00 + s) - F0 * c01) * inv;
-    const T half_diff = disc / (T(2) * tt);        // (s1 - s2)/2
+    const T itt = drcp(tt);
+    const T half_diff = T(0.5) * disc * itt;        // (s1 - s2)/2
     // (s1 + s2) - 2 = ((c00 - 1) + (c11 - 1) + 2 (s - 1)) / (s1 + s2 + 2); each bracket is
     // an exact subtraction for entries within a factor two of one
-    const T tm2 = ((c00 - T(1)) + (c11 - T(1)) + T(2) * (s - T(1))) / (tt + T(2));
+    const T tm2 = ((c00 - T(1)) + (c11 - T(1)) + T(2) * (s - T(1))) * drcp(tt + T(2));
     a = T(0.5) * tm2 + half_diff;
     b = T(0.5) * tm2 - half_diff;
   } else {
     // rank-deficient F: Gram-Schmidt frame of F's columns (any orthonormal completion)
     T n0 = dsqrt(c00);
-    if (n0 > T(0)) R0 = F0 * (T(1) / n0);
+    if (n0 > T(0)) R0 = F0 * drcp(n0);
     else R0 = v3<T>(1, 0, 0);
     Vec3<T> w = F1 - R0 * dot3(R0, F1);
     T nw = dsqrt(dot3(w, w));
-    if (nw > T(1e-30)) R1 = w * (T(1) / nw);
+    if (nw > T(1e-30)) R1 = w * drcp(nw);
     else {
       Vec3<T> ax = (R0.x * R0.x < T(0.5)) ? v3<T>(1, 0, 0) : v3<T>(0, 1, 0);
       w = ax - R0 * dot3(R0, ax);
-      R1 = w * (T(1) / dsqrt(dot3(w, w)));
+      R1 = w * drsqrt(dot3(w, w));
     }
     a = dsqrt(tr) - T(1);
     b = T(-1);
   }
   if (disc > T(0)) {
-    const T id = T(1) / disc;
+    const T id = drcp(disc);
     q_c = dl * id;
     q_s = of * id;
   } else {
@@ -108,17 +128,28 @@ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T
   // strain: s - clamp(s) per singular value
   const T ds1 = (a > s_max - T(1) ? a - (s_max - T(1)) : T(0)) + (a < s_min - T(1) ? a - (s_min - T(1)) : T(0));
   const T ds2 = (b > s_max - T(1) ? b - (s_max - T(1)) : T(0)) + (b < s_min - T(1) ? b - (s_min - T(1)) : T(0));
-  // area: eps = d - 1 by Newton on the shifted quartic
+  // area: eps = d - 1, the largest root of the shifted quartic. For s1 >= s2 exactly one
+  // root has d >= 1 and it is the nearest area-preserving stretch; it lies in
+  // [0, max(s1, 1)] in eps, where the quartic is <= 0 at the bottom and > 0 at the top.
+  // Newton from sqrt(s1/s2) - 1, falling back to bisection whenever a step leaves the bracket.
   const T s1 = T(1) + a, s2 = T(1) + b;
-  T eps = (s2 > T(0)) ? dsqrt(s1 / s2) - T(1) : T(0);
   const T k0 = b - a, k1 = T(2) - T(3) * a + b, k2 = T(3) - T(3) * a, k3 = T(3) - a;
-#pragma unroll
-  for (int it = 0; it < 4; ++it) {
+  T lo = T(0), hi = T(1) + (a > T(0) ? a : T(0));
+  T eps = (s2 > T(0)) ? dsqrt(s1 * drcp(s2)) - T(1) : T(0.5) * hi;
+  eps = (eps >= lo && eps <= hi) ? eps : T(0.5) * (lo + hi);
+  for (int it = 0; it < 40; ++it) {
     const T fv = k0 + eps * (k1 + eps * (k2 + eps * (k3 + eps)));
+    if (fv == T(0)) break;
     const T fp = k1 + eps * (T(2) * k2 + eps * (T(3) * k3 + T(4) * eps));
-    eps = (fp != T(0)) ? eps - fv / fp : eps;
+    if (fv > T(0)) hi = eps;
+    else lo = eps;
+    T nx = (fp > T(0)) ? eps - fv * drcp(fp) : T(-1);
+    if (!(nx >= lo && nx <= hi)) nx = T(0.5) * (lo + hi);
+    const T step = nx - eps;
+    eps = nx;
+    if ((step < T(0) ? -step : step) <= kRootTol<T>() * (T(1) + eps)) break;
   }
-  const T ip = T(1) / (T(1) + eps);
+  const T ip = drcp(T(1) + eps);
   const T sum_a = (a + b) - eps * eps * ip;                    // (s1 + s2) - (d + 1/d)
   const T dif_a = (a - b) - eps * (T(2) + eps) * ip;           // (s1 - s2) - (d - 1/d)
   const T alpha = T(0.5) * (w_s * (ds1 + ds2) + w_a * sum_a);
@@ -136,13 +167,13 @@ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T
 // p = r u/|u|, contribution w_b a_q (u - p) to vertex q; the contribution to i is minus the
 // sum of the other three so that the four add up to zero.
 template <typename T>
-__device__ __forceinline__ void hinge_residual(Vec3<T> pi, Vec3<T> pj, Vec3<T> pk, Vec3<T> pl,
+__host__ __device__ __forceinline__ void hinge_residual(Vec3<T> pi, Vec3<T> pj, Vec3<T> pk, Vec3<T> pl,
                                                T a1, T a2, T a3, T rest, T w_b, Vec3<T>& ri,
                                                Vec3<T>& rj, Vec3<T>& rk, Vec3<T>& rl) {
   const Vec3<T> u = (pj - pi) * a1 + (pk - pi) * a2 + (pl - pi) * a3;
   const T nu2 = dot3(u, u);
   T fac = T(0);
-  if (nu2 > T(0)) fac = w_b * (T(1) - rest / dsqrt(nu2));
+  if (nu2 > T(0)) fac = w_b * (T(1) - rest * drsqrt(nu2));
   const Vec3<T> W = u * fac;
   rj = W * a1;
   rk = W * a2;

@@ -58,6 +58,9 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1911_03062_amd.build_lib")
+    # PyTorch ships its own HIP runtime whose SONAME equals the system one; loading torch
+    # first makes the library bind to that same runtime instead of a second copy.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.npfem_create_celltype.argtypes = [POINTER(_Mesh), POINTER(_Material), c_double, POINTER(c_void_p)]
     L.npfem_create_celltype.restype = c_int32
@@ -77,6 +80,8 @@ def lib() -> ctypes.CDLL:
     L.npfem_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                              c_void_p, c_void_p]
     L.npfem_step.restype = c_int32
+    L.npfem_batch_set_active.argtypes = [c_void_p, POINTER(c_int32), c_int32, c_void_p]
+    L.npfem_batch_set_active.restype = c_int32
     L.npfem_batch_check.argtypes = [c_void_p, c_void_p]
     L.npfem_batch_check.restype = c_int32
     L.npfem_last_error.argtypes = []
@@ -177,6 +182,18 @@ class Batch:
         s = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().npfem_step(self._h, x.data_ptr(), v.data_ptr(), f.data_ptr(), float(dt),
                                 int(n_pd_iters), c_void_p(s.cuda_stream), c_void_p(va)))
+
+    def set_active(self, cell_ids, stream=None):
+        """Step only these cells from now on (None: all cells)."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        if cell_ids is None:
+            _check(lib().npfem_batch_set_active(self._h, None, -1, c_void_p(s.cuda_stream)))
+            return
+        ids = np.ascontiguousarray(cell_ids, dtype=np.int32)
+        self._active_ids = ids
+        _check(lib().npfem_batch_set_active(self._h, ids.ctypes.data_as(POINTER(c_int32)),
+                                            int(ids.size), c_void_p(s.cuda_stream)))
 
     def check(self, stream=None):
         """Synchronise and raise NpfemError(NPFEM_E_NONFINITE) if a step produced NaN/Inf."""
