@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnpfem.so")
+CHECK_LIB = os.path.join(HERE, "libnpfem_elemcheck.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -47,8 +48,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # host build of the element math for CPU checks
+    tmp = CHECK_LIB + ".tmp"
+    cmd = [HIPCC, *COMMON, "-shared", "-o", tmp, os.path.join(CSRC, "elemcheck.cpp")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CHECK_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", CHECK_LIB)
     return LIB
 
 

@@ -34,7 +34,8 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-__device__ __forceinline__ bool finite_f(float v) { return v == v && v - v == 0.0f; }
+// Class test (not v - v == 0, which FMA contraction can turn into a product's rounding error).
+__device__ __forceinline__ bool finite_f(float v) { return __builtin_isfinite(v); }
 
 // Per-type constants are read through pointers stored in device memory; marking them as
 // global-address-space pointers lets the compiler use global (not flat) loads.

@@ -216,8 +216,9 @@ k_plain_solve(const DevType* __restrict__ dtp, void* work) {
   for (int i = lane; i < n; i += 64) w.d[c * n + i] -= yc[i];
 }
 
+// Class test (not v - v == 0, which FMA contraction can turn into a product's rounding error).
 template <typename T>
-__device__ inline bool finite_val(T v) { return v == v && v - v == T(0); }
+__device__ inline bool finite_val(T v) { return __builtin_isfinite(v); }
 
 template <typename T>
 __global__ void __launch_bounds__(kPlainThreads)

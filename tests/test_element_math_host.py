@@ -1,0 +1,93 @@
+"""The kernels' element math (csrc/projections.h, compiled for the host) against the oracle's
+projections: per-triangle strain + area and per-hinge bending residual contributions, in
+FP64 and FP32, from the rest shape to strongly distorted triangles."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import npfem_inputs as I
+import oracle as O
+
+LIB = os.path.join(os.path.dirname(__file__), "..", "paper_1911_03062_amd", "libnpfem_elemcheck.so")
+dp = ctypes.POINTER(ctypes.c_double)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libnpfem_elemcheck.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB)
+    L.npfem_check_triangle.argtypes = [dp, dp] + [ctypes.c_double] * 5 + [dp, ctypes.c_int]
+    L.npfem_check_hinge.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data_as(dp)
+
+
+@pytest.mark.parametrize("kind", [I.RBC, I.PLT])
+@pytest.mark.parametrize("amp", [0.0, 0.01, 0.05])
+def test_triangle_residuals_match_oracle(lib, kind, amp):
+    x, t, m = I.cell_type_inputs()[kind]
+    ct = O.CellType(x, t, m, I.DT)
+    xd = ct.X + amp * np.random.default_rng(int(amp * 1000) + kind).normal(size=ct.X.shape)
+    F = O.deformation_gradients(xd[None], ct)
+    ps, pa = O.triangle_projections(F, ct)
+    M = ct.area[None, :, None, None] * (ct.w_s * (F - ps) + ct.w_a * (F - pa))
+    ref = np.einsum("nmdk,mjk->mjd", M, ct.G)
+    # FP32 noise floor: w_a A |g| times FP32 strain resolution (~1e-7 relative on positions)
+    floor32 = 1e-6 * np.max(ct.w_a * ct.area * np.abs(ct.G).max(axis=(1, 2)))
+    for prec, rtol in ((64, 1e-10), (32, 1e-5)):
+        err = 0.0
+        for ti in range(ct.m):
+            p = np.ascontiguousarray(xd[ct.tri[ti]].ravel())
+            g = np.ascontiguousarray([ct.G[ti, 1, 0], ct.G[ti, 1, 1], ct.G[ti, 2, 0], ct.G[ti, 2, 1]])
+            out = np.zeros(9)
+            lib.npfem_check_triangle(_ptr(p), _ptr(g), ct.area[ti], ct.w_s, ct.w_a, ct.s_min,
+                                     ct.s_max, _ptr(out), prec)
+            err = max(err, np.abs(out.reshape(3, 3) - ref[ti]).max())
+        tol = rtol * np.abs(ref).max() + (floor32 * 100 if prec == 32 else 1e-9)
+        assert err <= tol, (prec, err, tol)
+
+
+@pytest.mark.parametrize("kind", [I.RBC, I.PLT])
+def test_hinge_residuals_match_oracle(lib, kind):
+    x, t, m = I.cell_type_inputs()[kind]
+    ct = O.CellType(x, t, m, I.DT)
+    xd = ct.X + 0.05 * np.random.default_rng(3).normal(size=ct.X.shape)
+    u = O.bending_vectors(xd[None], ct)[0]
+    W = ct.w_b * (u - O.bending_projection(u[None], ct)[0])
+    ref = ct.coef[:, :, None] * W[:, None, :]
+    for prec, rtol in ((64, 1e-11), (32, 1e-5)):
+        err = 0.0
+        for h in range(ct.e):
+            p = np.ascontiguousarray(xd[ct.hinge[h]].ravel())
+            a = np.ascontiguousarray(ct.coef[h])
+            out = np.zeros(12)
+            lib.npfem_check_hinge(_ptr(p), _ptr(a), ct.rest_norm[h], ct.w_b, _ptr(out), prec)
+            err = max(err, np.abs(out.reshape(4, 3) - ref[h]).max())
+        assert err <= rtol * np.abs(ref).max(), (prec, err)
+
+
+def test_area_root_extreme_stretches(lib):
+    """Flat triangles stretched up to 5x one way and 0.2x the other: the FP64 residual equals
+    the oracle's (bracketed root), where a plain Newton from sqrt(s1/s2) diverges."""
+    X = np.array([[0, 0, 0], [1.0, 0, 0], [0.3, 0.8, 0]])
+    tri = np.array([[0, 1, 2], [0, 2, 1], [0, 1, 2], [0, 1, 2]])
+    G, area = O.triangle_rest_frames(X, tri[:1])
+    ct = O.CellType(*I.tetrahedron(), I.RBC_MATERIAL, I.DT)
+    for s1, s2 in [(5.0, 0.2), (2.2, 0.9), (1.6, 0.35), (0.5, 0.3), (3.0, 2.9)]:
+        xs = X * np.array([s1, s2, 1.0])
+        F = np.einsum("jd,jk->dk", xs, G[0])[None, None]
+        ps, pa = O.triangle_projections(F, ct)
+        M = area[0] * (ct.w_s * (F - ps) + ct.w_a * (F - pa))
+        ref = np.einsum("nmdk,jk->jd", M, G[0])
+        p = np.ascontiguousarray(xs.ravel())
+        g = np.ascontiguousarray([G[0, 1, 0], G[0, 1, 1], G[0, 2, 0], G[0, 2, 1]])
+        out = np.zeros(9)
+        lib.npfem_check_triangle(_ptr(p), _ptr(g), area[0], ct.w_s, ct.w_a, ct.s_min, ct.s_max,
+                                 _ptr(out), 64)
+        assert np.abs(out.reshape(3, 3) - ref).max() <= 1e-9 * np.abs(ref).max(), (s1, s2)
