@@ -55,6 +55,10 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,7 +66,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_24000")
     ap.add_argument("--force-pool", type=int, default=4)
-    ap.add_argument("--sample-cells", type=int, default=6)
+    ap.add_argument("--sample-cells", type=int, default=12)
     ap.add_argument("--plain-cells", type=int, default=8)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (a known-size "
@@ -82,6 +86,7 @@ def main():
     from paper_1911_03062_amd import npfem as N
 
     torch.cuda.set_device(0)
+    log(f"building workload {args.workload}")
     w = I.WORKLOADS[args.workload]
     b = w.batch()
     K = w.n_pd_iters
@@ -96,6 +101,7 @@ def main():
     pool = [torch.tensor(f, dtype=torch.float32, device="cuda") for f in pool_np]
     stream = torch.cuda.current_stream()
 
+    log("inputs resident; warm-up")
     for s in range(args.warmup):
         batch.step(x, v, pool[s % pool_n], I.DT, K)
     batch.check()
@@ -111,6 +117,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     batch.check()
+    log(f"timed {args.steps} steps in {wall:.3f} s")
     lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])  # ms
     gpu_ms = float(lat.sum())
     elapsed_s = max(wall, gpu_ms * 1e-3)
@@ -140,9 +147,9 @@ def main():
     pcells = np.sort(rng.choice(n_cells, size=min(args.plain_cells, n_cells), replace=False))
     idx = np.concatenate([np.arange(b.offsets[c], b.offsets[c + 1]) for c in pcells])
     pbatch = N.Batch([types[int(b.types[c])] for c in pcells], precision=32, form="plain")
-    px = torch.tensor(b.x0[:, idx], dtype=torch.float32, device="cuda")
-    pv = torch.tensor(b.v0[:, idx], dtype=torch.float32, device="cuda")
-    pf = torch.tensor(pool_np[0][:, idx], dtype=torch.float32, device="cuda")
+    px = torch.tensor(np.ascontiguousarray(b.x0[:, idx]), dtype=torch.float32, device="cuda")
+    pv = torch.tensor(np.ascontiguousarray(b.v0[:, idx]), dtype=torch.float32, device="cuda")
+    pf = torch.tensor(np.ascontiguousarray(pool_np[0][:, idx]), dtype=torch.float32, device="cuda")
     pbatch.step(px, pv, pf, I.DT, K)
     torch.cuda.synchronize()
     pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -194,7 +201,9 @@ def main():
         "kernel_source_hash": kernel_source_hash(),
     }
 
+    log(f"plain form: {plain_ms:.2f} ms per step of {len(pcells)} cells")
     if args.serve_seconds > 0:
+        log("serving run")
         from paper_1911_03062_amd import serving as S
         rest = {k: xx for k, (xx, tt, mm) in I.cell_type_inputs().items()}
         reqs, sessions = S.poisson_workload(args.serve_seconds, rate=200.0, seed=5)
@@ -232,6 +241,8 @@ def main():
             for s in range(n_steps_total):
                 xo, vo = O.step_batch(ot, b.types, b.offsets, xo, vo, pool_np[s % pool_n], K,
                                       cells=sample)
+                if s % 5 == 4:
+                    log(f"oracle step {s + 1}/{n_steps_total}")
             cpu_s = time.perf_counter() - c0
         xg = x.double().cpu().numpy()
         errs = []

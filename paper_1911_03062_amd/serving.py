@@ -217,6 +217,10 @@ class StepServer:
                     if s.remaining <= 0:
                         self._release(s)
             # admit: one request per idle session, in arrival order
+            def pending_admissible(ws):
+                # with nothing in flight every session is idle; only slot shortage blocks
+                return any(self.sessions[r.session].initialised for r in ws)
+
             batch_reqs = []
             if len(in_flight) < self.max_in_flight:
                 still = []
@@ -228,6 +232,8 @@ class StepServer:
                     else:
                         still.append(rq)
                 waiting = still
+            if not batch_reqs and not in_flight and waiting and not pending_admissible(waiting):
+                raise RuntimeError("slot pool too small: waiting requests can never be admitted")
             if batch_reqs:
                 ids = []
                 for rq in batch_reqs:
@@ -294,6 +300,9 @@ def poisson_workload(duration_s: float, rate: float, seed: int, n_min=50, n_max=
         used[sid] = used.get(sid, 0) + 1
         if used[sid] >= per_session:
             live.remove(sid)
+    # a session ends with its last request of the run (at most per_session of them)
+    for sid, s in sessions.items():
+        s.remaining = used.get(sid, 0)
     return reqs, sessions
 
 
