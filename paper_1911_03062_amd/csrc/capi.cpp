@@ -82,7 +82,7 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   p.npad = ct->npad; p.gw = ct->gw; p.slots = ct->slots;
   p.tri_rounds = ct->tri_rounds; p.hinge_rounds = ct->hinge_rounds;
   p.row_tiles = (ct->n + 15) / 16;
-  p.k_steps = ct->npad / 4;
+  p.k_steps = (ct->npad / 4 + kMfmaChunk - 1) / kMfmaChunk * kMfmaChunk;
   p.pad0 = 0;
   p.h = ct->h; p.mass = ct->mass; p.inv_h2m = ct->mass / (ct->h * ct->h);
   p.h2_over_m = ct->h * ct->h / ct->mass;

@@ -216,8 +216,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
+      TriRec rec_next = load_rec(T.tri_sched, e_s);
       for (int r = 0; r < T.p.tri_rounds; ++r) {
-        const TriRec rec = load_rec(T.tri_sched, r * S + e_s);
+        const TriRec rec = rec_next;
+        if (r + 1 < T.p.tri_rounds) rec_next = load_rec(T.tri_sched, (r + 1) * S + e_s);
         if (e_ok && rec.area > 0.0f) {
           const int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
           const Vec3<float> pa = v3<float>(Xe[a], Xe[npad + a], Xe[2 * npad + a]);
@@ -233,8 +235,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         __builtin_amdgcn_wave_barrier();
       }
       // ---- edge bending constraints
+      HingeRec hrec_next = load_rec(T.hinge_sched, e_s);
       for (int r = 0; r < T.p.hinge_rounds; ++r) {
-        const HingeRec rec = load_rec(T.hinge_sched, r * S + e_s);
+        const HingeRec rec = hrec_next;
+        if (r + 1 < T.p.hinge_rounds) hrec_next = load_rec(T.hinge_sched, (r + 1) * S + e_s);
         if (e_ok && rec.rest >= 0.0f) {
           const int i = (int)(rec.ij & 0xffffu), j = (int)(rec.ij >> 16);
           const int kk = (int)(rec.kl & 0xffffu), l = (int)(rec.kl >> 16);
@@ -253,21 +257,49 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       }
       __syncthreads();
       // ---- global step: D = -L^-1 R on the matrix cores
+      // A fragments stream from L2 in chunks of kMfmaChunk k steps, the next chunk loaded
+      // while the current one feeds the matrix cores; the chunk's B reads are issued before
+      // its MFMAs. k steps past the padded column count read a clamped row of R against
+      // zero A entries.
       f4 acc[kMaxTilesPerWave];
       const float* Lt = T.linv_tiles;
+      const int kmax_row = npad - 1;
 #pragma unroll
       for (int i = 0; i < kMaxTilesPerWave; ++i) {
         acc[i] = f4{0.f, 0.f, 0.f, 0.f};
         const int t = t0 + i;
         if (t < t1) {
           const int rt = t / CT, ct = t - rt * CT;
-          const __attribute__((address_space(1))) float* La = gptr(Lt) + (size_t)rt * KS * 64 + lane;
+          const __attribute__((address_space(1))) float* La =
+              gptr(Lt) + (size_t)rt * KS * 64 + lane;
           int col = ct * 16 + (lane & 15);
           col = col < ncols ? col : 0;
-          const float* Rb = R + col * npad + (lane >> 4);
+          const float* Rb = R + col * npad;
+          const int kq = lane >> 4;
           f4 a4 = f4{0.f, 0.f, 0.f, 0.f};
-          for (int s = 0; s < KS; ++s)
-            a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(La[s * 64], Rb[4 * s], a4, 0, 0, 0);
+          float an[kMfmaChunk];
+#pragma unroll
+          for (int j = 0; j < kMfmaChunk; ++j) an[j] = La[j * 64];
+          for (int s0 = 0; s0 < KS; s0 += kMfmaChunk) {
+            float ac[kMfmaChunk];
+#pragma unroll
+            for (int j = 0; j < kMfmaChunk; ++j) ac[j] = an[j];
+            if (s0 + kMfmaChunk < KS) {
+#pragma unroll
+              for (int j = 0; j < kMfmaChunk; ++j) an[j] = La[(s0 + kMfmaChunk + j) * 64];
+            }
+            float bv[kMfmaChunk];
+#pragma unroll
+            for (int j = 0; j < kMfmaChunk; ++j) {
+              int row = 4 * (s0 + j) + kq;
+              row = row < kmax_row ? row : kmax_row;
+              bv[j] = Rb[row];
+            }
+            __builtin_amdgcn_sched_barrier(0);   // all B reads in flight before the MFMAs
+#pragma unroll
+            for (int j = 0; j < kMfmaChunk; ++j)
+              a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[j], bv[j], a4, 0, 0, 0);
+          }
           acc[i] = a4;
         }
       }

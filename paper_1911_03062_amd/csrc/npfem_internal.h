@@ -45,7 +45,8 @@ struct TypeParams {
   int32_t slots;                // element slots per cell in a wave (64 / gw)
   int32_t tri_rounds, hinge_rounds;
   int32_t row_tiles;            // ceil(n / 16): MFMA row tiles of L^-1
-  int32_t k_steps;              // npad / 4: MFMA k steps
+  int32_t k_steps;              // MFMA k steps of L^-1 tiles: npad / 4 rounded up to a
+                                // multiple of kMfmaChunk (the extra steps hold zeros)
   int32_t pad0;
   double h, mass, inv_h2m;      // h, m, m / h^2
   double h2_over_m;             // h^2 / m
@@ -139,6 +140,7 @@ struct FusedGroup {
   int32_t cells[kMaxGroupCells]; // batch cell ids
 };
 
+constexpr int kMfmaChunk = 8;               // k steps per prefetched L^-1 chunk
 constexpr int kMaxTilesPerWave = 9;         // MFMA 16x16 output tiles held per wave
 
 // Kernel launchers and sizes (kernels_plain.hip, kernels_fused.hip).
