@@ -1,7 +1,10 @@
 // Fused batched form of the npFEM step: every cell of the batch advanced by one launch.
 //
 // One workgroup (4 waves) takes a group of up to 4*gw cells of one type. Per cell, LDS holds
-// the current positions X and the gradient/update column R (FP32, [cell][coord][npad]).
+// the current positions X and the gradient/update R, FP32, vertex-interleaved
+// [cell][vertex][xyz] with a cell stride of 3*npad words (npad >= n, a multiple of 4 whose
+// quarter is odd, so 3*npad = 12 mod 64 and an MFMA B tile of 16 columns x 4 rows spreads
+// over distinct banks).
 // Each wave owns gw cells for everything except the global step:
 //   prediction      delta^0 = h v + h^2 F/m, kept with delta and the cell-local rest of x_n
 //                   in the owning lanes' registers (supplementary material, npFEM
@@ -70,11 +73,17 @@ __device__ __forceinline__ void refresh_items(int (&item)[NQ]) {
   for (int it = 0; it < NQ; ++it) asm volatile("" : "+v"(item[it]));
 }
 
-// Volume gradient of vertex vi of the cell whose X columns start at Xc, from its one ring.
+__device__ __forceinline__ Vec3<float> ld3(const float* p) { return v3<float>(p[0], p[1], p[2]); }
+__device__ __forceinline__ void add3(float* p, Vec3<float> v) {
+  p[0] += v.x;
+  p[1] += v.y;
+  p[2] += v.z;
+}
+
+// Volume gradient of vertex vi of the cell whose X block starts at Xc, from its one ring.
 // Also returns the vertex's third of the incident triangles' area (sum |N_t| / 6).
-__device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const float* Xc,
-                                                        int npad, int vi, Vec3<float> pi,
-                                                        float& area_third) {
+__device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const float* Xc, int vi,
+                                                        Vec3<float> pi, float& area_third) {
   const uint32_t info = gptr(T.ring_info)[vi];
   const int off = (int)(info >> 8), deg = (int)(info & 255u);
   Vec3<float> g = v3<float>(0.f, 0.f, 0.f);
@@ -82,8 +91,8 @@ __device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const 
   for (int s = 0; s < deg; ++s) {
     const uint32_t pr = gptr(T.ring_pairs)[off + s];
     const int b = (int)(pr & 0xffffu), c = (int)(pr >> 16);
-    const Vec3<float> pb = v3<float>(Xc[b], Xc[npad + b], Xc[2 * npad + b]) - pi;
-    const Vec3<float> pc = v3<float>(Xc[c], Xc[npad + c], Xc[2 * npad + c]) - pi;
+    const Vec3<float> pb = ld3(Xc + 3 * b) - pi;
+    const Vec3<float> pc = ld3(Xc + 3 * c) - pi;
     const Vec3<float> nt = cross3(pb, pc);
     g = g + nt;
     ar += dsqrt(dot3(nt, nt));
@@ -110,11 +119,12 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const DevType& T = types[grp.type];
     const int n = T.p.n, npad = T.p.npad, gw = T.p.gw, S = T.p.slots;
     const int G4 = kFusedWaves * gw;
+    const int CS = 3 * npad;                 // words per cell block
     float* X = lds;
-    float* R = lds + G4 * 3 * npad;
+    float* R = lds + G4 * CS;
 
     __syncthreads();   // the previous group's last reads of LDS are done
-    for (int i = tid; i < G4 * 3 * npad; i += kFusedThreads) R[i] = 0.0f;
+    for (int i = tid; i < G4 * CS; i += kFusedThreads) R[i] = 0.0f;
 
     // ---- owner items: (cell gc of this wave, vertex vi), q = lane + 64 * it, packed as
     //      vi | gc << 16; gc >= G4 marks an empty item
@@ -129,6 +139,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #define ITEM_OK(it) ((item[it] >> 16) < G4)
 #define ITEM_V(it) (item[it] & 0xffff)
 #define ITEM_C(it) (item[it] >> 16)
+#define ITEM_W(it) (ITEM_C(it) * CS + 3 * ITEM_V(it))   // word offset of the item's xyz
     const float h = (float)T.p.h, h2m = (float)T.p.h2_over_m, ih2m = (float)T.p.inv_h2m;
     const float w_v = (float)T.p.w_v, ih = (float)(1.0 / T.p.h);
     if (tid < count) off_lds[tid] = offsets[grp.cells[tid]];
@@ -143,12 +154,12 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       if (ITEM_OK(it)) {
         const int64_t off = off_lds[ITEM_C(it)];
         const int vi = ITEM_V(it);
-        float* Xc = X + ITEM_C(it) * 3 * npad;
+        float* Xv = X + ITEM_W(it);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const float dd = h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi];
           // cell-local coordinates: positions relative to the cell's first vertex
-          Xc[c * npad + vi] = (x[c * vt + off + vi] - x[c * vt + off]) + dd;
+          Xv[c] = (x[c * vt + off + vi] - x[c * vt + off]) + dd;
         }
       }
     }
@@ -158,13 +169,13 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const int e_cw = lane / S, e_s = lane - e_cw * S;
     const int e_gc = wave * gw + e_cw;
     const bool e_ok = e_gc < count;
-    const float* Xe = X + e_gc * 3 * npad;
-    float* Re = R + e_gc * 3 * npad;
+    const float* Xe = X + e_gc * CS;
+    float* Re = R + e_gc * CS;
     const float w_s = (float)T.p.w_s, w_a = (float)T.p.w_a, w_b = (float)T.p.w_b;
     const float s_min = (float)T.p.s_min, s_max = (float)T.p.s_max;
 
     // MFMA tiling of this wave
-    const int RT = T.p.row_tiles, KS = T.p.k_steps;
+    const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
     const int ncols = 3 * count, CT = (ncols + 15) / 16, ntiles = RT * CT;
     const int t0 = (ntiles * wave) / kFusedWaves, t1 = (ntiles * (wave + 1)) / kFusedWaves;
 
@@ -177,13 +188,12 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         vpart[it] = 0.0f;
         gpart[it] = 0.0f;
         if (ITEM_OK(it)) {
-          const float* Xc = X + ITEM_C(it) * 3 * npad;
-          float* Rc = R + ITEM_C(it) * 3 * npad;
-          const int vi = ITEM_V(it);
-          const Vec3<float> pi = v3<float>(Xc[vi], Xc[npad + vi], Xc[2 * npad + vi]);
+          const float* Xc = X + ITEM_C(it) * CS;
+          const Vec3<float> pi = ld3(X + ITEM_W(it));
           float at;
-          const Vec3<float> gg = ring_volume_grad(T, Xc, npad, vi, pi, at);
-          Rc[vi] = gg.x; Rc[npad + vi] = gg.y; Rc[2 * npad + vi] = gg.z;
+          const Vec3<float> gg = ring_volume_grad(T, Xc, ITEM_V(it), pi, at);
+          float* Rv = R + ITEM_W(it);
+          Rv[0] = gg.x; Rv[1] = gg.y; Rv[2] = gg.z;
           vpart[it] = dot3(pi, gg);
           gpart[it] = dot3(gg, gg);
         }
@@ -207,12 +217,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #pragma unroll
       for (int it = 0; it < NQ; ++it)
         if (ITEM_OK(it)) {
-          float* Rc = R + ITEM_C(it) * 3 * npad;
-          const int vi = ITEM_V(it);
+          float* Rv = R + ITEM_W(it);
           const float lw = w_v * lam_lds[ITEM_C(it)];
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            Rc[c * npad + vi] = ih2m * e[it][c] - lw * Rc[c * npad + vi];
+          for (int c = 0; c < 3; ++c) Rv[c] = ih2m * e[it][c] - lw * Rv[c];
         }
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
@@ -222,15 +230,13 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         if (r + 1 < T.p.tri_rounds) rec_next = load_rec(T.tri_sched, (r + 1) * S + e_s);
         if (e_ok && rec.area > 0.0f) {
           const int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
-          const Vec3<float> pa = v3<float>(Xe[a], Xe[npad + a], Xe[2 * npad + a]);
-          const Vec3<float> pb = v3<float>(Xe[b], Xe[npad + b], Xe[2 * npad + b]);
-          const Vec3<float> pc = v3<float>(Xe[c], Xe[npad + c], Xe[2 * npad + c]);
           Vec3<float> ra, rb, rc;
-          triangle_residual<float>(pa, pb, pc, rec.gb0, rec.gb1, rec.gc0, rec.gc1, rec.area, w_s,
-                                   w_a, s_min, s_max, ra, rb, rc);
-          Re[a] += ra.x; Re[npad + a] += ra.y; Re[2 * npad + a] += ra.z;
-          Re[b] += rb.x; Re[npad + b] += rb.y; Re[2 * npad + b] += rb.z;
-          Re[c] += rc.x; Re[npad + c] += rc.y; Re[2 * npad + c] += rc.z;
+          triangle_residual<float>(ld3(Xe + 3 * a), ld3(Xe + 3 * b), ld3(Xe + 3 * c), rec.gb0,
+                                   rec.gb1, rec.gc0, rec.gc1, rec.area, w_s, w_a, s_min, s_max,
+                                   ra, rb, rc);
+          add3(Re + 3 * a, ra);
+          add3(Re + 3 * b, rb);
+          add3(Re + 3 * c, rc);
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -243,29 +249,27 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const int i = (int)(rec.ij & 0xffffu), j = (int)(rec.ij >> 16);
           const int kk = (int)(rec.kl & 0xffffu), l = (int)(rec.kl >> 16);
           Vec3<float> ri, rj, rk, rl;
-          hinge_residual<float>(v3<float>(Xe[i], Xe[npad + i], Xe[2 * npad + i]),
-                                v3<float>(Xe[j], Xe[npad + j], Xe[2 * npad + j]),
-                                v3<float>(Xe[kk], Xe[npad + kk], Xe[2 * npad + kk]),
-                                v3<float>(Xe[l], Xe[npad + l], Xe[2 * npad + l]), rec.a1, rec.a2,
-                                rec.a3, rec.rest, w_b, ri, rj, rk, rl);
-          Re[i] += ri.x; Re[npad + i] += ri.y; Re[2 * npad + i] += ri.z;
-          Re[j] += rj.x; Re[npad + j] += rj.y; Re[2 * npad + j] += rj.z;
-          Re[kk] += rk.x; Re[npad + kk] += rk.y; Re[2 * npad + kk] += rk.z;
-          Re[l] += rl.x; Re[npad + l] += rl.y; Re[2 * npad + l] += rl.z;
+          hinge_residual<float>(ld3(Xe + 3 * i), ld3(Xe + 3 * j), ld3(Xe + 3 * kk),
+                                ld3(Xe + 3 * l), rec.a1, rec.a2, rec.a3, rec.rest, w_b, ri, rj,
+                                rk, rl);
+          add3(Re + 3 * i, ri);
+          add3(Re + 3 * j, rj);
+          add3(Re + 3 * kk, rk);
+          add3(Re + 3 * l, rl);
         }
         __builtin_amdgcn_wave_barrier();
       }
       __syncthreads();
-      // ---- global step: D = -L^-1 R on the matrix cores
-      // A fragments stream from L2 in chunks of kMfmaChunk k steps, the next chunk loaded
-      // while the current one feeds the matrix cores; the chunk's B reads are issued before
-      // its MFMAs. k steps past the padded column count read a clamped row of R against
-      // zero A entries.
+      // ---- global step: D = -L^-1 R on the matrix cores. Column col = 3 cell + coord,
+      // row k = vertex: B(k, col) = R[cell][k][coord]. A fragments stream from L2 in chunks
+      // of kMfmaChunk k steps (the next chunk loads while the current one runs); each
+      // chunk's B reads are issued before its MFMAs. The last, partial chunk clamps its rows
+      // to the zero row npad - 1 (A is zero there).
       f4 acc[kMaxTilesPerWave];
       const float* Lt = T.linv_tiles;
-      const int kmax_row = npad - 1;
 #pragma unroll
       for (int i = 0; i < kMaxTilesPerWave; ++i) {
+        __builtin_amdgcn_sched_barrier(0);   // keep tiles apart: one tile's operands live at a time
         acc[i] = f4{0.f, 0.f, 0.f, 0.f};
         const int t = t0 + i;
         if (t < t1) {
@@ -274,8 +278,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               gptr(Lt) + (size_t)rt * KS * 64 + lane;
           int col = ct * 16 + (lane & 15);
           col = col < ncols ? col : 0;
-          const float* Rb = R + col * npad;
+          const int ccell = col / 3, ccoord = col - 3 * ccell;
           const int kq = lane >> 4;
+          const float* Rb = R + ccell * CS + ccoord + 3 * kq;    // row kq of this column
           f4 a4 = f4{0.f, 0.f, 0.f, 0.f};
           float an[kMfmaChunk];
 #pragma unroll
@@ -289,11 +294,15 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               for (int j = 0; j < kMfmaChunk; ++j) an[j] = La[(s0 + kMfmaChunk + j) * 64];
             }
             float bv[kMfmaChunk];
+            if (s0 + kMfmaChunk <= KR) {
 #pragma unroll
-            for (int j = 0; j < kMfmaChunk; ++j) {
-              int row = 4 * (s0 + j) + kq;
-              row = row < kmax_row ? row : kmax_row;
-              bv[j] = Rb[row];
+              for (int j = 0; j < kMfmaChunk; ++j) bv[j] = Rb[12 * (s0 + j)];
+            } else {
+#pragma unroll
+              for (int j = 0; j < kMfmaChunk; ++j) {
+                const int row = min(4 * (s0 + j) + kq, npad - 1);
+                bv[j] = R[ccell * CS + ccoord + 3 * row];
+              }
             }
             __builtin_amdgcn_sched_barrier(0);   // all B reads in flight before the MFMAs
 #pragma unroll
@@ -312,9 +321,11 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const int col = ct * 16 + (lane & 15);
           const int row0 = rt * 16 + 4 * (lane >> 4);
           if (col < ncols) {
+            const int ccell = col / 3, ccoord = col - 3 * ccell;
+            float* Rw = R + ccell * CS + ccoord;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (row0 + r < n) R[col * npad + row0 + r] = -acc[i][r];
+              if (row0 + r < n) Rw[3 * (row0 + r)] = -acc[i][r];
           }
         }
       }
@@ -324,14 +335,13 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #pragma unroll
       for (int it = 0; it < NQ; ++it)
         if (ITEM_OK(it)) {
-          const float* Rc = R + ITEM_C(it) * 3 * npad;
-          float* Xc = X + ITEM_C(it) * 3 * npad;
-          const int vi = ITEM_V(it);
+          const float* Rv = R + ITEM_W(it);
+          float* Xv = X + ITEM_W(it);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float dd = Rc[c * npad + vi];
+            const float dd = Rv[c];
             e[it][c] += dd;
-            Xc[c * npad + vi] += dd;
+            Xv[c] += dd;
           }
         }
       __builtin_amdgcn_wave_barrier();
@@ -346,11 +356,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         vpart[it] = 0.0f;
         apart[it] = 0.0f;
         if (ITEM_OK(it)) {
-          const float* Xc = X + ITEM_C(it) * 3 * npad;
-          const int vi = ITEM_V(it);
-          const Vec3<float> pi = v3<float>(Xc[vi], Xc[npad + vi], Xc[2 * npad + vi]);
+          const float* Xc = X + ITEM_C(it) * CS;
+          const Vec3<float> pi = ld3(X + ITEM_W(it));
           float at;
-          const Vec3<float> gg = ring_volume_grad(T, Xc, npad, vi, pi, at);
+          const Vec3<float> gg = ring_volume_grad(T, Xc, ITEM_V(it), pi, at);
           vpart[it] = dot3(pi, gg);
           apart[it] = at;
         }
@@ -394,6 +403,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #undef ITEM_OK
 #undef ITEM_V
 #undef ITEM_C
+#undef ITEM_W
   }
 }
 
