@@ -35,11 +35,36 @@ inline V3 scale(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
 // cot of the angle between u and v
 inline double cot(V3 u, V3 v) { return dot(u, v) / norm(cross(u, v)); }
 
-// Greedy packing of elements (each touching `arity` vertices) into rounds of at most
-// `slots` elements whose vertex sets are pairwise disjoint. Elements touching the busiest
-// vertices are placed first; each goes to the least-filled round it fits in.
+// ---- fused-kernel element schedules
+//
+// A schedule lists, round by round, the element each lane of a cell handles; the elements of
+// one round share no vertex, so one wave accumulates their residuals into LDS without atomics.
+// Each lane reads the positions of its element's vertices (one LDS access per vertex role and
+// coordinate) and read-modify-writes the residuals at the same words. The LDS has 32 banks of
+// 4 bytes; a wave64 access is served a half-wave at a time, each half taking as many cycles as
+// its busiest bank has distinct words. Vertex v of a cell sits at word 3v + coordinate, so the
+// bank of a role's access is fixed by v mod 32 (3 is odd). Two choices spread the accesses:
+//   packing   which elements share a round: a residue class mod M should hold no more
+//             vertices than there are roles (the arity), M = 32 when a cell fills a half-wave;
+//   roles     which vertex of an element is read in which role: an edge colouring of the
+//             bipartite multigraph (elements) x (residue classes) with arity colours, which
+//             exists when every class has at most arity vertices (Koenig's theorem); a class
+//             with more is split into sub-classes of at most arity vertices first.
+// A few packings are tried and the one with the lowest modelled cost is kept (per round, the
+// larger of its LDS cycles under the bank model and its VALU work per wave, plus part of the
+// smaller).
+
+struct Schedule {
+  std::vector<std::vector<std::vector<int>>> rounds;  // [round][slot] -> vertices in role order
+  std::vector<std::vector<int>> ids;                  // [round][slot] -> element
+  double cost = 0.0;
+};
+
+// Greedy packing into rounds of at most `slots` vertex-disjoint elements. Elements touching
+// the busiest vertices go first; each takes the fitting round with the fewest vertices beyond
+// `cap` per residue class mod M (with `hard`, none beyond), then the least-filled one.
 std::vector<std::vector<int>> pack_rounds(const std::vector<std::vector<int>>& elems, int n,
-                                          int slots) {
+                                          int slots, int M, int cap, bool hard) {
   std::vector<int> deg(n, 0);
   for (auto& el : elems)
     for (int v : el) deg[v]++;
@@ -53,28 +78,197 @@ std::vector<std::vector<int>> pack_rounds(const std::vector<std::vector<int>>& e
   });
   int max_deg = 0;
   for (int d : deg) max_deg = std::max(max_deg, d);
-  int lower = std::max<int>(max_deg, (int)((elems.size() + slots - 1) / slots));
+  const int lower = std::max<int>(max_deg, (int)((elems.size() + slots - 1) / slots));
   std::vector<std::vector<int>> rounds(lower);
   std::vector<std::vector<char>> used(lower, std::vector<char>(n, 0));
+  std::vector<std::vector<int>> rc(lower, std::vector<int>(M, 0));
   for (int id : order) {
-    int best = -1;
-    size_t best_fill = (size_t)slots;
+    int best = -1, best_over = 0;
+    size_t best_fill = 0;
     for (int r = 0; r < (int)rounds.size(); ++r) {
       if (rounds[r].size() >= (size_t)slots) continue;
       bool ok = true;
       for (int v : elems[id])
         if (used[r][v]) { ok = false; break; }
-      if (ok && rounds[r].size() < best_fill) { best = r; best_fill = rounds[r].size(); }
+      if (!ok) continue;
+      int over = 0;
+      for (size_t q = 0; q < elems[id].size(); ++q) {
+        const int cls = elems[id][q] % M;
+        int same = 0;   // earlier vertices of this element in the same class
+        for (size_t p = 0; p < q; ++p) same += (elems[id][p] % M == cls);
+        over += (rc[r][cls] + same >= cap);
+      }
+      if (hard && over > 0) continue;
+      if (best < 0 || over < best_over || (over == best_over && rounds[r].size() < best_fill)) {
+        best = r;
+        best_over = over;
+        best_fill = rounds[r].size();
+      }
     }
     if (best < 0) {
       rounds.emplace_back();
       used.emplace_back(n, 0);
+      rc.emplace_back(M, 0);
       best = (int)rounds.size() - 1;
     }
     rounds[best].push_back(id);
-    for (int v : elems[id]) used[best][v] = 1;
+    for (int v : elems[id]) {
+      used[best][v] = 1;
+      rc[best][v % M]++;
+    }
   }
   return rounds;
+}
+
+// Role assignment of one round: returns, per element, its vertices in role order such that
+// within each role the vertices' residue classes mod M repeat as little as possible.
+std::vector<std::vector<int>> assign_roles(const std::vector<std::vector<int>>& els, int M) {
+  const int E = (int)els.size();
+  if (E == 0) return {};
+  const int arity = (int)els[0].size();
+  // residue sub-classes: the c vertices of class r go round-robin to ceil(c / arity) nodes
+  std::vector<int> cnt(M, 0);
+  for (auto& el : els)
+    for (int v : el) cnt[v % M]++;
+  std::vector<int> first(M + 1, 0);
+  for (int r = 0; r < M; ++r) first[r + 1] = first[r] + (cnt[r] + arity - 1) / arity;
+  const int n_nodes = E + first[M];
+  std::vector<int> seen(M, 0);
+  struct Edge { int u, w, v; };
+  std::vector<Edge> edges;
+  for (int e = 0; e < E; ++e)
+    for (int v : els[e]) {
+      const int r = v % M, nsub = first[r + 1] - first[r];
+      edges.push_back({e, E + first[r] + (seen[r]++ % nsub), v});
+    }
+  std::vector<int> at((size_t)n_nodes * arity, -1);   // node x colour -> edge
+  std::vector<int> col(edges.size(), -1);
+  auto free_colour = [&](int node) {
+    for (int c = 0; c < arity; ++c)
+      if (at[(size_t)node * arity + c] < 0) return c;
+    return -1;
+  };
+  for (int id = 0; id < (int)edges.size(); ++id) {
+    const int u = edges[id].u, w = edges[id].w;
+    const int a = free_colour(u), b = free_colour(w);
+    if (at[(size_t)w * arity + a] >= 0) {
+      // swap colours a and b along the alternating path leaving w by its a-coloured edge;
+      // afterwards a is free at w and still free at u (bipartite graph)
+      std::vector<int> path;
+      int node = w, c = a;
+      while (at[(size_t)node * arity + c] >= 0) {
+        const int pe = at[(size_t)node * arity + c];
+        path.push_back(pe);
+        node = (edges[pe].u == node) ? edges[pe].w : edges[pe].u;
+        c = (c == a) ? b : a;
+      }
+      for (int pe : path) {
+        at[(size_t)edges[pe].u * arity + col[pe]] = -1;
+        at[(size_t)edges[pe].w * arity + col[pe]] = -1;
+      }
+      for (int pe : path) {
+        col[pe] = (col[pe] == a) ? b : a;
+        at[(size_t)edges[pe].u * arity + col[pe]] = pe;
+        at[(size_t)edges[pe].w * arity + col[pe]] = pe;
+      }
+    }
+    col[id] = a;
+    at[(size_t)u * arity + a] = id;
+    at[(size_t)w * arity + a] = id;
+  }
+  std::vector<std::vector<int>> out(E, std::vector<int>(arity, -1));
+  for (int id = 0; id < (int)edges.size(); ++id) out[edges[id].u][col[id]] = edges[id].v;
+  return out;
+}
+
+// Cycles of one wave64 LDS access to 4-byte words (negative: lane inactive).
+int lds_access_cycles(const int* words) {
+  int total = 0;
+  for (int h = 0; h < 2; ++h) {
+    int worst = 0;
+    for (int i = 32 * h; i < 32 * h + 32; ++i) {
+      if (words[i] < 0) continue;
+      bool dup = false;   // count each distinct word once
+      for (int j = 32 * h; j < i && !dup; ++j) dup = (words[j] == words[i]);
+      if (dup) continue;
+      int k = 0;
+      for (int j = 32 * h; j < 32 * h + 32; ++j) {
+        if (words[j] < 0 || (words[j] & 31) != (words[i] & 31)) continue;
+        bool dj = false;
+        for (int l = 32 * h; l < j && !dj; ++l) dj = (words[l] == words[j]);
+        k += !dj;
+      }
+      worst = std::max(worst, k);
+    }
+    total += worst;
+  }
+  return total;
+}
+
+// Modelled cost of a schedule: per round, the larger of the LDS cycles of its accesses and its
+// VALU instructions, plus a quarter of the smaller (the waves sharing a CU overlap the two only
+// in part). Each role costs a position read, a residual read and a residual write per coordinate.
+double schedule_cost(const std::vector<std::vector<std::vector<int>>>& rounds, int gw,
+                     int slots, int cell_words, double valu_per_round) {
+  double cost = 0.0;
+  int words[64];
+  for (auto& rr : rounds) {
+    if (rr.empty()) continue;
+    const int arity = (int)rr[0].size();
+    int lds = 0;
+    for (int q = 0; q < arity; ++q) {
+      for (int lane = 0; lane < 64; ++lane) {
+        const int cw = lane / slots, s = lane % slots;
+        words[lane] = (cw < gw && s < (int)rr.size()) ? cw * cell_words + 3 * rr[s][q] : -1;
+      }
+      lds += 3 * 3 * lds_access_cycles(words);
+    }
+    cost += std::max((double)lds, valu_per_round) + 0.25 * std::min((double)lds, valu_per_round);
+  }
+  return cost;
+}
+
+Schedule best_schedule(const std::vector<std::vector<int>>& elems, int n, int gw, int slots,
+                       int cell_words, double valu_per_round) {
+  Schedule best;
+  bool have = false;
+  const int arity = elems.empty() ? 1 : (int)elems[0].size();
+  const int m_role = std::min(slots, 32);
+  for (int M : {1, 2, 4, 8, 16, 32}) {
+    if (M > m_role) break;
+    for (int capf : {1, 2})
+      for (int hard : {0, 1}) {
+        if (M == 1 && (capf > 1 || hard)) continue;
+        const auto packed = pack_rounds(elems, n, slots, M, M == 1 ? 1 << 30 : capf * arity,
+                                        hard != 0);
+        Schedule s;
+        for (auto& r : packed) {
+          std::vector<std::vector<int>> els;
+          for (int id : r) els.push_back(elems[id]);
+          s.rounds.push_back(assign_roles(els, m_role));
+          s.ids.push_back(r);
+        }
+        s.cost = schedule_cost(s.rounds, gw, slots, cell_words, valu_per_round);
+        if (!have || s.cost < best.cost ||
+            (s.cost == best.cost && s.rounds.size() < best.rounds.size())) {
+          best = std::move(s);
+          have = true;
+        }
+      }
+  }
+  return best;
+}
+
+// D_m^-1 of the triangle (a, b, c): F = [x_b - x_a, x_c - x_a] D_m^-1 with D_m upper triangular
+// in the frame whose first axis is b - a. Returns {gb0, gb1, gc0, gc1}.
+std::array<double, 4> rest_frame(V3 a, V3 b, V3 c) {
+  V3 e1 = sub(b, a), e2 = sub(c, a);
+  double l1 = norm(e1);
+  V3 t1 = scale(e1, 1.0 / l1);
+  double d12 = dot(e2, t1);
+  double l2 = norm(sub(e2, scale(t1, d12)));
+  // D_m = [[l1, d12], [0, l2]],  D_m^-1 = [[1/l1, -d12/(l1 l2)], [0, 1/l2]]
+  return {1.0 / l1, -d12 / (l1 * l2), 0.0, 1.0 / l2};
 }
 
 }  // namespace
@@ -153,14 +347,9 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   ct->A.assign(m, 0.0);
   for (int t = 0; t < m; ++t) {
     V3 a = P(ct->tri[3 * t]), b = P(ct->tri[3 * t + 1]), c = P(ct->tri[3 * t + 2]);
+    const auto fr = rest_frame(a, b, c);
+    const double gb0 = fr[0], gb1 = fr[1], gc0 = fr[2], gc1 = fr[3];
     V3 e1 = sub(b, a), e2 = sub(c, a);
-    double l1 = norm(e1);
-    V3 t1 = scale(e1, 1.0 / l1);
-    double d12 = dot(e2, t1);
-    double l2 = norm(sub(e2, scale(t1, d12)));
-    // D_m = [[l1, d12], [0, l2]],  D_m^-1 = [[1/l1, -d12/(l1 l2)], [0, 1/l2]]
-    double gb0 = 1.0 / l1, gb1 = -d12 / (l1 * l2);
-    double gc0 = 0.0, gc1 = 1.0 / l2;
     double* g = &ct->G[6 * (size_t)t];
     g[2] = gb0; g[3] = gb1;
     g[4] = gc0; g[5] = gc1;
@@ -333,34 +522,45 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     for (int t = 0; t < m; ++t) tel[t] = {ct->tri[3 * t], ct->tri[3 * t + 1], ct->tri[3 * t + 2]};
     for (int h = 0; h < e; ++h)
       hel[h] = {ct->hinge[4 * h], ct->hinge[4 * h + 1], ct->hinge[4 * h + 2], ct->hinge[4 * h + 3]};
-    auto tr = pack_rounds(tel, n, ct->slots);
-    auto hr = pack_rounds(hel, n, ct->slots);
-    ct->tri_rounds = (int)tr.size();
-    ct->hinge_rounds = (int)hr.size();
+    // approximate VALU instructions per wave of one triangle / hinge round of the fused
+    // kernel (its gfx950 code), weighed against the rounds' modelled LDS cycles
+    const double kTriRoundValu = 270.0, kHingeRoundValu = 81.0;
+    const Schedule tr = best_schedule(tel, n, gw, ct->slots, 3 * npad, kTriRoundValu);
+    const Schedule hr = best_schedule(hel, n, gw, ct->slots, 3 * npad, kHingeRoundValu);
+    ct->tri_rounds = (int)tr.rounds.size();
+    ct->hinge_rounds = (int)hr.rounds.size();
     ct->tri_sched.assign((size_t)ct->tri_rounds * ct->slots, TriRec{0, 0, 0, 0, 0, 0, 0.0f, 0});
     ct->hinge_sched.assign((size_t)ct->hinge_rounds * ct->slots,
                            HingeRec{0, 0, 0, 0, 0, 0, -1.0f, 0});
     for (int r = 0; r < ct->tri_rounds; ++r)
-      for (size_t s = 0; s < tr[r].size(); ++s) {
-        int t = tr[r][s];
-        const double* g = &ct->G[6 * (size_t)t];
+      for (size_t s = 0; s < tr.rounds[r].size(); ++s) {
+        // roles (a, b, c) in the order the schedule chose; the rest frame follows it
+        const auto& v = tr.rounds[r][s];
+        const int t = tr.ids[r][s];
+        const auto fr = rest_frame(P(v[0]), P(v[1]), P(v[2]));
         TriRec rec;
-        rec.ab = (uint32_t)ct->tri[3 * t] | ((uint32_t)ct->tri[3 * t + 1] << 16);
-        rec.c = (uint32_t)ct->tri[3 * t + 2];
-        rec.gb0 = (float)g[2]; rec.gb1 = (float)g[3];
-        rec.gc0 = (float)g[4]; rec.gc1 = (float)g[5];
+        rec.ab = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+        rec.c = (uint32_t)v[2];
+        rec.gb0 = (float)fr[0]; rec.gb1 = (float)fr[1];
+        rec.gc0 = (float)fr[2]; rec.gc1 = (float)fr[3];
         rec.area = (float)ct->A[t];
         rec.pad = 0;
         ct->tri_sched[(size_t)r * ct->slots + s] = rec;
       }
     for (int r = 0; r < ct->hinge_rounds; ++r)
-      for (size_t s = 0; s < hr[r].size(); ++s) {
-        int h = hr[r][s];
+      for (size_t s = 0; s < hr.rounds[r].size(); ++s) {
+        // any vertex may lead the difference form: the stencil's coefficients sum to zero
+        const auto& v = hr.rounds[r][s];
+        const int h = hr.ids[r][s];
+        double a[4];
+        for (int q = 0; q < 4; ++q)
+          for (int p = 0; p < 4; ++p)
+            if (ct->hinge[4 * h + p] == v[q]) a[q] = ct->coef[4 * h + p];
         HingeRec rec;
-        rec.ij = (uint32_t)ct->hinge[4 * h] | ((uint32_t)ct->hinge[4 * h + 1] << 16);
-        rec.kl = (uint32_t)ct->hinge[4 * h + 2] | ((uint32_t)ct->hinge[4 * h + 3] << 16);
-        rec.a0 = (float)ct->coef[4 * h]; rec.a1 = (float)ct->coef[4 * h + 1];
-        rec.a2 = (float)ct->coef[4 * h + 2]; rec.a3 = (float)ct->coef[4 * h + 3];
+        rec.ij = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+        rec.kl = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+        rec.a0 = (float)a[0]; rec.a1 = (float)a[1];
+        rec.a2 = (float)a[2]; rec.a3 = (float)a[3];
         rec.rest = (float)ct->rest_norm[h];
         rec.pad = 0;
         ct->hinge_sched[(size_t)r * ct->slots + s] = rec;

@@ -91,3 +91,49 @@ def test_area_root_extreme_stretches(lib):
         lib.npfem_check_triangle(_ptr(p), _ptr(g), area[0], ct.w_s, ct.w_a, ct.s_min, ct.s_max,
                                  _ptr(out), 64)
         assert np.abs(out.reshape(3, 3) - ref).max() <= 1e-9 * np.abs(ref).max(), (s1, s2)
+
+
+@pytest.mark.parametrize("kind", [I.RBC, I.PLT])
+def test_vertex_roles_are_interchangeable(lib, kind):
+    """The fused schedules may list an element's vertices in any order (chosen to spread LDS
+    accesses over banks). Strain, area and bending energies do not depend on that order: a
+    triangle's rest frame only fixes F up to an orthogonal factor on the right, which the
+    projections carry along, and the bending stencil sums to zero, so any vertex can lead its
+    difference form. All six orders of a triangle (frame rebuilt for each) and all rotations of a
+    hinge give the oracle's per-vertex residuals."""
+    import itertools
+    x, t, m = I.cell_type_inputs()[kind]
+    ct = O.CellType(x, t, m, I.DT)
+    rng = np.random.default_rng(11 + kind)
+    xd = ct.X * np.array([1.3, 0.8, 1.0]) + 0.05 * rng.normal(size=ct.X.shape)
+    F = O.deformation_gradients(xd[None], ct)
+    ps, pa = O.triangle_projections(F, ct)
+    M = ct.area[None, :, None, None] * (ct.w_s * (F - ps) + ct.w_a * (F - pa))
+    ref = np.einsum("nmdk,mjk->mjd", M, ct.G)
+    scale = np.abs(ref).max()
+    for ti in rng.choice(ct.m, 12, replace=False):
+        for perm in itertools.permutations(range(3)):
+            tp = ct.tri[ti][list(perm)]
+            G, area = O.triangle_rest_frames(ct.X, tp[None])
+            p = np.ascontiguousarray(xd[tp].ravel())
+            g = np.ascontiguousarray([G[0, 1, 0], G[0, 1, 1], G[0, 2, 0], G[0, 2, 1]])
+            out = np.zeros(9)
+            lib.npfem_check_triangle(_ptr(p), _ptr(g), area[0], ct.w_s, ct.w_a, ct.s_min,
+                                     ct.s_max, _ptr(out), 64)
+            back = np.empty((3, 3))
+            back[list(perm)] = out.reshape(3, 3)
+            assert np.abs(back - ref[ti]).max() <= 1e-10 * scale, (ti, perm)
+    u = O.bending_vectors(xd[None], ct)[0]
+    W = ct.w_b * (u - O.bending_projection(u[None], ct)[0])
+    href = ct.coef[:, :, None] * W[:, None, :]
+    hscale = np.abs(href).max()
+    for h in rng.choice(ct.e, 12, replace=False):
+        for perm in itertools.permutations(range(4)):
+            idx = list(perm)
+            p = np.ascontiguousarray(xd[ct.hinge[h][idx]].ravel())
+            a = np.ascontiguousarray(ct.coef[h][idx])
+            out = np.zeros(12)
+            lib.npfem_check_hinge(_ptr(p), _ptr(a), ct.rest_norm[h], ct.w_b, _ptr(out), 64)
+            back = np.empty((4, 3))
+            back[idx] = out.reshape(4, 3)
+            assert np.abs(back - href[h]).max() <= 1e-10 * hscale, (h, perm)
