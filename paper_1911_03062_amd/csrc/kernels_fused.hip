@@ -10,14 +10,16 @@
 //                   in the owning lanes' registers (supplementary material, npFEM
 //                   subsection: y_n with C = 0);
 //   volume          grad_i V = 1/6 sum over incident triangles of their doubled area vector,
-//                   V = 1/3 sum_i x_i . grad_i V and |grad V|^2 reduced per cell in FP64;
+//                   accumulated into R over the triangle schedule, V = 1/6 sum_t x_a . N_t;
+//                   V and |grad V|^2 summed per cell in FP64 over the cell's lanes;
 //   local step      R = (m/h^2)(delta - delta^0) - k_vol lambda grad V, then every triangle
 //                   and hinge adds its constraint residual; the schedule packs vertex-disjoint
 //                   elements into rounds, so one wave updates R without atomics or barriers
 //                   and the summation order is fixed (bitwise reproducible);
 //   global step     D = -L^-1 R for all 3 * cells columns of the group at once as an FP32
 //                   MFMA product (v_mfma_f32_16x16x4_f32), A = L^-1 tiles streamed from L2,
-//                   B = R from LDS; the 4 waves split the output tiles;
+//                   B = R from LDS, both double-buffered; the 4 waves split the output tiles
+//                   in pairs that share A;
 //   update          delta += D (quasi-Newton step of the fourth displayed equation).
 // Three workgroup barriers per iteration; everything else is wave-local.
 #include <hip/hip_runtime.h>
@@ -78,6 +80,109 @@ __device__ __forceinline__ void add3(float* p, Vec3<float> v) {
   p[0] += v.x;
   p[1] += v.y;
   p[2] += v.z;
+}
+
+typedef const __attribute__((address_space(1))) float gfloat;
+
+// Word offset of MFMA column col (3 cell + coord) of row 0; columns past the group's last
+// read column 0 (their results are discarded).
+__device__ __forceinline__ int col_base(int col, int ncols, int CS) {
+  col = col < ncols ? col : 0;
+  const int cell = col / 3;
+  return cell * CS + (col - 3 * cell);
+}
+
+// One k chunk of A fragments (kMfmaChunk k steps, 64 lane-ordered values each) from L2. The
+// tile array is padded with zero steps to whole chunks, so a chunk load stays in bounds.
+__device__ __forceinline__ void load_a(float (&a)[kMfmaChunk], gfloat* La, int c) {
+#pragma unroll
+  for (int j = 0; j < kMfmaChunk; ++j) a[j] = La[(c * kMfmaChunk + j) * 64];
+}
+
+// B values of chunk c: row 4 s + lane / 16 of the lane's column, s = c * kMfmaChunk + j, read
+// at Rb[12 s]. Steps past the last real one (KR - 1) re-read that step (A is zero there).
+template <bool TWO>
+__device__ __forceinline__ void load_b(float (&b0)[kMfmaChunk], float (&b1)[kMfmaChunk],
+                                       const float* RbA, const float* RbB, int c, int KR) {
+  const int s0 = c * kMfmaChunk;
+  if (s0 + kMfmaChunk <= KR) {
+#pragma unroll
+    for (int j = 0; j < kMfmaChunk; ++j) {
+      b0[j] = RbA[12 * (s0 + j)];
+      if (TWO) b1[j] = RbB[12 * (s0 + j)];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMfmaChunk; ++j) {
+      const int sj = min(s0 + j, KR - 1);
+      b0[j] = RbA[12 * sj];
+      if (TWO) b1[j] = RbB[12 * sj];
+    }
+  }
+}
+
+template <bool TWO>
+__device__ __forceinline__ void mma_chunk(const float (&a)[kMfmaChunk], const float (&b0)[kMfmaChunk],
+                                          const float (&b1)[kMfmaChunk], int cnt, f4& acc0,
+                                          f4& acc1) {
+  if (cnt >= kMfmaChunk) {
+#pragma unroll
+    for (int j = 0; j < kMfmaChunk; ++j) {
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b0[j], acc0, 0, 0, 0);
+      if (TWO) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b1[j], acc1, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMfmaChunk; ++j)
+      if (j < cnt) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b0[j], acc0, 0, 0, 0);
+        if (TWO) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b1[j], acc1, 0, 0, 0);
+      }
+  }
+}
+
+// D tiles of one L^-1 row tile: acc0 (and acc1 with TWO) += A x B over the k steps s < KR.
+// Two register sets alternate: while one chunk's MFMAs run, the next chunk's A fragments
+// (from L2) and B values (from LDS) are already in flight.
+template <bool TWO>
+__device__ __forceinline__ void mfma_rows(gfloat* La, const float* RbA, const float* RbB, int KR,
+                                          f4& acc0, f4& acc1) {
+  const int nch = (KR + kMfmaChunk - 1) / kMfmaChunk;
+  float aP[kMfmaChunk], aQ[kMfmaChunk], bP0[kMfmaChunk], bP1[kMfmaChunk], bQ0[kMfmaChunk],
+      bQ1[kMfmaChunk];
+  load_a(aP, La, 0);
+  load_b<TWO>(bP0, bP1, RbA, RbB, 0, KR);
+  for (int c = 0; c < nch; c += 2) {
+    if (c + 1 < nch) {
+      load_a(aQ, La, c + 1);
+      load_b<TWO>(bQ0, bQ1, RbA, RbB, c + 1, KR);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    mma_chunk<TWO>(aP, bP0, bP1, KR - c * kMfmaChunk, acc0, acc1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (c + 2 < nch) {
+      load_a(aP, La, c + 2);
+      load_b<TWO>(bP0, bP1, RbA, RbB, c + 2, KR);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (c + 1 < nch) mma_chunk<TWO>(aQ, bQ0, bQ1, KR - (c + 1) * kMfmaChunk, acc0, acc1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// D = -acc for output tile (rt, ct) into R: lane holds rows rt*16 + 4 (lane/16) + r of
+// column ct*16 + lane%16.
+__device__ __forceinline__ void write_tile(float* R, f4 acc, int rt, int ct, int lane, int n,
+                                           int ncols, int CS) {
+  const int col = ct * 16 + (lane & 15);
+  const int row0 = rt * 16 + 4 * (lane >> 4);
+  if (col < ncols) {
+    const int cell = col / 3;
+    float* Rw = R + cell * CS + (col - 3 * cell);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (row0 + r < n) Rw[3 * (row0 + r)] = -acc[r];
+  }
 }
 
 // Volume gradient of vertex vi of the cell whose X block starts at Xc, from its one ring.
@@ -174,42 +279,55 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const float w_s = (float)T.p.w_s, w_a = (float)T.p.w_a, w_b = (float)T.p.w_b;
     const float s_min = (float)T.p.s_min, s_max = (float)T.p.s_max;
 
-    // MFMA tiling of this wave
+    // MFMA work items of this wave
     const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
-    const int ncols = 3 * count, CT = (ncols + 15) / 16, ntiles = RT * CT;
-    const int t0 = (ntiles * wave) / kFusedWaves, t1 = (ntiles * (wave + 1)) / kFusedWaves;
+    const int ncols = 3 * count, CT = (ncols + 15) / 16, CP = (CT + 1) / 2;
+    const bool pairs = CT >= 2;
+    const int n_items = mfma_items(RT, CT);
+    const int m0 = (n_items * wave) / kFusedWaves, m1 = (n_items * (wave + 1)) / kFusedWaves;
 
     for (int k = 0; k < K; ++k) {
-      refresh_items(item);
-      // ---- volume constraint: grad V per vertex (staged in R), V and |grad V|^2 per cell
-      float vpart[NQ], gpart[NQ];
-#pragma unroll
-      for (int it = 0; it < NQ; ++it) {
-        vpart[it] = 0.0f;
-        gpart[it] = 0.0f;
-        if (ITEM_OK(it)) {
-          const float* Xc = X + ITEM_C(it) * CS;
-          const Vec3<float> pi = ld3(X + ITEM_W(it));
-          float at;
-          const Vec3<float> gg = ring_volume_grad(T, Xc, ITEM_V(it), pi, at);
-          float* Rv = R + ITEM_W(it);
-          Rv[0] = gg.x; Rv[1] = gg.y; Rv[2] = gg.z;
-          vpart[it] = dot3(pi, gg);
-          gpart[it] = dot3(gg, gg);
+      // ---- volume constraint. R is zero here. Over the triangle rounds every triangle adds
+      // its outward doubled area vector N_t = (x_b - x_a) x (x_c - x_a) (sign-corrected when
+      // the schedule lists its vertices in reversed order) to R at its three vertices,
+      // so that R_i = 6 grad_i V, and x_a . N_t (= 6 x its signed volume) to the lane's sum.
+      float v6 = 0.0f;
+      {
+        TriRec rec_next = load_rec(T.tri_sched, e_s);
+        for (int r = 0; r < T.p.tri_rounds; ++r) {
+          const TriRec rec = rec_next;
+          if (r + 1 < T.p.tri_rounds) rec_next = load_rec(T.tri_sched, (r + 1) * S + e_s);
+          if (e_ok && rec.area > 0.0f) {
+            const int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
+            const Vec3<float> xa = ld3(Xe + 3 * a);
+            const Vec3<float> nt =
+                cross3(ld3(Xe + 3 * b) - xa, ld3(Xe + 3 * c) - xa) * rec.orient;
+            add3(Re + 3 * a, nt);
+            add3(Re + 3 * b, nt);
+            add3(Re + 3 * c, nt);
+            v6 += dot3(xa, nt);
+          }
+          __builtin_amdgcn_wave_barrier();
         }
       }
-      for (int cw = 0; cw < gw; ++cw) {
-        const int gc = wave * gw + cw;
-        double vs = 0.0, gs = 0.0;
-#pragma unroll
-        for (int it = 0; it < NQ; ++it)
-          if (ITEM_C(it) == gc) {
-            vs += (double)vpart[it];
-            gs += (double)gpart[it];
-          }
-        vs = wave_sum_d(vs);
-        gs = wave_sum_d(gs);
-        if (lane == 0) lam_lds[gc] = (float)(gs > 0.0 ? (T.p.V0 - vs / 3.0) / gs : 0.0);
+      // |6 grad V|^2 of the cell: lane (cell, slot s) takes its vertices s, s + S, ...
+      float g36 = 0.0f;
+      if (e_ok)
+        for (int vv = e_s; vv < n; vv += S) {
+          const Vec3<float> gv = ld3(Re + 3 * vv);
+          g36 += dot3(gv, gv);
+        }
+      {
+        // FP64 sums over the S lanes of each cell (all cells of the wave at once)
+        double vs = (double)v6, gs = (double)g36;
+        for (int o = S >> 1; o > 0; o >>= 1) {
+          vs += __shfl_xor(vs, o, 64);
+          gs += __shfl_xor(gs, o, 64);
+        }
+        // lambda = (V0 - V) / |grad V|^2 with V = vs / 6, |grad V|^2 = gs / 36; stored as
+        // lambda / 6, the factor that multiplies R = 6 grad V
+        if (e_ok && e_s == 0)
+          lam_lds[e_gc] = (float)(gs > 0.0 ? (T.p.V0 - vs / 6.0) / gs * 6.0 : 0.0);
       }
       __builtin_amdgcn_wave_barrier();
       // ---- gradient of g: inertia + volume terms
@@ -218,7 +336,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       for (int it = 0; it < NQ; ++it)
         if (ITEM_OK(it)) {
           float* Rv = R + ITEM_W(it);
-          const float lw = w_v * lam_lds[ITEM_C(it)];
+          const float lw = w_v * lam_lds[ITEM_C(it)];   // w_v lambda / 6
 #pragma unroll
           for (int c = 0; c < 3; ++c) Rv[c] = ih2m * e[it][c] - lw * Rv[c];
         }
@@ -261,71 +379,60 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       }
       __syncthreads();
       // ---- global step: D = -L^-1 R on the matrix cores. Column col = 3 cell + coord,
-      // row k = vertex: B(k, col) = R[cell][k][coord]. A fragments stream from L2 in chunks
-      // of kMfmaChunk k steps (the next chunk loads while the current one runs); each
-      // chunk's B reads are issued before its MFMAs. The last, partial chunk clamps its rows
-      // to the zero row npad - 1 (A is zero there).
+      // row k = vertex: B(k, col) = R[cell][k][coord]. Work items are two 16x16 output tiles:
+      // one row tile of L^-1 against two column tiles (sharing every A fragment), or, when the
+      // group has a single column tile, two row tiles. Each wave holds its items' tiles in
+      // registers until every wave has read R, then writes D over R.
       f4 acc[kMaxTilesPerWave];
-      const float* Lt = T.linv_tiles;
 #pragma unroll
-      for (int i = 0; i < kMaxTilesPerWave; ++i) {
-        __builtin_amdgcn_sched_barrier(0);   // keep tiles apart: one tile's operands live at a time
-        acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-        const int t = t0 + i;
-        if (t < t1) {
-          const int rt = t / CT, ct = t - rt * CT;
-          const __attribute__((address_space(1))) float* La =
-              gptr(Lt) + (size_t)rt * KS * 64 + lane;
-          int col = ct * 16 + (lane & 15);
-          col = col < ncols ? col : 0;
-          const int ccell = col / 3, ccoord = col - 3 * ccell;
-          const int kq = lane >> 4;
-          const float* Rb = R + ccell * CS + ccoord + 3 * kq;    // row kq of this column
-          f4 a4 = f4{0.f, 0.f, 0.f, 0.f};
-          float an[kMfmaChunk];
-#pragma unroll
-          for (int j = 0; j < kMfmaChunk; ++j) an[j] = La[j * 64];
-          for (int s0 = 0; s0 < KS; s0 += kMfmaChunk) {
-            float ac[kMfmaChunk];
-#pragma unroll
-            for (int j = 0; j < kMfmaChunk; ++j) ac[j] = an[j];
-            if (s0 + kMfmaChunk < KS) {
-#pragma unroll
-              for (int j = 0; j < kMfmaChunk; ++j) an[j] = La[(s0 + kMfmaChunk + j) * 64];
-            }
-            float bv[kMfmaChunk];
-            if (s0 + kMfmaChunk <= KR) {
-#pragma unroll
-              for (int j = 0; j < kMfmaChunk; ++j) bv[j] = Rb[12 * (s0 + j)];
+      for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+      {
+        const gfloat* Lt = gptr(T.linv_tiles) + lane;
+        const int kq = lane >> 4;
+        for (int it = m0; it < m1; ++it) {
+          f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
+          if (pairs) {
+            const int rt = it / CP, ctA = 2 * (it - rt * CP);
+            const float* RbA = R + col_base(ctA * 16 + (lane & 15), ncols, CS) + 3 * kq;
+            if (ctA + 1 < CT) {
+              const float* RbB = R + col_base(ctA * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq;
+              mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
             } else {
-#pragma unroll
-              for (int j = 0; j < kMfmaChunk; ++j) {
-                const int row = min(4 * (s0 + j) + kq, npad - 1);
-                bv[j] = R[ccell * CS + ccoord + 3 * row];
-              }
+              mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
             }
-            __builtin_amdgcn_sched_barrier(0);   // all B reads in flight before the MFMAs
-#pragma unroll
-            for (int j = 0; j < kMfmaChunk; ++j)
-              a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[j], bv[j], a4, 0, 0, 0);
+          } else {
+            const int rt = 2 * it;
+            const float* Rb = R + col_base(lane & 15, ncols, CS) + 3 * kq;
+            mfma_rows<false>(Lt + (size_t)rt * KS * 64, Rb, Rb, KR, d0, d1);
+            if (rt + 1 < RT) mfma_rows<false>(Lt + (size_t)(rt + 1) * KS * 64, Rb, Rb, KR, d1, d0);
           }
-          acc[i] = a4;
+          // keep the item's tiles at the end of the held set (indices stay compile-time)
+#pragma unroll
+          for (int i = 0; i + 2 < kMaxTilesPerWave; ++i) acc[i] = acc[i + 2];
+          acc[kMaxTilesPerWave - 2] = d0;
+          acc[kMaxTilesPerWave - 1] = d1;
         }
       }
       __syncthreads();
+      {
+        const int held = m1 - m0;
 #pragma unroll
-      for (int i = 0; i < kMaxTilesPerWave; ++i) {
-        const int t = t0 + i;
-        if (t < t1) {
-          const int rt = t / CT, ct = t - rt * CT;
-          const int col = ct * 16 + (lane & 15);
-          const int row0 = rt * 16 + 4 * (lane >> 4);
-          if (col < ncols) {
-            const int ccell = col / 3, ccoord = col - 3 * ccell;
-            float* Rw = R + ccell * CS + ccoord;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (row0 + r < n) Rw[3 * (row0 + r)] = -acc[i][r];
+        for (int q = 0; q < kMaxTilesPerWave / 2; ++q) {
+          const int pidx = q - (kMaxTilesPerWave / 2 - held);
+          if (pidx >= 0) {
+            const int it = m0 + pidx;
+            int rtA, ctA, rtB, ctB;
+            if (pairs) {
+              rtA = rtB = it / CP;
+              ctA = 2 * (it - rtA * CP);
+              ctB = ctA + 1;
+            } else {
+              rtA = 2 * it;
+              rtB = rtA + 1;
+              ctA = ctB = 0;
+            }
+            write_tile(R, acc[2 * q], rtA, ctA, lane, n, ncols, CS);
+            if (rtB < RT && ctB < CT) write_tile(R, acc[2 * q + 1], rtB, ctB, lane, n, ncols, CS);
           }
         }
       }
@@ -335,13 +442,14 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #pragma unroll
       for (int it = 0; it < NQ; ++it)
         if (ITEM_OK(it)) {
-          const float* Rv = R + ITEM_W(it);
+          float* Rv = R + ITEM_W(it);
           float* Xv = X + ITEM_W(it);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const float dd = Rv[c];
             e[it][c] += dd;
             Xv[c] += dd;
+            Rv[c] = 0.0f;   // R starts the next iteration at zero
           }
         }
       __builtin_amdgcn_wave_barrier();

@@ -24,7 +24,7 @@ struct TriRec {
   uint32_t c;         // c
   float gb0, gb1, gc0, gc1;
   float area;
-  float pad;
+  float orient;       // +1 if (a, b, c) is a rotation of the mesh's (outward) order, else -1
 };
 
 // One hinge slot (32 bytes): edge (i, j), opposite vertices k, l, stencil a_e, rest norm.
@@ -141,7 +141,18 @@ struct FusedGroup {
 };
 
 constexpr int kMfmaChunk = 8;               // k steps per prefetched L^-1 chunk
-constexpr int kMaxTilesPerWave = 9;         // MFMA 16x16 output tiles held per wave
+constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
+
+// MFMA work items of the global step for row_tiles x col_tiles output tiles: pairs of column
+// tiles of one row tile (sharing A), or pairs of row tiles when there is one column tile.
+#ifdef __HIPCC__
+#define NPFEM_HD __host__ __device__
+#else
+#define NPFEM_HD
+#endif
+inline NPFEM_HD int mfma_items(int row_tiles, int col_tiles) {
+  return col_tiles >= 2 ? row_tiles * ((col_tiles + 1) / 2) : (row_tiles + 1) / 2;
+}
 
 // Kernel launchers and sizes (kernels_plain.hip, kernels_fused.hip).
 size_t plain_work_bytes(int precision, int n, int m, int e);

@@ -505,8 +505,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     if (kFusedWaves * cand * per_cell > kFusedLdsBudget) continue;
     if ((cand * n + 63) / 64 > kMaxItems) continue;
     if (kFusedWaves * cand > kMaxGroupCells) continue;
-    const int tiles = ((n + 15) / 16) * ((3 * kFusedWaves * cand + 15) / 16);
-    if ((tiles + kFusedWaves - 1) / kFusedWaves > kMaxTilesPerWave) continue;
+    const int items = mfma_items((n + 15) / 16, (3 * kFusedWaves * cand + 15) / 16);
+    if (2 * ((items + kFusedWaves - 1) / kFusedWaves) > kMaxTilesPerWave) continue;
     gw = cand;
     break;
   }
@@ -529,7 +529,7 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     const Schedule hr = best_schedule(hel, n, gw, ct->slots, 3 * npad, kHingeRoundValu);
     ct->tri_rounds = (int)tr.rounds.size();
     ct->hinge_rounds = (int)hr.rounds.size();
-    ct->tri_sched.assign((size_t)ct->tri_rounds * ct->slots, TriRec{0, 0, 0, 0, 0, 0, 0.0f, 0});
+    ct->tri_sched.assign((size_t)ct->tri_rounds * ct->slots, TriRec{0, 0, 0, 0, 0, 0, 0.0f, 0.0f});
     ct->hinge_sched.assign((size_t)ct->hinge_rounds * ct->slots,
                            HingeRec{0, 0, 0, 0, 0, 0, -1.0f, 0});
     for (int r = 0; r < ct->tri_rounds; ++r)
@@ -544,7 +544,10 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
         rec.gb0 = (float)fr[0]; rec.gb1 = (float)fr[1];
         rec.gc0 = (float)fr[2]; rec.gc1 = (float)fr[3];
         rec.area = (float)ct->A[t];
-        rec.pad = 0;
+        // the roles may reverse the triangle's orientation, which the volume terms see
+        int k0 = 0;
+        while (ct->tri[3 * t + k0] != v[0]) ++k0;
+        rec.orient = (ct->tri[3 * t + (k0 + 1) % 3] == v[1]) ? 1.0f : -1.0f;
         ct->tri_sched[(size_t)r * ct->slots + s] = rec;
       }
     for (int r = 0; r < ct->hinge_rounds; ++r)
