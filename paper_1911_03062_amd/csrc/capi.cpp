@@ -82,7 +82,8 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   p.npad = ct->npad; p.gw = ct->gw; p.slots = ct->slots;
   p.tri_rounds = ct->tri_rounds; p.hinge_rounds = ct->hinge_rounds;
   p.row_tiles = (ct->n + 15) / 16;
-  p.k_steps = (ct->npad / 4 + kMfmaChunk - 1) / kMfmaChunk * kMfmaChunk;
+  // whole chunks plus two zero chunks read by the global step's look-ahead loads
+  p.k_steps = ((ct->npad / 4 + kMfmaChunk - 1) / kMfmaChunk + 2) * kMfmaChunk;
   p.pad0 = 0;
   p.h = ct->h; p.mass = ct->mass; p.inv_h2m = ct->mass / (ct->h * ct->h);
   p.h2_over_m = ct->h * ct->h / ct->mass;
@@ -107,15 +108,24 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
     chk(upload_raw(&d->hinge_sched, ct->hinge_sched.data(), ct->hinge_sched.size()));
     chk(upload(&d->ring_info, ct->ring_info));
     chk(upload(&d->ring_pairs, ct->ring_pairs));
-    // L^-1 in MFMA A-operand order: tile rt, k step s, lane l -> (row rt*16 + l%16, col 4s + l/16)
+    // L^-1 in MFMA A-operand order: row tile rt, chunk c, step j, lane l -> (row rt*16 + l%16,
+    // col 4 s + l/16) with s = s0(c) + j. Chunk c starts at s0(c) = min(c C, KR - C) (C =
+    // kMfmaChunk, KR = npad / 4 >= C): the last chunk ends at the last step and overlaps the
+    // one before it, so its overlapping steps are stored as zeros; the two chunks after the last
+    // one are zero too (the kernel's look-ahead loads read them).
     const int RT = p.row_tiles, KS = p.k_steps, n = ct->n;
+    const int KR = ct->npad / 4, C = kMfmaChunk, nch = (KR + C - 1) / C;
     std::vector<float> lt((size_t)RT * KS * 64, 0.0f);
     for (int rt = 0; rt < RT; ++rt)
-      for (int s = 0; s < KS; ++s)
-        for (int l = 0; l < 64; ++l) {
-          const int row = rt * 16 + (l & 15), col = 4 * s + (l >> 4);
-          if (row < n && col < n)
-            lt[((size_t)rt * KS + s) * 64 + l] = (float)ct->Linv[(size_t)row * n + col];
+      for (int c = 0; c < nch; ++c)
+        for (int j = 0; j < C; ++j) {
+          const int s = std::min(c * C, KR - C) + j;
+          if (s < c * C) continue;   // covered by the previous chunk
+          for (int l = 0; l < 64; ++l) {
+            const int row = rt * 16 + (l & 15), col = 4 * s + (l >> 4);
+            if (row < n && col < n)
+              lt[((size_t)rt * KS + c * C + j) * 64 + l] = (float)ct->Linv[(size_t)row * n + col];
+          }
         }
     chk(upload(&d->linv_tiles, lt));
   }

@@ -83,6 +83,7 @@ __device__ __forceinline__ void add3(float* p, Vec3<float> v) {
 }
 
 typedef const __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(3))) float lfloat;
 
 // Word offset of MFMA column col (3 cell + coord) of row 0; columns past the group's last
 // read column 0 (their results are discarded).
@@ -92,82 +93,67 @@ __device__ __forceinline__ int col_base(int col, int ncols, int CS) {
   return cell * CS + (col - 3 * cell);
 }
 
-// One k chunk of A fragments (kMfmaChunk k steps, 64 lane-ordered values each) from L2. The
-// tile array is padded with zero steps to whole chunks, so a chunk load stays in bounds.
+// One k chunk of A fragments (kMfmaChunk k steps, 64 lane-ordered values each) from L2. A row
+// tile stores its chunks plus two zero chunks, so every chunk load below is in bounds.
 __device__ __forceinline__ void load_a(float (&a)[kMfmaChunk], gfloat* La, int c) {
 #pragma unroll
   for (int j = 0; j < kMfmaChunk; ++j) a[j] = La[(c * kMfmaChunk + j) * 64];
 }
 
-// B values of chunk c: row 4 s + lane / 16 of the lane's column, s = c * kMfmaChunk + j, read
-// at Rb[12 s]. Steps past the last real one (KR - 1) re-read that step (A is zero there).
+// B values of chunk c: row 4 s + lane / 16 of the lane's column for the chunk's k steps
+// s = s0 + j, read at Rb[12 s]. Chunks start at s0 = min(c kMfmaChunk, KR - kMfmaChunk): the
+// last chunk is shifted back to end at the last step and overlaps its predecessor, whose
+// overlapping steps hold zero A fragments in that chunk (as do the zero chunks after it).
 template <bool TWO>
 __device__ __forceinline__ void load_b(float (&b0)[kMfmaChunk], float (&b1)[kMfmaChunk],
-                                       const float* RbA, const float* RbB, int c, int KR) {
-  const int s0 = c * kMfmaChunk;
-  if (s0 + kMfmaChunk <= KR) {
+                                       const lfloat* RbA, const lfloat* RbB, int c, int KR) {
+  const int s0 = min(c * kMfmaChunk, KR - kMfmaChunk);
+  const lfloat* pa = RbA + 12 * s0;
+  const lfloat* pb = RbB + 12 * s0;
 #pragma unroll
-    for (int j = 0; j < kMfmaChunk; ++j) {
-      b0[j] = RbA[12 * (s0 + j)];
-      if (TWO) b1[j] = RbB[12 * (s0 + j)];
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < kMfmaChunk; ++j) {
-      const int sj = min(s0 + j, KR - 1);
-      b0[j] = RbA[12 * sj];
-      if (TWO) b1[j] = RbB[12 * sj];
-    }
+  for (int j = 0; j < kMfmaChunk; ++j) {
+    b0[j] = pa[12 * j];
+    if (TWO) b1[j] = pb[12 * j];
   }
 }
 
 template <bool TWO>
 __device__ __forceinline__ void mma_chunk(const float (&a)[kMfmaChunk], const float (&b0)[kMfmaChunk],
-                                          const float (&b1)[kMfmaChunk], int cnt, f4& acc0,
-                                          f4& acc1) {
-  if (cnt >= kMfmaChunk) {
+                                          const float (&b1)[kMfmaChunk], f4& acc0, f4& acc1) {
 #pragma unroll
-    for (int j = 0; j < kMfmaChunk; ++j) {
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b0[j], acc0, 0, 0, 0);
-      if (TWO) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b1[j], acc1, 0, 0, 0);
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < kMfmaChunk; ++j)
-      if (j < cnt) {
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b0[j], acc0, 0, 0, 0);
-        if (TWO) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b1[j], acc1, 0, 0, 0);
-      }
+  for (int j = 0; j < kMfmaChunk; ++j) {
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b0[j], acc0, 0, 0, 0);
+    if (TWO) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b1[j], acc1, 0, 0, 0);
   }
 }
 
-// D tiles of one L^-1 row tile: acc0 (and acc1 with TWO) += A x B over the k steps s < KR.
-// Two register sets alternate: while one chunk's MFMAs run, the next chunk's A fragments
-// (from L2) and B values (from LDS) are already in flight.
+// D tiles of one L^-1 row tile: acc0 (and acc1 with TWO) += A x B over the chunks covering
+// the k steps s < KR (KR >= kMfmaChunk). Two register sets alternate: while one chunk's MFMAs run, the next
+// chunk's A fragments (from L2) and B values (from LDS) are in flight. The loads are the same
+// on every pass (the last pass fetches a zero chunk), so each chunk waits only for its own
+// operands.
 template <bool TWO>
-__device__ __forceinline__ void mfma_rows(gfloat* La, const float* RbA, const float* RbB, int KR,
-                                          f4& acc0, f4& acc1) {
+__device__ __forceinline__ void mfma_rows(gfloat* La, const lfloat* RbA, const lfloat* RbB,
+                                          int KR, f4& acc0, f4& acc1) {
   const int nch = (KR + kMfmaChunk - 1) / kMfmaChunk;
   float aP[kMfmaChunk], aQ[kMfmaChunk], bP0[kMfmaChunk], bP1[kMfmaChunk], bQ0[kMfmaChunk],
       bQ1[kMfmaChunk];
   load_a(aP, La, 0);
   load_b<TWO>(bP0, bP1, RbA, RbB, 0, KR);
-  for (int c = 0; c < nch; c += 2) {
-    if (c + 1 < nch) {
-      load_a(aQ, La, c + 1);
-      load_b<TWO>(bQ0, bQ1, RbA, RbB, c + 1, KR);
-    }
+  int c = 0;
+  for (; c + 1 < nch; c += 2) {
+    load_a(aQ, La, c + 1);
+    load_b<TWO>(bQ0, bQ1, RbA, RbB, c + 1, KR);
     __builtin_amdgcn_sched_barrier(0);
-    mma_chunk<TWO>(aP, bP0, bP1, KR - c * kMfmaChunk, acc0, acc1);
+    mma_chunk<TWO>(aP, bP0, bP1, acc0, acc1);
     __builtin_amdgcn_sched_barrier(0);
-    if (c + 2 < nch) {
-      load_a(aP, La, c + 2);
-      load_b<TWO>(bP0, bP1, RbA, RbB, c + 2, KR);
-    }
+    load_a(aP, La, c + 2);
+    load_b<TWO>(bP0, bP1, RbA, RbB, c + 2, KR);
     __builtin_amdgcn_sched_barrier(0);
-    if (c + 1 < nch) mma_chunk<TWO>(aQ, bQ0, bQ1, KR - (c + 1) * kMfmaChunk, acc0, acc1);
+    mma_chunk<TWO>(aQ, bQ0, bQ1, acc0, acc1);
     __builtin_amdgcn_sched_barrier(0);
   }
+  if (c < nch) mma_chunk<TWO>(aP, bP0, bP1, acc0, acc1);
 }
 
 // D = -acc for output tile (rt, ct) into R: lane holds rows rt*16 + 4 (lane/16) + r of
@@ -393,16 +379,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
           if (pairs) {
             const int rt = it / CP, ctA = 2 * (it - rt * CP);
-            const float* RbA = R + col_base(ctA * 16 + (lane & 15), ncols, CS) + 3 * kq;
+            const lfloat* RbA = (const lfloat*)(R + col_base(ctA * 16 + (lane & 15), ncols, CS) + 3 * kq);
             if (ctA + 1 < CT) {
-              const float* RbB = R + col_base(ctA * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq;
+              const lfloat* RbB = (const lfloat*)(R + col_base(ctA * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq);
               mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
             } else {
               mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
             }
           } else {
             const int rt = 2 * it;
-            const float* Rb = R + col_base(lane & 15, ncols, CS) + 3 * kq;
+            const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * kq);
             mfma_rows<false>(Lt + (size_t)rt * KS * 64, Rb, Rb, KR, d0, d1);
             if (rt + 1 < RT) mfma_rows<false>(Lt + (size_t)(rt + 1) * KS * 64, Rb, Rb, KR, d1, d0);
           }

@@ -45,8 +45,8 @@ struct TypeParams {
   int32_t slots;                // element slots per cell in a wave (64 / gw)
   int32_t tri_rounds, hinge_rounds;
   int32_t row_tiles;            // ceil(n / 16): MFMA row tiles of L^-1
-  int32_t k_steps;              // MFMA k steps of L^-1 tiles: npad / 4 rounded up to a
-                                // multiple of kMfmaChunk (the extra steps hold zeros)
+  int32_t k_steps;              // MFMA k steps stored per L^-1 row tile: npad / 4 rounded
+                                // up to whole kMfmaChunk chunks plus two chunks (zeros)
   int32_t pad0;
   double h, mass, inv_h2m;      // h, m, m / h^2
   double h2_over_m;             // h^2 / m

@@ -496,7 +496,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   // ---- fused-form layout and element schedules
   // LDS column stride: a multiple of 4 (MFMA k step) whose quarter is odd, so that the 16
   // columns x 4 rows of an MFMA B tile fall in 64 distinct LDS banks.
-  int npad = (n + 3) / 4 * 4;
+  // (at least 36: the global step's k chunks of kMfmaChunk steps need npad / 4 >= kMfmaChunk)
+  int npad = std::max((n + 3) / 4 * 4, 4 * kMfmaChunk);
   if ((npad / 4) % 2 == 0) npad += 4;
   ct->npad = npad;
   const int per_cell = 2 * 3 * npad * 4;  // X and R columns, FP32
