@@ -50,20 +50,47 @@ __device__ __forceinline__ const __attribute__((address_space(1))) P* gptr(const
 }
 
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
-// 32-byte schedule record i as two 16-byte global loads.
-template <typename Rec>
-__device__ __forceinline__ Rec load_rec(const Rec* base, int i) {
-  static_assert(sizeof(Rec) == 32, "schedule records are 32 bytes");
-  const __attribute__((address_space(1))) u4* q =
-      (const __attribute__((address_space(1))) u4*)(base) + 2 * i;
-  union {
-    u4 v[2];
-    Rec r;
-  } u;
-  u.v[0] = q[0];
-  u.v[1] = q[1];
-  return u.r;
+// Schedule records are read with loads of exactly the words a pass uses: a load whose result
+// words are partly unused lets the register allocator reuse those words' registers, which
+// then forces a wait for the load to land before the reuse.
+struct TriHead {   // first 16 bytes of a TriRec
+  uint32_t ab, c;
+  float area, orient;
+};
+struct TriElem {   // first 28 bytes of a TriRec
+  uint32_t ab, c;
+  float area, orient, gb0, gb1, gc1;
+};
+struct HingeElem { // first 24 bytes of a HingeRec
+  uint32_t ij, kl;
+  float a1, a2, a3, rest;
+};
+
+template <typename V>
+__device__ __forceinline__ V load_words(const void* base, int rec, int word) {
+  static_assert(sizeof(TriRec) == 32 && sizeof(HingeRec) == 32, "32-byte records");
+  typedef const __attribute__((address_space(1))) uint32_t gword;
+  typedef const __attribute__((address_space(1))) V gvec;
+  return *(gvec*)((gword*)base + 8 * rec + word);
+}
+__device__ __forceinline__ TriHead load_tri_head(const TriRec* base, int i) {
+  const u4 v = load_words<u4>(base, i, 0);
+  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(v.w)};
+}
+__device__ __forceinline__ TriElem load_tri_elem(const TriRec* base, int i) {
+  const u4 v = load_words<u4>(base, i, 0);
+  const u3 w = load_words<u3>(base, i, 4);
+  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(v.w), __uint_as_float(w.x),
+          __uint_as_float(w.y), __uint_as_float(w.z)};
+}
+__device__ __forceinline__ HingeElem load_hinge(const HingeRec* base, int i) {
+  const u4 v = load_words<u4>(base, i, 0);
+  const u2 w = load_words<u2>(base, i, 4);
+  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(v.w), __uint_as_float(w.x),
+          __uint_as_float(w.y)};
 }
 
 // Makes the packed owner-item codes opaque to the optimiser so that the per-item LDS
@@ -76,6 +103,11 @@ __device__ __forceinline__ void refresh_items(int (&item)[NQ]) {
 }
 
 __device__ __forceinline__ Vec3<float> ld3(const float* p) { return v3<float>(p[0], p[1], p[2]); }
+__device__ __forceinline__ void st3(float* p, Vec3<float> v) {
+  p[0] = v.x;
+  p[1] = v.y;
+  p[2] = v.z;
+}
 __device__ __forceinline__ void add3(float* p, Vec3<float> v) {
   p[0] += v.x;
   p[1] += v.y;
@@ -279,21 +311,33 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       // so that R_i = 6 grad_i V, and x_a . N_t (= 6 x its signed volume) to the lane's sum.
       float v6 = 0.0f;
       {
-        TriRec rec_next = load_rec(T.tri_sched, e_s);
-        for (int r = 0; r < T.p.tri_rounds; ++r) {
-          const TriRec rec = rec_next;
-          if (r + 1 < T.p.tri_rounds) rec_next = load_rec(T.tri_sched, (r + 1) * S + e_s);
+        // software-pipelined rounds: while round r computes, the positions of round r + 1
+        // and the record of round r + 2 are in flight, and round r's residual reads were
+        // issued before its arithmetic. Reads of empty slots (vertex 0) and of cells past the
+        // group's count stay inside the LDS blocks; only their writes are skipped.
+        const int NR = T.p.tri_rounds;
+        TriHead rec = load_tri_head(T.tri_sched, e_s);
+        TriHead rec_n = load_tri_head(T.tri_sched, min(1, NR - 1) * S + e_s);
+        int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
+        Vec3<float> xa = ld3(Xe + 3 * a), xb = ld3(Xe + 3 * b), xc = ld3(Xe + 3 * c);
+        for (int r = 0; r < NR; ++r) {
+          const TriHead rec_nn = load_tri_head(T.tri_sched, min(r + 2, NR - 1) * S + e_s);
+          const int an = (int)(rec_n.ab & 0xffffu), bn = (int)(rec_n.ab >> 16), cn = (int)rec_n.c;
+          const Vec3<float> nxa = ld3(Xe + 3 * an), nxb = ld3(Xe + 3 * bn), nxc = ld3(Xe + 3 * cn);
+          const Vec3<float> oa = ld3(Re + 3 * a), ob = ld3(Re + 3 * b), oc = ld3(Re + 3 * c);
+          __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
+          const Vec3<float> nt = cross3(xb - xa, xc - xa) * rec.orient;
           if (e_ok && rec.area > 0.0f) {
-            const int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
-            const Vec3<float> xa = ld3(Xe + 3 * a);
-            const Vec3<float> nt =
-                cross3(ld3(Xe + 3 * b) - xa, ld3(Xe + 3 * c) - xa) * rec.orient;
-            add3(Re + 3 * a, nt);
-            add3(Re + 3 * b, nt);
-            add3(Re + 3 * c, nt);
+            st3(Re + 3 * a, oa + nt);
+            st3(Re + 3 * b, ob + nt);
+            st3(Re + 3 * c, oc + nt);
             v6 += dot3(xa, nt);
           }
           __builtin_amdgcn_wave_barrier();
+          rec = rec_n;
+          rec_n = rec_nn;
+          a = an; b = bn; c = cn;
+          xa = nxa; xb = nxb; xc = nxc;
         }
       }
       // |6 grad V|^2 of the cell: lane (cell, slot s) takes its vertices s, s + S, ...
@@ -328,40 +372,67 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
-      TriRec rec_next = load_rec(T.tri_sched, e_s);
-      for (int r = 0; r < T.p.tri_rounds; ++r) {
-        const TriRec rec = rec_next;
-        if (r + 1 < T.p.tri_rounds) rec_next = load_rec(T.tri_sched, (r + 1) * S + e_s);
-        if (e_ok && rec.area > 0.0f) {
-          const int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
-          Vec3<float> ra, rb, rc;
-          triangle_residual<float>(ld3(Xe + 3 * a), ld3(Xe + 3 * b), ld3(Xe + 3 * c), rec.gb0,
-                                   rec.gb1, rec.gc0, rec.gc1, rec.area, w_s, w_a, s_min, s_max,
-                                   ra, rb, rc);
-          add3(Re + 3 * a, ra);
-          add3(Re + 3 * b, rb);
-          add3(Re + 3 * c, rc);
+      {
+        // pipelined as the volume rounds (positions of the next round in flight)
+        const int NR = T.p.tri_rounds;
+        TriElem rec = load_tri_elem(T.tri_sched, e_s);
+        TriElem rec_n = load_tri_elem(T.tri_sched, min(1, NR - 1) * S + e_s);
+        int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
+        Vec3<float> xa = ld3(Xe + 3 * a), xb = ld3(Xe + 3 * b), xc = ld3(Xe + 3 * c);
+        for (int r = 0; r < NR; ++r) {
+          const TriElem rec_nn = load_tri_elem(T.tri_sched, min(r + 2, NR - 1) * S + e_s);
+          const int an = (int)(rec_n.ab & 0xffffu), bn = (int)(rec_n.ab >> 16), cn = (int)rec_n.c;
+          const Vec3<float> nxa = ld3(Xe + 3 * an), nxb = ld3(Xe + 3 * bn), nxc = ld3(Xe + 3 * cn);
+          __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
+          if (e_ok && rec.area > 0.0f) {
+            Vec3<float> ra, rb, rc;
+            triangle_residual<float>(xa, xb, xc, rec.gb0, rec.gb1, 0.0f, rec.gc1, rec.area, w_s,
+                                     w_a, s_min, s_max, ra, rb, rc);
+            add3(Re + 3 * a, ra);
+            add3(Re + 3 * b, rb);
+            add3(Re + 3 * c, rc);
+          }
+          __builtin_amdgcn_wave_barrier();
+          rec = rec_n;
+          rec_n = rec_nn;
+          a = an; b = bn; c = cn;
+          xa = nxa; xb = nxb; xc = nxc;
         }
-        __builtin_amdgcn_wave_barrier();
       }
       // ---- edge bending constraints
-      HingeRec hrec_next = load_rec(T.hinge_sched, e_s);
-      for (int r = 0; r < T.p.hinge_rounds; ++r) {
-        const HingeRec rec = hrec_next;
-        if (r + 1 < T.p.hinge_rounds) hrec_next = load_rec(T.hinge_sched, (r + 1) * S + e_s);
-        if (e_ok && rec.rest >= 0.0f) {
-          const int i = (int)(rec.ij & 0xffffu), j = (int)(rec.ij >> 16);
-          const int kk = (int)(rec.kl & 0xffffu), l = (int)(rec.kl >> 16);
+      {
+        // pipelined as the volume rounds above
+        const int NR = T.p.hinge_rounds;
+        HingeElem rec = load_hinge(T.hinge_sched, e_s);
+        HingeElem rec_n = load_hinge(T.hinge_sched, min(1, NR - 1) * S + e_s);
+        int i = (int)(rec.ij & 0xffffu), j = (int)(rec.ij >> 16);
+        int kk = (int)(rec.kl & 0xffffu), l = (int)(rec.kl >> 16);
+        Vec3<float> xi = ld3(Xe + 3 * i), xj = ld3(Xe + 3 * j), xk = ld3(Xe + 3 * kk),
+                    xl = ld3(Xe + 3 * l);
+        for (int r = 0; r < NR; ++r) {
+          const HingeElem rec_nn = load_hinge(T.hinge_sched, min(r + 2, NR - 1) * S + e_s);
+          const int in = (int)(rec_n.ij & 0xffffu), jn = (int)(rec_n.ij >> 16);
+          const int kn = (int)(rec_n.kl & 0xffffu), ln = (int)(rec_n.kl >> 16);
+          const Vec3<float> nxi = ld3(Xe + 3 * in), nxj = ld3(Xe + 3 * jn),
+                            nxk = ld3(Xe + 3 * kn), nxl = ld3(Xe + 3 * ln);
+          const Vec3<float> oi = ld3(Re + 3 * i), oj = ld3(Re + 3 * j), ok3 = ld3(Re + 3 * kk),
+                            ol = ld3(Re + 3 * l);
+          __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
           Vec3<float> ri, rj, rk, rl;
-          hinge_residual<float>(ld3(Xe + 3 * i), ld3(Xe + 3 * j), ld3(Xe + 3 * kk),
-                                ld3(Xe + 3 * l), rec.a1, rec.a2, rec.a3, rec.rest, w_b, ri, rj,
+          hinge_residual<float>(xi, xj, xk, xl, rec.a1, rec.a2, rec.a3, rec.rest, w_b, ri, rj,
                                 rk, rl);
-          add3(Re + 3 * i, ri);
-          add3(Re + 3 * j, rj);
-          add3(Re + 3 * kk, rk);
-          add3(Re + 3 * l, rl);
+          if (e_ok && rec.rest >= 0.0f) {
+            st3(Re + 3 * i, oi + ri);
+            st3(Re + 3 * j, oj + rj);
+            st3(Re + 3 * kk, ok3 + rk);
+            st3(Re + 3 * l, ol + rl);
+          }
+          __builtin_amdgcn_wave_barrier();
+          rec = rec_n;
+          rec_n = rec_nn;
+          i = in; j = jn; kk = kn; l = ln;
+          xi = nxi; xj = nxj; xk = nxk; xl = nxl;
         }
-        __builtin_amdgcn_wave_barrier();
       }
       __syncthreads();
       // ---- global step: D = -L^-1 R on the matrix cores. Column col = 3 cell + coord,

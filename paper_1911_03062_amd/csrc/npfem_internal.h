@@ -18,22 +18,27 @@ namespace npfem {
 // ------------------------------------------------------------------------------------------
 
 // One triangle slot of the per-wave round schedule (32 bytes). A slot with area == 0 is
-// empty. g_b, g_c are the rest-frame gradient vectors (g_a = -g_b - g_c).
+// empty. g_b, g_c are the rest-frame gradient vectors (g_a = -g_b - g_c); the rest frame makes
+// D_m upper triangular, so g_c0 is always zero. The fields a pass reads come first: the volume
+// pass reads the first 16 bytes, the strain/area pass the first 28.
 struct TriRec {
   uint32_t ab;        // a | b << 16
   uint32_t c;         // c
-  float gb0, gb1, gc0, gc1;
   float area;
   float orient;       // +1 if (a, b, c) is a rotation of the mesh's (outward) order, else -1
+  float gb0, gb1, gc1;
+  float gc0;          // 0
 };
 
 // One hinge slot (32 bytes): edge (i, j), opposite vertices k, l, stencil a_e, rest norm.
-// A slot with rest < 0 is empty.
+// A slot with rest < 0 is empty. The kernel reads the first 24 bytes (a_0 = -(a_1 + a_2 + a_3)
+// is implied by the stencil summing to zero).
 struct HingeRec {
   uint32_t ij;        // i | j << 16
   uint32_t kl;        // k | l << 16
-  float a0, a1, a2, a3;
+  float a1, a2, a3;
   float rest;
+  float a0;
   float pad;
 };
 

@@ -17,7 +17,8 @@
 // Area root: d minimises (d - s1)^2 + (1/d - s2)^2, i.e. solves d^4 - s1 d^3 + s2 d - 1 = 0;
 // with d = 1 + eps, a = s1 - 1, b = s2 - 1 the quartic reads
 //   (b - a) + eps (2 - 3a + b) + eps^2 (3 - 3a) + eps^3 (3 - a) + eps^4 = 0,
-// solved by bracketed Newton for its largest root (exact start eps0 = 0 when s1 = s2 <= 2).
+// solved by bracketed Newton for its largest root, started by one Halley step from
+// sqrt(s1/s2) - 1 (which is exact when s1 = s2 <= 2).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -73,50 +74,65 @@ __host__ __device__ __forceinline__ T clamp_dev(T v, T lo, T hi) { return v < lo
 // Triangle residual contributions. Inputs: vertex positions pa, pb, pc (any common origin),
 // rest gradients gb, gc (g_a = -g_b - g_c), rest area, weights. Outputs: contributions to
 // the gradient of g at vertices a, b, c.
+//
+// The polar factor is not formed: R = P A with P = F, A = adj(C + s I) / (s t) in the regular
+// case (P = an orthonormal frame, A = I when F is rank deficient), so that the contribution
+// to vertex j is A_t P (A T g_j) with the 2x2 matrix T = alpha I + beta Q.
 template <typename T>
 __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T> pc, T gb0,
                                                   T gb1, T gc0, T gc1, T area, T w_s, T w_a,
                                                   T s_min, T s_max, Vec3<T>& ra, Vec3<T>& rb,
                                                   Vec3<T>& rc) {
   const Vec3<T> e1 = pb - pa, e2 = pc - pa;
-  const Vec3<T> F0 = e1 * gb0 + e2 * gc0;
+  // the rest frames in use make D_m upper triangular (g_c0 = 0); a literal zero here lets the
+  // compiler drop those terms, which it may not do for x * 0 in general (NaN, signed zero)
+  const bool lower0 = gc0 == T(0);
+  const Vec3<T> F0 = lower0 ? e1 * gb0 : e1 * gb0 + e2 * gc0;
   const Vec3<T> F1 = e1 * gb1 + e2 * gc1;
   const T c00 = dot3(F0, F0), c01 = dot3(F0, F1), c11 = dot3(F1, F1);
-  const Vec3<T> nr = cross3(F0, F1);
-  const T s = dsqrt(dot3(nr, nr));                 // s1 s2
+  const T det2 = c00 * c11 - c01 * c01;            // |F0 x F1|^2 (Lagrange identity)
+  const T s = dsqrt(det2 > T(0) ? det2 : T(0));    // s1 s2
   const T tr = c00 + c11;
   const T tt = dsqrt(tr + T(2) * s);               // s1 + s2
   const T dl = c00 - c11, of = T(2) * c01;
   const T disc = dsqrt(dl * dl + of * of);         // s1^2 - s2^2
-  Vec3<T> R0, R1;
-  T a, b, q_c, q_s;
+  Vec3<T> P0, P1;
+  T A00, A01, A11, a, b, rs;
   if (s > T(1e-30) * (tr + T(1e-30))) {
-    const T inv = drcp(s * tt);
-    R0 = (F0 * (c11 + s) - F1 * c01) * inv;
-    R1 = (F1 * (c00 + s) - F0 * c01) * inv;
-    const T itt = drcp(tt);
-    const T half_diff = T(0.5) * disc * itt;        // (s1 - s2)/2
+    const T inv = drcp(s * tt);                    // 1 / (s t)
+    P0 = F0;
+    P1 = F1;
+    A00 = (c11 + s) * inv;
+    A01 = -c01 * inv;
+    A11 = (c00 + s) * inv;
+    const T half_diff = T(0.5) * disc * (inv * s);  // (s1 - s2)/2
     // (s1 + s2) - 2 = ((c00 - 1) + (c11 - 1) + 2 (s - 1)) / (s1 + s2 + 2); each bracket is
     // an exact subtraction for entries within a factor two of one
     const T tm2 = ((c00 - T(1)) + (c11 - T(1)) + T(2) * (s - T(1))) * drcp(tt + T(2));
     a = T(0.5) * tm2 + half_diff;
     b = T(0.5) * tm2 - half_diff;
+    rs = drsqrt(s);                                // sqrt(s1 / s2) = s1 / sqrt(s)
   } else {
     // rank-deficient F: Gram-Schmidt frame of F's columns (any orthonormal completion)
     T n0 = dsqrt(c00);
-    if (n0 > T(0)) R0 = F0 * drcp(n0);
-    else R0 = v3<T>(1, 0, 0);
-    Vec3<T> w = F1 - R0 * dot3(R0, F1);
+    if (n0 > T(0)) P0 = F0 * drcp(n0);
+    else P0 = v3<T>(1, 0, 0);
+    Vec3<T> w = F1 - P0 * dot3(P0, F1);
     T nw = dsqrt(dot3(w, w));
-    if (nw > T(1e-30)) R1 = w * drcp(nw);
+    if (nw > T(1e-30)) P1 = w * drcp(nw);
     else {
-      Vec3<T> ax = (R0.x * R0.x < T(0.5)) ? v3<T>(1, 0, 0) : v3<T>(0, 1, 0);
-      w = ax - R0 * dot3(R0, ax);
-      R1 = w * drsqrt(dot3(w, w));
+      Vec3<T> ax = (P0.x * P0.x < T(0.5)) ? v3<T>(1, 0, 0) : v3<T>(0, 1, 0);
+      w = ax - P0 * dot3(P0, ax);
+      P1 = w * drsqrt(dot3(w, w));
     }
+    A00 = T(1);
+    A01 = T(0);
+    A11 = T(1);
     a = dsqrt(tr) - T(1);
     b = T(-1);
+    rs = T(0);
   }
+  T q_c, q_s;
   if (disc > T(0)) {
     const T id = drcp(disc);
     q_c = dl * id;
@@ -131,11 +147,20 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
   // area: eps = d - 1, the largest root of the shifted quartic. For s1 >= s2 exactly one
   // root has d >= 1 and it is the nearest area-preserving stretch; it lies in
   // [0, max(s1, 1)] in eps, where the quartic is <= 0 at the bottom and > 0 at the top.
-  // Newton from sqrt(s1/s2) - 1, falling back to bisection whenever a step leaves the bracket.
-  const T s1 = T(1) + a, s2 = T(1) + b;
+  // Start: one Halley step from sqrt(s1/s2) - 1; then Newton, falling back to bisection
+  // whenever a step leaves the bracket.
+  const T s1 = T(1) + a;
   const T k0 = b - a, k1 = T(2) - T(3) * a + b, k2 = T(3) - T(3) * a, k3 = T(3) - a;
   T lo = T(0), hi = T(1) + (a > T(0) ? a : T(0));
-  T eps = (s2 > T(0)) ? dsqrt(s1 * drcp(s2)) - T(1) : T(0.5) * hi;
+  T eps = T(0.5) * hi;
+  if (rs > T(0)) {
+    const T e0 = s1 * rs - T(1);
+    const T f0 = k0 + e0 * (k1 + e0 * (k2 + e0 * (k3 + e0)));
+    const T f1 = k1 + e0 * (T(2) * k2 + e0 * (T(3) * k3 + T(4) * e0));
+    const T f2 = T(2) * k2 + e0 * (T(6) * k3 + T(12) * e0);
+    const T den = T(2) * f1 * f1 - f0 * f2;
+    eps = (den > T(0)) ? e0 - T(2) * f0 * f1 * drcp(den) : e0;
+  }
   eps = (eps >= lo && eps <= hi) ? eps : T(0.5) * (lo + hi);
   for (int it = 0; it < 40; ++it) {
     const T fv = k0 + eps * (k1 + eps * (k2 + eps * (k3 + eps)));
@@ -152,14 +177,17 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
   const T ip = drcp(T(1) + eps);
   const T sum_a = (a + b) - eps * eps * ip;                    // (s1 + s2) - (d + 1/d)
   const T dif_a = (a - b) - eps * (T(2) + eps) * ip;           // (s1 - s2) - (d - 1/d)
-  const T alpha = T(0.5) * (w_s * (ds1 + ds2) + w_a * sum_a);
-  const T beta = T(0.5) * (w_s * (ds1 - ds2) + w_a * dif_a);
-  // T = alpha I + beta Q ; M = area R T (columns M0, M1)
+  const T alpha = T(0.5) * area * (w_s * (ds1 + ds2) + w_a * sum_a);
+  const T beta = T(0.5) * area * (w_s * (ds1 - ds2) + w_a * dif_a);
+  // area T = area (alpha I + beta Q), K = A (area T) (A and T symmetric)
   const T t00 = alpha + beta * q_c, t01 = beta * q_s, t11 = alpha - beta * q_c;
-  const Vec3<T> M0 = (R0 * t00 + R1 * t01) * area;
-  const Vec3<T> M1 = (R0 * t01 + R1 * t11) * area;
-  rb = M0 * gb0 + M1 * gb1;
-  rc = M0 * gc0 + M1 * gc1;
+  const T K00 = A00 * t00 + A01 * t01, K01 = A00 * t01 + A01 * t11;
+  const T K10 = A01 * t00 + A11 * t01, K11 = A01 * t01 + A11 * t11;
+  const T kb0 = K00 * gb0 + K01 * gb1, kb1 = K10 * gb0 + K11 * gb1;
+  const T kc0 = lower0 ? K01 * gc1 : K00 * gc0 + K01 * gc1;
+  const T kc1 = lower0 ? K11 * gc1 : K10 * gc0 + K11 * gc1;
+  rb = P0 * kb0 + P1 * kb1;
+  rc = P0 * kc0 + P1 * kc1;
   ra = v3<T>(-(rb.x + rc.x), -(rb.y + rc.y), -(rb.z + rc.z));
 }
 

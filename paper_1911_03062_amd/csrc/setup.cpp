@@ -530,9 +530,12 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     const Schedule hr = best_schedule(hel, n, gw, ct->slots, 3 * npad, kHingeRoundValu);
     ct->tri_rounds = (int)tr.rounds.size();
     ct->hinge_rounds = (int)hr.rounds.size();
-    ct->tri_sched.assign((size_t)ct->tri_rounds * ct->slots, TriRec{0, 0, 0, 0, 0, 0, 0.0f, 0.0f});
-    ct->hinge_sched.assign((size_t)ct->hinge_rounds * ct->slots,
-                           HingeRec{0, 0, 0, 0, 0, 0, -1.0f, 0});
+    TriRec empty_tri{};
+    empty_tri.area = 0.0f;
+    ct->tri_sched.assign((size_t)ct->tri_rounds * ct->slots, empty_tri);
+    HingeRec empty_hinge{};
+    empty_hinge.rest = -1.0f;
+    ct->hinge_sched.assign((size_t)ct->hinge_rounds * ct->slots, empty_hinge);
     for (int r = 0; r < ct->tri_rounds; ++r)
       for (size_t s = 0; s < tr.rounds[r].size(); ++s) {
         // roles (a, b, c) in the order the schedule chose; the rest frame follows it
