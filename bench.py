@@ -78,7 +78,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(cells shard statically across GPUs, see DESIGN.md)", file=sys.stderr)
+              "(the cells of a batch are independent: a multi-GPU run would give each GPU its "
+              "own batch of cells, which this build does not do)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -139,13 +139,39 @@ npfem_status npfem_step(npfem_batch* batch, void* x, void* v, const void* ext_fo
  * n < 0 restores the list of all cells; n = 0 makes steps do nothing. The group work list is
  * built on the host and copied asynchronously on `stream` into one of two device lists, so a
  * step enqueued on the same stream after this call uses it while the previous list may still
- * be in use by an earlier step. Cells outside the subset are not read or written. The group
- * count lives in device memory, so a step captured into a HIP graph replays with the list
- * current at replay time. Errors: NPFEM_E_INVALID (id out of range or repeated),
- * NPFEM_E_UNSUPPORTED (plain form), NPFEM_E_HIP.
+ * be in use by an earlier step. Cells outside the subset are not read or written. A graph
+ * made by npfem_graph_create keeps its own copy of the list current at its creation.
+ * Errors: NPFEM_E_INVALID (id out of range or repeated), NPFEM_E_UNSUPPORTED (plain form),
+ * NPFEM_E_HIP.
  */
 npfem_status npfem_batch_set_active(npfem_batch* batch, const int32_t* cell_ids, int32_t n,
                                     void* stream);
+
+typedef struct npfem_graph npfem_graph;         /* opaque, library-owned */
+
+/*
+ * Record n_steps consecutive steps of the batch (each exactly as npfem_step with the same
+ * x, v, dt and n_pd_iters; step s uses ext_forces[s]) into a HIP graph and instantiate it,
+ * so that a fixed sequence of steps can be replayed with one launch. x, v, every
+ * ext_forces[s] (host array of n_steps device pointers, read during the call) and
+ * cell_volume_area (optional, written by every step) are device buffers whose addresses are
+ * baked into the graph: they must stay allocated while the graph exists, and their contents
+ * at replay time are what the steps read. For the fused form the graph holds its own copy of
+ * the batch's current active-cell list (npfem_batch_set_active), so later changes of the list
+ * do not affect it. Recording happens on a private stream of the batch's device and enqueues
+ * no work. The graph holds no reference to `batch` after creation beyond its device data:
+ * destroy the graph before the batch. Errors: NPFEM_E_INVALID (null argument, n_steps < 1,
+ * n_pd_iters < 0), NPFEM_E_DT, NPFEM_E_NOMEM, NPFEM_E_HIP.
+ */
+npfem_status npfem_graph_create(npfem_batch* batch, void* x, void* v,
+                                const void* const* ext_forces, int32_t n_steps, double dt,
+                                int32_t n_pd_iters, double* cell_volume_area,
+                                npfem_graph** out);
+/* Enqueue one replay of the recorded steps on `stream` (a hipStream_t; NULL = default).
+ * Errors: NPFEM_E_INVALID, NPFEM_E_HIP. Non-finite results are flagged as for npfem_step. */
+npfem_status npfem_graph_launch(npfem_graph* graph, void* stream);
+/* Release the graph (waits for its replays to finish). NULL is ignored. */
+void npfem_graph_destroy(npfem_graph* graph);
 
 /*
  * Synchronise `stream` and report NPFEM_E_NONFINITE if any step since the last check

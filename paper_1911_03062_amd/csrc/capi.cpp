@@ -152,6 +152,28 @@ npfem_celltype::~npfem_celltype() {
   }
 }
 
+// A recorded sequence of steps (npfem_graph_create).
+struct npfem_graph {
+  int device = 0;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  FusedGroup* d_groups = nullptr;   // the graph's own work list (fused form)
+  int* d_count = nullptr;
+  ~npfem_graph() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();   // replays may be in flight on any stream
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture) (void)hipStreamDestroy(capture);
+    if (d_groups) (void)hipFree(d_groups);
+    if (d_count) (void)hipFree(d_count);
+    (void)hipSetDevice(cur);
+  }
+};
+
 struct npfem_batch {
   int n_cells = 0, precision = 32, form = NPFEM_FORM_FUSED, device = 0;
   double dt = 0;
@@ -381,6 +403,35 @@ void npfem_batch_destroy(npfem_batch* batch) { delete batch; }
 
 int64_t npfem_batch_vertex_count(const npfem_batch* b) { return b ? b->offsets.back() : -1; }
 
+}  // extern "C"
+
+namespace {
+
+// Makes `device` current for the guard's scope.
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int device) {
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(device);
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+npfem_status step_fused(npfem_batch* b, const FusedGroup* groups, const int* count, void* x,
+                        void* v, const void* f, int32_t n_pd_iters, void* stream,
+                        double* cell_volume_area) {
+  hipError_t e = launch_fused_step(b->d_types, (int)b->types.size(), groups, count, b->n_groups,
+                                   b->d_offsets, b->offsets.back(), (float*)x, (float*)v,
+                                   (const float*)f, n_pd_iters, cell_volume_area, b->d_flag,
+                                   b->lds_bytes, stream);
+  if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
+  return NPFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 npfem_status npfem_step(npfem_batch* b, void* x, void* v, const void* f, double dt,
                         int32_t n_pd_iters, void* stream, double* cell_volume_area) {
   if (!b) return fail(NPFEM_E_INVALID, "batch is null");
@@ -405,12 +456,7 @@ npfem_status npfem_step(npfem_batch* b, void* x, void* v, const void* f, double 
   }
   const FusedGroup* groups = b->ring_cur < 0 ? b->d_groups : b->d_ring[b->ring_cur];
   const int* count = b->ring_cur < 0 ? b->d_count_all : b->d_ring_count[b->ring_cur];
-  hipError_t e = launch_fused_step(b->d_types, (int)b->types.size(), groups, count, b->n_groups,
-                                   b->d_offsets, vtot, (float*)x, (float*)v, (const float*)f,
-                                   n_pd_iters, cell_volume_area, b->d_flag, b->lds_bytes,
-                                   stream);
-  if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
-  return NPFEM_OK;
+  return step_fused(b, groups, count, x, v, f, n_pd_iters, stream, cell_volume_area);
 }
 
 npfem_status npfem_batch_set_active(npfem_batch* b, const int32_t* cell_ids, int32_t n,
@@ -447,6 +493,77 @@ npfem_status npfem_batch_set_active(npfem_batch* b, const int32_t* cell_ids, int
   b->ring_cur = slot;
   return NPFEM_OK;
 }
+
+npfem_status npfem_graph_create(npfem_batch* b, void* x, void* v, const void* const* f,
+                                int32_t n_steps, double dt, int32_t n_pd_iters,
+                                double* cell_volume_area, npfem_graph** out) {
+  if (!out) return fail(NPFEM_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!b || !x || !v || !f) return fail(NPFEM_E_INVALID, "null batch, state or force list");
+  if (n_steps < 1) return fail(NPFEM_E_INVALID, "n_steps < 1");
+  if (n_pd_iters < 0) return fail(NPFEM_E_INVALID, "n_pd_iters < 0");
+  for (int s = 0; s < n_steps; ++s)
+    if (!f[s]) return fail(NPFEM_E_INVALID, "null force buffer");
+  if (!(std::fabs(dt - b->dt) <= 1e-12 * b->dt))
+    return fail(NPFEM_E_DT, "dt differs from the cell types' factorised dt");
+  DeviceGuard guard(b->device);
+  npfem_graph* g = new (std::nothrow) npfem_graph();
+  if (!g) return fail(NPFEM_E_NOMEM, "host allocation");
+  g->device = b->device;
+  auto bail = [&](npfem_status st) { delete g; return st; };
+  const FusedGroup* groups = nullptr;
+  const int* count = nullptr;
+  if (b->form == NPFEM_FORM_FUSED && b->n_cells > 0) {
+    // the graph's own copy of the current work list (group count included)
+    const FusedGroup* src = b->ring_cur < 0 ? b->d_groups : b->d_ring[b->ring_cur];
+    const int* src_count = b->ring_cur < 0 ? b->d_count_all : b->d_ring_count[b->ring_cur];
+    const size_t gbytes = std::max<size_t>(b->n_groups, 1) * sizeof(FusedGroup);
+    if (hipMalloc((void**)&g->d_groups, gbytes) != hipSuccess ||
+        hipMalloc((void**)&g->d_count, sizeof(int)) != hipSuccess)
+      return bail(fail(NPFEM_E_NOMEM, "graph work list"));
+    // the source list may have been filled asynchronously: order the copies after it
+    if (b->ring_cur >= 0 && hipEventSynchronize(b->ring_ev[b->ring_cur]) != hipSuccess)
+      return bail(fail(NPFEM_E_HIP, "active-list event"));
+    if (hipMemcpy(g->d_groups, src, gbytes, hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(g->d_count, src_count, sizeof(int), hipMemcpyDeviceToDevice) != hipSuccess)
+      return bail(fail(NPFEM_E_HIP, "graph work list copy"));
+    groups = g->d_groups;
+    count = g->d_count;
+  }
+  if (hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(NPFEM_E_HIP, "capture stream"));
+  if (hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return bail(fail(NPFEM_E_HIP, "begin capture"));
+  npfem_status st = NPFEM_OK;
+  for (int s = 0; s < n_steps && st == NPFEM_OK; ++s) {
+    if (b->n_cells == 0) break;
+    if (b->form == NPFEM_FORM_FUSED)
+      st = step_fused(b, groups, count, x, v, f[s], n_pd_iters, g->capture, cell_volume_area);
+    else
+      st = npfem_step(b, x, v, f[s], dt, n_pd_iters, g->capture, cell_volume_area);
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(g->capture, &graph);
+  if (st != NPFEM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return bail(st);
+  }
+  if (ec != hipSuccess || !graph) return bail(fail(NPFEM_E_HIP, "end capture"));
+  g->graph = graph;
+  if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+    return bail(fail(NPFEM_E_HIP, "graph instantiate"));
+  *out = g;
+  g_last_error.clear();
+  return NPFEM_OK;
+}
+
+npfem_status npfem_graph_launch(npfem_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(NPFEM_E_INVALID, "graph is null");
+  HIP_TRY(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)));
+  return NPFEM_OK;
+}
+
+void npfem_graph_destroy(npfem_graph* g) { delete g; }
 
 npfem_status npfem_batch_check(npfem_batch* b, void* stream) {
   if (!b) return fail(NPFEM_E_INVALID, "batch is null");

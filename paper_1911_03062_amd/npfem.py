@@ -84,6 +84,13 @@ def lib() -> ctypes.CDLL:
     L.npfem_batch_set_active.restype = c_int32
     L.npfem_batch_check.argtypes = [c_void_p, c_void_p]
     L.npfem_batch_check.restype = c_int32
+    L.npfem_graph_create.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_void_p), c_int32,
+                                     c_double, c_int32, c_void_p, POINTER(c_void_p)]
+    L.npfem_graph_create.restype = c_int32
+    L.npfem_graph_launch.argtypes = [c_void_p, c_void_p]
+    L.npfem_graph_launch.restype = c_int32
+    L.npfem_graph_destroy.argtypes = [c_void_p]
+    L.npfem_graph_destroy.restype = None
     L.npfem_last_error.argtypes = []
     L.npfem_last_error.restype = c_char_p
     _lib = L
@@ -183,6 +190,23 @@ class Batch:
         _check(lib().npfem_step(self._h, x.data_ptr(), v.data_ptr(), f.data_ptr(), float(dt),
                                 int(n_pd_iters), c_void_p(s.cuda_stream), c_void_p(va)))
 
+    def _check_state(self, x, v, forces, vol_area):
+        import torch
+        dtype = torch.float64 if self.precision == 64 else torch.float32
+        named = [("x", x), ("v", v)] + [(f"forces[{i}]", t) for i, t in enumerate(forces)]
+        for name, t in named:
+            if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()
+                    and tuple(t.shape) == (3, self.vertex_count)):
+                raise ValueError(f"{name} must be a contiguous device tensor [3][{self.vertex_count}] of {dtype}")
+        if vol_area is not None and not (vol_area.is_cuda and vol_area.dtype == torch.float64
+                                         and vol_area.is_contiguous()
+                                         and tuple(vol_area.shape) == (self.n_cells, 2)):
+            raise ValueError("vol_area must be a contiguous float64 device tensor [n_cells][2]")
+
+    def graph(self, x, v, forces, dt: float, n_pd_iters: int, vol_area=None) -> "Graph":
+        """Record len(forces) steps on these buffers into a HIP graph (see Graph)."""
+        return Graph(self, x, v, forces, dt, n_pd_iters, vol_area)
+
     def set_active(self, cell_ids, stream=None):
         """Step only these cells from now on (None: all cells)."""
         import torch
@@ -205,6 +229,37 @@ class Batch:
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None:
             _lib.npfem_batch_destroy(h)
+            self._h = None
+
+
+class Graph:
+    """A recorded sequence of steps of one batch on fixed buffers (npfem_graph_create).
+
+    Step s of a replay uses forces[s]; x, v, the force tensors and vol_area are kept alive by
+    the graph, and their contents at replay time are what the steps read.
+    """
+
+    def __init__(self, batch: Batch, x, v, forces, dt: float, n_pd_iters: int, vol_area=None):
+        forces = list(forces)
+        batch._check_state(x, v, forces, vol_area)
+        arr = (c_void_p * max(len(forces), 1))(*[f.data_ptr() for f in forces])
+        h = c_void_p()
+        va = vol_area.data_ptr() if vol_area is not None else None
+        _check(lib().npfem_graph_create(batch._h, x.data_ptr(), v.data_ptr(), arr, len(forces),
+                                        float(dt), int(n_pd_iters), va, ctypes.byref(h)))
+        self._h = h
+        self._keep = (batch, x, v, forces, vol_area)
+        self.n_steps = len(forces)
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_graph_launch(self._h, c_void_p(s.cuda_stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.npfem_graph_destroy(h)
             self._h = None
 
 

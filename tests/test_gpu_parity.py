@@ -98,6 +98,11 @@ def _mixed(n_rbc=10, n_plt=37, seed=21):
 
 @pytest.mark.parametrize("form", ["fused", "plain"])
 def test_mixed_ragged_batch_20_steps(form):
+    """Cells sit up to ~350 um from the origin and the state is stored in FP32, so every
+    step's write rounds each coordinate by up to ulp(350 um)/2 ~ 1.5e-5 um. Over 20 steps
+    that storage floor alone is ~1e-5 platelet diameters typically (random walk) and up to
+    ~1.5e-4 in the worst case, whatever the kernel computes. The max is gated at the
+    workload tolerance (1e-4 of the diameter), the median at 2e-5."""
     b = _mixed()
     forces = list(I.force_stream(b, seed=22, sigma=5.0, n_steps=20))
     _say(f"case: {form} fp32 mixed batch 10 RBC + 37 PLT, 20 steps")
@@ -105,7 +110,8 @@ def test_mixed_ragged_batch_20_steps(form):
     xg, vg = run_gpu(_ltypes(), b.types, b.x0, b.v0, forces, 10, form=form)
     err = cell_errors(b.types, b.offsets, xg, xo)
     _say(f"{form}: max err/diam {err.max():.3e} (median {np.median(err):.3e})")
-    assert err.max() <= 1e-5
+    assert err.max() <= 1e-4
+    assert np.median(err) <= 2e-5
 
 
 def test_fused_volume_area_outputs():
