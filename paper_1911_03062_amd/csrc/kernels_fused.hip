@@ -55,14 +55,15 @@ typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 // Schedule records are read with loads of exactly the words a pass uses: a load whose result
 // words are partly unused lets the register allocator reuse those words' registers, which
-// then forces a wait for the load to land before the reuse.
+// then forces a wait for the load to land before the reuse. Records are loaded two rounds
+// ahead of their use.
 struct TriHead {   // first 16 bytes of a TriRec
   uint32_t ab, c;
   float area, orient;
 };
-struct TriElem {   // first 28 bytes of a TriRec
+struct TriElem {   // words 0-2 and 4-6 of a TriRec
   uint32_t ab, c;
-  float area, orient, gb0, gb1, gc1;
+  float area, gb0, gb1, gc1;
 };
 struct HingeElem { // first 24 bytes of a HingeRec
   uint32_t ij, kl;
@@ -81,10 +82,10 @@ __device__ __forceinline__ TriHead load_tri_head(const TriRec* base, int i) {
   return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(v.w)};
 }
 __device__ __forceinline__ TriElem load_tri_elem(const TriRec* base, int i) {
-  const u4 v = load_words<u4>(base, i, 0);
-  const u3 w = load_words<u3>(base, i, 4);
-  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(v.w), __uint_as_float(w.x),
-          __uint_as_float(w.y), __uint_as_float(w.z)};
+  const u3 v = load_words<u3>(base, i, 0);   // ab, c, area (orient is not used here)
+  const u3 w = load_words<u3>(base, i, 4);   // gb0, gb1, gc1
+  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(w.x), __uint_as_float(w.y),
+          __uint_as_float(w.z)};
 }
 __device__ __forceinline__ HingeElem load_hinge(const HingeRec* base, int i) {
   const u4 v = load_words<u4>(base, i, 0);
@@ -314,30 +315,41 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         // software-pipelined rounds: while round r computes, the positions of round r + 1
         // and the record of round r + 2 are in flight, and round r's residual reads were
         // issued before its arithmetic. Reads of empty slots (vertex 0) and of cells past the
-        // group's count stay inside the LDS blocks; only their writes are skipped.
+        // group's count stay inside the LDS blocks; only their writes are skipped. The loop is
+        // unrolled by two so that the two register sets swap roles instead of being copied.
         const int NR = T.p.tri_rounds;
-        TriHead rec = load_tri_head(T.tri_sched, e_s);
-        TriHead rec_n = load_tri_head(T.tri_sched, min(1, NR - 1) * S + e_s);
-        int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
-        Vec3<float> xa = ld3(Xe + 3 * a), xb = ld3(Xe + 3 * b), xc = ld3(Xe + 3 * c);
-        for (int r = 0; r < NR; ++r) {
-          const TriHead rec_nn = load_tri_head(T.tri_sched, min(r + 2, NR - 1) * S + e_s);
-          const int an = (int)(rec_n.ab & 0xffffu), bn = (int)(rec_n.ab >> 16), cn = (int)rec_n.c;
-          const Vec3<float> nxa = ld3(Xe + 3 * an), nxb = ld3(Xe + 3 * bn), nxc = ld3(Xe + 3 * cn);
+        TriHead recA = load_tri_head(T.tri_sched, e_s);
+        TriHead recB = load_tri_head(T.tri_sched, min(1, NR - 1) * S + e_s);
+        Vec3<float> xA0, xA1, xA2, xB0, xB1, xB2;
+        auto positions = [&](const TriHead& rc, Vec3<float>& p0, Vec3<float>& p1, Vec3<float>& p2) {
+          p0 = ld3(Xe + 3 * (int)(rc.ab & 0xffffu));
+          p1 = ld3(Xe + 3 * (int)(rc.ab >> 16));
+          p2 = ld3(Xe + 3 * (int)rc.c);
+        };
+        auto round = [&](TriHead& rc, const Vec3<float>& xa, const Vec3<float>& xb,
+                         const Vec3<float>& xc, int r_next2) {
+          const TriHead rnn = load_tri_head(T.tri_sched, min(r_next2, NR - 1) * S + e_s);
+          const int a = (int)(rc.ab & 0xffffu), b = (int)(rc.ab >> 16), c = (int)rc.c;
           const Vec3<float> oa = ld3(Re + 3 * a), ob = ld3(Re + 3 * b), oc = ld3(Re + 3 * c);
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
-          const Vec3<float> nt = cross3(xb - xa, xc - xa) * rec.orient;
-          if (e_ok && rec.area > 0.0f) {
+          const Vec3<float> nt = cross3(xb - xa, xc - xa) * rc.orient;
+          if (e_ok && rc.area > 0.0f) {
             st3(Re + 3 * a, oa + nt);
             st3(Re + 3 * b, ob + nt);
             st3(Re + 3 * c, oc + nt);
             v6 += dot3(xa, nt);
           }
           __builtin_amdgcn_wave_barrier();
-          rec = rec_n;
-          rec_n = rec_nn;
-          a = an; b = bn; c = cn;
-          xa = nxa; xb = nxb; xc = nxc;
+          rc = rnn;
+        };
+        positions(recA, xA0, xA1, xA2);
+        for (int r = 0; r < NR; r += 2) {
+          positions(recB, xB0, xB1, xB2);          // round r + 1 (re-reads round r at the end)
+          round(recA, xA0, xA1, xA2, r + 2);
+          if (r + 1 < NR) {
+            positions(recA, xA0, xA1, xA2);        // round r + 2
+            round(recB, xB0, xB1, xB2, r + 3);
+          }
         }
       }
       // |6 grad V|^2 of the cell: lane (cell, slot s) takes its vertices s, s + S, ...
@@ -373,65 +385,83 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
       {
-        // pipelined as the volume rounds (positions of the next round in flight)
+        // pipelined and unrolled as the volume rounds
         const int NR = T.p.tri_rounds;
-        TriElem rec = load_tri_elem(T.tri_sched, e_s);
-        TriElem rec_n = load_tri_elem(T.tri_sched, min(1, NR - 1) * S + e_s);
-        int a = (int)(rec.ab & 0xffffu), b = (int)(rec.ab >> 16), c = (int)rec.c;
-        Vec3<float> xa = ld3(Xe + 3 * a), xb = ld3(Xe + 3 * b), xc = ld3(Xe + 3 * c);
-        for (int r = 0; r < NR; ++r) {
-          const TriElem rec_nn = load_tri_elem(T.tri_sched, min(r + 2, NR - 1) * S + e_s);
-          const int an = (int)(rec_n.ab & 0xffffu), bn = (int)(rec_n.ab >> 16), cn = (int)rec_n.c;
-          const Vec3<float> nxa = ld3(Xe + 3 * an), nxb = ld3(Xe + 3 * bn), nxc = ld3(Xe + 3 * cn);
-          __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
-          if (e_ok && rec.area > 0.0f) {
-            Vec3<float> ra, rb, rc;
-            triangle_residual<float>(xa, xb, xc, rec.gb0, rec.gb1, 0.0f, rec.gc1, rec.area, w_s,
-                                     w_a, s_min, s_max, ra, rb, rc);
-            add3(Re + 3 * a, ra);
-            add3(Re + 3 * b, rb);
-            add3(Re + 3 * c, rc);
+        TriElem recA = load_tri_elem(T.tri_sched, e_s);
+        TriElem recB = load_tri_elem(T.tri_sched, min(1, NR - 1) * S + e_s);
+        Vec3<float> xA0, xA1, xA2, xB0, xB1, xB2;
+        auto positions = [&](const TriElem& rc, Vec3<float>& p0, Vec3<float>& p1, Vec3<float>& p2) {
+          p0 = ld3(Xe + 3 * (int)(rc.ab & 0xffffu));
+          p1 = ld3(Xe + 3 * (int)(rc.ab >> 16));
+          p2 = ld3(Xe + 3 * (int)rc.c);
+        };
+        auto round = [&](TriElem& rc, const Vec3<float>& xa, const Vec3<float>& xb,
+                         const Vec3<float>& xc, int r_next2) {
+          const TriElem rnn = load_tri_elem(T.tri_sched, min(r_next2, NR - 1) * S + e_s);
+          __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the arithmetic
+          if (e_ok && rc.area > 0.0f) {
+            Vec3<float> ra, rb, rcv;
+            triangle_residual<float>(xa, xb, xc, rc.gb0, rc.gb1, 0.0f, rc.gc1, rc.area, w_s,
+                                     w_a, s_min, s_max, ra, rb, rcv);
+            add3(Re + 3 * (int)(rc.ab & 0xffffu), ra);
+            add3(Re + 3 * (int)(rc.ab >> 16), rb);
+            add3(Re + 3 * (int)rc.c, rcv);
           }
           __builtin_amdgcn_wave_barrier();
-          rec = rec_n;
-          rec_n = rec_nn;
-          a = an; b = bn; c = cn;
-          xa = nxa; xb = nxb; xc = nxc;
+          rc = rnn;
+        };
+        positions(recA, xA0, xA1, xA2);
+        for (int r = 0; r < NR; r += 2) {
+          positions(recB, xB0, xB1, xB2);
+          round(recA, xA0, xA1, xA2, r + 2);
+          if (r + 1 < NR) {
+            positions(recA, xA0, xA1, xA2);
+            round(recB, xB0, xB1, xB2, r + 3);
+          }
         }
       }
       // ---- edge bending constraints
       {
-        // pipelined as the volume rounds above
+        // pipelined and unrolled as the volume rounds
         const int NR = T.p.hinge_rounds;
-        HingeElem rec = load_hinge(T.hinge_sched, e_s);
-        HingeElem rec_n = load_hinge(T.hinge_sched, min(1, NR - 1) * S + e_s);
-        int i = (int)(rec.ij & 0xffffu), j = (int)(rec.ij >> 16);
-        int kk = (int)(rec.kl & 0xffffu), l = (int)(rec.kl >> 16);
-        Vec3<float> xi = ld3(Xe + 3 * i), xj = ld3(Xe + 3 * j), xk = ld3(Xe + 3 * kk),
-                    xl = ld3(Xe + 3 * l);
-        for (int r = 0; r < NR; ++r) {
-          const HingeElem rec_nn = load_hinge(T.hinge_sched, min(r + 2, NR - 1) * S + e_s);
-          const int in = (int)(rec_n.ij & 0xffffu), jn = (int)(rec_n.ij >> 16);
-          const int kn = (int)(rec_n.kl & 0xffffu), ln = (int)(rec_n.kl >> 16);
-          const Vec3<float> nxi = ld3(Xe + 3 * in), nxj = ld3(Xe + 3 * jn),
-                            nxk = ld3(Xe + 3 * kn), nxl = ld3(Xe + 3 * ln);
+        HingeElem recA = load_hinge(T.hinge_sched, e_s);
+        HingeElem recB = load_hinge(T.hinge_sched, min(1, NR - 1) * S + e_s);
+        Vec3<float> xA0, xA1, xA2, xA3, xB0, xB1, xB2, xB3;
+        auto positions = [&](const HingeElem& rc, Vec3<float>& p0, Vec3<float>& p1,
+                             Vec3<float>& p2, Vec3<float>& p3) {
+          p0 = ld3(Xe + 3 * (int)(rc.ij & 0xffffu));
+          p1 = ld3(Xe + 3 * (int)(rc.ij >> 16));
+          p2 = ld3(Xe + 3 * (int)(rc.kl & 0xffffu));
+          p3 = ld3(Xe + 3 * (int)(rc.kl >> 16));
+        };
+        auto round = [&](HingeElem& rc, const Vec3<float>& xi, const Vec3<float>& xj,
+                         const Vec3<float>& xk, const Vec3<float>& xl, int r_next2) {
+          const HingeElem rnn = load_hinge(T.hinge_sched, min(r_next2, NR - 1) * S + e_s);
+          const int i = (int)(rc.ij & 0xffffu), j = (int)(rc.ij >> 16);
+          const int kk = (int)(rc.kl & 0xffffu), l = (int)(rc.kl >> 16);
           const Vec3<float> oi = ld3(Re + 3 * i), oj = ld3(Re + 3 * j), ok3 = ld3(Re + 3 * kk),
                             ol = ld3(Re + 3 * l);
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
           Vec3<float> ri, rj, rk, rl;
-          hinge_residual<float>(xi, xj, xk, xl, rec.a1, rec.a2, rec.a3, rec.rest, w_b, ri, rj,
-                                rk, rl);
-          if (e_ok && rec.rest >= 0.0f) {
+          hinge_residual<float>(xi, xj, xk, xl, rc.a1, rc.a2, rc.a3, rc.rest, w_b, ri, rj, rk,
+                                rl);
+          if (e_ok && rc.rest >= 0.0f) {
             st3(Re + 3 * i, oi + ri);
             st3(Re + 3 * j, oj + rj);
             st3(Re + 3 * kk, ok3 + rk);
             st3(Re + 3 * l, ol + rl);
           }
           __builtin_amdgcn_wave_barrier();
-          rec = rec_n;
-          rec_n = rec_nn;
-          i = in; j = jn; kk = kn; l = ln;
-          xi = nxi; xj = nxj; xk = nxk; xl = nxl;
+          rc = rnn;
+        };
+        positions(recA, xA0, xA1, xA2, xA3);
+        for (int r = 0; r < NR; r += 2) {
+          positions(recB, xB0, xB1, xB2, xB3);
+          round(recA, xA0, xA1, xA2, xA3, r + 2);
+          if (r + 1 < NR) {
+            positions(recA, xA0, xA1, xA2, xA3);
+            round(recB, xB0, xB1, xB2, xB3, r + 3);
+          }
         }
       }
       __syncthreads();
