@@ -298,12 +298,12 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const float w_s = (float)T.p.w_s, w_a = (float)T.p.w_a, w_b = (float)T.p.w_b;
     const float s_min = (float)T.p.s_min, s_max = (float)T.p.s_max;
 
-    // MFMA work items of this wave
+    // MFMA output tiles of this wave: an equal share [u0, u1) of the RT x CT tiles in
+    // row-major order, processed as pairs of neighbouring tiles (see the global step)
     const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
-    const int ncols = 3 * count, CT = (ncols + 15) / 16, CP = (CT + 1) / 2;
-    const bool pairs = CT >= 2;
-    const int n_items = mfma_items(RT, CT);
-    const int m0 = (n_items * wave) / kFusedWaves, m1 = (n_items * (wave + 1)) / kFusedWaves;
+    const int ncols = 3 * count, CT = (ncols + 15) / 16;
+    const int n_units = RT * CT;
+    const int u0 = (n_units * wave) / kFusedWaves, u1 = (n_units * (wave + 1)) / kFusedWaves;
 
     for (int k = 0; k < K; ++k) {
       // ---- volume constraint. R is zero here. Over the triangle rounds every triangle adds
@@ -466,60 +466,67 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       }
       __syncthreads();
       // ---- global step: D = -L^-1 R on the matrix cores. Column col = 3 cell + coord,
-      // row k = vertex: B(k, col) = R[cell][k][coord]. Work items are two 16x16 output tiles:
-      // one row tile of L^-1 against two column tiles (sharing every A fragment), or, when the
-      // group has a single column tile, two row tiles. Each wave holds its items' tiles in
-      // registers until every wave has read R, then writes D over R.
+      // row k = vertex: B(k, col) = R[cell][k][coord]. A work item is one tile or two
+      // neighbouring tiles of the wave's share: with two or more column tiles, two column
+      // tiles of one row tile (sharing every A fragment); with one column tile, two row tiles
+      // (sharing B). Each wave holds its tiles in registers until every wave has read R, then
+      // writes D over R.
       f4 acc[kMaxTilesPerWave];
 #pragma unroll
       for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+      int n_items = 0;
       {
         const gfloat* Lt = gptr(T.linv_tiles) + lane;
         const int kq = lane >> 4;
-        for (int it = m0; it < m1; ++it) {
+        for (int u = u0; u < u1;) {
           f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
-          if (pairs) {
-            const int rt = it / CP, ctA = 2 * (it - rt * CP);
-            const lfloat* RbA = (const lfloat*)(R + col_base(ctA * 16 + (lane & 15), ncols, CS) + 3 * kq);
-            if (ctA + 1 < CT) {
-              const lfloat* RbB = (const lfloat*)(R + col_base(ctA * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq);
+          if (CT >= 2) {
+            const int rt = u / CT, ct = u - rt * CT;
+            const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * kq);
+            if (ct + 1 < CT && u + 1 < u1) {
+              const lfloat* RbB =
+                  (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq);
               mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
+              u += 2;
             } else {
               mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
+              u += 1;
             }
           } else {
-            const int rt = 2 * it;
             const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * kq);
-            mfma_rows<false>(Lt + (size_t)rt * KS * 64, Rb, Rb, KR, d0, d1);
-            if (rt + 1 < RT) mfma_rows<false>(Lt + (size_t)(rt + 1) * KS * 64, Rb, Rb, KR, d1, d0);
+            mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
+            if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
+            u += (u + 1 < u1) ? 2 : 1;
           }
           // keep the item's tiles at the end of the held set (indices stay compile-time)
 #pragma unroll
           for (int i = 0; i + 2 < kMaxTilesPerWave; ++i) acc[i] = acc[i + 2];
           acc[kMaxTilesPerWave - 2] = d0;
           acc[kMaxTilesPerWave - 1] = d1;
+          ++n_items;
         }
       }
       __syncthreads();
       {
-        const int held = m1 - m0;
+        // replay the item sequence to place the held tiles
+        int u = u0;
 #pragma unroll
         for (int q = 0; q < kMaxTilesPerWave / 2; ++q) {
-          const int pidx = q - (kMaxTilesPerWave / 2 - held);
-          if (pidx >= 0) {
-            const int it = m0 + pidx;
-            int rtA, ctA, rtB, ctB;
-            if (pairs) {
-              rtA = rtB = it / CP;
-              ctA = 2 * (it - rtA * CP);
-              ctB = ctA + 1;
+          if (q >= kMaxTilesPerWave / 2 - n_items) {
+            if (CT >= 2) {
+              const int rt = u / CT, ct = u - rt * CT;
+              write_tile(R, acc[2 * q], rt, ct, lane, n, ncols, CS);
+              if (ct + 1 < CT && u + 1 < u1) {
+                write_tile(R, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS);
+                u += 2;
+              } else {
+                u += 1;
+              }
             } else {
-              rtA = 2 * it;
-              rtB = rtA + 1;
-              ctA = ctB = 0;
+              write_tile(R, acc[2 * q], u, 0, lane, n, ncols, CS);
+              if (u + 1 < u1) write_tile(R, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS);
+              u += (u + 1 < u1) ? 2 : 1;
             }
-            write_tile(R, acc[2 * q], rtA, ctA, lane, n, ncols, CS);
-            if (rtB < RT && ctB < CT) write_tile(R, acc[2 * q + 1], rtB, ctB, lane, n, ncols, CS);
           }
         }
       }

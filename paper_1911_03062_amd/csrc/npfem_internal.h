@@ -148,15 +148,28 @@ struct FusedGroup {
 constexpr int kMfmaChunk = 8;               // k steps per prefetched L^-1 chunk
 constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
 
-// MFMA work items of the global step for row_tiles x col_tiles output tiles: pairs of column
-// tiles of one row tile (sharing A), or pairs of row tiles when there is one column tile.
+// MFMA output tiles of the global step: each wave takes an equal share of the
+// row_tiles x col_tiles tiles (row-major) and works on items of one or two neighbouring
+// tiles, each item held in a pair of the kMaxTilesPerWave accumulator slots.
 #ifdef __HIPCC__
 #define NPFEM_HD __host__ __device__
 #else
 #define NPFEM_HD
 #endif
-inline NPFEM_HD int mfma_items(int row_tiles, int col_tiles) {
-  return col_tiles >= 2 ? row_tiles * ((col_tiles + 1) / 2) : (row_tiles + 1) / 2;
+// Number of work items the global step forms from the share [u0, u1) of the row-major tiles
+// of a group with col_tiles column tiles (the kernel's pairing rule: two column tiles of one
+// row tile, or two row tiles when there is one column tile).
+inline NPFEM_HD int mfma_share_items(int col_tiles, int u0, int u1) {
+  int items = 0;
+  for (int u = u0; u < u1; ++items) {
+    if (col_tiles >= 2) {
+      const int ct = u % col_tiles;
+      u += (ct + 1 < col_tiles && u + 1 < u1) ? 2 : 1;
+    } else {
+      u += (u + 1 < u1) ? 2 : 1;
+    }
+  }
+  return items;
 }
 
 // Kernel launchers and sizes (kernels_plain.hip, kernels_fused.hip).

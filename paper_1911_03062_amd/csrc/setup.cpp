@@ -506,8 +506,17 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     if (kFusedWaves * cand * per_cell > kFusedLdsBudget) continue;
     if ((cand * n + 63) / 64 > kMaxItems) continue;
     if (kFusedWaves * cand > kMaxGroupCells) continue;
-    const int items = mfma_items((n + 15) / 16, (3 * kFusedWaves * cand + 15) / 16);
-    if (2 * ((items + kFusedWaves - 1) / kFusedWaves) > kMaxTilesPerWave) continue;
+    // every wave's share of the global step's output tiles, for every group size, must form
+    // at most kMaxTilesPerWave / 2 items (the kernel holds two tiles per item)
+    bool fits = true;
+    const int rt_n = (n + 15) / 16;
+    for (int count = 1; count <= kFusedWaves * cand && fits; ++count) {
+      const int ct_n = (3 * count + 15) / 16, units = rt_n * ct_n;
+      for (int w = 0; w < kFusedWaves && fits; ++w)
+        fits = mfma_share_items(ct_n, units * w / kFusedWaves, units * (w + 1) / kFusedWaves) <=
+               kMaxTilesPerWave / 2;
+    }
+    if (!fits) continue;
     gw = cand;
     break;
   }

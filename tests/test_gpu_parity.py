@@ -205,3 +205,20 @@ def test_dt_mismatch_is_rejected():
     with pytest.raises(N.NpfemError) as ei:
         b.step(x, x.clone(), x.clone(), 0.2, 10)
     assert ei.value.name == "NPFEM_E_DT"
+
+
+@pytest.mark.parametrize("n_rbc,n_plt", [(0, 13), (0, 26), (3, 0), (6, 0), (9, 17)])
+def test_fused_partial_groups(n_rbc, n_plt):
+    """Groups with fewer cells than a full group: 13 platelets give 3 MFMA column tiles, 26
+    give 5 (odd counts, with single-tile work items at row ends), 3 RBC give 1 column tile
+    (row-tile pairs), 6 RBC 2; the global step's tile shares and pairing must cover every
+    output tile exactly once."""
+    types = np.array([I.RBC] * n_rbc + [I.PLT] * n_plt, dtype=np.int32)
+    b = I.make_batch(types, seed=100 + n_rbc + n_plt)
+    forces = list(I.force_stream(b, seed=7, sigma=40.0, n_steps=3))
+    _say(f"case: fused partial groups {n_rbc} RBC + {n_plt} PLT, 3 steps")
+    xo, _ = run_oracle(_otypes(), b.types, b.offsets, b.x0, b.v0, forces, 10)
+    xg, _ = run_gpu(_ltypes(), b.types, b.x0, b.v0, forces, 10)
+    err = cell_errors(b.types, b.offsets, xg, xo)
+    _say(f"partial groups {n_rbc}+{n_plt}: max err/diam {err.max():.3e}")
+    assert err.max() <= 1e-5
