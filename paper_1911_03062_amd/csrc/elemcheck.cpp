@@ -12,7 +12,7 @@ template <typename T>
 void tri(const double* p, const double* g, double area, double ws, double wa, double smin,
          double smax, double* out) {
   const Vec3<T> a = v3<T>(p[0], p[1], p[2]), b = v3<T>(p[3], p[4], p[5]), c = v3<T>(p[6], p[7], p[8]);
-  Vec3<T> ra, rb, rc;
+  Vec3<T> ra = v3<T>(0, 0, 0), rb = ra, rc = ra;
   triangle_residual<T>(a, b, c, (T)g[0], (T)g[1], (T)g[2], (T)g[3], (T)area, (T)ws, (T)wa,
                        (T)smin, (T)smax, ra, rb, rc);
   const Vec3<T> r[3] = {ra, rb, rc};
@@ -25,7 +25,7 @@ void tri(const double* p, const double* g, double area, double ws, double wa, do
 
 template <typename T>
 void hin(const double* p, const double* a, double rest, double wb, double* out) {
-  Vec3<T> r[4];
+  Vec3<T> r[4] = {v3<T>(0, 0, 0), v3<T>(0, 0, 0), v3<T>(0, 0, 0), v3<T>(0, 0, 0)};
   hinge_residual<T>(v3<T>(p[0], p[1], p[2]), v3<T>(p[3], p[4], p[5]), v3<T>(p[6], p[7], p[8]),
                     v3<T>(p[9], p[10], p[11]), (T)a[1], (T)a[2], (T)a[3], (T)rest, (T)wb, r[0],
                     r[1], r[2], r[3]);

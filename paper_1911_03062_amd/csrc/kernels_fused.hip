@@ -400,12 +400,15 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const TriElem rnn = load_tri_elem(T.tri_sched, min(r_next2, NR - 1) * S + e_s);
           __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the arithmetic
           if (e_ok && rc.area > 0.0f) {
-            Vec3<float> ra, rb, rcv;
+            float* pa = Re + 3 * (int)(rc.ab & 0xffffu);
+            float* pb = Re + 3 * (int)(rc.ab >> 16);
+            float* pc = Re + 3 * (int)rc.c;
+            Vec3<float> ra = ld3(pa), rb = ld3(pb), rcv = ld3(pc);
             triangle_residual<float>(xa, xb, xc, rc.gb0, rc.gb1, 0.0f, rc.gc1, rc.area, w_s,
                                      w_a, s_min, s_max, ra, rb, rcv);
-            add3(Re + 3 * (int)(rc.ab & 0xffffu), ra);
-            add3(Re + 3 * (int)(rc.ab >> 16), rb);
-            add3(Re + 3 * (int)rc.c, rcv);
+            st3(pa, ra);
+            st3(pb, rb);
+            st3(pc, rcv);
           }
           __builtin_amdgcn_wave_barrier();
           rc = rnn;
@@ -439,17 +442,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const HingeElem rnn = load_hinge(T.hinge_sched, min(r_next2, NR - 1) * S + e_s);
           const int i = (int)(rc.ij & 0xffffu), j = (int)(rc.ij >> 16);
           const int kk = (int)(rc.kl & 0xffffu), l = (int)(rc.kl >> 16);
-          const Vec3<float> oi = ld3(Re + 3 * i), oj = ld3(Re + 3 * j), ok3 = ld3(Re + 3 * kk),
-                            ol = ld3(Re + 3 * l);
+          Vec3<float> ri = ld3(Re + 3 * i), rj = ld3(Re + 3 * j), rk = ld3(Re + 3 * kk),
+                      rl = ld3(Re + 3 * l);
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
-          Vec3<float> ri, rj, rk, rl;
           hinge_residual<float>(xi, xj, xk, xl, rc.a1, rc.a2, rc.a3, rc.rest, w_b, ri, rj, rk,
                                 rl);
           if (e_ok && rc.rest >= 0.0f) {
-            st3(Re + 3 * i, oi + ri);
-            st3(Re + 3 * j, oj + rj);
-            st3(Re + 3 * kk, ok3 + rk);
-            st3(Re + 3 * l, ol + rl);
+            st3(Re + 3 * i, ri);
+            st3(Re + 3 * j, rj);
+            st3(Re + 3 * kk, rk);
+            st3(Re + 3 * l, rl);
           }
           __builtin_amdgcn_wave_barrier();
           rc = rnn;

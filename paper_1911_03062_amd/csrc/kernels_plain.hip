@@ -125,7 +125,7 @@ k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t 
     const Vec3<T> pa = cell_pos(x, vt, off, w.d, n, a);
     const Vec3<T> pb = cell_pos(x, vt, off, w.d, n, b);
     const Vec3<T> pc = cell_pos(x, vt, off, w.d, n, c);
-    Vec3<T> ra, rb, rc;
+    Vec3<T> ra = v3<T>(0, 0, 0), rb = ra, rc = ra;   // contributions are accumulated
     triangle_residual<T>(pa, pb, pc, G[6 * t + 2], G[6 * t + 3], G[6 * t + 4], G[6 * t + 5],
                          A[t], T(p.w_s), T(p.w_a), T(p.s_min), T(p.s_max), ra, rb, rc);
     T* tc = w.tcon + 9 * t;
@@ -137,7 +137,7 @@ k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t 
   }
   for (int h = threadIdx.x; h < e; h += blockDim.x) {
     const int* hv = dt.hinge + 4 * h;
-    Vec3<T> ri, rj, rk, rl;
+    Vec3<T> ri = v3<T>(0, 0, 0), rj = ri, rk = ri, rl = ri;
     hinge_residual<T>(cell_pos(x, vt, off, w.d, n, hv[0]), cell_pos(x, vt, off, w.d, n, hv[1]),
                       cell_pos(x, vt, off, w.d, n, hv[2]), cell_pos(x, vt, off, w.d, n, hv[3]),
                       coef[4 * h + 1], coef[4 * h + 2], coef[4 * h + 3], rest[h], T(p.w_b),

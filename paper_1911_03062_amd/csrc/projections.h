@@ -73,7 +73,7 @@ __host__ __device__ __forceinline__ T clamp_dev(T v, T lo, T hi) { return v < lo
 
 // Triangle residual contributions. Inputs: vertex positions pa, pb, pc (any common origin),
 // rest gradients gb, gc (g_a = -g_b - g_c), rest area, weights. Outputs: contributions to
-// the gradient of g at vertices a, b, c.
+// the gradient of g at vertices a, b, c, added to ra, rb, rc.
 //
 // The polar factor is not formed: R = P A with P = F, A = adj(C + s I) / (s t) in the regular
 // case (P = an orthonormal frame, A = I when F is rank deficient), so that the contribution
@@ -141,9 +141,16 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
     q_c = T(1);
     q_s = T(0);
   }
-  // strain: s - clamp(s) per singular value
-  const T ds1 = (a > s_max - T(1) ? a - (s_max - T(1)) : T(0)) + (a < s_min - T(1) ? a - (s_min - T(1)) : T(0));
-  const T ds2 = (b > s_max - T(1) ? b - (s_max - T(1)) : T(0)) + (b < s_min - T(1) ? b - (s_min - T(1)) : T(0));
+  // strain: s - clamp(s) per singular value (the polar factor when s_min = s_max = 1; the
+  // bounds are the same for all lanes, so this is a uniform branch)
+  T ds1, ds2;
+  if (s_min == T(1) && s_max == T(1)) {
+    ds1 = a;
+    ds2 = b;
+  } else {
+    ds1 = (a > s_max - T(1) ? a - (s_max - T(1)) : T(0)) + (a < s_min - T(1) ? a - (s_min - T(1)) : T(0));
+    ds2 = (b > s_max - T(1) ? b - (s_max - T(1)) : T(0)) + (b < s_min - T(1) ? b - (s_min - T(1)) : T(0));
+  }
   // area: eps = d - 1, the largest root of the shifted quartic. For s1 >= s2 exactly one
   // root has d >= 1 and it is the nearest area-preserving stretch; it lies in
   // [0, max(s1, 1)] in eps, where the quartic is <= 0 at the bottom and > 0 at the top.
@@ -186,14 +193,16 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
   const T kb0 = K00 * gb0 + K01 * gb1, kb1 = K10 * gb0 + K11 * gb1;
   const T kc0 = lower0 ? K01 * gc1 : K00 * gc0 + K01 * gc1;
   const T kc1 = lower0 ? K11 * gc1 : K10 * gc0 + K11 * gc1;
-  rb = P0 * kb0 + P1 * kb1;
-  rc = P0 * kc0 + P1 * kc1;
-  ra = v3<T>(-(rb.x + rc.x), -(rb.y + rc.y), -(rb.z + rc.z));
+  // contributions P k (b, c) and -(those two) (a, since g_a = -g_b - g_c), accumulated
+  const T ka0 = -(kb0 + kc0), ka1 = -(kb1 + kc1);
+  ra = ra + P0 * ka0 + P1 * ka1;
+  rb = rb + P0 * kb0 + P1 * kb1;
+  rc = rc + P0 * kc0 + P1 * kc1;
 }
 
 // Hinge residual: u = sum_q a_q x_q (written relative to x_i, since sum_q a_q = 0),
-// p = r u/|u|, contribution w_b a_q (u - p) to vertex q; the contribution to i is minus the
-// sum of the other three so that the four add up to zero.
+// p = r u/|u|, contribution w_b a_q (u - p) to vertex q (a_i = -(a_j + a_k + a_l)), added to
+// ri, rj, rk, rl.
 template <typename T>
 __host__ __device__ __forceinline__ void hinge_residual(Vec3<T> pi, Vec3<T> pj, Vec3<T> pk, Vec3<T> pl,
                                                T a1, T a2, T a3, T rest, T w_b, Vec3<T>& ri,
@@ -203,10 +212,11 @@ __host__ __device__ __forceinline__ void hinge_residual(Vec3<T> pi, Vec3<T> pj, 
   T fac = T(0);
   if (nu2 > T(0)) fac = w_b * (T(1) - rest * drsqrt(nu2));
   const Vec3<T> W = u * fac;
-  rj = W * a1;
-  rk = W * a2;
-  rl = W * a3;
-  ri = v3<T>(-(rj.x + rk.x + rl.x), -(rj.y + rk.y + rl.y), -(rj.z + rk.z + rl.z));
+  const T a0 = -(a1 + a2 + a3);
+  ri = ri + W * a0;
+  rj = rj + W * a1;
+  rk = rk + W * a2;
+  rl = rl + W * a3;
 }
 
 }  // namespace npfem
