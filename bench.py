@@ -75,6 +75,12 @@ def main():
                     help="length of the Poisson-arrival serving run (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (accuracy check and CPU baseline)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default fused layouts instead of timing them first")
+    ap.add_argument("--cells-per-wave", default=None,
+                    help="fused layouts as 'RBC,PLT' cells per wave (skips the autotuner)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time plain npfem_step calls instead of HIP-graph replays")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -101,10 +107,28 @@ def main():
     v = torch.tensor(b.v0, dtype=torch.float32, device="cuda")
     pool = [torch.tensor(f, dtype=torch.float32, device="cuda") for f in pool_np]
     stream = torch.cuda.current_stream()
+    present = {name: k for name, k in (("RBC", I.RBC), ("PLT", I.PLT)) if (b.types == k).any()}
+    if args.cells_per_wave:
+        for name, gw in zip(("RBC", "PLT"), args.cells_per_wave.split(",")):
+            if name in present:
+                batch.set_cells_per_wave(types[present[name]], int(gw))
+    elif not args.no_autotune:
+        log("autotuning the fused layouts (scratch state)")
+        batch.autotune(K, reps=2)
+    layouts = {name: batch.cells_per_wave(types[k]) for name, k in present.items()}
+    log(f"cells per wave: {layouts}")
+    # one single-step graph per force buffer, replayed in the same order as eager steps
+    graphs = None if args.eager else [batch.graph(x, v, [f], I.DT, K) for f in pool]
+
+    def step(s):
+        if graphs is None:
+            batch.step(x, v, pool[s % pool_n], I.DT, K)
+        else:
+            graphs[s % pool_n].launch(stream)
 
     log("inputs resident; warm-up")
     for s in range(args.warmup):
-        batch.step(x, v, pool[s % pool_n], I.DT, K)
+        step(s)
     batch.check()
     torch.cuda.synchronize()
 
@@ -113,7 +137,7 @@ def main():
     t0 = time.perf_counter()
     ev[0].record(stream)
     for s in range(args.steps):
-        batch.step(x, v, pool[(args.warmup + s) % pool_n], I.DT, K)
+        step(args.warmup + s)
         ev[s + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -133,6 +157,26 @@ def main():
     achieved_tflops = flop_launch / avg_launch_s / 1e12
     alg_bytes = BYTES_PER_VERTEX_STEP * b.v_total
     traffic = measured_traffic()
+
+    # the other launch path on copies of the state (the state above must keep exactly the
+    # warm-up + timed steps for the accuracy check)
+    xc, vc = x.clone(), v.clone()
+    other = None
+    if graphs is None:
+        other_graphs = [batch.graph(xc, vc, [f], I.DT, K) for f in pool]
+        run_other = lambda s: other_graphs[s % pool_n].launch(stream)
+    else:
+        run_other = lambda s: batch.step(xc, vc, pool[s % pool_n], I.DT, K)
+    run_other(0)
+    torch.cuda.synchronize()
+    oe0, oe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    oe0.record(stream)
+    for s in range(5):
+        run_other(s)
+    oe1.record(stream)
+    torch.cuda.synchronize()
+    other = oe0.elapsed_time(oe1) / 5
+    del xc, vc
 
     if args.copy_calibration_mb > 0:
         nbytes = args.copy_calibration_mb << 20
@@ -183,9 +227,14 @@ def main():
             "n_cells": n_cells, "n_vertices": b.v_total, "n_pd_iters": K,
             "form": "fused", "dt_us": I.DT, "force_pool": pool_n,
             "reductions": "fp64 (volume, area)",
+            "cells_per_wave": layouts,
+            "autotuned": not (args.no_autotune or args.cells_per_wave),
+            "launch": "eager npfem_step" if graphs is None else
+                      "hipGraph replays (one single-step graph per force buffer)",
         },
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(np.mean(lat))},
+        ("eager_ms_per_step" if graphs is not None else "graph_ms_per_step"): other,
         "plain_gpu": {"value": plain_value, "unit": "cell-PD-iterations/s", "cells": len(pcells),
                       "ms_per_step": plain_ms, "launches_per_cell_step": 2 * K + 2,
                       "speedup_fused_over_plain": value / plain_value},

@@ -147,6 +147,38 @@ npfem_status npfem_step(npfem_batch* batch, void* x, void* v, const void* ext_fo
 npfem_status npfem_batch_set_active(npfem_batch* batch, const int32_t* cell_ids, int32_t n,
                                     void* stream);
 
+/*
+ * Fused-form layouts. A fused step gives each wave of a workgroup `cells_per_wave` cells of one
+ * type (the workgroup takes 4 x cells_per_wave cells) and 64 / cells_per_wave lanes per cell
+ * for the element rounds; every value that fits the kernel's LDS and register budget has its
+ * own element schedule. These calls choose among them (by hand, or by timing with
+ * npfem_batch_autotune); results of different layouts agree to rounding (the element
+ * summation order differs).
+ *
+ * npfem_celltype_cells_per_wave: writes up to max_out feasible values (largest first; the
+ * first is the default of new batches) to out (host, may be NULL) and returns their number,
+ * or a negative status.
+ */
+int32_t npfem_celltype_cells_per_wave(const npfem_celltype* type, int32_t* out, int32_t max_out);
+/* Layout of `type` in a fused-form batch (host out). Errors: NPFEM_E_INVALID (type not in the
+ * batch), NPFEM_E_UNSUPPORTED (plain form). */
+npfem_status npfem_batch_get_cells_per_wave(const npfem_batch* batch, const npfem_celltype* type,
+                                            int32_t* cells_per_wave);
+/* Switch `type` to another feasible layout. Synchronises the device, rebuilds the batch's work
+ * lists and makes the all-cells list current (an active list set earlier is dropped).
+ * Errors: NPFEM_E_INVALID, NPFEM_E_UNSUPPORTED (plain form, or not a layout of the type),
+ * NPFEM_E_NOMEM, NPFEM_E_HIP. */
+npfem_status npfem_batch_set_cells_per_wave(npfem_batch* batch, const npfem_celltype* type,
+                                            int32_t cells_per_wave);
+/* Time every feasible layout of every type of the batch (warm-up step, then `reps` steps of
+ * n_pd_iters iterations on `stream`, with only that type's cells active, on library-allocated
+ * scratch state: each cell at its rest shape under small pseudo-random forces) and keep the
+ * fastest per cell. Synchronises the device; the caller's state buffers are not touched. The
+ * all-cells list is current afterwards. Errors: NPFEM_E_INVALID (n_pd_iters or reps < 1),
+ * NPFEM_E_UNSUPPORTED (plain form), NPFEM_E_NOMEM, NPFEM_E_HIP. */
+npfem_status npfem_batch_autotune(npfem_batch* batch, int32_t n_pd_iters, int32_t reps,
+                                  void* stream);
+
 typedef struct npfem_graph npfem_graph;         /* opaque, library-owned */
 
 /*

@@ -55,7 +55,8 @@ npfem_status fail(npfem_status s, const std::string& msg) {
 
 void free_devtype(DevType* d) {
   if (!d) return;
-  void* ptrs[] = {d->tri_sched, d->hinge_sched, d->ring_info, d->ring_pairs, d->linv_tiles,
+  // (schedules belong to the cell type's per-layout cache)
+  void* ptrs[] = {d->ring_info, d->ring_pairs, d->linv_tiles,
                   d->tri,       d->hinge,       d->vt_off,    d->vt_list,    d->vh_off,
                   d->vh_list,   d->G64,         d->G32,       d->A64,        d->A32,
                   d->coef64,    d->coef32,      d->rest64,    d->rest32,     d->cband64,
@@ -63,6 +64,29 @@ void free_devtype(DevType* d) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete d;
+}
+
+// Device copies of layout li's schedules on device dev (uploaded once). Caller holds ct->mu.
+npfem_status layout_schedules_locked(npfem_celltype* ct, int dev, int li, TriRec** tri,
+                                     HingeRec** hinge) {
+  auto& v = ct->dev_sched[dev];
+  if (v.empty()) v.assign(ct->layouts.size(), {nullptr, nullptr});
+  if (!v[li].first) {
+    const FusedLayout& lay = ct->layouts[li];
+    TriRec* t = nullptr;
+    HingeRec* h = nullptr;
+    npfem_status st = upload_raw(&t, lay.tri_sched.data(), lay.tri_sched.size());
+    if (st == NPFEM_OK) st = upload_raw(&h, lay.hinge_sched.data(), lay.hinge_sched.size());
+    if (st != NPFEM_OK) {
+      if (t) (void)hipFree(t);
+      if (h) (void)hipFree(h);
+      return st;
+    }
+    v[li] = {t, h};
+  }
+  *tri = v[li].first;
+  *hinge = v[li].second;
+  return NPFEM_OK;
 }
 
 // Device copy of a cell type for the current device (created once, then shared).
@@ -104,8 +128,7 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   chk(upload(&d->rest64, ct->rest_norm)); chk(upload(&d->rest32, ct->rest_norm));
   chk(upload(&d->cband64, ct->cband)); chk(upload(&d->cband32, ct->cband));
   if (ct->fused_ok) {
-    chk(upload_raw(&d->tri_sched, ct->tri_sched.data(), ct->tri_sched.size()));
-    chk(upload_raw(&d->hinge_sched, ct->hinge_sched.data(), ct->hinge_sched.size()));
+    chk(layout_schedules_locked(ct, dev, 0, &d->tri_sched, &d->hinge_sched));
     chk(upload(&d->ring_info, ct->ring_info));
     chk(upload(&d->ring_pairs, ct->ring_pairs));
     // L^-1 in MFMA A-operand order: row tile rt, chunk c, step j, lane l -> (row rt*16 + l%16,
@@ -138,18 +161,45 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   return NPFEM_OK;
 }
 
+// The kernels' view of a cell type with layout li (fused form) on the current device.
+npfem_status devtype_value(npfem_celltype* ct, int li, DevType* out) {
+  DevType* base = nullptr;
+  npfem_status st = upload_celltype(ct, &base);
+  if (st != NPFEM_OK) return st;
+  *out = *base;
+  if (!ct->fused_ok) return NPFEM_OK;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(ct->mu);
+  st = layout_schedules_locked(ct, dev, li, &out->tri_sched, &out->hinge_sched);
+  if (st != NPFEM_OK) return st;
+  const FusedLayout& lay = ct->layouts[li];
+  out->p.gw = lay.gw;
+  out->p.slots = lay.slots;
+  out->p.tri_rounds = lay.tri_rounds;
+  out->p.hinge_rounds = lay.hinge_rounds;
+  return NPFEM_OK;
+}
+
 }  // namespace npfem
 
 using namespace npfem;
 
 npfem_celltype::~npfem_celltype() {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
   for (auto& kv : dev) {
-    int cur = 0;
-    (void)hipGetDevice(&cur);
     (void)hipSetDevice(kv.first);
     free_devtype(kv.second);
-    (void)hipSetDevice(cur);
   }
+  for (auto& kv : dev_sched) {
+    (void)hipSetDevice(kv.first);
+    for (auto& p : kv.second) {
+      if (p.first) (void)hipFree(p.first);
+      if (p.second) (void)hipFree(p.second);
+    }
+  }
+  (void)hipSetDevice(cur);
 }
 
 // A recorded sequence of steps (npfem_graph_create).
@@ -181,6 +231,7 @@ struct npfem_batch {
   std::vector<int64_t> offsets;
   std::vector<npfem_celltype*> types;
   std::vector<int> type_of;                 // per cell, index into types
+  std::vector<int> layout_of;               // per type, index into its fused layouts
   std::vector<DevType*> dev_types;          // host pointers to per-type device copies
   DevType* d_types = nullptr;               // device array of DevType (by value)
   DevType** d_type_ptrs = nullptr;          // device pointers to each type's device DevType
@@ -191,6 +242,7 @@ struct npfem_batch {
   FusedGroup* d_groups = nullptr;           // all cells
   int* d_count_all = nullptr;
   int n_groups = 0;                         // groups of the all-cells list (grid capacity)
+  size_t list_capacity = 0;                 // groups the device lists can hold
   FusedGroup* d_ring[2] = {nullptr, nullptr};
   int* d_ring_count[2] = {nullptr, nullptr};
   FusedGroup* h_stage[2] = {nullptr, nullptr};
@@ -235,7 +287,7 @@ void build_groups(const npfem_batch* b, const int32_t* ids, int n, std::vector<F
   out.clear();
   const int nt = (int)b->types.size();
   for (int ti = 0; ti < nt; ++ti) {
-    const int cap = kFusedWaves * b->types[ti]->gw;
+    const int cap = kFusedWaves * b->types[ti]->layouts[b->layout_of[ti]].gw;
     FusedGroup gcur{};
     gcur.type = ti;
     gcur.count = 0;
@@ -250,6 +302,57 @@ void build_groups(const npfem_batch* b, const int32_t* ids, int n, std::vector<F
     }
     if (gcur.count) out.push_back(gcur);
   }
+}
+
+void free_lists(npfem_batch* b) {
+  if (b->d_groups) (void)hipFree(b->d_groups);
+  b->d_groups = nullptr;
+  for (int i = 0; i < 2; ++i) {
+    if (b->ring_ev[i]) (void)hipEventSynchronize(b->ring_ev[i]);
+    if (b->d_ring[i]) (void)hipFree(b->d_ring[i]);
+    if (b->h_stage[i]) (void)hipHostFree(b->h_stage[i]);
+    b->d_ring[i] = nullptr;
+    b->h_stage[i] = nullptr;
+  }
+  b->list_capacity = 0;
+}
+
+// (Re)builds a fused-form batch's type table, all-cells work list, LDS size and list
+// capacity for the types' current layouts and makes the all-cells list current. No step of
+// the batch may be in flight.
+npfem_status relayout(npfem_batch* b) {
+  const int nt = (int)b->types.size();
+  b->lds_bytes = 0;
+  for (int ti = 0; ti < nt; ++ti) {
+    npfem_celltype* t = b->types[ti];
+    DevType v;
+    npfem_status st = devtype_value(t, b->layout_of[ti], &v);
+    if (st != NPFEM_OK) return st;
+    HIP_TRY(hipMemcpy(b->d_types + ti, &v, sizeof(DevType), hipMemcpyHostToDevice));
+    const int cap = kFusedWaves * t->layouts[b->layout_of[ti]].gw;
+    b->lds_bytes = std::max(b->lds_bytes, (size_t)2 * cap * 3 * t->npad * sizeof(float));
+  }
+  std::vector<FusedGroup> groups;
+  build_groups(b, nullptr, b->n_cells, groups);
+  const size_t need = std::max<size_t>(groups.size(), 1);
+  if (need > b->list_capacity) {
+    free_lists(b);
+    const size_t gbytes = need * sizeof(FusedGroup);
+    if (hipMalloc((void**)&b->d_groups, gbytes) != hipSuccess)
+      return fail(NPFEM_E_NOMEM, "device work list");
+    for (int i = 0; i < 2; ++i)
+      if (hipMalloc((void**)&b->d_ring[i], gbytes) != hipSuccess ||
+          hipHostMalloc((void**)&b->h_stage[i], gbytes, hipHostMallocDefault) != hipSuccess)
+        return fail(NPFEM_E_NOMEM, "active-list ring");
+    b->list_capacity = need;
+  }
+  b->n_groups = (int)groups.size();
+  if (b->n_groups)
+    HIP_TRY(hipMemcpy(b->d_groups, groups.data(), groups.size() * sizeof(FusedGroup),
+                      hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_count_all, &b->n_groups, sizeof(int), hipMemcpyHostToDevice));
+  b->ring_cur = -1;
+  return NPFEM_OK;
 }
 
 }  // namespace
@@ -364,30 +467,16 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
     for (npfem_celltype* t : b->types) wb = std::max(wb, plain_work_bytes(precision, t->n, t->m, t->e));
     if (wb && hipMalloc(&b->work, wb) != hipSuccess) return bail(fail(NPFEM_E_NOMEM, "plain workspace"));
   } else {
-    std::vector<FusedGroup> groups;
-    build_groups(b, nullptr, n_cells, groups);
-    for (int ti = 0; ti < nt; ++ti) {
-      const npfem_celltype* t = b->types[ti];
-      const int cap = kFusedWaves * t->gw;
-      b->lds_bytes = std::max(b->lds_bytes, (size_t)2 * cap * 3 * t->npad * sizeof(float));
-    }
-    b->n_groups = (int)groups.size();
-    const size_t gbytes = std::max<size_t>(groups.size(), 1) * sizeof(FusedGroup);
-    if (hipMalloc((void**)&b->d_groups, gbytes) != hipSuccess ||
-        hipMalloc((void**)&b->d_count_all, sizeof(int)) != hipSuccess)
+    b->layout_of.assign(nt, 0);
+    if (hipMalloc((void**)&b->d_count_all, sizeof(int)) != hipSuccess)
       return bail(fail(NPFEM_E_NOMEM, "device work list"));
-    if ((b->n_groups && hipMemcpy(b->d_groups, groups.data(), groups.size() * sizeof(FusedGroup),
-                                  hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(b->d_count_all, &b->n_groups, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
-      return bail(fail(NPFEM_E_HIP, "work list upload"));
-    for (int i = 0; i < 2; ++i) {
-      if (hipMalloc((void**)&b->d_ring[i], gbytes) != hipSuccess ||
-          hipMalloc((void**)&b->d_ring_count[i], sizeof(int)) != hipSuccess ||
-          hipHostMalloc((void**)&b->h_stage[i], gbytes, hipHostMallocDefault) != hipSuccess ||
+    for (int i = 0; i < 2; ++i)
+      if (hipMalloc((void**)&b->d_ring_count[i], sizeof(int)) != hipSuccess ||
           hipHostMalloc((void**)&b->h_stage_count[i], sizeof(int), hipHostMallocDefault) != hipSuccess ||
           hipEventCreateWithFlags(&b->ring_ev[i], hipEventDisableTiming) != hipSuccess)
         return bail(fail(NPFEM_E_NOMEM, "active-list ring"));
-    }
+    const npfem_status st = relayout(b);
+    if (st != NPFEM_OK) return bail(st);
     b->mark.assign(n_cells, 0);
     if (hipMalloc((void**)&b->d_offsets, (n_cells + 1) * sizeof(int64_t)) != hipSuccess ||
         hipMemcpy(b->d_offsets, b->offsets.data(), (n_cells + 1) * sizeof(int64_t),
@@ -564,6 +653,139 @@ npfem_status npfem_graph_launch(npfem_graph* g, void* stream) {
 }
 
 void npfem_graph_destroy(npfem_graph* g) { delete g; }
+
+int32_t npfem_celltype_cells_per_wave(const npfem_celltype* t, int32_t* out, int32_t max_out) {
+  if (!t) return fail(NPFEM_E_INVALID, "type is null");
+  const int n = (int)t->layouts.size();
+  for (int i = 0; i < n && i < max_out; ++i)
+    if (out) out[i] = t->layouts[i].gw;
+  return n;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Index of `type` among the batch's types, or -1.
+int batch_type_index(const npfem_batch* b, const npfem_celltype* type) {
+  for (size_t i = 0; i < b->types.size(); ++i)
+    if (b->types[i] == type) return (int)i;
+  return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+npfem_status npfem_batch_get_cells_per_wave(const npfem_batch* b, const npfem_celltype* type,
+                                            int32_t* cells_per_wave) {
+  if (!b || !type || !cells_per_wave) return fail(NPFEM_E_INVALID, "null argument");
+  if (b->form != NPFEM_FORM_FUSED) return fail(NPFEM_E_UNSUPPORTED, "plain-form batch");
+  const int ti = batch_type_index(b, type);
+  if (ti < 0) return fail(NPFEM_E_INVALID, "type is not in the batch");
+  *cells_per_wave = b->types[ti]->layouts[b->layout_of[ti]].gw;
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_set_cells_per_wave(npfem_batch* b, const npfem_celltype* type,
+                                            int32_t cells_per_wave) {
+  if (!b || !type) return fail(NPFEM_E_INVALID, "null argument");
+  if (b->form != NPFEM_FORM_FUSED) return fail(NPFEM_E_UNSUPPORTED, "plain-form batch");
+  const int ti = batch_type_index(b, type);
+  if (ti < 0) return fail(NPFEM_E_INVALID, "type is not in the batch");
+  const auto& lays = b->types[ti]->layouts;
+  int li = -1;
+  for (size_t i = 0; i < lays.size(); ++i)
+    if (lays[i].gw == cells_per_wave) li = (int)i;
+  if (li < 0) return fail(NPFEM_E_UNSUPPORTED, "cells_per_wave is not a layout of this type");
+  DeviceGuard guard(b->device);
+  HIP_TRY(hipDeviceSynchronize());   // the batch's lists may be in use by enqueued steps
+  b->layout_of[ti] = li;
+  return relayout(b);
+}
+
+npfem_status npfem_batch_autotune(npfem_batch* b, int32_t n_pd_iters, int32_t reps, void* stream) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  if (b->form != NPFEM_FORM_FUSED) return fail(NPFEM_E_UNSUPPORTED, "plain-form batch");
+  if (n_pd_iters < 1 || reps < 1) return fail(NPFEM_E_INVALID, "n_pd_iters and reps must be >= 1");
+  if (b->n_cells == 0) return NPFEM_OK;
+  DeviceGuard guard(b->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipDeviceSynchronize());
+  // scratch state: every cell at its rest shape, at rest, under small pseudo-random forces
+  const int64_t vt = b->offsets.back();
+  std::vector<float> hx((size_t)3 * vt), hf((size_t)3 * vt);
+  uint64_t rng = 0x9e3779b97f4a7c15ull;
+  for (int c = 0; c < b->n_cells; ++c) {
+    const npfem_celltype* t = b->types[b->type_of[c]];
+    for (int i = 0; i < t->n; ++i)
+      for (int d = 0; d < 3; ++d) {
+        hx[(size_t)d * vt + b->offsets[c] + i] = (float)t->X[3 * i + d];
+        rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17;   // xorshift64
+        hf[(size_t)d * vt + b->offsets[c] + i] = (float)((double)(rng >> 11) * 0x1.0p-53 - 0.5);
+      }
+  }
+  float *x = nullptr, *v = nullptr, *f = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (x) (void)hipFree(x);
+    if (v) (void)hipFree(v);
+    if (f) (void)hipFree(f);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  const size_t bytes = (size_t)3 * vt * sizeof(float);
+  if (hipMalloc((void**)&x, bytes) != hipSuccess || hipMalloc((void**)&v, bytes) != hipSuccess ||
+      hipMalloc((void**)&f, bytes) != hipSuccess) {
+    cleanup();
+    return fail(NPFEM_E_NOMEM, "autotune scratch state");
+  }
+  if (hipMemcpy(x, hx.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f, hf.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(v, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(NPFEM_E_HIP, "autotune setup");
+  }
+  npfem_status st = NPFEM_OK;
+  for (int ti = 0; ti < (int)b->types.size() && st == NPFEM_OK; ++ti) {
+    const int n_lay = (int)b->types[ti]->layouts.size();
+    if (n_lay < 2) continue;
+    std::vector<int32_t> ids;
+    for (int c = 0; c < b->n_cells; ++c)
+      if (b->type_of[c] == ti) ids.push_back(c);
+    int best = b->layout_of[ti];
+    float best_ms = 0.0f;
+    for (int li = 0; li < n_lay && st == NPFEM_OK; ++li) {
+      b->layout_of[ti] = li;
+      st = relayout(b);
+      if (st == NPFEM_OK) st = npfem_batch_set_active(b, ids.data(), (int32_t)ids.size(), stream);
+      if (st == NPFEM_OK) st = npfem_step(b, x, v, f, b->dt, n_pd_iters, stream, nullptr);  // warm-up
+      if (st != NPFEM_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(NPFEM_E_HIP, "event"); break; }
+      for (int r = 0; r < reps && st == NPFEM_OK; ++r)
+        st = npfem_step(b, x, v, f, b->dt, n_pd_iters, stream, nullptr);
+      float ms = 0.0f;
+      if (st == NPFEM_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(NPFEM_E_HIP, "autotune timing");
+      if (st == NPFEM_OK && (li == 0 || ms < best_ms)) {
+        best = li;
+        best_ms = ms;
+      }
+    }
+    b->layout_of[ti] = best;
+  }
+  (void)hipStreamSynchronize(s);
+  cleanup();
+  // the scratch steps may have set the non-finite flag: clear it, then restore all cells
+  (void)hipMemset(b->d_flag, 0, sizeof(int));
+  const npfem_status st2 = relayout(b);
+  if (st != NPFEM_OK) return st;
+  if (st2 == NPFEM_OK) g_last_error.clear();
+  return st2;
+}
 
 npfem_status npfem_batch_check(npfem_batch* b, void* stream) {
   if (!b) return fail(NPFEM_E_INVALID, "batch is null");

@@ -42,6 +42,14 @@ struct HingeRec {
   float pad;
 };
 
+// Element schedules of the fused form for one number of cells per wave (gw): slots = 64 / gw
+// lanes per cell, rounds of vertex-disjoint elements.
+struct FusedLayout {
+  int gw = 0, slots = 0, tri_rounds = 0, hinge_rounds = 0;
+  std::vector<TriRec> tri_sched;      // [tri_rounds][slots]
+  std::vector<HingeRec> hinge_sched;  // [hinge_rounds][slots]
+};
+
 // Scalar parameters of a cell type as seen by the kernels.
 struct TypeParams {
   int32_t n, m, e, bw;          // vertices, triangles, hinges, band width of L
@@ -106,15 +114,18 @@ struct npfem_celltype {
   std::vector<double> Linv;       // [n][n]
   std::vector<int32_t> vt_off, vt_list, vh_off, vh_list;
   std::vector<uint32_t> ring_info, ring_pairs;
-  // fused-form schedule
+  // fused form: LDS column length and one element-schedule layout per feasible number of
+  // cells per wave (largest first; layouts[0] is the default). gw, slots and the rounds
+  // below describe layouts[0].
   int gw = 0, slots = 0, npad = 0, tri_rounds = 0, hinge_rounds = 0;
-  std::vector<npfem::TriRec> tri_sched;
-  std::vector<npfem::HingeRec> hinge_sched;
+  std::vector<npfem::FusedLayout> layouts;
   bool fused_ok = false;
   std::string fused_reason;
 
   std::mutex mu;
-  std::map<int, npfem::DevType*> dev;   // per HIP device
+  std::map<int, npfem::DevType*> dev;   // per HIP device: shared device data, layouts[0]
+  // per HIP device, per layout: device copies of that layout's schedules
+  std::map<int, std::vector<std::pair<npfem::TriRec*, npfem::HingeRec*>>> dev_sched;
   ~npfem_celltype();
 };
 

@@ -501,7 +501,7 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   if ((npad / 4) % 2 == 0) npad += 4;
   ct->npad = npad;
   const int per_cell = 2 * 3 * npad * 4;  // X and R columns, FP32
-  int gw = 0;
+  std::vector<int> feasible;
   for (int cand : {16, 8, 4, 2, 1}) {
     if (kFusedWaves * cand * per_cell > kFusedLdsBudget) continue;
     if ((cand * n + 63) / 64 > kMaxItems) continue;
@@ -516,36 +516,35 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
         fits = mfma_share_items(ct_n, units * w / kFusedWaves, units * (w + 1) / kFusedWaves) <=
                kMaxTilesPerWave / 2;
     }
-    if (!fits) continue;
-    gw = cand;
-    break;
+    if (fits) feasible.push_back(cand);
   }
-  ct->fused_ok = gw > 0;
+  ct->fused_ok = !feasible.empty();
   if (!ct->fused_ok) {
     ct->fused_reason = "mesh too large for the fused kernel's LDS layout (n <= 576)";
     return NPFEM_OK;
   }
-  ct->gw = gw;
-  ct->slots = 64 / gw;
-  {
-    std::vector<std::vector<int>> tel(m), hel(e);
-    for (int t = 0; t < m; ++t) tel[t] = {ct->tri[3 * t], ct->tri[3 * t + 1], ct->tri[3 * t + 2]};
-    for (int h = 0; h < e; ++h)
-      hel[h] = {ct->hinge[4 * h], ct->hinge[4 * h + 1], ct->hinge[4 * h + 2], ct->hinge[4 * h + 3]};
-    // approximate VALU instructions per wave of one triangle / hinge round of the fused
-    // kernel (its gfx950 code), weighed against the rounds' modelled LDS cycles
-    const double kTriRoundValu = 270.0, kHingeRoundValu = 81.0;
-    const Schedule tr = best_schedule(tel, n, gw, ct->slots, 3 * npad, kTriRoundValu);
-    const Schedule hr = best_schedule(hel, n, gw, ct->slots, 3 * npad, kHingeRoundValu);
-    ct->tri_rounds = (int)tr.rounds.size();
-    ct->hinge_rounds = (int)hr.rounds.size();
+  std::vector<std::vector<int>> tel(m), hel(e);
+  for (int t = 0; t < m; ++t) tel[t] = {ct->tri[3 * t], ct->tri[3 * t + 1], ct->tri[3 * t + 2]};
+  for (int h = 0; h < e; ++h)
+    hel[h] = {ct->hinge[4 * h], ct->hinge[4 * h + 1], ct->hinge[4 * h + 2], ct->hinge[4 * h + 3]};
+  // approximate VALU instructions per wave of one triangle / hinge round of the fused
+  // kernel (its gfx950 code), weighed against the rounds' modelled LDS cycles
+  const double kTriRoundValu = 270.0, kHingeRoundValu = 81.0;
+  for (int gw : feasible) {
+    FusedLayout lay;
+    lay.gw = gw;
+    lay.slots = 64 / gw;
+    const Schedule tr = best_schedule(tel, n, gw, lay.slots, 3 * npad, kTriRoundValu);
+    const Schedule hr = best_schedule(hel, n, gw, lay.slots, 3 * npad, kHingeRoundValu);
+    lay.tri_rounds = (int)tr.rounds.size();
+    lay.hinge_rounds = (int)hr.rounds.size();
     TriRec empty_tri{};
     empty_tri.area = 0.0f;
-    ct->tri_sched.assign((size_t)ct->tri_rounds * ct->slots, empty_tri);
+    lay.tri_sched.assign((size_t)lay.tri_rounds * lay.slots, empty_tri);
     HingeRec empty_hinge{};
     empty_hinge.rest = -1.0f;
-    ct->hinge_sched.assign((size_t)ct->hinge_rounds * ct->slots, empty_hinge);
-    for (int r = 0; r < ct->tri_rounds; ++r)
+    lay.hinge_sched.assign((size_t)lay.hinge_rounds * lay.slots, empty_hinge);
+    for (int r = 0; r < lay.tri_rounds; ++r)
       for (size_t s = 0; s < tr.rounds[r].size(); ++s) {
         // roles (a, b, c) in the order the schedule chose; the rest frame follows it
         const auto& v = tr.rounds[r][s];
@@ -561,9 +560,9 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
         int k0 = 0;
         while (ct->tri[3 * t + k0] != v[0]) ++k0;
         rec.orient = (ct->tri[3 * t + (k0 + 1) % 3] == v[1]) ? 1.0f : -1.0f;
-        ct->tri_sched[(size_t)r * ct->slots + s] = rec;
+        lay.tri_sched[(size_t)r * lay.slots + s] = rec;
       }
-    for (int r = 0; r < ct->hinge_rounds; ++r)
+    for (int r = 0; r < lay.hinge_rounds; ++r)
       for (size_t s = 0; s < hr.rounds[r].size(); ++s) {
         // any vertex may lead the difference form: the stencil's coefficients sum to zero
         const auto& v = hr.rounds[r][s];
@@ -579,9 +578,14 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
         rec.a2 = (float)a[2]; rec.a3 = (float)a[3];
         rec.rest = (float)ct->rest_norm[h];
         rec.pad = 0;
-        ct->hinge_sched[(size_t)r * ct->slots + s] = rec;
+        lay.hinge_sched[(size_t)r * lay.slots + s] = rec;
       }
+    ct->layouts.push_back(std::move(lay));
   }
+  ct->gw = ct->layouts[0].gw;
+  ct->slots = ct->layouts[0].slots;
+  ct->tri_rounds = ct->layouts[0].tri_rounds;
+  ct->hinge_rounds = ct->layouts[0].hinge_rounds;
   return NPFEM_OK;
 }
 

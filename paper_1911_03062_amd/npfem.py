@@ -84,6 +84,14 @@ def lib() -> ctypes.CDLL:
     L.npfem_batch_set_active.restype = c_int32
     L.npfem_batch_check.argtypes = [c_void_p, c_void_p]
     L.npfem_batch_check.restype = c_int32
+    L.npfem_celltype_cells_per_wave.argtypes = [c_void_p, POINTER(c_int32), c_int32]
+    L.npfem_celltype_cells_per_wave.restype = c_int32
+    L.npfem_batch_get_cells_per_wave.argtypes = [c_void_p, c_void_p, POINTER(c_int32)]
+    L.npfem_batch_get_cells_per_wave.restype = c_int32
+    L.npfem_batch_set_cells_per_wave.argtypes = [c_void_p, c_void_p, c_int32]
+    L.npfem_batch_set_cells_per_wave.restype = c_int32
+    L.npfem_batch_autotune.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
+    L.npfem_batch_autotune.restype = c_int32
     L.npfem_graph_create.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_void_p), c_int32,
                                      c_double, c_int32, c_void_p, POINTER(c_void_p)]
     L.npfem_graph_create.restype = c_int32
@@ -136,6 +144,14 @@ class CellType:
         i = _Info()
         _check(lib().npfem_celltype_get_info(self._h, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    def cells_per_wave(self) -> list:
+        """Feasible fused-form layouts (cells per wave), the default first."""
+        buf = (c_int32 * 8)()
+        n = lib().npfem_celltype_cells_per_wave(self._h, buf, 8)
+        if n < 0:
+            _check(n)
+        return [int(buf[i]) for i in range(min(n, 8))]
 
     def matrix(self) -> np.ndarray:
         n = self.info()["n_vertices"]
@@ -202,6 +218,25 @@ class Batch:
                                          and vol_area.is_contiguous()
                                          and tuple(vol_area.shape) == (self.n_cells, 2)):
             raise ValueError("vol_area must be a contiguous float64 device tensor [n_cells][2]")
+
+    def cells_per_wave(self, cell_type: CellType) -> int:
+        out = c_int32()
+        _check(lib().npfem_batch_get_cells_per_wave(self._h, cell_type.handle, ctypes.byref(out)))
+        return int(out.value)
+
+    def set_cells_per_wave(self, cell_type: CellType, cells_per_wave: int):
+        _check(lib().npfem_batch_set_cells_per_wave(self._h, cell_type.handle, int(cells_per_wave)))
+
+    def autotune(self, n_pd_iters: int, reps: int = 3, stream=None) -> dict:
+        """Time every layout of every type and keep the fastest; returns {type handle: gw}."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_batch_autotune(self._h, int(n_pd_iters), int(reps), c_void_p(s.cuda_stream)))
+        seen = []
+        for t in self._types:
+            if all(t is not u for u in seen):
+                seen.append(t)
+        return {t.handle.value: self.cells_per_wave(t) for t in seen}
 
     def graph(self, x, v, forces, dt: float, n_pd_iters: int, vol_area=None) -> "Graph":
         """Record len(forces) steps on these buffers into a HIP graph (see Graph)."""

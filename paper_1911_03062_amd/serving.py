@@ -186,8 +186,51 @@ class StepServer:
         sess.rbc = sess.plt = (0, 0)
         sess.initialised = False
 
+    def warmup(self):
+        """Run one tick of the whole request path (state set-up, seeded forces, active list,
+        step, copy-out) on one slot of each cell type, outside any timing. The first use of
+        these paths in a process loads GPU code and creates generators (~150 ms here), which
+        would otherwise land on the first requests. Slot allocation is left as it was, and the
+        slots' contents are rewritten when a session is admitted to them."""
+        import torch
+        tmp = Session(sid=-1, n_rbc=1 if self.pool.cap[RBC] else 0,
+                      n_plt=1 if self.pool.cap[PLT] else 0, remaining=1)
+        if not self._admit(tmp):
+            return
+        request_forces(self.pool, tmp, 0, self.sigma)
+        ids = np.concatenate([self.pool.cell_ids(RBC, tmp.rbc), self.pool.cell_ids(PLT, tmp.plt)])
+        self.pool.batch.set_active(ids)
+        ev = torch.cuda.Event(enable_timing=True)
+        self.pool.batch.step(self.pool.x, self.pool.v, self.pool.f, self.pool.dt, self.K)
+        ev.record(torch.cuda.current_stream())
+        while not ev.query():
+            time.sleep(0.0002)
+        self._snapshot(tmp)
+        self.finals.pop(tmp.sid, None)
+        self.pool.alloc[RBC].release(tmp.rbc)
+        self.pool.alloc[PLT].release(tmp.plt)
+        self.pool.batch.set_active(None)
+        self.pool.batch.check()
+
     def run(self, requests: list, sessions: dict, on_tick=None):
-        """Serve `requests` (sorted by arrival) in real time; returns per-request latencies."""
+        """Serve `requests` (sorted by arrival) in real time; returns per-request latencies.
+
+        One warm-up tick runs first (see warmup). The Python garbage collector is paused for
+        the duration of the loop (after one full collection): a collection pass over a large
+        heap stalls the host for up to a few hundred milliseconds, and every request in flight
+        would wait for it."""
+        import gc
+        self.warmup()
+        was_enabled = gc.isenabled()
+        gc.collect()
+        gc.disable()
+        try:
+            return self._run(requests, sessions, on_tick)
+        finally:
+            if was_enabled:
+                gc.enable()
+
+    def _run(self, requests: list, sessions: dict, on_tick=None):
         import torch
         self.sessions = sessions
         stream = torch.cuda.current_stream()

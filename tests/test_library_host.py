@@ -82,3 +82,13 @@ def test_small_meshes_match_oracle_matrix():
         ct = _create(x, t)
         oc = O.CellType(x, t, I.RBC_MATERIAL, I.DT)
         assert np.abs(ct.matrix() - oc.L).max() <= 1e-13 * np.abs(oc.L).max()
+
+
+def test_fused_layouts_of_the_cell_types():
+    """Feasible cells-per-wave layouts (largest first): RBC (258 vertices) fits 2 cells per
+    wave in the LDS budget, platelets (66 vertices) 8; smaller values are always feasible."""
+    from paper_1911_03062_amd import npfem as N
+    types = {k: N.CellType(x, t, m, I.DT) for k, (x, t, m) in I.cell_type_inputs().items()}
+    assert types[I.RBC].cells_per_wave() == [2, 1]
+    assert types[I.PLT].cells_per_wave() == [8, 4, 2, 1]
+    assert types[I.RBC].info()["tri_rounds"] >= 16    # pole valence bounds the rounds
