@@ -28,7 +28,8 @@ class Material:
     """Membrane constants (parameter table of the supplementary material).
 
     shear_B, area_C, skalak_D in pN/um; k_bend in pN um; k_vol in pN/um (per vertex);
-    strain_min/max clamp the singular values of the strain projection (1, 1 = polar factor).
+    strain_min/max clamp the singular values of the strain projection (1, 1 = polar factor);
+    pbd_kappa in [0, 1] is the position-based damping factor (kappa_damping of the table).
     """
     density: float = DENSITY
     shear_B: float = 5.0
@@ -38,10 +39,16 @@ class Material:
     k_vol: float = 250.0
     strain_min: float = 1.0
     strain_max: float = 1.0
+    pbd_kappa: float = 0.0    # position-based velocity damping (kappa_damping), 0 = off
 
     def scaled(self, s: float) -> "Material":
         return Material(self.density, self.shear_B * s, self.area_C * s, self.skalak_D * s,
-                        self.k_bend * s, self.k_vol * s, self.strain_min, self.strain_max)
+                        self.k_bend * s, self.k_vol * s, self.strain_min, self.strain_max,
+                        self.pbd_kappa)
+
+    def with_kappa(self, kappa: float) -> "Material":
+        return Material(self.density, self.shear_B, self.area_C, self.skalak_D, self.k_bend,
+                        self.k_vol, self.strain_min, self.strain_max, kappa)
 
 
 RBC_MATERIAL = Material()

@@ -23,7 +23,10 @@ w/2 ||A x - p(x)||^2 with exact projections p:
     Wardetzky et al. 2007) projected onto its rest norm, weight k_bending;
   * per cell: volume, projected by one linearised step onto V = V0, weight k_volume per vertex;
   * uniform lumped mass m = density * V0 / n (the mass matrix is the lumped total mass,
-    interior fluid included, npFEM subsection).
+    interior fluid included, npFEM subsection);
+  * optional position-based damping of the velocities (npFEM subsection, after Mueller et al.
+    2007): per cell the rigid part of v_n is kept and the rest scaled by 1 - kappa, applied
+    to v_n before the prediction (the order of position-based dynamics: damp, then predict).
 Everything is float64, vectorised over the cells of one type (arrays [N][n][3]).
 """
 from __future__ import annotations
@@ -65,6 +68,7 @@ class CellType:
         self.w_v = float(material.k_vol)
         self.s_min = float(material.strain_min)
         self.s_max = float(material.strain_max)
+        self.kappa = float(getattr(material, "pbd_kappa", 0.0))
 
         self.G, self.area = triangle_rest_frames(X, tri)
         self.hinge, self.coef, self.rest_norm = bending_stencils(X, tri)
@@ -351,9 +355,36 @@ def solve(ct, b, method: str = "cholesky"):
     return np.transpose(X.reshape(ct.n, N, 3), (1, 0, 2))
 
 
+def rigid_velocity_fit(x, v):
+    """Centre-of-mass velocity v_cm, angular velocity w and centre x_cm of the rigid motion
+    that conserves the linear and angular momentum of the velocity field v at x (equal
+    masses): v_cm = mean v, w = I^-1 L with L = sum r x v, I = sum (|r|^2 1 - r r^T),
+    r = x - x_cm. x, v: [N][n][3]; returns ([N][3], [N][3], [N][3])."""
+    xcm = x.mean(axis=1)
+    vcm = v.mean(axis=1)
+    r = x - xcm[:, None, :]
+    Lm = np.cross(r, v).sum(axis=1)
+    rr = np.einsum("nid,nid->n", r, r)
+    I = rr[:, None, None] * np.eye(3)[None] - np.einsum("nid,nie->nde", r, r)
+    w = np.linalg.solve(I, Lm[:, :, None])[:, :, 0]
+    return vcm, w, xcm
+
+
+def pbd_damp(x, v, kappa: float):
+    """Position-based damping of velocities (npFEM subsection; Mueller et al. 2007):
+    v <- v + kappa (v_cm + w x r - v), keeping the rigid part of each cell's motion."""
+    if kappa == 0.0:
+        return v
+    vcm, w, xcm = rigid_velocity_fit(x, v)
+    r = x - xcm[:, None, :]
+    rigid = vcm[:, None, :] + np.cross(w[:, None, :], r)
+    return v + kappa * (rigid - v)
+
+
 def predict(x, v, f, ct):
-    """y = x_n + h v_n + h^2 F_ext / m (third displayed equation, C = 0)."""
-    return x + ct.h * v + (ct.h ** 2 / ct.mass) * f
+    """y = x_n + h v_n + h^2 F_ext / m (third displayed equation, C = 0), with v_n damped
+    first when the type has position-based damping."""
+    return x + ct.h * pbd_damp(x, v, ct.kappa) + (ct.h ** 2 / ct.mass) * f
 
 
 def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",

@@ -422,3 +422,86 @@ def test_lumped_mass_is_total_mass(kind):
     assert abs(ct.n * ct.mass - mat.density * vol) < 1e-9 * mat.density * vol
     # the system matrix diagonal carries m/h^2 + k_vol on top of non-negative stiffness terms
     assert np.all(np.diag(ct.L) >= ct.mass / ct.h ** 2 + ct.w_v - 1e-9)
+
+
+# ------------------------------------------------------------ position-based damping (PBD)
+
+
+def _cloud(seed, kind=I.RBC, n_cells=3):
+    ct = _ct(kind)
+    rng = np.random.default_rng(seed)
+    x = ct.X[None] + 0.1 * rng.normal(size=(n_cells,) + ct.X.shape) + rng.normal(size=(n_cells, 1, 3)) * 20
+    return ct, x, rng
+
+
+def test_pbd_damping_keeps_rigid_velocity_fields():
+    """v = a + w0 x (x - c) (any a, w0, c) is already rigid: damping leaves it unchanged."""
+    ct, x, rng = _cloud(31)
+    a = rng.normal(size=(3, 1, 3))
+    w0 = rng.normal(size=(3, 1, 3))
+    c = rng.normal(size=(3, 1, 3)) * 5
+    v = a + np.cross(w0, x - c)
+    for kappa in (0.3, 0.8, 1.0):
+        assert np.allclose(O.pbd_damp(x, v, kappa), v, atol=1e-11 * np.abs(v).max())
+
+
+def test_pbd_damping_conserves_linear_and_angular_momentum():
+    """sum v and sum (x - x_cm) x v (equal masses) are unchanged for any kappa."""
+    ct, x, rng = _cloud(32)
+    v = rng.normal(size=x.shape)
+    xcm = x.mean(axis=1, keepdims=True)
+    for kappa in (0.5, 0.9):
+        vd = O.pbd_damp(x, v, kappa)
+        assert np.allclose(vd.sum(axis=1), v.sum(axis=1), atol=1e-10)
+        assert np.allclose(np.cross(x - xcm, vd).sum(axis=1), np.cross(x - xcm, v).sum(axis=1),
+                           atol=1e-9)
+        # and the non-rigid part shrinks by exactly 1 - kappa
+        rig = O.pbd_damp(x, v, 1.0)
+        assert np.allclose(vd - rig, (1 - kappa) * (v - rig), atol=1e-10)
+
+
+def test_pbd_angular_velocity_is_the_least_squares_rigid_fit():
+    """w = I^-1 L is the angular velocity of the least-squares rigid fit of v, found here
+    independently with a generic least-squares solve of v - v_cm = w x r = -[r]_x w."""
+    ct, x, rng = _cloud(33, kind=I.PLT, n_cells=2)
+    v = rng.normal(size=x.shape)
+    vcm, w, xcm = O.rigid_velocity_fit(x, v)
+    for c in range(x.shape[0]):
+        r = x[c] - x[c].mean(axis=0)
+        A = np.zeros((3 * ct.n, 3))
+        for i in range(ct.n):
+            rx, ry, rz = r[i]
+            A[3 * i:3 * i + 3] = -np.array([[0, -rz, ry], [rz, 0, -rx], [-ry, rx, 0]])
+        b = (v[c] - v[c].mean(axis=0)).ravel()
+        w_ls = np.linalg.lstsq(A, b, rcond=None)[0]
+        assert np.allclose(w[c], w_ls, rtol=1e-10, atol=1e-12)
+        assert np.allclose(vcm[c], v[c].mean(axis=0))
+
+
+def test_pbd_damping_with_kappa_one_is_idempotent():
+    ct, x, rng = _cloud(34)
+    v = rng.normal(size=x.shape)
+    v1 = O.pbd_damp(x, v, 1.0)
+    assert np.allclose(O.pbd_damp(x, v1, 1.0), v1, atol=1e-11)
+    assert np.allclose(O.pbd_damp(x, v1, 0.6), v1, atol=1e-11)
+
+
+def test_damped_step_conserves_linear_momentum_and_reduces_to_undamped():
+    """With kappa = 0 the step is the undamped one; with kappa > 0 the prediction's
+    velocity keeps sum m v, so sum m (x_{n+1} - x_n) = h sum m v_n + h^2 sum F still holds."""
+    x0, t0, mat = I.cell_type_inputs()[I.RBC]
+    ct0 = O.CellType(x0, t0, mat, I.DT)
+    ctk = O.CellType(x0, t0, mat.with_kappa(0.8), I.DT)
+    ctz = O.CellType(x0, t0, mat.with_kappa(0.0), I.DT)
+    rng = np.random.default_rng(35)
+    x = ct0.X[None] + 0.05 * rng.normal(size=(1,) + ct0.X.shape)
+    v = rng.normal(size=x.shape)
+    f = 50 * rng.normal(size=x.shape)
+    xa, _ = O.step(ct0, x, v, f, 5)
+    xz, _ = O.step(ctz, x, v, f, 5)
+    assert np.array_equal(xa, xz)
+    xk, vk = O.step(ctk, x, v, f, 5)
+    lhs = ctk.mass * (xk - x).sum(axis=1)
+    rhs = ctk.h * ctk.mass * v.sum(axis=1) + ctk.h ** 2 * f.sum(axis=1)
+    assert np.allclose(lhs, rhs, rtol=1e-10, atol=1e-10 * np.abs(rhs).max())
+    assert np.abs(xk - xa).max() > 1e-4        # damping changes the result
