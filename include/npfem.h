@@ -60,6 +60,10 @@ typedef struct {
   double k_vol;         /* pN/um: volume-constraint weight per vertex                      */
   double strain_min;    /* singular-value clamp of the strain projection (1, 1 = polar)    */
   double strain_max;
+  double pbd_kappa;     /* position-based velocity damping in [0, 1] (0 = off): per cell,   */
+                        /* v_n -> v_n + kappa (v_cm + w x r - v_n) before the prediction,   */
+                        /* keeping the rigid part (centre-of-mass velocity v_cm, angular     */
+                        /* velocity w about the centre of mass) of the velocity field        */
 } npfem_material;
 
 typedef struct npfem_celltype npfem_celltype;   /* opaque, library-owned */

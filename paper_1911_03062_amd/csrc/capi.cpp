@@ -112,7 +112,7 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   p.h = ct->h; p.mass = ct->mass; p.inv_h2m = ct->mass / (ct->h * ct->h);
   p.h2_over_m = ct->h * ct->h / ct->mass;
   p.w_s = ct->w_s; p.w_a = ct->w_a; p.w_b = ct->w_b; p.w_v = ct->w_v;
-  p.s_min = ct->s_min; p.s_max = ct->s_max; p.V0 = ct->V0;
+  p.s_min = ct->s_min; p.s_max = ct->s_max; p.V0 = ct->V0; p.kappa = ct->kappa;
 
   npfem_status st = NPFEM_OK;
   auto chk = [&](npfem_status s) { if (st == NPFEM_OK) st = s; };
@@ -330,7 +330,8 @@ npfem_status relayout(npfem_batch* b) {
     if (st != NPFEM_OK) return st;
     HIP_TRY(hipMemcpy(b->d_types + ti, &v, sizeof(DevType), hipMemcpyHostToDevice));
     const int cap = kFusedWaves * t->layouts[b->layout_of[ti]].gw;
-    b->lds_bytes = std::max(b->lds_bytes, (size_t)2 * cap * 3 * t->npad * sizeof(float));
+    const size_t per_cell = (2 * 3 * (size_t)t->npad + (t->kappa > 0.0 ? kDampWords : 0)) * sizeof(float);
+    b->lds_bytes = std::max(b->lds_bytes, (size_t)cap * per_cell);
   }
   std::vector<FusedGroup> groups;
   build_groups(b, nullptr, b->n_cells, groups);

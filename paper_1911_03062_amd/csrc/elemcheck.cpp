@@ -45,6 +45,46 @@ void npfem_check_triangle(const double* p, const double* g, double area, double 
   if (precision == 64) tri<double>(p, g, area, w_s, w_a, s_min, s_max, out);
   else tri<float>(p, g, area, w_s, w_a, s_min, s_max, out);
 }
+// Position-based damping of one cell with the kernels' helpers: x, v [n][3]; out [n][3] damped
+// velocities. Two passes in FP64 (centre of mass, then momentum and inertia), as the kernels.
+void npfem_check_pbd(const double* x, const double* v, int n, double kappa, double* out) {
+  double xc[3] = {0, 0, 0}, vc[3] = {0, 0, 0};
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      xc[d] += x[3 * i + d];
+      vc[d] += v[3 * i + d];
+    }
+  for (int d = 0; d < 3; ++d) {
+    xc[d] /= n;
+    vc[d] /= n;
+  }
+  double Isym[6] = {0, 0, 0, 0, 0, 0}, Lm[3] = {0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    const double r[3] = {x[3 * i] - xc[0], x[3 * i + 1] - xc[1], x[3 * i + 2] - xc[2]};
+    const double* u = v + 3 * i;
+    Lm[0] += r[1] * u[2] - r[2] * u[1];
+    Lm[1] += r[2] * u[0] - r[0] * u[2];
+    Lm[2] += r[0] * u[1] - r[1] * u[0];
+    const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    Isym[0] += rr - r[0] * r[0];
+    Isym[1] += rr - r[1] * r[1];
+    Isym[2] += rr - r[2] * r[2];
+    Isym[3] -= r[0] * r[1];
+    Isym[4] -= r[0] * r[2];
+    Isym[5] -= r[1] * r[2];
+  }
+  double w[3];
+  solve_sym3(Isym, Lm, w);
+  for (int i = 0; i < n; ++i) {
+    const Vec3<double> r = v3<double>(x[3 * i] - xc[0], x[3 * i + 1] - xc[1], x[3 * i + 2] - xc[2]);
+    const Vec3<double> o = pbd_velocity<double>(v3<double>(v[3 * i], v[3 * i + 1], v[3 * i + 2]), r,
+                                                v3<double>(vc[0], vc[1], vc[2]),
+                                                v3<double>(w[0], w[1], w[2]), kappa);
+    out[3 * i] = o.x;
+    out[3 * i + 1] = o.y;
+    out[3 * i + 2] = o.z;
+  }
+}
 // p: [4][3] positions i, j, k, l; a: stencil [4]; out: [4][3] contributions.
 void npfem_check_hinge(const double* p, const double* a, double rest, double w_b, double* out,
                        int precision) {

@@ -268,8 +268,17 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const float w_v = (float)T.p.w_v, ih = (float)(1.0 / T.p.h);
     if (tid < count) off_lds[tid] = offsets[grp.cells[tid]];
     __syncthreads();
+    // element-phase lane mapping: cell cw = lane / S, slot s = lane % S
+    const int e_cw = lane / S, e_s = lane - e_cw * S;
+    const int e_gc = wave * gw + e_cw;
+    const bool e_ok = e_gc < count;
     // e = delta - delta^0 is the only per-vertex state kept in registers; delta^0 is
-    // recomputed from v and F when the step is written back
+    // recomputed from v and F when the step is written back. With position-based damping
+    // each cell's centre of mass x_cm, its velocity v_cm, angular velocity w and first vertex
+    // x_n[0] (kDampWords floats per cell after R) define the damped velocity used in delta^0.
+    const bool damp = T.p.kappa > 0.0;
+    const float kappa = (float)T.p.kappa;
+    float* Dm = R + G4 * CS;
     float e[NQ][3];
 #pragma unroll
     for (int it = 0; it < NQ; ++it) {
@@ -279,20 +288,86 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         const int64_t off = off_lds[ITEM_C(it)];
         const int vi = ITEM_V(it);
         float* Xv = X + ITEM_W(it);
+        float* Rv = R + ITEM_W(it);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float dd = h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi];
           // cell-local coordinates: positions relative to the cell's first vertex
-          Xv[c] = (x[c * vt + off + vi] - x[c * vt + off]) + dd;
+          const float xl = x[c * vt + off + vi] - x[c * vt + off];
+          if (damp) {
+            Xv[c] = xl;                       // x_n and v_n staged for the reductions
+            Rv[c] = v[c * vt + off + vi];
+            if (vi == 0) Dm[kDampWords * ITEM_C(it) + 9 + c] = x[c * vt + off];
+          } else {
+            Xv[c] = xl + (h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi]);
+          }
         }
       }
     }
+    if (damp) {
+      __builtin_amdgcn_wave_barrier();
+      // per cell, over its lanes: centre of mass and its velocity, then angular momentum and
+      // inertia about it (FP64 sums), w = I^-1 L; all cells of the wave at once
+      const float* Xe0 = X + e_gc * CS;
+      const float* Re0 = R + e_gc * CS;
+      double sm[6] = {0, 0, 0, 0, 0, 0};
+      if (e_ok)
+        for (int vv = e_s; vv < n; vv += S) {
+          const Vec3<float> a = ld3(Xe0 + 3 * vv), b = ld3(Re0 + 3 * vv);
+          sm[0] += a.x; sm[1] += a.y; sm[2] += a.z;
+          sm[3] += b.x; sm[4] += b.y; sm[5] += b.z;
+        }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        for (int o = S >> 1; o > 0; o >>= 1) sm[k] += __shfl_xor(sm[k], o, 64);
+        sm[k] /= n;
+      }
+      double q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // L (3), I (xx, yy, zz, xy, xz, yz)
+      if (e_ok)
+        for (int vv = e_s; vv < n; vv += S) {
+          const Vec3<float> a = ld3(Xe0 + 3 * vv), b = ld3(Re0 + 3 * vv);
+          const double r0 = (double)a.x - sm[0], r1 = (double)a.y - sm[1], r2 = (double)a.z - sm[2];
+          q[0] += r1 * b.z - r2 * b.y;
+          q[1] += r2 * b.x - r0 * b.z;
+          q[2] += r0 * b.y - r1 * b.x;
+          const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+          q[3] += rr - r0 * r0; q[4] += rr - r1 * r1; q[5] += rr - r2 * r2;
+          q[6] -= r0 * r1; q[7] -= r0 * r2; q[8] -= r1 * r2;
+        }
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        for (int o = S >> 1; o > 0; o >>= 1) q[k] += __shfl_xor(q[k], o, 64);
+      if (e_ok && e_s == 0) {
+        double wv[3];
+        solve_sym3(q + 3, q, wv);
+        float* d = Dm + kDampWords * e_gc;
+        d[0] = (float)sm[0]; d[1] = (float)sm[1]; d[2] = (float)sm[2];
+        d[3] = (float)sm[3]; d[4] = (float)sm[4]; d[5] = (float)sm[5];
+        d[6] = (float)wv[0]; d[7] = (float)wv[1]; d[8] = (float)wv[2];
+      }
+      __builtin_amdgcn_wave_barrier();
+      // delta^0 with the damped velocity; R back to zero
+#pragma unroll
+      for (int it = 0; it < NQ; ++it)
+        if (ITEM_OK(it)) {
+          const int64_t off = off_lds[ITEM_C(it)];
+          const int vi = ITEM_V(it);
+          float* Xv = X + ITEM_W(it);
+          float* Rv = R + ITEM_W(it);
+          const float* d = Dm + kDampWords * ITEM_C(it);
+          const Vec3<float> xl = ld3(Xv);
+          const Vec3<float> vd = pbd_velocity<float>(ld3(Rv), xl - v3<float>(d[0], d[1], d[2]),
+                                                     v3<float>(d[3], d[4], d[5]),
+                                                     v3<float>(d[6], d[7], d[8]), kappa);
+          const float vdc[3] = {vd.x, vd.y, vd.z};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            Xv[c] += h * vdc[c] + h2m * f[c * vt + off + vi];
+            Rv[c] = 0.0f;
+          }
+        }
+    }
     __syncthreads();   // R zeroed, X written
 
-    // element-phase lane mapping: cell cw = lane / S, slot s = lane % S
-    const int e_cw = lane / S, e_s = lane - e_cw * S;
-    const int e_gc = wave * gw + e_cw;
-    const bool e_ok = e_gc < count;
     const float* Xe = X + e_gc * CS;
     float* Re = R + e_gc * CS;
     const float w_s = (float)T.p.w_s, w_a = (float)T.p.w_a, w_b = (float)T.p.w_b;
@@ -585,7 +660,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       }
     }
-    // ---- x_{n+1} = x_n + delta, v_{n+1} = delta / h with delta = delta^0 + e
+    // ---- x_{n+1} = x_n + delta, v_{n+1} = delta / h with delta = delta^0 + e (delta^0
+    //      recomputed exactly as at the start of the step; with damping the cell's first
+    //      vertex x_n[0] comes from LDS, since its owner may already have overwritten it)
     refresh_items(item);
     bool bad = false;
 #pragma unroll
@@ -593,10 +670,25 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       if (ITEM_OK(it)) {
         const int64_t off = off_lds[ITEM_C(it)];
         const int vi = ITEM_V(it);
+        float vin[3], xin[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float dl = (h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi]) + e[it][c];
-          const float xn = x[c * vt + off + vi] + dl;
+          vin[c] = v[c * vt + off + vi];
+          xin[c] = x[c * vt + off + vi];
+        }
+        if (damp) {
+          const float* d = Dm + kDampWords * ITEM_C(it);
+          const Vec3<float> xl = v3<float>(xin[0] - d[9], xin[1] - d[10], xin[2] - d[11]);
+          const Vec3<float> vd = pbd_velocity<float>(v3<float>(vin[0], vin[1], vin[2]),
+                                                     xl - v3<float>(d[0], d[1], d[2]),
+                                                     v3<float>(d[3], d[4], d[5]),
+                                                     v3<float>(d[6], d[7], d[8]), kappa);
+          vin[0] = vd.x; vin[1] = vd.y; vin[2] = vd.z;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float dl = (h * vin[c] + h2m * f[c * vt + off + vi]) + e[it][c];
+          const float xn = xin[c] + dl;
           const float vn = dl * ih;
           x[c * vt + off + vi] = xn;
           v[c * vt + off + vi] = vn;

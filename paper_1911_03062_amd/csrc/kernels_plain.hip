@@ -71,18 +71,62 @@ __device__ inline Vec3<T> cell_pos(const T* x, int64_t vt, int64_t off, const T*
                (x[2 * vt + off + i] - x[2 * vt + off]) + d[2 * n + i]);
 }
 
+// delta^0 = h v_n + h^2 F/m, with v_n first damped (position-based damping) when kappa > 0:
+// centre of mass and its velocity, then angular momentum and inertia about it (positions
+// relative to the cell's first vertex, FP64 block sums), w = I^-1 L.
 template <typename T>
 __global__ void __launch_bounds__(kPlainThreads)
-k_plain_predict(TypeParams p, const T* __restrict__ v, const T* __restrict__ f, int64_t vt,
-                int64_t off, void* work) {
+k_plain_predict(TypeParams p, const T* __restrict__ x, const T* __restrict__ v,
+                const T* __restrict__ f, int64_t vt, int64_t off, void* work) {
   PlainWork<T> w = plain_layout<T>(work, p.n, p.m, p.e);
   const T h = T(p.h), h2m = T(p.h2_over_m);
-  for (int i = threadIdx.x; i < p.n; i += blockDim.x)
-    for (int c = 0; c < 3; ++c) {
-      const T d0 = h * v[c * vt + off + i] + h2m * f[c * vt + off + i];
-      w.d0[c * p.n + i] = d0;
-      w.d[c * p.n + i] = d0;
+  const int n = p.n;
+  __shared__ double sh[8];
+  auto xl = [&](int i) {
+    return v3<T>(x[off + i] - x[off], x[vt + off + i] - x[vt + off],
+                 x[2 * vt + off + i] - x[2 * vt + off]);
+  };
+  auto vel = [&](int i) { return v3<T>(v[off + i], v[vt + off + i], v[2 * vt + off + i]); };
+  Vec3<T> vcm = v3<T>(0, 0, 0), xcm = vcm, om = vcm;
+  const bool damp = p.kappa > 0.0;
+  if (damp) {
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const Vec3<T> a = xl(i), b = vel(i);
+      s[0] += a.x; s[1] += a.y; s[2] += a.z;
+      s[3] += b.x; s[4] += b.y; s[5] += b.z;
     }
+    double c[6];
+    for (int k = 0; k < 6; ++k) c[k] = block_sum(s[k], sh) / n;
+    double q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // L (3), I (xx, yy, zz, xy, xz, yz)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const Vec3<T> a = xl(i), b = vel(i);
+      const double r0 = (double)a.x - c[0], r1 = (double)a.y - c[1], r2 = (double)a.z - c[2];
+      q[0] += r1 * b.z - r2 * b.y;
+      q[1] += r2 * b.x - r0 * b.z;
+      q[2] += r0 * b.y - r1 * b.x;
+      const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+      q[3] += rr - r0 * r0; q[4] += rr - r1 * r1; q[5] += rr - r2 * r2;
+      q[6] -= r0 * r1; q[7] -= r0 * r2; q[8] -= r1 * r2;
+    }
+    double t[9];
+    for (int k = 0; k < 9; ++k) t[k] = block_sum(q[k], sh);
+    double wv[3];
+    solve_sym3(t + 3, t, wv);
+    xcm = v3<T>(T(c[0]), T(c[1]), T(c[2]));
+    vcm = v3<T>(T(c[3]), T(c[4]), T(c[5]));
+    om = v3<T>(T(wv[0]), T(wv[1]), T(wv[2]));
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    Vec3<T> vi = vel(i);
+    if (damp) vi = pbd_velocity<T>(vi, xl(i) - xcm, vcm, om, T(p.kappa));
+    const T vv[3] = {vi.x, vi.y, vi.z};
+    for (int c = 0; c < 3; ++c) {
+      const T d0 = h * vv[c] + h2m * f[c * vt + off + i];
+      w.d0[c * n + i] = d0;
+      w.d[c * n + i] = d0;
+    }
+  }
 }
 
 template <typename T>
@@ -265,8 +309,8 @@ template <typename T>
 hipError_t plain_step_t(const DevType* dt_dev, const TypeParams& p, T* x, T* v, const T* f,
                         int64_t vt, int64_t off, int K, void* work, double* vol_area, int* flag,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_plain_predict<T>, dim3(1), dim3(kPlainThreads), 0, s, p, v, f, vt, off,
-                     work);
+  hipLaunchKernelGGL(k_plain_predict<T>, dim3(1), dim3(kPlainThreads), 0, s, p, x, v, f, vt,
+                     off, work);
   for (int k = 0; k < K; ++k) {
     hipLaunchKernelGGL(k_plain_local<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt, off,
                        work);

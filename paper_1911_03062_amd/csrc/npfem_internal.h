@@ -66,6 +66,7 @@ struct TypeParams {
   double w_s, w_a, w_b, w_v;
   double s_min, s_max;
   double V0;
+  double kappa;                 // position-based damping factor (0 = off)
 };
 
 // Device copy of a cell type's constants. Pointers are device pointers.
@@ -100,7 +101,7 @@ struct DevType {
 struct npfem_celltype {
   int n = 0, m = 0, e = 0, bw = 0;
   double h = 0, V0 = 0, area0 = 0, mass = 0;
-  double w_s = 0, w_a = 0, w_b = 0, w_v = 0, s_min = 1, s_max = 1;
+  double w_s = 0, w_a = 0, w_b = 0, w_v = 0, s_min = 1, s_max = 1, kappa = 0;
   std::vector<double> X;          // [n][3]
   std::vector<int32_t> tri;       // [m][3]
   std::vector<double> G;          // [m][3][2]
@@ -157,6 +158,7 @@ struct FusedGroup {
 };
 
 constexpr int kMfmaChunk = 8;               // k steps per prefetched L^-1 chunk
+constexpr int kDampWords = 12;              // LDS floats per cell for position-based damping
 constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
 
 // MFMA output tiles of the global step: each wave takes an equal share of the

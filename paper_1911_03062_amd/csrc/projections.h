@@ -219,4 +219,33 @@ __host__ __device__ __forceinline__ void hinge_residual(Vec3<T> pi, Vec3<T> pj, 
   rl = rl + W * a3;
 }
 
+// Position-based damping (Mueller et al. 2007): the angular velocity of a cell's rigid motion
+// solves I w = L with the inertia tensor I = sum (|r|^2 1 - r r^T) and angular momentum
+// L = sum r x v about the centre of mass (equal masses cancel). Isym = (xx, yy, zz, xy, xz, yz).
+// Solved by the adjugate in FP64; a singular I (all vertices on a line) gives w = 0.
+__host__ __device__ __forceinline__ void solve_sym3(const double Isym[6], const double Lm[3],
+                                                    double w[3]) {
+  const double a = Isym[0], b = Isym[1], c = Isym[2], d = Isym[3], e = Isym[4], f = Isym[5];
+  // [[a, d, e], [d, b, f], [e, f, c]]
+  const double c00 = b * c - f * f, c01 = e * f - d * c, c02 = d * f - b * e;
+  const double c11 = a * c - e * e, c12 = d * e - a * f, c22 = a * b - d * d;
+  const double det = a * c00 + d * c01 + e * c02;
+  if (!(det > 0.0)) {
+    w[0] = w[1] = w[2] = 0.0;
+    return;
+  }
+  const double id = 1.0 / det;
+  w[0] = (c00 * Lm[0] + c01 * Lm[1] + c02 * Lm[2]) * id;
+  w[1] = (c01 * Lm[0] + c11 * Lm[1] + c12 * Lm[2]) * id;
+  w[2] = (c02 * Lm[0] + c12 * Lm[1] + c22 * Lm[2]) * id;
+}
+
+// Damped velocity v + kappa (v_cm + w x r - v) of a vertex at r from the centre of mass.
+template <typename T>
+__host__ __device__ __forceinline__ Vec3<T> pbd_velocity(Vec3<T> v, Vec3<T> r, Vec3<T> vcm,
+                                                         Vec3<T> w, T kappa) {
+  const Vec3<T> rigid = vcm + cross3(w, r);
+  return v + (rigid - v) * kappa;
+}
+
 }  // namespace npfem

@@ -282,7 +282,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   if (n > 65535) return fail(NPFEM_E_UNSUPPORTED, "meshes above 65535 vertices");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_E_INVALID, "dt must be > 0");
   if (!(mat->density > 0) || mat->shear_B < 0 || mat->area_C < 0 || mat->k_bend < 0 ||
-      mat->k_vol < 0 || !(mat->strain_min > 0) || mat->strain_max < mat->strain_min)
+      mat->k_vol < 0 || !(mat->strain_min > 0) || mat->strain_max < mat->strain_min ||
+      !(mat->pbd_kappa >= 0.0 && mat->pbd_kappa <= 1.0))
     return fail(NPFEM_E_INVALID, "material constants out of range");
 
   ct->n = n;
@@ -294,6 +295,7 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   ct->w_v = mat->k_vol;
   ct->s_min = mat->strain_min;
   ct->s_max = mat->strain_max;
+  ct->kappa = mat->pbd_kappa;
   ct->X.assign(mesh->rest_xyz, mesh->rest_xyz + 3 * (size_t)n);
   ct->tri.assign(mesh->tri, mesh->tri + 3 * (size_t)m);
   for (double c : ct->X)
@@ -500,7 +502,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   int npad = std::max((n + 3) / 4 * 4, 4 * kMfmaChunk);
   if ((npad / 4) % 2 == 0) npad += 4;
   ct->npad = npad;
-  const int per_cell = 2 * 3 * npad * 4;  // X and R columns, FP32
+  // X and R columns (FP32), plus the per-cell damping data when the type is damped
+  const int per_cell = 2 * 3 * npad * 4 + (ct->kappa > 0.0 ? kDampWords * 4 : 0);
   std::vector<int> feasible;
   for (int cand : {16, 8, 4, 2, 1}) {
     if (kFusedWaves * cand * per_cell > kFusedLdsBudget) continue;

@@ -38,7 +38,7 @@ class _Mesh(ctypes.Structure):
 class _Material(ctypes.Structure):
     _fields_ = [("density", c_double), ("shear_B", c_double), ("area_C", c_double),
                 ("skalak_D", c_double), ("k_bend", c_double), ("k_vol", c_double),
-                ("strain_min", c_double), ("strain_max", c_double)]
+                ("strain_min", c_double), ("strain_max", c_double), ("pbd_kappa", c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -129,7 +129,8 @@ class CellType:
         mesh = _Mesh(x.shape[0], t.shape[0], x.ctypes.data_as(POINTER(c_double)),
                      t.ctypes.data_as(POINTER(c_int32)))
         mat = _Material(material.density, material.shear_B, material.area_C, material.skalak_D,
-                        material.k_bend, material.k_vol, material.strain_min, material.strain_max)
+                        material.k_bend, material.k_vol, material.strain_min, material.strain_max,
+                        float(getattr(material, "pbd_kappa", 0.0)))
         h = c_void_p()
         _check(lib().npfem_create_celltype(ctypes.byref(mesh), ctypes.byref(mat), float(dt),
                                            ctypes.byref(h)))

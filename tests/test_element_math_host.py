@@ -137,3 +137,20 @@ def test_vertex_roles_are_interchangeable(lib, kind):
             back = np.empty((4, 3))
             back[idx] = out.reshape(4, 3)
             assert np.abs(back - href[h]).max() <= 1e-10 * hscale, (h, perm)
+
+
+def test_pbd_damping_helpers_match_oracle(lib):
+    """The kernels' damping helpers (3x3 adjugate solve of I w = L, damped velocity), in a
+    host build with FP64 sums, against the oracle's position-based damping."""
+    lib.npfem_check_pbd.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp]
+    rng = np.random.default_rng(44)
+    for kind in (I.RBC, I.PLT):
+        x0, t, m = I.cell_type_inputs()[kind]
+        x = x0 + 0.1 * rng.normal(size=x0.shape) + 30.0
+        v = rng.normal(size=x0.shape) + np.cross(rng.normal(size=3), x0)
+        for kappa in (0.5, 0.9):
+            ref = O.pbd_damp(x[None], v[None], kappa)[0]
+            out = np.zeros_like(v)
+            lib.npfem_check_pbd(_ptr(np.ascontiguousarray(x)), _ptr(np.ascontiguousarray(v)),
+                                x.shape[0], kappa, _ptr(out))
+            assert np.abs(out - ref).max() <= 1e-10 * np.abs(ref).max(), (kind, kappa)

@@ -1,0 +1,61 @@
+"""Position-based velocity damping on the GPU (both forms) against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import npfem_inputs as I
+import oracle as O
+from _runners import cell_errors, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = {I.RBC: 0.8, I.PLT: 0.5}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _types():
+    from paper_1911_03062_amd import npfem as N
+    inp = I.cell_type_inputs()
+    lt = {k: N.CellType(x, t, m.with_kappa(KAPPA[k]), I.DT) for k, (x, t, m) in inp.items()}
+    ot = {k: O.CellType(x, t, m.with_kappa(KAPPA[k]), I.DT) for k, (x, t, m) in inp.items()}
+    return lt, ot
+
+
+@pytest.mark.parametrize("form", ["fused", "plain"])
+def test_damped_mixed_batch(form):
+    lt, ot = _types()
+    tids = np.array([I.RBC] * 5 + [I.PLT] * 9, dtype=np.int32)
+    tids = tids[np.random.default_rng(131).permutation(len(tids))]
+    b = I.make_batch(tids, seed=131)
+    rng = np.random.default_rng(132)
+    v0 = rng.normal(0, 0.05, size=b.x0.shape).astype(np.float32).astype(np.float64)
+    forces = list(I.force_stream(b, seed=133, sigma=20.0, n_steps=6))
+    _say(f"case: {form} damped batch 5 RBC (kappa 0.8) + 9 PLT (0.5), 6 steps")
+    xo, vo = run_oracle(ot, b.types, b.offsets, b.x0, v0, forces, 10)
+    xg, vg = run_gpu(lt, b.types, b.x0, v0, forces, 10, form=form)
+    err = cell_errors(b.types, b.offsets, xg, xo)
+    # the damping must matter at this scale: compare with the undamped oracle
+    xu, _ = run_oracle({k: O.CellType(x, t, m, I.DT) for k, (x, t, m) in I.cell_type_inputs().items()},
+                       b.types, b.offsets, b.x0, v0, forces, 10)
+    sep = cell_errors(b.types, b.offsets, xu, xo)
+    _say(f"{form} damped: max err/diam {err.max():.3e}; damped vs undamped {sep.min():.3e}")
+    assert err.max() <= 1e-5
+    assert sep.min() > 100 * err.max()
+
+
+def test_damped_kicked_step_fused():
+    lt, ot = _types()
+    b = I.make_batch([I.RBC], seed=141, identity=True)
+    rng = np.random.default_rng(142)
+    v0 = rng.normal(0, 0.2, size=b.x0.shape).astype(np.float32).astype(np.float64)
+    f = [rng.normal(0, 200.0, size=b.x0.shape).astype(np.float32).astype(np.float64)]
+    xo, _ = run_oracle(ot, b.types, b.offsets, b.x0, v0, f, 10)
+    xg, _ = run_gpu(lt, b.types, b.x0, v0, f, 10)
+    err = cell_errors(b.types, b.offsets, xg, xo)[0]
+    _say(f"fused damped kicked step: err/diam {err:.3e}")
+    assert err <= 1e-7
