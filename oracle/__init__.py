@@ -5,4 +5,6 @@ from .npfem_oracle import (CellType, step, step_batch, predict, gradient, pd_rhs
                            triangle_projections, triangle_rest_frames, bending_stencils,
                            bending_vectors, bending_projection, volume_projection,
                            deformation_gradients, interior_edges, system_matrix,
-                           cell_volume_area, pbd_damp, rigid_velocity_fit)
+                           cell_volume_area, pbd_damp, rigid_velocity_fit,
+                           one_ring_neighbours, median_filter_forces, median_filter_batch,
+                           cap_velocities)

@@ -414,15 +414,52 @@ def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
 
 
 # ----------------------------------------------------------------------------------------
+# Boundary filters of the coupling (Fluid-structure interaction subsection): median filter of
+# the external forces over each vertex's one ring, and capping of the vertex velocities.
+# ----------------------------------------------------------------------------------------
+
+
+def one_ring_neighbours(tri, n):
+    """Sorted neighbour lists (vertices sharing an edge) of every vertex."""
+    nb = [set() for _ in range(n)]
+    for a, b, c in np.asarray(tri):
+        nb[a].update((b, c))
+        nb[b].update((a, c))
+        nb[c].update((a, b))
+    return [sorted(s) for s in nb]
+
+
+def median_filter_forces(f, ct):
+    """Component-wise median of F_ext over each vertex and its one-ring neighbours (the
+    median of an even count is the mean of the two middle values). f: [N][n][3]."""
+    nbs = one_ring_neighbours(ct.tri, ct.n)
+    out = np.empty_like(f)
+    for i, nb in enumerate(nbs):
+        out[:, i, :] = np.median(f[:, [i] + nb, :], axis=1)
+    return out
+
+
+def cap_velocities(v, v_max: float):
+    """Vertex velocities longer than v_max are scaled back to length v_max (direction kept);
+    v_max <= 0 leaves them unchanged."""
+    if v_max <= 0:
+        return v
+    s = np.linalg.norm(v, axis=-1, keepdims=True)
+    return np.where(s > v_max, v * (v_max / np.maximum(s, 1e-300)), v)
+
+
+# ----------------------------------------------------------------------------------------
 # Batch helpers: SoA [3][V_total] arrays with cells of mixed types.
 # ----------------------------------------------------------------------------------------
 
 
-def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=None):
+def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=None,
+               v_cap: float = 0.0):
     """Advance the listed cells (default: all) of a SoA batch; returns new (x, v) copies.
 
     cell_types maps type id -> CellType; x, v, f are float64 [3][V_total].
-    Cells of the same type are stepped together (they are independent).
+    Cells of the same type are stepped together (they are independent). v_cap > 0 caps the
+    new velocities (cap_velocities).
     """
     types = np.asarray(types)
     offsets = np.asarray(offsets)
@@ -437,9 +474,25 @@ def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=No
         vs = np.transpose(v[:, idx], (1, 2, 0))
         fs = np.transpose(f[:, idx], (1, 2, 0))
         xn, vn = step(ct, xs, vs, fs, n_iters)
+        vn = cap_velocities(vn, v_cap)
         xo[:, idx] = np.transpose(xn, (2, 0, 1))
         vo[:, idx] = np.transpose(vn, (2, 0, 1))
     return xo, vo
+
+
+def median_filter_batch(cell_types: dict, types, offsets, f):
+    """median_filter_forces of every cell of a SoA batch; returns a new [3][V_total] array."""
+    types = np.asarray(types)
+    offsets = np.asarray(offsets)
+    out = f.copy()
+    for t, ct in cell_types.items():
+        sel = np.nonzero(types == t)[0]
+        if sel.size == 0:
+            continue
+        idx = offsets[sel][:, None] + np.arange(ct.n)[None, :]
+        fs = np.transpose(f[:, idx], (1, 2, 0))
+        out[:, idx] = np.transpose(median_filter_forces(fs, ct), (2, 0, 1))
+    return out
 
 
 def cell_volume_area(cell_types: dict, types, offsets, x, cells=None):

@@ -505,3 +505,47 @@ def test_damped_step_conserves_linear_momentum_and_reduces_to_undamped():
     rhs = ctk.h * ctk.mass * v.sum(axis=1) + ctk.h ** 2 * f.sum(axis=1)
     assert np.allclose(lhs, rhs, rtol=1e-10, atol=1e-10 * np.abs(rhs).max())
     assert np.abs(xk - xa).max() > 1e-4        # damping changes the result
+
+
+# ------------------------------------------------- boundary filters: median of F, velocity cap
+
+
+def test_median_filter_constant_field_and_isolated_spike():
+    """A constant force field passes unchanged; a spike on one vertex (all others zero) is
+    removed everywhere, since no closed one ring holds it more than once."""
+    ct = _ct(I.RBC)
+    f = np.broadcast_to(np.array([1.5, -2.0, 0.25]), (1, ct.n, 3)).copy()
+    assert np.array_equal(O.median_filter_forces(f, ct), f)
+    g = np.zeros((1, ct.n, 3))
+    g[0, 37] = [1e3, -5e2, 7e2]
+    assert np.array_equal(O.median_filter_forces(g, ct), np.zeros_like(g))
+
+
+def test_median_filter_brute_force_small_meshes():
+    """On the octahedron each vertex's closed ring has 5 members (odd count), on the
+    tetrahedron 4 (even: mean of the two middle values); compared with a sort done here."""
+    rng = np.random.default_rng(41)
+    for mesh_fn in (I.octahedron, I.tetrahedron):
+        x, t = mesh_fn()
+        ct = O.CellType(x, t, I.RBC_MATERIAL, I.DT)
+        f = rng.normal(size=(2, ct.n, 3))
+        out = O.median_filter_forces(f, ct)
+        for i in range(ct.n):
+            members = {i} | {int(u) for tr in t for u in tr if i in tr}
+            vals = np.sort(f[:, sorted(members), :], axis=1)
+            k = len(members)
+            ref = vals[:, k // 2, :] if k % 2 else 0.5 * (vals[:, k // 2 - 1, :] + vals[:, k // 2, :])
+            assert np.allclose(out[:, i, :], ref), (mesh_fn.__name__, i)
+
+
+def test_velocity_cap():
+    rng = np.random.default_rng(42)
+    v = rng.normal(size=(2, 50, 3)) * 3
+    c = O.cap_velocities(v, 2.0)
+    s, sc = np.linalg.norm(v, axis=-1), np.linalg.norm(c, axis=-1)
+    assert np.all(sc <= 2.0 + 1e-12)
+    assert np.array_equal(c[s <= 2.0], v[s <= 2.0])
+    fast = s > 2.0
+    # direction kept
+    assert np.allclose(c[fast] / sc[fast][:, None], v[fast] / s[fast][:, None])
+    assert np.array_equal(O.cap_velocities(v, 0.0), v)
