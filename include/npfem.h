@@ -64,6 +64,11 @@ typedef struct {
                         /* v_n -> v_n + kappa (v_cm + w x r - v_n) before the prediction,   */
                         /* keeping the rigid part (centre-of-mass velocity v_cm, angular     */
                         /* velocity w about the centre of mass) of the velocity field        */
+  double v_max;         /* um/us, velocity cap (0 = off): after a step, a vertex velocity   */
+                        /* longer than v_max is scaled to length v_max, direction kept       */
+                        /* (positions unchanged); the truncation of the solid velocities     */
+                        /* for a stable immersed-boundary coupling (Fluid-structure          */
+                        /* interaction subsection)                                           */
 } npfem_material;
 
 typedef struct npfem_celltype npfem_celltype;   /* opaque, library-owned */
@@ -208,6 +213,22 @@ npfem_status npfem_graph_create(npfem_batch* batch, void* x, void* v,
 npfem_status npfem_graph_launch(npfem_graph* graph, void* stream);
 /* Release the graph (waits for its replays to finish). NULL is ignored. */
 void npfem_graph_destroy(npfem_graph* graph);
+
+/*
+ * Median filter of external forces (Fluid-structure interaction subsection): for every cell of
+ * the batch and every vertex, each component of the force becomes the median of that
+ * component over the vertex and its one-ring neighbours (vertices sharing an edge with it);
+ * the median of an even count is the mean of the two middle values. Attenuates isolated
+ * spikes of the coupling forces before they enter a step. Asynchronous on `stream`.
+ *   f_in, f_out  device, [3][V_total] of the batch's precision (float 32 / double 64); either
+ *                the same buffer (filtered in place) or non-overlapping.
+ * Buffers are caller-owned and borrowed for the duration of the enqueued work. Every cell of
+ * the batch is filtered, whatever npfem_batch_set_active selected.
+ * Any vertex degree is handled. Errors: NPFEM_E_INVALID (null batch or buffer),
+ * NPFEM_E_UNSUPPORTED (a cell so large that its forces plus one 4-byte index per vertex exceed
+ * 64 KiB: above 4096 vertices in FP32, 2340 in FP64), NPFEM_E_HIP.
+ */
+npfem_status npfem_filter_forces(npfem_batch* batch, const void* f_in, void* f_out, void* stream);
 
 /*
  * Synchronise `stream` and report NPFEM_E_NONFINITE if any step since the last check

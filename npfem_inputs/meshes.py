@@ -137,6 +137,20 @@ def icosahedron(scale: float = 1.0):
     return x, t
 
 
+def bipyramid(k: int, height: float = 1.0):
+    """Two apexes over a regular k-gon (k + 2 vertices): apexes of degree k, equator vertices
+    of degree 4; outward CCW triangles."""
+    ang = 2.0 * np.pi * np.arange(k) / k
+    x = np.concatenate([[[0.0, 0.0, height]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1),
+                        [[0.0, 0.0, -height]]])
+    t = []
+    for i in range(k):
+        a, b = 1 + i, 1 + (i + 1) % k
+        t.append((0, a, b))
+        t.append((k + 1, b, a))
+    return x, np.asarray(t, dtype=np.int32)
+
+
 def mesh_summary(x: np.ndarray, tri: np.ndarray) -> dict:
     """Plain geometric summary used to pin the generated geometry (not solver arithmetic)."""
     a, b, c = x[tri[:, 0]], x[tri[:, 1]], x[tri[:, 2]]

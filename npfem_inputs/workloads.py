@@ -9,6 +9,7 @@ Units: um, us, fg, pN (1 fg um / us^2 = 1 pN). Time step h = 0.1 us.
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -29,7 +30,8 @@ class Material:
 
     shear_B, area_C, skalak_D in pN/um; k_bend in pN um; k_vol in pN/um (per vertex);
     strain_min/max clamp the singular values of the strain projection (1, 1 = polar factor);
-    pbd_kappa in [0, 1] is the position-based damping factor (kappa_damping of the table).
+    pbd_kappa in [0, 1] is the position-based damping factor (kappa_damping of the table);
+    v_max > 0 caps the vertex speed after each step (um/us; 0 = no cap).
     """
     density: float = DENSITY
     shear_B: float = 5.0
@@ -40,15 +42,18 @@ class Material:
     strain_min: float = 1.0
     strain_max: float = 1.0
     pbd_kappa: float = 0.0    # position-based velocity damping (kappa_damping), 0 = off
+    v_max: float = 0.0        # velocity cap, 0 = off
 
     def scaled(self, s: float) -> "Material":
         return Material(self.density, self.shear_B * s, self.area_C * s, self.skalak_D * s,
                         self.k_bend * s, self.k_vol * s, self.strain_min, self.strain_max,
-                        self.pbd_kappa)
+                        self.pbd_kappa, self.v_max)
 
     def with_kappa(self, kappa: float) -> "Material":
-        return Material(self.density, self.shear_B, self.area_C, self.skalak_D, self.k_bend,
-                        self.k_vol, self.strain_min, self.strain_max, kappa)
+        return dataclasses.replace(self, pbd_kappa=kappa)
+
+    def with_v_max(self, v_max: float) -> "Material":
+        return dataclasses.replace(self, v_max=v_max)
 
 
 RBC_MATERIAL = Material()

@@ -26,7 +26,9 @@ w/2 ||A x - p(x)||^2 with exact projections p:
     interior fluid included, npFEM subsection);
   * optional position-based damping of the velocities (npFEM subsection, after Mueller et al.
     2007): per cell the rigid part of v_n is kept and the rest scaled by 1 - kappa, applied
-    to v_n before the prediction (the order of position-based dynamics: damp, then predict).
+    to v_n before the prediction (the order of position-based dynamics: damp, then predict);
+  * optional capping of the new vertex velocities at v_max (the velocity truncation for the
+    stability of the immersed-boundary coupling, Fluid-structure interaction subsection);
 Everything is float64, vectorised over the cells of one type (arrays [N][n][3]).
 """
 from __future__ import annotations
@@ -69,6 +71,7 @@ class CellType:
         self.s_min = float(material.strain_min)
         self.s_max = float(material.strain_max)
         self.kappa = float(getattr(material, "pbd_kappa", 0.0))
+        self.v_max = float(getattr(material, "v_max", 0.0))
 
         self.G, self.area = triangle_rest_frames(X, tri)
         self.hinge, self.coef, self.rest_norm = bending_stencils(X, tri)
@@ -394,7 +397,8 @@ def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
     The iteration starts at x^0 = y and performs ``n_iters`` quasi-Newton updates
     x^{k+1} = x^k - L^-1 grad g(x^k) (form "qn") or the algebraically identical
     projective-dynamics updates x^{k+1} = L^-1 rhs(x^k) (form "pd"). n_iters = 0 returns
-    the prediction. Returns (x_{n+1}, v_{n+1}) with v_{n+1} = (x_{n+1} - x_n)/h.
+    the prediction. Returns (x_{n+1}, v_{n+1}) with v_{n+1} = (x_{n+1} - x_n)/h, capped at
+    the type's v_max when it has one (positions are not changed by the cap).
     """
     x = np.asarray(x, dtype=np.float64)
     y = predict(x, v, f, ct)
@@ -410,7 +414,7 @@ def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
             raise ValueError(form)
         if history is not None:
             history.append(xk.copy())
-    return xk, (xk - x) / ct.h
+    return xk, cap_velocities((xk - x) / ct.h, ct.v_max)
 
 
 # ----------------------------------------------------------------------------------------
@@ -453,13 +457,11 @@ def cap_velocities(v, v_max: float):
 # ----------------------------------------------------------------------------------------
 
 
-def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=None,
-               v_cap: float = 0.0):
+def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=None):
     """Advance the listed cells (default: all) of a SoA batch; returns new (x, v) copies.
 
     cell_types maps type id -> CellType; x, v, f are float64 [3][V_total].
-    Cells of the same type are stepped together (they are independent). v_cap > 0 caps the
-    new velocities (cap_velocities).
+    Cells of the same type are stepped together (they are independent).
     """
     types = np.asarray(types)
     offsets = np.asarray(offsets)
@@ -474,7 +476,6 @@ def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=No
         vs = np.transpose(v[:, idx], (1, 2, 0))
         fs = np.transpose(f[:, idx], (1, 2, 0))
         xn, vn = step(ct, xs, vs, fs, n_iters)
-        vn = cap_velocities(vn, v_cap)
         xo[:, idx] = np.transpose(xn, (2, 0, 1))
         vo[:, idx] = np.transpose(vn, (2, 0, 1))
     return xo, vo

@@ -113,6 +113,7 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   p.h2_over_m = ct->h * ct->h / ct->mass;
   p.w_s = ct->w_s; p.w_a = ct->w_a; p.w_b = ct->w_b; p.w_v = ct->w_v;
   p.s_min = ct->s_min; p.s_max = ct->s_max; p.V0 = ct->V0; p.kappa = ct->kappa;
+  p.v_max = ct->v_max;
 
   npfem_status st = NPFEM_OK;
   auto chk = [&](npfem_status s) { if (st == NPFEM_OK) st = s; };
@@ -127,10 +128,11 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   chk(upload(&d->coef64, ct->coef)); chk(upload(&d->coef32, ct->coef));
   chk(upload(&d->rest64, ct->rest_norm)); chk(upload(&d->rest32, ct->rest_norm));
   chk(upload(&d->cband64, ct->cband)); chk(upload(&d->cband32, ct->cband));
+  // vertex rings: the fused form's volume gradient and the median filter (both forms)
+  chk(upload(&d->ring_info, ct->ring_info));
+  chk(upload(&d->ring_pairs, ct->ring_pairs));
   if (ct->fused_ok) {
     chk(layout_schedules_locked(ct, dev, 0, &d->tri_sched, &d->hinge_sched));
-    chk(upload(&d->ring_info, ct->ring_info));
-    chk(upload(&d->ring_pairs, ct->ring_pairs));
     // L^-1 in MFMA A-operand order: row tile rt, chunk c, step j, lane l -> (row rt*16 + l%16,
     // col 4 s + l/16) with s = s0(c) + j. Chunk c starts at s0(c) = min(c C, KR - C) (C =
     // kMfmaChunk, KR = npad / 4 >= C): the last chunk ends at the last step and overlaps the
@@ -227,7 +229,6 @@ struct npfem_graph {
 struct npfem_batch {
   int n_cells = 0, precision = 32, form = NPFEM_FORM_FUSED, device = 0;
   double dt = 0;
-  std::vector<npfem_celltype*> cell_type;
   std::vector<int64_t> offsets;
   std::vector<npfem_celltype*> types;
   std::vector<int> type_of;                 // per cell, index into types
@@ -251,6 +252,13 @@ struct npfem_batch {
   int ring_cur = -1;                        // -1: the all-cells list is active
   std::vector<char> mark;
   int64_t* d_offsets = nullptr;
+  // median filter of the external forces: blocks of consecutive whole cells
+  int32_t* d_type_of = nullptr;
+  FilterBlock* d_filter_blocks = nullptr;
+  int n_filter_blocks = 0;
+  int filter_net = 8;                       // keys of the kernel's sorting network (8 or 16)
+  size_t filter_lds = 0;
+  std::string filter_reason;                // non-empty: the filter is unavailable
   size_t lds_bytes = 0;
   void* work = nullptr;                     // plain-form workspace
   int* d_flag = nullptr;
@@ -274,6 +282,8 @@ struct npfem_batch {
       if (h_stage_count[i]) (void)hipHostFree(h_stage_count[i]);
     }
     if (d_offsets) (void)hipFree(d_offsets);
+    if (d_type_of) (void)hipFree(d_type_of);
+    if (d_filter_blocks) (void)hipFree(d_filter_blocks);
     if (work) (void)hipFree(work);
     if (d_flag) (void)hipFree(d_flag);
     (void)hipSetDevice(cur);
@@ -353,6 +363,50 @@ npfem_status relayout(npfem_batch* b) {
                       hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_count_all, &b->n_groups, sizeof(int), hipMemcpyHostToDevice));
   b->ring_cur = -1;
+  return NPFEM_OK;
+}
+
+// Work list of the median filter: consecutive whole cells per block, at most kFilterMaxCells
+// cells and kFilterMaxVerts vertices unless one cell alone is larger. The block's forces (and a
+// list of its wide-ring vertices) are staged in LDS, so the largest block must fit in 64 KiB;
+// otherwise the filter is unavailable for the batch, which the filter call reports. The
+// network width is 8 keys (degree <= 7) when at most 1/32 of the vertices have wider closed
+// rings, else 16; wider rings go to the kernel's rank-selection pass.
+npfem_status build_filter_blocks(npfem_batch* b) {
+  std::vector<int64_t> wide_of(b->types.size(), 0);
+  for (size_t ti = 0; ti < b->types.size(); ++ti)
+    for (uint32_t info : b->types[ti]->ring_info) wide_of[ti] += (int)(info & 255u) + 1 > 8;
+  int64_t wide8 = 0;
+  for (int c = 0; c < b->n_cells; ++c) wide8 += wide_of[b->type_of[c]];
+  b->filter_net = 32 * wide8 <= b->offsets.back() ? 8 : 16;
+  std::vector<FilterBlock> blocks;
+  int64_t max_nv = 0;
+  for (int c = 0; c < b->n_cells;) {
+    FilterBlock blk{c, 0};
+    int64_t nv = 0;
+    while (c < b->n_cells && blk.count < kFilterMaxCells) {
+      const int64_t n = b->offsets[c + 1] - b->offsets[c];
+      if (blk.count > 0 && nv + n > kFilterMaxVerts) break;
+      nv += n;
+      ++blk.count;
+      ++c;
+    }
+    max_nv = std::max(max_nv, nv);
+    blocks.push_back(blk);
+  }
+  const size_t el = b->precision == 64 ? 8 : 4;
+  b->filter_lds = (3 * el + sizeof(int)) * (size_t)max_nv;
+  b->n_filter_blocks = (int)blocks.size();
+  if (b->filter_lds > 65536)
+    b->filter_reason = "median filter: a cell's forces exceed 64 KiB of LDS";
+  if (b->n_cells == 0) return NPFEM_OK;
+  std::vector<int32_t> type_of(b->type_of.begin(), b->type_of.end());
+  HIP_TRY(hipMalloc((void**)&b->d_type_of, type_of.size() * sizeof(int32_t)));
+  HIP_TRY(hipMemcpy(b->d_type_of, type_of.data(), type_of.size() * sizeof(int32_t),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc((void**)&b->d_filter_blocks, blocks.size() * sizeof(FilterBlock)));
+  HIP_TRY(hipMemcpy(b->d_filter_blocks, blocks.data(), blocks.size() * sizeof(FilterBlock),
+                    hipMemcpyHostToDevice));
   return NPFEM_OK;
 }
 
@@ -463,6 +517,14 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
       if (hipMemcpy(b->d_types + i, b->dev_types[i], sizeof(DevType), hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(NPFEM_E_HIP, "type table copy"));
   }
+  if (hipMalloc((void**)&b->d_offsets, (n_cells + 1) * sizeof(int64_t)) != hipSuccess ||
+      hipMemcpy(b->d_offsets, b->offsets.data(), (n_cells + 1) * sizeof(int64_t),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(NPFEM_E_NOMEM, "device offsets"));
+  {
+    const npfem_status st = build_filter_blocks(b);
+    if (st != NPFEM_OK) return bail(st);
+  }
   if (form == NPFEM_FORM_PLAIN) {
     size_t wb = 0;
     for (npfem_celltype* t : b->types) wb = std::max(wb, plain_work_bytes(precision, t->n, t->m, t->e));
@@ -479,10 +541,6 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
     const npfem_status st = relayout(b);
     if (st != NPFEM_OK) return bail(st);
     b->mark.assign(n_cells, 0);
-    if (hipMalloc((void**)&b->d_offsets, (n_cells + 1) * sizeof(int64_t)) != hipSuccess ||
-        hipMemcpy(b->d_offsets, b->offsets.data(), (n_cells + 1) * sizeof(int64_t),
-                  hipMemcpyHostToDevice) != hipSuccess)
-      return bail(fail(NPFEM_E_NOMEM, "device offsets"));
   }
   *out = b;
   g_last_error.clear();
@@ -786,6 +844,19 @@ npfem_status npfem_batch_autotune(npfem_batch* b, int32_t n_pd_iters, int32_t re
   if (st != NPFEM_OK) return st;
   if (st2 == NPFEM_OK) g_last_error.clear();
   return st2;
+}
+
+npfem_status npfem_filter_forces(npfem_batch* b, const void* f_in, void* f_out, void* stream) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  if (b->n_cells == 0) return NPFEM_OK;
+  if (!f_in || !f_out) return fail(NPFEM_E_INVALID, "null force buffer");
+  if (!b->filter_reason.empty()) return fail(NPFEM_E_UNSUPPORTED, b->filter_reason);
+  DeviceGuard guard(b->device);
+  const hipError_t e = launch_median_filter(b->precision, b->filter_net, b->d_types, b->d_type_of,
+                                            b->d_offsets, b->d_filter_blocks, b->n_filter_blocks,
+                                            b->offsets.back(), f_in, f_out, b->filter_lds, stream);
+  if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("median filter launch: ") + hipGetErrorString(e));
+  return NPFEM_OK;
 }
 
 npfem_status npfem_batch_check(npfem_batch* b, void* stream) {

@@ -2,6 +2,7 @@
 // step's per-triangle and per-hinge residuals can be checked on the CPU in both precisions.
 #include <hip/hip_runtime.h>
 
+#include "filters.h"
 #include "projections.h"
 
 using namespace npfem;
@@ -84,6 +85,57 @@ void npfem_check_pbd(const double* x, const double* v, int n, double kappa, doub
     out[3 * i + 1] = o.y;
     out[3 * i + 2] = o.z;
   }
+}
+// Median of k (1..16) values with the kernels' sorting network and selection, in the given
+// precision.
+double npfem_check_median(const double* vals, int k, int precision) {
+  if (precision == 64) {
+    double a[16];
+    for (int q = 0; q < 16; ++q) a[q] = q < k ? vals[q] : __builtin_inf();
+    return median_keys<16>(a, k);
+  }
+  if (k <= 8) {
+    float a[8];
+    for (int q = 0; q < 8; ++q) a[q] = q < k ? (float)vals[q] : __builtin_inff();
+    return median_keys<8>(a, k);
+  }
+  float a[16];
+  for (int q = 0; q < 16; ++q) a[q] = q < k ? (float)vals[q] : __builtin_inff();
+  return median_keys<16>(a, k);
+}
+// Median of k values by the kernels' rank selection (the path of wide rings).
+double npfem_check_median_rank(const double* vals, int k, int precision) {
+  if (precision == 64) return median_rank<double>(k, [&](int i) { return vals[i]; });
+  return median_rank<float>(k, [&](int i) { return (float)vals[i]; });
+}
+// Number of 0/1 key vectors of length n (8 or 16) that the sorting network leaves unsorted
+// (zero-one principle: a comparator network sorts every input iff it sorts all 0/1 inputs).
+int npfem_check_sortnet01(int n) {
+  int bad = 0;
+  for (int m = 0; m < (1 << n); ++m) {
+    if (n == 8) {
+      float a[8];
+      for (int q = 0; q < 8; ++q) a[q] = (float)((m >> q) & 1);
+      sort_keys<8>(a);
+      for (int q = 1; q < 8; ++q) bad += a[q - 1] > a[q];
+    } else {
+      float a[16];
+      for (int q = 0; q < 16; ++q) a[q] = (float)((m >> q) & 1);
+      sort_keys<16>(a);
+      for (int q = 1; q < 16; ++q) bad += a[q - 1] > a[q];
+    }
+  }
+  return bad;
+}
+// Velocity cap of one vector with the kernels' helper.
+void npfem_check_cap(double* v, double v_max, int precision) {
+  if (precision == 64) {
+    cap_speed<double>(v[0], v[1], v[2], v_max);
+    return;
+  }
+  float f[3] = {(float)v[0], (float)v[1], (float)v[2]};
+  cap_speed<float>(f[0], f[1], f[2], (float)v_max);
+  for (int q = 0; q < 3; ++q) v[q] = f[q];
 }
 // p: [4][3] positions i, j, k, l; a: stencil [4]; out: [4][3] contributions.
 void npfem_check_hinge(const double* p, const double* a, double rest, double w_b, double* out,

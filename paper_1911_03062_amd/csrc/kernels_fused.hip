@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include "npfem_internal.h"
+#include "filters.h"
 #include "projections.h"
 
 namespace npfem {
@@ -278,6 +279,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     // x_n[0] (kDampWords floats per cell after R) define the damped velocity used in delta^0.
     const bool damp = T.p.kappa > 0.0;
     const float kappa = (float)T.p.kappa;
+    const float v_max = (float)T.p.v_max;
     float* Dm = R + G4 * CS;
     float e[NQ][3];
 #pragma unroll
@@ -660,9 +662,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       }
     }
-    // ---- x_{n+1} = x_n + delta, v_{n+1} = delta / h with delta = delta^0 + e (delta^0
-    //      recomputed exactly as at the start of the step; with damping the cell's first
-    //      vertex x_n[0] comes from LDS, since its owner may already have overwritten it)
+    // ---- x_{n+1} = x_n + delta, v_{n+1} = delta / h capped at v_max, with delta = delta^0 + e
+    //      (delta^0 recomputed exactly as at the start of the step; with damping the cell's
+    //      first vertex x_n[0] comes from LDS, since its owner may already have overwritten it)
     refresh_items(item);
     bool bad = false;
 #pragma unroll
@@ -685,14 +687,20 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
                                                      v3<float>(d[6], d[7], d[8]), kappa);
           vin[0] = vd.x; vin[1] = vd.y; vin[2] = vd.z;
         }
+        float vn[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const float dl = (h * vin[c] + h2m * f[c * vt + off + vi]) + e[it][c];
           const float xn = xin[c] + dl;
-          const float vn = dl * ih;
+          vn[c] = dl * ih;
           x[c * vt + off + vi] = xn;
-          v[c * vt + off + vi] = vn;
-          bad |= !(finite_f(xn) && finite_f(vn));
+          bad |= !finite_f(xn);
+        }
+        cap_speed(vn[0], vn[1], vn[2], v_max);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          v[c * vt + off + vi] = vn[c];
+          bad |= !finite_f(vn[c]);
         }
       }
     if (bad) atomicOr(flag, 1);

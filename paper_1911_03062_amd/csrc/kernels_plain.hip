@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include "npfem_internal.h"
+#include "filters.h"
 #include "projections.h"
 
 namespace npfem {
@@ -291,17 +292,23 @@ k_plain_finalize(const DevType* __restrict__ dtp, T* __restrict__ x, T* __restri
     }
   }
   __syncthreads();
-  const T ih = T(1) / T(p.h);
+  const T ih = T(1) / T(p.h), v_max = T(p.v_max);
   bool bad = false;
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T vn[3];
     for (int c = 0; c < 3; ++c) {
       const T d = w.d[c * n + i];
       const T xn = x[c * vt + off + i] + d;
-      const T vn = d * ih;
+      vn[c] = d * ih;
       x[c * vt + off + i] = xn;
-      v[c * vt + off + i] = vn;
-      bad |= !(finite_val(xn) && finite_val(vn));
+      bad |= !finite_val(xn);
     }
+    cap_speed(vn[0], vn[1], vn[2], v_max);
+    for (int c = 0; c < 3; ++c) {
+      v[c * vt + off + i] = vn[c];
+      bad |= !finite_val(vn[c]);
+    }
+  }
   if (bad) atomicOr(flag, 1);
 }
 

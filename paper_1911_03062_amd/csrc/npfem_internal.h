@@ -67,16 +67,18 @@ struct TypeParams {
   double s_min, s_max;
   double V0;
   double kappa;                 // position-based damping factor (0 = off)
+  double v_max;                 // velocity cap (0 = off)
 };
 
 // Device copy of a cell type's constants. Pointers are device pointers.
 struct DevType {
   TypeParams p;
+  // vertex rings (fused form and median filter): the triangles (i, b, c) around each vertex i
+  uint32_t* ring_info = nullptr;     // [n]: offset << 8 | degree
+  uint32_t* ring_pairs = nullptr;    // [sum deg]: b | c << 16
   // fused form
   TriRec* tri_sched = nullptr;       // [tri_rounds][slots]
   HingeRec* hinge_sched = nullptr;   // [hinge_rounds][slots]
-  uint32_t* ring_info = nullptr;     // [n]: offset << 8 | degree
-  uint32_t* ring_pairs = nullptr;    // [sum deg]: b | c << 16
   float* linv_tiles = nullptr;       // [row_tiles][k_steps][64] MFMA A-operand order
   // plain form (both precisions)
   int32_t* tri = nullptr;            // [m][3]
@@ -102,6 +104,7 @@ struct npfem_celltype {
   int n = 0, m = 0, e = 0, bw = 0;
   double h = 0, V0 = 0, area0 = 0, mass = 0;
   double w_s = 0, w_a = 0, w_b = 0, w_v = 0, s_min = 1, s_max = 1, kappa = 0;
+  double v_max = 0;
   std::vector<double> X;          // [n][3]
   std::vector<int32_t> tri;       // [m][3]
   std::vector<double> G;          // [m][3][2]
@@ -185,7 +188,15 @@ inline NPFEM_HD int mfma_share_items(int col_tiles, int u0, int u1) {
   return items;
 }
 
-// Kernel launchers and sizes (kernels_plain.hip, kernels_fused.hip).
+// Median filter of the external forces: one workgroup per block of consecutive whole cells.
+constexpr int kFilterThreads = 256;
+constexpr int kFilterMaxCells = 32;         // cells per block
+constexpr int kFilterMaxVerts = 2048;       // vertices per block (a larger cell is alone)
+struct FilterBlock {
+  int32_t cell0, count;
+};
+
+// Kernel launchers and sizes (kernels_plain.hip, kernels_fused.hip, kernels_filter.hip).
 size_t plain_work_bytes(int precision, int n, int m, int e);
 bool plain_supported(int n, int bw);
 hipError_t launch_plain_cell(int precision, const DevType* dt_dev, const TypeParams& p, void* x,
@@ -195,5 +206,9 @@ hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedG
                              const int* n_groups_dev, int max_groups, const int64_t* offsets,
                              int64_t vtot, float* x, float* v, const float* f, int K,
                              double* vol_area, int* flag, size_t lds_bytes, void* stream);
+hipError_t launch_median_filter(int precision, int net_keys, const DevType* types,
+                                const int32_t* type_of, const int64_t* offsets,
+                                const FilterBlock* blocks, int n_blocks, int64_t vt,
+                                const void* f, void* out, size_t lds_bytes, void* stream);
 
 }  // namespace npfem

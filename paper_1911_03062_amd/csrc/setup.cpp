@@ -283,7 +283,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_E_INVALID, "dt must be > 0");
   if (!(mat->density > 0) || mat->shear_B < 0 || mat->area_C < 0 || mat->k_bend < 0 ||
       mat->k_vol < 0 || !(mat->strain_min > 0) || mat->strain_max < mat->strain_min ||
-      !(mat->pbd_kappa >= 0.0 && mat->pbd_kappa <= 1.0))
+      !(mat->pbd_kappa >= 0.0 && mat->pbd_kappa <= 1.0) ||
+      !(mat->v_max >= 0.0 && std::isfinite(mat->v_max)))
     return fail(NPFEM_E_INVALID, "material constants out of range");
 
   ct->n = n;
@@ -296,6 +297,7 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   ct->s_min = mat->strain_min;
   ct->s_max = mat->strain_max;
   ct->kappa = mat->pbd_kappa;
+  ct->v_max = mat->v_max;
   ct->X.assign(mesh->rest_xyz, mesh->rest_xyz + 3 * (size_t)n);
   ct->tri.assign(mesh->tri, mesh->tri + 3 * (size_t)m);
   for (double c : ct->X)

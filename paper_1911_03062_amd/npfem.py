@@ -38,7 +38,8 @@ class _Mesh(ctypes.Structure):
 class _Material(ctypes.Structure):
     _fields_ = [("density", c_double), ("shear_B", c_double), ("area_C", c_double),
                 ("skalak_D", c_double), ("k_bend", c_double), ("k_vol", c_double),
-                ("strain_min", c_double), ("strain_max", c_double), ("pbd_kappa", c_double)]
+                ("strain_min", c_double), ("strain_max", c_double), ("pbd_kappa", c_double),
+                ("v_max", c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -83,6 +84,8 @@ def lib() -> ctypes.CDLL:
     L.npfem_batch_set_active.argtypes = [c_void_p, POINTER(c_int32), c_int32, c_void_p]
     L.npfem_batch_set_active.restype = c_int32
     L.npfem_batch_check.argtypes = [c_void_p, c_void_p]
+    L.npfem_filter_forces.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    L.npfem_filter_forces.restype = c_int32
     L.npfem_batch_check.restype = c_int32
     L.npfem_celltype_cells_per_wave.argtypes = [c_void_p, POINTER(c_int32), c_int32]
     L.npfem_celltype_cells_per_wave.restype = c_int32
@@ -130,7 +133,8 @@ class CellType:
                      t.ctypes.data_as(POINTER(c_int32)))
         mat = _Material(material.density, material.shear_B, material.area_C, material.skalak_D,
                         material.k_bend, material.k_vol, material.strain_min, material.strain_max,
-                        float(getattr(material, "pbd_kappa", 0.0)))
+                        float(getattr(material, "pbd_kappa", 0.0)),
+                        float(getattr(material, "v_max", 0.0)))
         h = c_void_p()
         _check(lib().npfem_create_celltype(ctypes.byref(mesh), ctypes.byref(mat), float(dt),
                                            ctypes.byref(h)))
@@ -206,6 +210,21 @@ class Batch:
         s = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().npfem_step(self._h, x.data_ptr(), v.data_ptr(), f.data_ptr(), float(dt),
                                 int(n_pd_iters), c_void_p(s.cuda_stream), c_void_p(va)))
+
+    def filter_forces(self, f_in, f_out=None, stream=None):
+        """One-ring median filter of external forces [3][V_total] into f_out (default: in
+        place); returns f_out."""
+        import torch
+        dtype = torch.float64 if self.precision == 64 else torch.float32
+        f_out = f_in if f_out is None else f_out
+        for name, t in (("f_in", f_in), ("f_out", f_out)):
+            if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()
+                    and tuple(t.shape) == (3, self.vertex_count)):
+                raise ValueError(f"{name} must be a contiguous device tensor [3][{self.vertex_count}] of {dtype}")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_filter_forces(self._h, f_in.data_ptr(), f_out.data_ptr(),
+                                         c_void_p(s.cuda_stream)))
+        return f_out
 
     def _check_state(self, x, v, forces, vol_area):
         import torch

@@ -154,3 +154,60 @@ def test_pbd_damping_helpers_match_oracle(lib):
             lib.npfem_check_pbd(_ptr(np.ascontiguousarray(x)), _ptr(np.ascontiguousarray(v)),
                                 x.shape[0], kappa, _ptr(out))
             assert np.abs(out - ref).max() <= 1e-10 * np.abs(ref).max(), (kind, kappa)
+
+
+def test_sorting_network_sorts_every_zero_one_input(lib):
+    """The filter's compare-exchange network (Batcher's odd-even merge sort) on 8 and 16 keys:
+    by the zero-one principle it sorts every input iff it sorts all 2^n vectors of 0s and 1s."""
+    lib.npfem_check_sortnet01.argtypes = [ctypes.c_int]
+    lib.npfem_check_sortnet01.restype = ctypes.c_int
+    assert lib.npfem_check_sortnet01(8) == 0
+    assert lib.npfem_check_sortnet01(16) == 0
+
+
+def test_median_helper_matches_numpy(lib):
+    """The kernels' median (network + middle selection) against numpy's median, bit for bit in
+    FP64 and, on FP32-rounded inputs, in FP32; odd and even counts, repeated values."""
+    lib.npfem_check_median.argtypes = [dp, ctypes.c_int, ctypes.c_int]
+    lib.npfem_check_median.restype = ctypes.c_double
+    rng = np.random.default_rng(45)
+    for trial in range(400):
+        k = int(rng.integers(1, 17))
+        vals = rng.normal(size=k) * 10.0 ** rng.integers(-3, 4)
+        if trial % 3 == 0:
+            vals = np.round(vals)                      # repeated values
+        vals = np.ascontiguousarray(vals)
+        assert lib.npfem_check_median(_ptr(vals), k, 64) == np.median(vals), (k, vals)
+        v32 = np.ascontiguousarray(vals.astype(np.float32).astype(np.float64))
+        got = np.float32(lib.npfem_check_median(_ptr(v32), k, 32))
+        assert got == np.float32(np.median(v32)), (k, v32)
+
+
+def test_rank_selection_median_matches_numpy(lib):
+    """The wide-ring path (rank selection) against numpy's median, rings of 1 to 40 members."""
+    lib.npfem_check_median_rank.argtypes = [dp, ctypes.c_int, ctypes.c_int]
+    lib.npfem_check_median_rank.restype = ctypes.c_double
+    rng = np.random.default_rng(48)
+    for trial in range(300):
+        k = int(rng.integers(1, 41))
+        vals = rng.normal(size=k) * 100.0
+        if trial % 2 == 0:
+            vals = np.round(vals / 50.0)                # many repeated values
+        vals = np.ascontiguousarray(vals)
+        assert lib.npfem_check_median_rank(_ptr(vals), k, 64) == np.median(vals), (k, vals)
+        v32 = np.ascontiguousarray(vals.astype(np.float32).astype(np.float64))
+        got = np.float32(lib.npfem_check_median_rank(_ptr(v32), k, 32))
+        assert got == np.float32(np.median(v32)), (k, v32)
+
+
+def test_velocity_cap_helper_matches_oracle(lib):
+    lib.npfem_check_cap.argtypes = [dp, ctypes.c_double, ctypes.c_int]
+    rng = np.random.default_rng(46)
+    v = rng.normal(size=(200, 3)) * 2.0
+    for prec, tol in ((64, 1e-15), (32, 3e-7)):
+        for vmax in (0.0, 0.5, 2.0):
+            ref = O.cap_velocities(v, vmax)
+            for i in range(v.shape[0]):
+                w = np.ascontiguousarray(v[i].copy())
+                lib.npfem_check_cap(_ptr(w), vmax, prec)
+                assert np.abs(w - ref[i]).max() <= tol * (1 + np.abs(ref[i]).max()), (prec, vmax, i)

@@ -75,6 +75,8 @@ def test_argument_errors():
     _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(strain_min=1.2, strain_max=1.1)))
     _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(pbd_kappa=1.5)))
     _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(pbd_kappa=-0.1)))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(v_max=-1.0)))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(v_max=float("inf"))))
     _expect("NPFEM_E_MESH", lambda: _create(x[:3], t[:3]))
 
 

@@ -549,3 +549,24 @@ def test_velocity_cap():
     # direction kept
     assert np.allclose(c[fast] / sc[fast][:, None], v[fast] / s[fast][:, None])
     assert np.array_equal(O.cap_velocities(v, 0.0), v)
+
+
+def test_step_caps_velocities_and_keeps_positions():
+    """A type with v_max returns the uncapped step's positions and the uncapped velocities
+    scaled to length v_max where they were longer (a kicked cell moves faster than the cap)."""
+    x0, t, m = I.cell_type_inputs()[I.PLT]
+    ct = O.CellType(x0, t, m, I.DT)
+    ctc = O.CellType(x0, t, m.with_v_max(0.05), I.DT)
+    rng = np.random.default_rng(47)
+    x = x0[None] + 0.02 * rng.normal(size=(1,) + x0.shape)
+    v = 0.05 * rng.normal(size=x.shape)
+    f = 0.0 * x
+    xa, va = O.step(ct, x, v, f, 3)
+    xb, vb = O.step(ctc, x, v, f, 3)
+    assert np.array_equal(xa, xb)
+    s = np.linalg.norm(va, axis=-1)
+    assert np.any(s > 0.05) and np.any(s <= 0.05)
+    assert np.array_equal(vb[s <= 0.05], va[s <= 0.05])
+    fast = s > 0.05
+    assert np.allclose(np.linalg.norm(vb[fast], axis=-1), 0.05, rtol=1e-14)
+    assert np.allclose(vb[fast] * (s[fast] / 0.05)[:, None], va[fast], rtol=1e-12)
