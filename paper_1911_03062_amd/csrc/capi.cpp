@@ -56,7 +56,7 @@ npfem_status fail(npfem_status s, const std::string& msg) {
 void free_devtype(DevType* d) {
   if (!d) return;
   // (schedules belong to the cell type's per-layout cache)
-  void* ptrs[] = {d->ring_info, d->ring_pairs, d->linv_tiles,
+  void* ptrs[] = {d->ring_info, d->ring_pairs, d->ring_nb8, d->ring_nb16, d->linv_tiles,
                   d->tri,       d->hinge,       d->vt_off,    d->vt_list,    d->vh_off,
                   d->vh_list,   d->G64,         d->G32,       d->A64,        d->A32,
                   d->coef64,    d->coef32,      d->rest64,    d->rest32,     d->cband64,
@@ -131,6 +131,8 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   // vertex rings: the fused form's volume gradient and the median filter (both forms)
   chk(upload(&d->ring_info, ct->ring_info));
   chk(upload(&d->ring_pairs, ct->ring_pairs));
+  chk(upload(&d->ring_nb8, ct->ring_nb8));
+  chk(upload(&d->ring_nb16, ct->ring_nb16));
   if (ct->fused_ok) {
     chk(layout_schedules_locked(ct, dev, 0, &d->tri_sched, &d->hinge_sched));
     // L^-1 in MFMA A-operand order: row tile rt, chunk c, step j, lane l -> (row rt*16 + l%16,
@@ -253,7 +255,6 @@ struct npfem_batch {
   std::vector<char> mark;
   int64_t* d_offsets = nullptr;
   // median filter of the external forces: blocks of consecutive whole cells
-  int32_t* d_type_of = nullptr;
   FilterBlock* d_filter_blocks = nullptr;
   int n_filter_blocks = 0;
   int filter_net = 8;                       // keys of the kernel's sorting network (8 or 16)
@@ -282,7 +283,6 @@ struct npfem_batch {
       if (h_stage_count[i]) (void)hipHostFree(h_stage_count[i]);
     }
     if (d_offsets) (void)hipFree(d_offsets);
-    if (d_type_of) (void)hipFree(d_type_of);
     if (d_filter_blocks) (void)hipFree(d_filter_blocks);
     if (work) (void)hipFree(work);
     if (d_flag) (void)hipFree(d_flag);
@@ -373,37 +373,50 @@ npfem_status relayout(npfem_batch* b) {
 // network width is 8 keys (degree <= 7) when at most 1/32 of the vertices have wider closed
 // rings, else 16; wider rings go to the kernel's rank-selection pass.
 npfem_status build_filter_blocks(npfem_batch* b) {
-  std::vector<int64_t> wide_of(b->types.size(), 0);
-  for (size_t ti = 0; ti < b->types.size(); ++ti)
-    for (uint32_t info : b->types[ti]->ring_info) wide_of[ti] += (int)(info & 255u) + 1 > 8;
+  const int nt = (int)b->types.size();
+  auto wide_count = [&](int ti, int keys) {
+    int64_t w = 0;
+    for (uint32_t info : b->types[ti]->ring_info) w += (int)(info & 255u) + 1 > keys;
+    return w;
+  };
   int64_t wide8 = 0;
-  for (int c = 0; c < b->n_cells; ++c) wide8 += wide_of[b->type_of[c]];
+  for (int c = 0; c < b->n_cells; ++c) wide8 += wide_count(b->type_of[c], 8);
   b->filter_net = 32 * wide8 <= b->offsets.back() ? 8 : 16;
+  std::vector<int64_t> wide_of(nt);
+  for (int ti = 0; ti < nt; ++ti) wide_of[ti] = wide_count(ti, b->filter_net);
   std::vector<FilterBlock> blocks;
-  int64_t max_nv = 0;
+  int64_t max_recs = 0, max_wide = 1;
   for (int c = 0; c < b->n_cells;) {
-    FilterBlock blk{c, 0};
-    int64_t nv = 0;
+    FilterBlock blk{};
+    blk.v0 = b->offsets[c];
+    int64_t nv = 0, wide = 0;
     while (c < b->n_cells && blk.count < kFilterMaxCells) {
       const int64_t n = b->offsets[c + 1] - b->offsets[c];
       if (blk.count > 0 && nv + n > kFilterMaxVerts) break;
+      blk.start[blk.count] = (int32_t)nv;
+      blk.type[blk.count] = (int16_t)b->type_of[c];
+      const DevType* dt = b->dev_types[b->type_of[c]];
+      blk.nb[blk.count] = b->filter_net == 8 ? dt->ring_nb8 : dt->ring_nb16;
       nv += n;
+      wide += wide_of[b->type_of[c]];
       ++blk.count;
       ++c;
     }
-    max_nv = std::max(max_nv, nv);
+    blk.start[blk.count] = (int32_t)nv;
+    blk.nv = (int32_t)nv;
+    max_recs = std::max(max_recs, nv + 2 * blk.count);
+    max_wide = std::max(max_wide, wide);
     blocks.push_back(blk);
   }
+  // LDS: one record of 4 values per vertex plus two pad records (-inf, +inf) per cell, then
+  // the list of wide-ring vertices
   const size_t el = b->precision == 64 ? 8 : 4;
-  b->filter_lds = (3 * el + sizeof(int)) * (size_t)max_nv;
+  b->filter_lds = 4 * el * (size_t)max_recs + sizeof(int) * (size_t)max_wide;
   b->n_filter_blocks = (int)blocks.size();
-  if (b->filter_lds > 65536)
+  if (nt > 32767) b->filter_reason = "median filter: more than 32767 cell types";
+  else if (b->filter_lds > 65536)
     b->filter_reason = "median filter: a cell's forces exceed 64 KiB of LDS";
   if (b->n_cells == 0) return NPFEM_OK;
-  std::vector<int32_t> type_of(b->type_of.begin(), b->type_of.end());
-  HIP_TRY(hipMalloc((void**)&b->d_type_of, type_of.size() * sizeof(int32_t)));
-  HIP_TRY(hipMemcpy(b->d_type_of, type_of.data(), type_of.size() * sizeof(int32_t),
-                    hipMemcpyHostToDevice));
   HIP_TRY(hipMalloc((void**)&b->d_filter_blocks, blocks.size() * sizeof(FilterBlock)));
   HIP_TRY(hipMemcpy(b->d_filter_blocks, blocks.data(), blocks.size() * sizeof(FilterBlock),
                     hipMemcpyHostToDevice));
@@ -852,8 +865,8 @@ npfem_status npfem_filter_forces(npfem_batch* b, const void* f_in, void* f_out, 
   if (!f_in || !f_out) return fail(NPFEM_E_INVALID, "null force buffer");
   if (!b->filter_reason.empty()) return fail(NPFEM_E_UNSUPPORTED, b->filter_reason);
   DeviceGuard guard(b->device);
-  const hipError_t e = launch_median_filter(b->precision, b->filter_net, b->d_types, b->d_type_of,
-                                            b->d_offsets, b->d_filter_blocks, b->n_filter_blocks,
+  const hipError_t e = launch_median_filter(b->precision, b->filter_net, b->d_types,
+                                            b->d_filter_blocks, b->n_filter_blocks,
                                             b->offsets.back(), f_in, f_out, b->filter_lds, stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("median filter launch: ") + hipGetErrorString(e));
   return NPFEM_OK;

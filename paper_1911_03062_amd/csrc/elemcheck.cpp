@@ -37,6 +37,19 @@ void hin(const double* p, const double* a, double rest, double wb, double* out) 
   }
 }
 
+template <typename T, int N>
+double median_net(const double* vals, int k) {
+  T a[N];
+  for (int q = 0; q < N; ++q) a[q] = q < k ? (T)vals[q] : (T)__builtin_inf();
+  return median_keys<N>(a, k);
+}
+template <typename T>
+double median_any(const double* vals, int k) {
+  if (k <= 8) return median_net<T, 8>(vals, k);
+  if (k <= 16) return median_net<T, 16>(vals, k);
+  return median_net<T, 32>(vals, k);
+}
+
 }  // namespace
 
 extern "C" {
@@ -86,22 +99,10 @@ void npfem_check_pbd(const double* x, const double* v, int n, double kappa, doub
     out[3 * i + 2] = o.z;
   }
 }
-// Median of k (1..16) values with the kernels' sorting network and selection, in the given
-// precision.
+// Median of k (1..32) values with the kernels' sorting networks (8, 16 or 32 keys, the
+// smallest that holds k) and middle selection, in the given precision.
 double npfem_check_median(const double* vals, int k, int precision) {
-  if (precision == 64) {
-    double a[16];
-    for (int q = 0; q < 16; ++q) a[q] = q < k ? vals[q] : __builtin_inf();
-    return median_keys<16>(a, k);
-  }
-  if (k <= 8) {
-    float a[8];
-    for (int q = 0; q < 8; ++q) a[q] = q < k ? (float)vals[q] : __builtin_inff();
-    return median_keys<8>(a, k);
-  }
-  float a[16];
-  for (int q = 0; q < 16; ++q) a[q] = q < k ? (float)vals[q] : __builtin_inff();
-  return median_keys<16>(a, k);
+  return precision == 64 ? median_any<double>(vals, k) : median_any<float>(vals, k);
 }
 // Median of k values by the kernels' rank selection (the path of wide rings).
 double npfem_check_median_rank(const double* vals, int k, int precision) {

@@ -59,6 +59,69 @@ __host__ __device__ __forceinline__ void sort_keys(T (&a)[N]) {
   sort_net_apply<N>(a, std::make_integer_sequence<int, kSortNet<N>.count>{});
 }
 
+// The comparators of SortNet<N> that the two middle outputs (N/2 - 1, N/2) depend on, found
+// by a backward pass from those outputs; a comparator whose min (max) output is not needed
+// later keeps only its max (min).
+template <int N>
+struct MiddleNet {
+  int count = 0;
+  unsigned char lo[N * N] = {};
+  unsigned char hi[N * N] = {};
+  bool keep_min[N * N] = {};
+  bool keep_max[N * N] = {};
+  constexpr MiddleNet() {
+    constexpr SortNet<N> full{};
+    unsigned long long need = (1ull << (N / 2 - 1)) | (1ull << (N / 2));
+    int m = 0;
+    unsigned char rl[N * N] = {}, rh[N * N] = {};
+    bool rmin[N * N] = {}, rmax[N * N] = {};
+    for (int q = full.count - 1; q >= 0; --q) {
+      const int i = full.lo[q], j = full.hi[q];
+      const bool ni = (need >> i) & 1ull, nj = (need >> j) & 1ull;
+      if (!ni && !nj) continue;
+      rl[m] = (unsigned char)i;
+      rh[m] = (unsigned char)j;
+      rmin[m] = ni;
+      rmax[m] = nj;
+      ++m;
+      need |= (1ull << i) | (1ull << j);
+    }
+    for (int q = 0; q < m; ++q) {
+      lo[q] = rl[m - 1 - q];
+      hi[q] = rh[m - 1 - q];
+      keep_min[q] = rmin[m - 1 - q];
+      keep_max[q] = rmax[m - 1 - q];
+    }
+    count = m;
+  }
+};
+
+template <int N>
+inline constexpr MiddleNet<N> kMiddleNet{};
+
+template <int N, typename T, int... Q>
+__host__ __device__ __forceinline__ void middle_net_apply(T (&a)[N], std::integer_sequence<int, Q...>) {
+  ((void)([&] {
+     constexpr int i = kMiddleNet<N>.lo[Q], j = kMiddleNet<N>.hi[Q];
+     constexpr bool mn = kMiddleNet<N>.keep_min[Q], mx = kMiddleNet<N>.keep_max[Q];
+     const T x = a[i], y = a[j];
+     if (mn) a[i] = kmin(x, y);
+     if (mx) a[j] = kmax(x, y);
+   }()),
+   ...);
+}
+
+// Median of the k members of a closed ring padded to N keys with floor((N - k) / 2) copies of
+// -inf and the rest +inf: the padding puts the ring's middle at positions N/2 - 1 (odd k) or
+// N/2 - 1 and N/2 (even k) of the sorted keys, so only the comparators feeding those two
+// positions run. a is overwritten.
+template <int N, typename T>
+__host__ __device__ __forceinline__ T median_padded(T (&a)[N], int k) {
+  middle_net_apply<N>(a, std::make_integer_sequence<int, kMiddleNet<N>.count>{});
+  const T lo = a[N / 2 - 1], hi = a[N / 2];
+  return (k & 1) ? lo : T(0.5) * (lo + hi);
+}
+
 // Median of the first k keys of a (1 <= k <= N); a[k..N) must hold +inf. Sorts a in place.
 template <int N, typename T>
 __host__ __device__ __forceinline__ T median_keys(T (&a)[N], int k) {

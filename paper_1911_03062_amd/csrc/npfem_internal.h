@@ -13,6 +13,12 @@
 
 namespace npfem {
 
+// Per-vertex neighbour tables of the median filter for closed rings padded to N = 8 or 16 keys:
+// slot 0 holds the degree, slots 1..N-1 the neighbours as cell-local index + 2, then the pads
+// as codes 0 (-inf) and 1 (+inf): floor((N - 1 - degree) / 2) of code 0, the rest code 1 (rows
+// of vertices whose closed ring exceeds N keys hold only the degree).
+constexpr uint16_t kPadNeg = 0, kPadPos = 1, kNbBias = 2;
+
 // ------------------------------------------------------------------------------------------
 // Device-side records (plain structs, identical layout on host and device).
 // ------------------------------------------------------------------------------------------
@@ -76,6 +82,8 @@ struct DevType {
   // vertex rings (fused form and median filter): the triangles (i, b, c) around each vertex i
   uint32_t* ring_info = nullptr;     // [n]: offset << 8 | degree
   uint32_t* ring_pairs = nullptr;    // [sum deg]: b | c << 16
+  uint16_t* ring_nb8 = nullptr;      // [n][8]: median-filter neighbour table, 8 keys
+  uint16_t* ring_nb16 = nullptr;     // [n][16]: the same for 16 keys
   // fused form
   TriRec* tri_sched = nullptr;       // [tri_rounds][slots]
   HingeRec* hinge_sched = nullptr;   // [hinge_rounds][slots]
@@ -118,6 +126,7 @@ struct npfem_celltype {
   std::vector<double> Linv;       // [n][n]
   std::vector<int32_t> vt_off, vt_list, vh_off, vh_list;
   std::vector<uint32_t> ring_info, ring_pairs;
+  std::vector<uint16_t> ring_nb8, ring_nb16;  // [n][8], [n][16]
   // fused form: LDS column length and one element-schedule layout per feasible number of
   // cells per wave (largest first; layouts[0] is the default). gw, slots and the rounds
   // below describe layouts[0].
@@ -191,10 +200,18 @@ inline NPFEM_HD int mfma_share_items(int col_tiles, int u0, int u1) {
 // Median filter of the external forces: one workgroup per block of consecutive whole cells.
 constexpr int kFilterThreads = 256;
 constexpr int kFilterMaxCells = 32;         // cells per block
-constexpr int kFilterMaxVerts = 2048;       // vertices per block (a larger cell is alone)
+constexpr int kFilterMaxVerts = 1024;       // vertices per block (a larger cell is alone)
+constexpr int kFilterWideKeys = 32;         // network keys of the wide-ring pass
+// Header of one block, read by the kernel with one load per lane.
 struct FilterBlock {
-  int32_t cell0, count;
+  int64_t v0;                          // first vertex of the block in the batch
+  int32_t count, nv;                   // cells, vertices
+  const uint16_t* nb[kFilterMaxCells]; // each cell's neighbour table (device, 8 or 16 keys)
+  int32_t start[kFilterMaxCells + 1];  // first vertex of each cell, relative to v0
+  int16_t type[kFilterMaxCells];       // index of each cell's type in the batch's type table
+  int32_t pad[2];
 };
+static_assert(sizeof(FilterBlock) % 16 == 0, "FilterBlock is read as whole dwords");
 
 // Kernel launchers and sizes (kernels_plain.hip, kernels_fused.hip, kernels_filter.hip).
 size_t plain_work_bytes(int precision, int n, int m, int e);
@@ -207,7 +224,6 @@ hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedG
                              int64_t vtot, float* x, float* v, const float* f, int K,
                              double* vol_area, int* flag, size_t lds_bytes, void* stream);
 hipError_t launch_median_filter(int precision, int net_keys, const DevType* types,
-                                const int32_t* type_of, const int64_t* offsets,
                                 const FilterBlock* blocks, int n_blocks, int64_t vt,
                                 const void* f, void* out, size_t lds_bytes, void* stream);
 

@@ -496,6 +496,22 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   if (max_deg > 255) return fail(NPFEM_E_UNSUPPORTED, "vertex degree above 255");
   for (int i = 0; i < n; ++i)
     ct->ring_info[i] = ((uint32_t)ct->vt_off[i] << 8) | (uint32_t)(ct->vt_off[i + 1] - ct->vt_off[i]);
+  // median-filter neighbour tables: the second vertex of each ring triangle (i, b, c) is every
+  // neighbour once; short rings are padded evenly with -inf and +inf codes
+  for (int keys : {8, 16}) {
+    std::vector<uint16_t>& tab = keys == 8 ? ct->ring_nb8 : ct->ring_nb16;
+    tab.assign((size_t)n * keys, kPadPos);
+    for (int i = 0; i < n; ++i) {
+      const int deg = ct->vt_off[i + 1] - ct->vt_off[i];
+      uint16_t* row = &tab[(size_t)i * keys];
+      row[0] = (uint16_t)deg;
+      if (deg + 1 > keys) continue;
+      const int neg = (keys - 1 - deg) / 2;
+      for (int q = 0; q < keys - 1; ++q)
+        row[1 + q] = q < deg ? (uint16_t)((ct->ring_pairs[ct->vt_off[i] + q] & 0xffffu) + kNbBias)
+                             : (q - deg < neg ? kPadNeg : kPadPos);
+    }
+  }
 
   // ---- fused-form layout and element schedules
   // LDS column stride: a multiple of 4 (MFMA k step) whose quarter is odd, so that the 16

@@ -166,13 +166,14 @@ def test_sorting_network_sorts_every_zero_one_input(lib):
 
 
 def test_median_helper_matches_numpy(lib):
-    """The kernels' median (network + middle selection) against numpy's median, bit for bit in
-    FP64 and, on FP32-rounded inputs, in FP32; odd and even counts, repeated values."""
+    """The kernels' median (8-, 16- and 32-key networks + middle selection) against numpy's
+    median, bit for bit in FP64 and, on FP32-rounded inputs, in FP32; odd and even counts,
+    repeated values."""
     lib.npfem_check_median.argtypes = [dp, ctypes.c_int, ctypes.c_int]
     lib.npfem_check_median.restype = ctypes.c_double
     rng = np.random.default_rng(45)
-    for trial in range(400):
-        k = int(rng.integers(1, 17))
+    for trial in range(1200):
+        k = int(rng.integers(1, 33))
         vals = rng.normal(size=k) * 10.0 ** rng.integers(-3, 4)
         if trial % 3 == 0:
             vals = np.round(vals)                      # repeated values
