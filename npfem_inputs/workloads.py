@@ -31,7 +31,8 @@ class Material:
     shear_B, area_C, skalak_D in pN/um; k_bend in pN um; k_vol in pN/um (per vertex);
     strain_min/max clamp the singular values of the strain projection (1, 1 = polar factor);
     pbd_kappa in [0, 1] is the position-based damping factor (kappa_damping of the table);
-    v_max > 0 caps the vertex speed after each step (um/us; 0 = no cap).
+    v_max > 0 caps the vertex speed after each step (um/us; 0 = no cap); rayleigh_alpha (1/us)
+    and rayleigh_beta (us) give Rayleigh damping C = alpha M + beta K (0, 0 = off).
     """
     density: float = DENSITY
     shear_B: float = 5.0
@@ -43,17 +44,22 @@ class Material:
     strain_max: float = 1.0
     pbd_kappa: float = 0.0    # position-based velocity damping (kappa_damping), 0 = off
     v_max: float = 0.0        # velocity cap, 0 = off
+    rayleigh_alpha: float = 0.0   # Rayleigh damping C = alpha M + beta K: alpha in 1/us
+    rayleigh_beta: float = 0.0    # beta in us (alpha_D, beta_D of the table)
 
     def scaled(self, s: float) -> "Material":
         return Material(self.density, self.shear_B * s, self.area_C * s, self.skalak_D * s,
                         self.k_bend * s, self.k_vol * s, self.strain_min, self.strain_max,
-                        self.pbd_kappa, self.v_max)
+                        self.pbd_kappa, self.v_max, self.rayleigh_alpha, self.rayleigh_beta)
 
     def with_kappa(self, kappa: float) -> "Material":
         return dataclasses.replace(self, pbd_kappa=kappa)
 
     def with_v_max(self, v_max: float) -> "Material":
         return dataclasses.replace(self, v_max=v_max)
+
+    def with_rayleigh(self, alpha: float, beta: float) -> "Material":
+        return dataclasses.replace(self, rayleigh_alpha=alpha, rayleigh_beta=beta)
 
 
 RBC_MATERIAL = Material()

@@ -7,4 +7,4 @@ from .npfem_oracle import (CellType, step, step_batch, predict, gradient, pd_rhs
                            deformation_gradients, interior_edges, system_matrix,
                            cell_volume_area, pbd_damp, rigid_velocity_fit,
                            one_ring_neighbours, median_filter_forces, median_filter_batch,
-                           cap_velocities)
+                           cap_velocities, stiffness_matrix)

@@ -27,6 +27,11 @@ w/2 ||A x - p(x)||^2 with exact projections p:
   * optional position-based damping of the velocities (npFEM subsection, after Mueller et al.
     2007): per cell the rigid part of v_n is kept and the rest scaled by 1 - kappa, applied
     to v_n before the prediction (the order of position-based dynamics: damp, then predict);
+  * optional Rayleigh damping C = alpha M + beta K (parameter table: alpha_D, beta_D), with K
+    the constant stiffness of the strain, area and bending energies (the quadratic part of L
+    without the mass and volume terms): M~ = M + h C enters y_n and g(x) as in the
+    minimisation form (npFEM subsection), and the quasi-Newton matrix becomes
+    M~/h^2 + w_v I + K; alpha in 1/us and beta in us (the solver's time unit);
   * optional capping of the new vertex velocities at v_max (the velocity truncation for the
     stability of the immersed-boundary coupling, Fluid-structure interaction subsection);
 Everything is float64, vectorised over the cells of one type (arrays [N][n][3]).
@@ -72,6 +77,8 @@ class CellType:
         self.s_max = float(material.strain_max)
         self.kappa = float(getattr(material, "pbd_kappa", 0.0))
         self.v_max = float(getattr(material, "v_max", 0.0))
+        self.alpha = float(getattr(material, "rayleigh_alpha", 0.0))
+        self.beta = float(getattr(material, "rayleigh_beta", 0.0))
 
         self.G, self.area = triangle_rest_frames(X, tri)
         self.hinge, self.coef, self.rest_norm = bending_stencils(X, tri)
@@ -80,6 +87,12 @@ class CellType:
         self.mass = float(material.density) * self.V0 / self.n
         self.L = system_matrix(self)
         self.cho = scipy.linalg.cho_factor(self.L, lower=True)
+        self.rayleigh = self.alpha != 0.0 or self.beta != 0.0
+        if self.rayleigh:
+            # M~ = (1 + h alpha) M + h beta K
+            self.K = stiffness_matrix(self)
+            self.Mt = (1.0 + self.h * self.alpha) * self.mass * np.eye(self.n) + self.h * self.beta * self.K
+            self.cho_Mt = scipy.linalg.cho_factor(self.Mt, lower=True)
 
 
 def triangle_rest_frames(X, tri):
@@ -150,13 +163,33 @@ def bending_stencils(X, tri):
     return H, coef, np.linalg.norm(u, axis=1)
 
 
+def stiffness_matrix(ct: CellType) -> np.ndarray:
+    """K = sum_t (w_s + w_a) A_t G_t^T G_t + sum_e w_b a_e a_e^T: the constant stiffness of the
+    strain, area and bending energies (the K of Rayleigh damping)."""
+    n = ct.n
+    K = np.zeros((n, n))
+    wt = (ct.w_s + ct.w_a) * ct.area
+    for p in range(3):
+        for q in range(3):
+            np.add.at(K, (ct.tri[:, p], ct.tri[:, q]),
+                      wt * np.einsum("tk,tk->t", ct.G[:, p, :], ct.G[:, q, :]))
+    for p in range(4):
+        for q in range(4):
+            np.add.at(K, (ct.hinge[:, p], ct.hinge[:, q]), ct.w_b * ct.coef[:, p] * ct.coef[:, q])
+    return K
+
+
 def system_matrix(ct: CellType) -> np.ndarray:
     """L = (m/h^2 + w_v) I + sum_t (w_s + w_a) A_t G_t^T G_t + sum_e w_b a_e a_e^T.
 
     It is the Hessian of the quadratic part of g, shared by the three coordinates and by
-    every cell of the type.
+    every cell of the type. With Rayleigh damping the mass term is M~/h^2:
+    L = ((1 + h alpha) m/h^2 + w_v) I + (1 + beta/h) K.
     """
     n = ct.n
+    if ct.alpha != 0.0 or ct.beta != 0.0:
+        return (np.eye(n) * ((1.0 + ct.h * ct.alpha) * ct.mass / ct.h ** 2 + ct.w_v)
+                + (1.0 + ct.beta / ct.h) * stiffness_matrix(ct))
     L = np.eye(n) * (ct.mass / ct.h ** 2 + ct.w_v)
     wt = (ct.w_s + ct.w_a) * ct.area
     for p in range(3):
@@ -298,6 +331,13 @@ def _scatter_hinges(ct, W, N):
     return out
 
 
+def _mass_term(ct, d):
+    """(M~/h^2) d for d [N][n][3]: (m/h^2) d without damping."""
+    if not ct.rayleigh:
+        return (ct.mass / ct.h ** 2) * d
+    return (np.einsum("ij,njd->nid", ct.Mt, d)) / ct.h ** 2
+
+
 def gradient(x, y, ct):
     """grad g(x) [N][n][3] with projections recomputed at x (local step of the iteration)."""
     N = x.shape[0]
@@ -307,7 +347,7 @@ def gradient(x, y, ct):
     u = bending_vectors(x, ct)
     p_b = bending_projection(u, ct)
     p_v, _, _ = volume_projection(x, ct)
-    g = (ct.mass / ct.h ** 2) * (x - y)
+    g = _mass_term(ct, x - y)
     g += _scatter_triangles(ct, M, N)
     g += _scatter_hinges(ct, ct.w_b * (u - p_b), N)
     g += ct.w_v * (x - p_v)
@@ -323,7 +363,7 @@ def pd_rhs(x, y, ct):
     u = bending_vectors(x, ct)
     p_b = bending_projection(u, ct)
     p_v, _, _ = volume_projection(x, ct)
-    b = (ct.mass / ct.h ** 2) * y
+    b = _mass_term(ct, y)
     b += _scatter_triangles(ct, M, N)
     b += _scatter_hinges(ct, ct.w_b * p_b, N)
     b += ct.w_v * p_v
@@ -337,7 +377,7 @@ def energy(x, y, ct):
     u = bending_vectors(x, ct)
     p_b = bending_projection(u, ct)
     p_v, _, _ = volume_projection(x, ct)
-    e = 0.5 * ct.mass / ct.h ** 2 * np.einsum("nid,nid->n", x - y, x - y)
+    e = 0.5 * np.einsum("nid,nid->n", x - y, _mass_term(ct, x - y))
     e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_s, (F - p_s) ** 2)
     e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_a, (F - p_a) ** 2)
     e += 0.5 * ct.w_b * np.einsum("ned,ned->n", u - p_b, u - p_b)
@@ -385,9 +425,17 @@ def pbd_damp(x, v, kappa: float):
 
 
 def predict(x, v, f, ct):
-    """y = x_n + h v_n + h^2 F_ext / m (third displayed equation, C = 0), with v_n damped
-    first when the type has position-based damping."""
-    return x + ct.h * pbd_damp(x, v, ct.kappa) + (ct.h ** 2 / ct.mass) * f
+    """y_n = x_n + h M~^-1 M v_n + h^2 M~^-1 F_ext (third displayed equation; M~ = M without
+    Rayleigh damping: y_n = x_n + h v_n + h^2 F_ext / m), with v_n damped first when the type
+    has position-based damping."""
+    vd = pbd_damp(x, v, ct.kappa)
+    if not ct.rayleigh:
+        return x + ct.h * vd + (ct.h ** 2 / ct.mass) * f
+    rhs = ct.h * ct.mass * vd + ct.h ** 2 * f                                   # [N][n][3]
+    N = x.shape[0]
+    B = np.transpose(rhs, (1, 0, 2)).reshape(ct.n, N * 3)
+    Y = scipy.linalg.cho_solve(ct.cho_Mt, B)
+    return x + np.transpose(Y.reshape(ct.n, N, 3), (1, 0, 2))
 
 
 def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",

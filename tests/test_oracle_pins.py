@@ -570,3 +570,73 @@ def test_step_caps_velocities_and_keeps_positions():
     fast = s > 0.05
     assert np.allclose(np.linalg.norm(vb[fast], axis=-1), 0.05, rtol=1e-14)
     assert np.allclose(vb[fast] * (s[fast] / 0.05)[:, None], va[fast], rtol=1e-12)
+
+
+# ------------------------------------------------------------------ Rayleigh damping (f1)
+
+
+def _deformed_plt(seed, amp=0.03):
+    x0, t, m = I.cell_type_inputs()[I.PLT]
+    rng = np.random.default_rng(seed)
+    return x0, t, m, x0[None] + amp * rng.normal(size=(1,) + x0.shape)
+
+
+def test_rayleigh_free_flight_closed_form():
+    """With alpha only, M~ = (1 + h alpha) M, so the prediction (K = 0 iterations) is
+    y = x + (h v + h^2 F/m) / (1 + h alpha), straight from the definitions of M~ and y_n."""
+    x0, t, m, x = _deformed_plt(60)
+    alpha = 0.7
+    ct = O.CellType(x0, t, m.with_rayleigh(alpha, 0.0), I.DT)
+    rng = np.random.default_rng(61)
+    v, f = rng.normal(size=x.shape), 30.0 * rng.normal(size=x.shape)
+    y, _ = O.step(ct, x, v, f, 0)
+    ref = x + (I.DT * v + I.DT ** 2 * f / ct.mass) / (1.0 + I.DT * alpha)
+    assert np.allclose(y, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_rayleigh_keeps_rigid_translation():
+    """K annihilates a uniform translation (sum_j g_j = 0, sum_q a_q = 0), so beta damping
+    leaves a cell translating at rest shape exactly on its free-flight path."""
+    x0, t, m = I.cell_type_inputs()[I.RBC]
+    ct = O.CellType(x0, t, m.with_rayleigh(0.0, 0.05), I.DT)
+    u = np.array([0.3, -0.2, 0.5])
+    x = x0[None] + 10.0
+    v = np.broadcast_to(u, x.shape).copy()
+    x1, v1 = O.step(ct, x, v, 0 * x, 5)
+    assert np.abs(x1 - (x + I.DT * u)).max() <= 1e-11
+    assert np.abs(v1 - u).max() <= 1e-9
+    assert np.abs(ct.K.sum(axis=1)).max() <= 1e-9 * np.abs(ct.K).max()
+
+
+def test_rayleigh_converged_step_satisfies_newtons_law():
+    """A converged damped step solves the implicit-Euler equation of motion with
+    C = alpha M + beta K: F_int(x1) + F_ext - C v1 = M (v1 - v0)/h. F_int comes from an
+    undamped type (gradient at y = x has no mass term) and K from its system matrix minus the
+    mass and volume diagonal, so neither shares the damped type's M~ or y_n."""
+    x0, t, m, x = _deformed_plt(62, amp=0.02)
+    alpha, beta = 0.3, 0.05
+    ct = O.CellType(x0, t, m.with_rayleigh(alpha, beta), I.DT)
+    ct0 = O.CellType(x0, t, m, I.DT)
+    rng = np.random.default_rng(63)
+    v0, f = 0.05 * rng.normal(size=x.shape), 20.0 * rng.normal(size=x.shape)
+    x1, v1 = O.step(ct, x, v0, f, 200)
+    K = ct0.L - np.eye(ct0.n) * (ct0.mass / ct0.h ** 2 + ct0.w_v)
+    f_int = -O.gradient(x1, x1, ct0)
+    Cv = alpha * ct0.mass * v1 + beta * np.einsum("ij,njd->nid", K, v1)
+    res = f_int + f - Cv - ct0.mass * (v1 - v0) / I.DT
+    scale = np.abs(ct0.mass * (v1 - v0) / I.DT).max() + np.abs(f).max()
+    assert np.abs(res).max() <= 1e-10 * scale, np.abs(res).max() / scale   # 5e-13 here
+    # and damping matters at this size: the undamped step differs by more than the step
+    xu, _ = O.step(ct0, x, v0, f, 200)
+    assert np.abs(xu - x1).max() > 0.5 * np.abs(x1 - x).max()
+
+
+def test_rayleigh_quasi_newton_equals_projective_dynamics():
+    """x - L~^-1 grad g(x) = L~^-1 rhs(x) with the damped M~ in both g and rhs."""
+    x0, t, m, x = _deformed_plt(64)
+    ct = O.CellType(x0, t, m.with_rayleigh(0.2, 0.03), I.DT)
+    rng = np.random.default_rng(65)
+    v, f = 0.05 * rng.normal(size=x.shape), 10.0 * rng.normal(size=x.shape)
+    a, _ = O.step(ct, x, v, f, 4, form="qn")
+    b, _ = O.step(ct, x, v, f, 4, form="pd")
+    assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
