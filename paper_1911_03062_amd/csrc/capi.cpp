@@ -60,7 +60,7 @@ void free_devtype(DevType* d) {
                   d->tri,       d->hinge,       d->vt_off,    d->vt_list,    d->vh_off,
                   d->vh_list,   d->G64,         d->G32,       d->A64,        d->A32,
                   d->coef64,    d->coef32,      d->rest64,    d->rest32,     d->cband64,
-                  d->cband32};
+                  d->cband32,   d->mband64,     d->mband32,   d->kband64,    d->kband32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete d;
@@ -109,8 +109,14 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   // whole chunks plus two zero chunks read by the global step's look-ahead loads
   p.k_steps = ((ct->npad / 4 + kMfmaChunk - 1) / kMfmaChunk + 2) * kMfmaChunk;
   p.pad0 = 0;
-  p.h = ct->h; p.mass = ct->mass; p.inv_h2m = ct->mass / (ct->h * ct->h);
+  p.h = ct->h; p.mass = ct->mass;
+  // Rayleigh damping: M~/h^2 = (1 + h alpha) m/h^2 I + (beta/h) K
+  const double ma = 1.0 + ct->h * ct->alpha;
+  p.inv_h2m = ma * ct->mass / (ct->h * ct->h);
   p.h2_over_m = ct->h * ct->h / ct->mass;
+  p.pred_h = ct->h / ma;
+  p.pred_h2m = p.h2_over_m / ma;
+  p.ray_k = ct->beta / ct->h;
   p.w_s = ct->w_s; p.w_a = ct->w_a; p.w_b = ct->w_b; p.w_v = ct->w_v;
   p.s_min = ct->s_min; p.s_max = ct->s_max; p.V0 = ct->V0; p.kappa = ct->kappa;
   p.v_max = ct->v_max;
@@ -128,6 +134,10 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   chk(upload(&d->coef64, ct->coef)); chk(upload(&d->coef32, ct->coef));
   chk(upload(&d->rest64, ct->rest_norm)); chk(upload(&d->rest32, ct->rest_norm));
   chk(upload(&d->cband64, ct->cband)); chk(upload(&d->cband32, ct->cband));
+  if (!ct->mband.empty()) {
+    chk(upload(&d->mband64, ct->mband)); chk(upload(&d->mband32, ct->mband));
+    chk(upload(&d->kband64, ct->kband)); chk(upload(&d->kband32, ct->kband));
+  }
   // vertex rings: the fused form's volume gradient and the median filter (both forms)
   chk(upload(&d->ring_info, ct->ring_info));
   chk(upload(&d->ring_pairs, ct->ring_pairs));

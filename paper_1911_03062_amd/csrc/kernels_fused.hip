@@ -265,7 +265,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #define ITEM_V(it) (item[it] & 0xffff)
 #define ITEM_C(it) (item[it] >> 16)
 #define ITEM_W(it) (ITEM_C(it) * CS + 3 * ITEM_V(it))   // word offset of the item's xyz
-    const float h = (float)T.p.h, h2m = (float)T.p.h2_over_m, ih2m = (float)T.p.inv_h2m;
+    // delta^0 = pred_h v + pred_h2m F (h v + h^2 F/m, over 1 + h alpha with Rayleigh alpha)
+    const float h = (float)T.p.pred_h, h2m = (float)T.p.pred_h2m, ih2m = (float)T.p.inv_h2m;
     const float w_v = (float)T.p.w_v, ih = (float)(1.0 / T.p.h);
     if (tid < count) off_lds[tid] = offsets[grp.cells[tid]];
     __syncthreads();

@@ -4,10 +4,13 @@
 // FP64 instance runs the whole path in double.
 //
 // Step (supplementary material, npFEM subsection, implicit Euler and its quasi-Newton
-// iteration, damping C = 0): delta = x - x_n; delta^0 = h v_n + h^2 F/m (prediction y);
-// iterate delta <- delta - L^-1 grad g(x_n + delta); then x_{n+1} = x_n + delta,
-// v_{n+1} = delta / h. Positions inside the kernels are taken relative to the cell's first
-// vertex, which leaves every difference, and the enclosed volume, unchanged.
+// iteration): delta = x - x_n; delta^0 = y_n - x_n = h M~^-1 (M v_n + h F) (the prediction;
+// h v_n + h^2 F/m without damping); iterate delta <- delta - L^-1 grad g(x_n + delta) with
+// grad g = (M~/h^2) e + constraint residuals, e = delta - delta^0; then x_{n+1} = x_n + delta,
+// v_{n+1} = delta / h. Rayleigh damping C = alpha M + beta K gives M~ = (1 + h alpha) M +
+// h beta K: its prediction is one banded solve with M~'s factor, its gradient term
+// (beta/h) K e a banded product. Positions inside the kernels are taken relative to the
+// cell's first vertex, which leaves every difference, and the enclosed volume, unchanged.
 #include <hip/hip_runtime.h>
 
 #include "npfem_internal.h"
@@ -118,14 +121,22 @@ k_plain_predict(TypeParams p, const T* __restrict__ x, const T* __restrict__ v,
     vcm = v3<T>(T(c[3]), T(c[4]), T(c[5]));
     om = v3<T>(T(wv[0]), T(wv[1]), T(wv[2]));
   }
+  // Rayleigh damping with beta > 0: the right-hand side M (h v + h^2 F/m) of M~ delta^0 goes
+  // to r for the solve that follows; otherwise delta^0 = (h v + h^2 F/m) / (1 + h alpha)
+  const bool ray_solve = p.ray_k > 0.0;
+  const T ph = T(p.pred_h), ph2m = T(p.pred_h2m), mm = T(p.mass);
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     Vec3<T> vi = vel(i);
     if (damp) vi = pbd_velocity<T>(vi, xl(i) - xcm, vcm, om, T(p.kappa));
     const T vv[3] = {vi.x, vi.y, vi.z};
     for (int c = 0; c < 3; ++c) {
-      const T d0 = h * vv[c] + h2m * f[c * vt + off + i];
-      w.d0[c * n + i] = d0;
-      w.d[c * n + i] = d0;
+      if (ray_solve) {
+        w.r[c * n + i] = mm * (h * vv[c] + h2m * f[c * vt + off + i]);
+      } else {
+        const T d0 = ph * vv[c] + ph2m * f[c * vt + off + i];
+        w.d0[c * n + i] = d0;
+        w.d[c * n + i] = d0;
+      }
     }
   }
 }
@@ -139,6 +150,8 @@ struct PlainConst<float> {
   static __device__ const float* coef(const DevType& t) { return t.coef32; }
   static __device__ const float* rest(const DevType& t) { return t.rest32; }
   static __device__ const float* cband(const DevType& t) { return t.cband32; }
+  static __device__ const float* mband(const DevType& t) { return t.mband32; }
+  static __device__ const float* kband(const DevType& t) { return t.kband32; }
 };
 template <>
 struct PlainConst<double> {
@@ -147,6 +160,8 @@ struct PlainConst<double> {
   static __device__ const double* coef(const DevType& t) { return t.coef64; }
   static __device__ const double* rest(const DevType& t) { return t.rest64; }
   static __device__ const double* cband(const DevType& t) { return t.cband64; }
+  static __device__ const double* mband(const DevType& t) { return t.mband64; }
+  static __device__ const double* kband(const DevType& t) { return t.kband64; }
 };
 
 // Local step: projections of every constraint at x^k and assembly of grad g(x^k) into r.
@@ -214,10 +229,20 @@ k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t 
   if (threadIdx.x == 0) lam_sh = G2 > 0 ? (p.V0 - V) / G2 : 0.0;
   __syncthreads();
   const T lam_w = T(lam_sh * p.w_v);
-  const T ih2m = T(p.inv_h2m);
+  const T ih2m = T(p.inv_h2m), ray_k = T(p.ray_k);
+  const T* kb = PlainConst<T>::kband(dt);
+  const int bw = p.bw, bs = bw + 1;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     for (int c = 0; c < 3; ++c) {
       T acc = ih2m * (w.d[c * n + i] - w.d0[c * n + i]);
+      if (p.ray_k > 0.0) {   // Rayleigh: (beta/h) (K e)_i, K symmetric, lower band stored
+        const T* dc = w.d + c * n;
+        const T* d0c = w.d0 + c * n;
+        T ke = 0;
+        for (int k = 0; k <= bw && k <= i; ++k) ke += kb[i * bs + k] * (dc[i - k] - d0c[i - k]);
+        for (int k = 1; k <= bw && i + k < n; ++k) ke += kb[(i + k) * bs + k] * (dc[i + k] - d0c[i + k]);
+        acc += ray_k * ke;
+      }
       for (int s = dt.vt_off[i]; s < dt.vt_off[i + 1]; ++s) acc += w.tcon[3 * dt.vt_list[s] + c];
       for (int s = dt.vh_off[i]; s < dt.vh_off[i + 1]; ++s) acc += w.hcon[3 * dt.vh_list[s] + c];
       acc -= lam_w * w.gv[c * n + i];
@@ -226,15 +251,17 @@ k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t 
   }
 }
 
-// Global step: solve L D = r with the banded Cholesky factor (three right-hand sides, one
-// wave per coordinate, band products reduced across the wave), then delta -= D.
+// Banded solve of r (three right-hand sides, one wave per coordinate, band products reduced
+// across the wave). Global step (predict = false): L D = r with L's factor, then
+// delta -= D. Prediction (predict = true, Rayleigh damping with beta > 0): M~ D = r with
+// M~'s factor, then delta^0 = delta = D.
 template <typename T>
 __global__ void __launch_bounds__(192)
-k_plain_solve(const DevType* __restrict__ dtp, void* work) {
+k_plain_solve(const DevType* __restrict__ dtp, void* work, bool predict) {
   const DevType& dt = *dtp;
   const int n = dt.p.n, bw = dt.p.bw, bs = bw + 1;
   PlainWork<T> w = plain_layout<T>(work, n, dt.p.m, dt.p.e);
-  const T* cb = PlainConst<T>::cband(dt);
+  const T* cb = predict ? PlainConst<T>::mband(dt) : PlainConst<T>::cband(dt);
   __shared__ T y[3][kMaxBand];
   const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
   T* yc = y[c];
@@ -258,7 +285,14 @@ k_plain_solve(const DevType* __restrict__ dtp, void* work) {
     if (lane == 0) yc[i] = xi;
     __builtin_amdgcn_wave_barrier();
   }
-  for (int i = lane; i < n; i += 64) w.d[c * n + i] -= yc[i];
+  if (predict) {
+    for (int i = lane; i < n; i += 64) {
+      w.d0[c * n + i] = yc[i];
+      w.d[c * n + i] = yc[i];
+    }
+  } else {
+    for (int i = lane; i < n; i += 64) w.d[c * n + i] -= yc[i];
+  }
 }
 
 // Class test (not v - v == 0, which FMA contraction can turn into a product's rounding error).
@@ -318,10 +352,12 @@ hipError_t plain_step_t(const DevType* dt_dev, const TypeParams& p, T* x, T* v, 
                         hipStream_t s) {
   hipLaunchKernelGGL(k_plain_predict<T>, dim3(1), dim3(kPlainThreads), 0, s, p, x, v, f, vt,
                      off, work);
+  if (p.ray_k > 0.0)
+    hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, true);
   for (int k = 0; k < K; ++k) {
     hipLaunchKernelGGL(k_plain_local<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt, off,
                        work);
-    hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work);
+    hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, false);
   }
   hipLaunchKernelGGL(k_plain_finalize<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, v, vt,
                      off, work, vol_area, flag);

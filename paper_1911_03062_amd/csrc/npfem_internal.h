@@ -74,6 +74,10 @@ struct TypeParams {
   double V0;
   double kappa;                 // position-based damping factor (0 = off)
   double v_max;                 // velocity cap (0 = off)
+  double pred_h, pred_h2m;      // prediction without a solve: delta^0 = pred_h v + pred_h2m F
+                                // (h and h^2/m over 1 + h alpha of Rayleigh damping)
+  double ray_k;                 // beta / h of Rayleigh damping (0 = off): the gradient gains
+                                // ray_k K e and the prediction solves with M~
 };
 
 // Device copy of a cell type's constants. Pointers are device pointers.
@@ -100,6 +104,8 @@ struct DevType {
   double* coef64 = nullptr; float* coef32 = nullptr;     // [e][4]
   double* rest64 = nullptr; float* rest32 = nullptr;     // [e]
   double* cband64 = nullptr; float* cband32 = nullptr;   // [n][bw+1]: C[i][i-k]
+  double* mband64 = nullptr; float* mband32 = nullptr;   // [n][bw+1]: factor of M~ (Rayleigh)
+  double* kband64 = nullptr; float* kband32 = nullptr;   // [n][bw+1]: K[i][i-k] (Rayleigh)
 };
 
 }  // namespace npfem
@@ -113,6 +119,9 @@ struct npfem_celltype {
   double h = 0, V0 = 0, area0 = 0, mass = 0;
   double w_s = 0, w_a = 0, w_b = 0, w_v = 0, s_min = 1, s_max = 1, kappa = 0;
   double v_max = 0;
+  double alpha = 0, beta = 0;     // Rayleigh damping
+  std::vector<double> mband;      // [n][bw+1] banded Cholesky factor of M~ (beta > 0)
+  std::vector<double> kband;      // [n][bw+1] lower band of K (beta > 0)
   std::vector<double> X;          // [n][3]
   std::vector<int32_t> tri;       // [m][3]
   std::vector<double> G;          // [m][3][2]

@@ -271,6 +271,29 @@ std::array<double, 4> rest_frame(V3 a, V3 b, V3 c) {
   return {1.0 / l1, -d12 / (l1 * l2), 0.0, 1.0 / l2};
 }
 
+// Cholesky A = C C^T (lower, FP64, dense storage) of an SPD matrix whose nonzeros lie within
+// bw of the diagonal; the factor keeps that band (zero fill outside it). False on a pivot
+// that is not positive.
+bool band_cholesky(const std::vector<double>& A, int n, int bw, std::vector<double>& C) {
+  C.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    int k0 = std::max(0, j - bw);
+    for (int k = k0; k < j; ++k) d -= C[(size_t)j * n + k] * C[(size_t)j * n + k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    double cjj = std::sqrt(d);
+    C[(size_t)j * n + j] = cjj;
+    int i1 = std::min(n - 1, j + bw);
+    for (int i = j + 1; i <= i1; ++i) {
+      double s = A[(size_t)i * n + j];
+      int kk = std::max(k0, i - bw);
+      for (int k = kk; k < j; ++k) s -= C[(size_t)i * n + k] * C[(size_t)j * n + k];
+      C[(size_t)i * n + j] = s / cjj;
+    }
+  }
+  return true;
+}
+
 }  // namespace
 
 npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, double dt,
@@ -284,7 +307,9 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   if (!(mat->density > 0) || mat->shear_B < 0 || mat->area_C < 0 || mat->k_bend < 0 ||
       mat->k_vol < 0 || !(mat->strain_min > 0) || mat->strain_max < mat->strain_min ||
       !(mat->pbd_kappa >= 0.0 && mat->pbd_kappa <= 1.0) ||
-      !(mat->v_max >= 0.0 && std::isfinite(mat->v_max)))
+      !(mat->v_max >= 0.0 && std::isfinite(mat->v_max)) ||
+      !(mat->rayleigh_alpha >= 0.0 && std::isfinite(mat->rayleigh_alpha)) ||
+      !(mat->rayleigh_beta >= 0.0 && std::isfinite(mat->rayleigh_beta)))
     return fail(NPFEM_E_INVALID, "material constants out of range");
 
   ct->n = n;
@@ -298,6 +323,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   ct->s_max = mat->strain_max;
   ct->kappa = mat->pbd_kappa;
   ct->v_max = mat->v_max;
+  ct->alpha = mat->rayleigh_alpha;
+  ct->beta = mat->rayleigh_beta;
   ct->X.assign(mesh->rest_xyz, mesh->rest_xyz + 3 * (size_t)n);
   ct->tri.assign(mesh->tri, mesh->tri + 3 * (size_t)m);
   for (double c : ct->X)
@@ -412,6 +439,31 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
       for (int q = 0; q < 4; ++q)
         L[(size_t)ct->hinge[4 * h + p] * n + ct->hinge[4 * h + q]] +=
             ct->w_b * ct->coef[4 * h + p] * ct->coef[4 * h + q];
+  // ---- Rayleigh damping C = alpha M + beta K, K the element part of L assembled above:
+  //      L = M~/h^2 + w_v I + K = ((1 + h alpha) m/h^2 + w_v) I + (1 + beta/h) K
+  const bool rayleigh = ct->alpha != 0.0 || ct->beta != 0.0;
+  std::vector<double> K;
+  if (rayleigh) {
+    K.assign((size_t)n * n, 0.0);   // the element part of L, summed from zero
+    for (int t = 0; t < m; ++t) {
+      const double w = (ct->w_s + ct->w_a) * ct->A[t];
+      const double* g = &ct->G[6 * (size_t)t];
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+          int vp = ct->tri[3 * t + p], vq = ct->tri[3 * t + q];
+          K[(size_t)vp * n + vq] += w * (g[2 * p] * g[2 * q] + g[2 * p + 1] * g[2 * q + 1]);
+        }
+    }
+    for (int h = 0; h < e; ++h)
+      for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 4; ++q)
+          K[(size_t)ct->hinge[4 * h + p] * n + ct->hinge[4 * h + q]] +=
+              ct->w_b * ct->coef[4 * h + p] * ct->coef[4 * h + q];
+    const double kb = 1.0 + ct->beta / dt;
+    const double dd = (1.0 + dt * ct->alpha) * ct->mass / (dt * dt) + ct->w_v;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) L[(size_t)i * n + j] = kb * K[(size_t)i * n + j] + (i == j ? dd : 0.0);
+  }
   int bw = 0;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j)
@@ -420,25 +472,29 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
 
   // ---- Cholesky L = C C^T (lower), FP64; zero fill outside the band is preserved
   std::vector<double>& C = ct->chol;
-  C.assign((size_t)n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    double d = L[(size_t)j * n + j];
-    int k0 = std::max(0, j - bw);
-    for (int k = k0; k < j; ++k) d -= C[(size_t)j * n + k] * C[(size_t)j * n + k];
-    if (!(d > 0.0) || !std::isfinite(d)) return fail(NPFEM_E_NOT_SPD, "Cholesky pivot <= 0");
-    double cjj = std::sqrt(d);
-    C[(size_t)j * n + j] = cjj;
-    int i1 = std::min(n - 1, j + bw);
-    for (int i = j + 1; i <= i1; ++i) {
-      double s = L[(size_t)i * n + j];
-      int kk = std::max(k0, i - bw);
-      for (int k = kk; k < j; ++k) s -= C[(size_t)i * n + k] * C[(size_t)j * n + k];
-      C[(size_t)i * n + j] = s / cjj;
-    }
-  }
+  if (!band_cholesky(L, n, bw, C)) return fail(NPFEM_E_NOT_SPD, "Cholesky pivot <= 0");
   ct->cband.assign((size_t)n * (bw + 1), 0.0);
   for (int i = 0; i < n; ++i)
     for (int k = 0; k <= bw && k <= i; ++k) ct->cband[(size_t)i * (bw + 1) + k] = C[(size_t)i * n + i - k];
+  // M~ = (1 + h alpha) m I + h beta K and the band of K, for the prediction's solve and the
+  // gradient's damping term (beta > 0; with alpha alone M~ is diagonal)
+  ct->mband.clear();
+  ct->kband.clear();
+  if (ct->beta > 0.0) {
+    std::vector<double> Mt((size_t)n * n), Cm;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        Mt[(size_t)i * n + j] = dt * ct->beta * K[(size_t)i * n + j] +
+                                (i == j ? (1.0 + dt * ct->alpha) * ct->mass : 0.0);
+    if (!band_cholesky(Mt, n, bw, Cm)) return fail(NPFEM_E_NOT_SPD, "Cholesky pivot of M~ <= 0");
+    ct->mband.assign((size_t)n * (bw + 1), 0.0);
+    ct->kband.assign((size_t)n * (bw + 1), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k <= bw && k <= i; ++k) {
+        ct->mband[(size_t)i * (bw + 1) + k] = Cm[(size_t)i * n + i - k];
+        ct->kband[(size_t)i * (bw + 1) + k] = K[(size_t)i * n + i - k];
+      }
+  }
 
   // ---- dense inverse: column by column through the factor (FP64)
   ct->Linv.assign((size_t)n * n, 0.0);
@@ -542,6 +598,11 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   ct->fused_ok = !feasible.empty();
   if (!ct->fused_ok) {
     ct->fused_reason = "mesh too large for the fused kernel's LDS layout (n <= 576)";
+    return NPFEM_OK;
+  }
+  if (ct->beta > 0.0) {
+    ct->fused_ok = false;
+    ct->fused_reason = "Rayleigh damping with beta > 0 runs in the plain form";
     return NPFEM_OK;
   }
   std::vector<std::vector<int>> tel(m), hel(e);

@@ -59,3 +59,66 @@ def test_damped_kicked_step_fused():
     err = cell_errors(b.types, b.offsets, xg, xo)[0]
     _say(f"fused damped kicked step: err/diam {err:.3e}")
     assert err <= 1e-7
+
+
+def _rayleigh_types(alpha, beta, kappa=None):
+    from paper_1911_03062_amd import npfem as N
+    inp = I.cell_type_inputs()
+    def mat(k, m):
+        m = m.with_rayleigh(alpha, beta)
+        return m.with_kappa(kappa[k]) if kappa else m
+    lt = {k: N.CellType(x, t, mat(k, m), I.DT) for k, (x, t, m) in inp.items()}
+    ot = {k: O.CellType(x, t, mat(k, m), I.DT) for k, (x, t, m) in inp.items()}
+    return lt, ot
+
+
+@pytest.mark.parametrize("precision,alpha,beta,kappa", [(64, 0.3, 0.05, None), (32, 0.3, 0.05, None),
+                                                         (64, 0.0, 0.02, KAPPA)])
+def test_rayleigh_plain_mixed_batch(precision, alpha, beta, kappa):
+    """Rayleigh damping (M~ solve in the prediction, (beta/h) K e in every gradient) in the
+    plain form, alone and with position-based damping, against the oracle."""
+    lt, ot = _rayleigh_types(alpha, beta, kappa)
+    tids = np.array([I.RBC] * 3 + [I.PLT] * 4, dtype=np.int32)
+    tids = tids[np.random.default_rng(170).permutation(len(tids))]
+    b = I.make_batch(tids, seed=170)
+    rng = np.random.default_rng(171)
+    v0 = rng.normal(0, 0.05, size=b.x0.shape).astype(np.float32).astype(np.float64)
+    forces = list(I.force_stream(b, seed=172, sigma=20.0, n_steps=4))
+    _say(f"case: Rayleigh plain FP{precision}, alpha {alpha}, beta {beta}, kappa {kappa}, "
+         f"3 RBC + 4 PLT, 4 steps")
+    xo, vo = run_oracle(ot, b.types, b.offsets, b.x0, v0, forces, 10)
+    xg, vg = run_gpu(lt, b.types, b.x0, v0, forces, 10, form="plain", precision=precision)
+    err = cell_errors(b.types, b.offsets, xg, xo)
+    xu, _ = run_oracle({k: O.CellType(x, t, m, I.DT) for k, (x, t, m) in I.cell_type_inputs().items()},
+                       b.types, b.offsets, b.x0, v0, forces, 10)
+    sep = cell_errors(b.types, b.offsets, xu, xo)
+    verr = np.abs(vg - vo).max() / np.abs(vo).max()
+    _say(f"Rayleigh plain FP{precision}: max err/diam {err.max():.3e}, v err {verr:.3e}, "
+         f"damped vs undamped {sep.min():.3e}")
+    if precision == 64:
+        assert err.max() <= 1e-10 and verr <= 1e-8
+    else:
+        assert err.max() <= 1e-5
+    assert sep.min() > 100 * err.max()
+
+
+def test_rayleigh_alpha_fused_and_beta_rejected():
+    """alpha alone (M~ = (1 + h alpha) M: a scaled prediction and mass term, L with that
+    mass) runs in the fused form; beta > 0 is reported as unsupported there."""
+    from paper_1911_03062_amd import npfem as N
+    lt, ot = _rayleigh_types(0.5, 0.0)
+    tids = np.array([I.RBC] * 5 + [I.PLT] * 9, dtype=np.int32)
+    b = I.make_batch(tids, seed=173)
+    rng = np.random.default_rng(174)
+    v0 = rng.normal(0, 0.05, size=b.x0.shape).astype(np.float32).astype(np.float64)
+    forces = list(I.force_stream(b, seed=175, sigma=20.0, n_steps=4))
+    _say("case: Rayleigh alpha 0.5 fused FP32, 5 RBC + 9 PLT, 4 steps")
+    xo, _ = run_oracle(ot, b.types, b.offsets, b.x0, v0, forces, 10)
+    xg, _ = run_gpu(lt, b.types, b.x0, v0, forces, 10)
+    err = cell_errors(b.types, b.offsets, xg, xo)
+    _say(f"Rayleigh alpha fused: max err/diam {err.max():.3e}")
+    assert err.max() <= 1e-5
+    lb, _ = _rayleigh_types(0.0, 0.05)
+    with pytest.raises(N.NpfemError) as ei:
+        N.Batch([lb[I.RBC]], precision=32, form="fused")
+    assert ei.value.name == "NPFEM_E_UNSUPPORTED"

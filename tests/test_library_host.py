@@ -77,6 +77,8 @@ def test_argument_errors():
     _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(pbd_kappa=-0.1)))
     _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(v_max=-1.0)))
     _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(v_max=float("inf"))))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(rayleigh_alpha=-0.1)))
+    _expect("NPFEM_E_INVALID", lambda: _create(x, t, I.Material(rayleigh_beta=float("nan"))))
     _expect("NPFEM_E_MESH", lambda: _create(x[:3], t[:3]))
 
 
@@ -96,3 +98,18 @@ def test_fused_layouts_of_the_cell_types():
     assert types[I.RBC].cells_per_wave() == [2, 1]
     assert types[I.PLT].cells_per_wave() == [8, 4, 2, 1]
     assert types[I.RBC].info()["tri_rounds"] >= 16    # pole valence bounds the rounds
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.5, 0.0), (0.0, 0.05), (0.3, 0.02)])
+def test_rayleigh_system_matrix_matches_oracle(alpha, beta):
+    """L = ((1 + h alpha) m/h^2 + w_v) I + (1 + beta/h) K from the host setup against the
+    oracle's; beta > 0 takes the type out of the fused form."""
+    x, t, m = I.cell_type_inputs()[I.RBC]
+    mat = m.with_rayleigh(alpha, beta)
+    ct = N.CellType(x, t, mat, I.DT)
+    oc = O.CellType(x, t, mat, I.DT)
+    assert np.abs(ct.matrix() - oc.L).max() <= 1e-13 * np.abs(oc.L).max()
+    if beta > 0:
+        assert ct.cells_per_wave() == []
+    else:
+        assert ct.cells_per_wave() != []
