@@ -271,6 +271,7 @@ struct npfem_batch {
   size_t filter_lds = 0;
   std::string filter_reason;                // non-empty: the filter is unavailable
   size_t lds_bytes = 0;
+  bool fused_extras = false;                // a type damps or caps velocities (kernel variant)
   void* work = nullptr;                     // plain-form workspace
   int* d_flag = nullptr;
   ~npfem_batch() {
@@ -515,6 +516,7 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
     b->offsets[c + 1] = b->offsets[c] + t->n;
   }
   for (npfem_celltype* t : b->types) {
+    b->fused_extras = b->fused_extras || t->kappa > 0.0 || t->v_max > 0.0;
     if (b->dt == 0) b->dt = t->h;
     if (std::fabs(t->h - b->dt) > 1e-12 * b->dt)
       return bail(fail(NPFEM_E_DT, "cell types of one batch must share dt"));
@@ -594,7 +596,7 @@ npfem_status step_fused(npfem_batch* b, const FusedGroup* groups, const int* cou
   hipError_t e = launch_fused_step(b->d_types, (int)b->types.size(), groups, count, b->n_groups,
                                    b->d_offsets, b->offsets.back(), (float*)x, (float*)v,
                                    (const float*)f, n_pd_iters, cell_volume_area, b->d_flag,
-                                   b->lds_bytes, stream);
+                                   b->lds_bytes, b->fused_extras, stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
   return NPFEM_OK;
 }

@@ -226,7 +226,9 @@ __device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const 
   return g * (1.0f / 6.0f);
 }
 
-template <int NQ>
+// EXTRAS: some type of the batch has position-based damping or a velocity cap; without them
+// the kernel is built without those code paths.
+template <int NQ, bool EXTRAS>
 __global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
              const int* __restrict__ n_groups_dev, const int64_t* __restrict__ offsets, int64_t vt,
@@ -278,7 +280,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     // recomputed from v and F when the step is written back. With position-based damping
     // each cell's centre of mass x_cm, its velocity v_cm, angular velocity w and first vertex
     // x_n[0] (kDampWords floats per cell after R) define the damped velocity used in delta^0.
-    const bool damp = T.p.kappa > 0.0;
+    const bool damp = EXTRAS && T.p.kappa > 0.0;
     const float kappa = (float)T.p.kappa;
     const float v_max = (float)T.p.v_max;
     float* Dm = R + G4 * CS;
@@ -697,7 +699,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           x[c * vt + off + vi] = xn;
           bad |= !finite_f(xn);
         }
-        cap_speed(vn[0], vn[1], vn[2], v_max);
+        if (EXTRAS) cap_speed(vn[0], vn[1], vn[2], v_max);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           v[c * vt + off + vi] = vn[c];
@@ -717,14 +719,19 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
                              const int* n_groups_dev, int max_groups, const int64_t* offsets,
                              int64_t vtot, float* x, float* v, const float* f, int K,
-                             double* vol_area, int* flag, size_t lds_bytes, void* stream) {
+                             double* vol_area, int* flag, size_t lds_bytes, bool extras,
+                             void* stream) {
   (void)n_types;
   if (max_groups == 0) return hipSuccess;
   // one workgroup per group up to a few waves of the chip; beyond that workgroups loop
   const int grid = max_groups < kMaxFusedGrid ? max_groups : kMaxFusedGrid;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_fused_step<kMaxItems>, dim3(grid), dim3(kFusedThreads), lds_bytes, s,
-                     types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, K, vol_area, flag);
+  if (extras)
+    hipLaunchKernelGGL((k_fused_step<kMaxItems, true>), dim3(grid), dim3(kFusedThreads), lds_bytes,
+                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, K, vol_area, flag);
+  else
+    hipLaunchKernelGGL((k_fused_step<kMaxItems, false>), dim3(grid), dim3(kFusedThreads), lds_bytes,
+                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, K, vol_area, flag);
   return hipGetLastError();
 }
 

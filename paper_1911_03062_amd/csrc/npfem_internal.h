@@ -231,7 +231,8 @@ hipError_t launch_plain_cell(int precision, const DevType* dt_dev, const TypePar
 hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
                              const int* n_groups_dev, int max_groups, const int64_t* offsets,
                              int64_t vtot, float* x, float* v, const float* f, int K,
-                             double* vol_area, int* flag, size_t lds_bytes, void* stream);
+                             double* vol_area, int* flag, size_t lds_bytes, bool extras,
+                             void* stream);
 hipError_t launch_median_filter(int precision, int net_keys, const DevType* types,
                                 const FilterBlock* blocks, int n_blocks, int64_t vt,
                                 const void* f, void* out, size_t lds_bytes, void* stream);
