@@ -72,9 +72,7 @@ typedef struct {
   double rayleigh_alpha;/* 1/us, Rayleigh damping C = alpha M + beta K (0, 0 = off), K the    */
   double rayleigh_beta; /* us,   constant strain + area + bending stiffness: M~ = M + h C     */
                         /* enters y_n = x_n + h M~^-1 (M v_n + h F_ext) and the mass term of */
-                        /* g, and L = M~/h^2 + k_vol I + K (npFEM subsection). beta > 0 runs */
-                        /* in the plain form only (the fused form reports                    */
-                        /* NPFEM_E_UNSUPPORTED); alpha alone runs in both                    */
+                        /* g, and L = M~/h^2 + k_vol I + K (npFEM subsection); both forms    */
 } npfem_material;
 
 typedef struct npfem_celltype npfem_celltype;   /* opaque, library-owned */

@@ -56,7 +56,7 @@ npfem_status fail(npfem_status s, const std::string& msg) {
 void free_devtype(DevType* d) {
   if (!d) return;
   // (schedules belong to the cell type's per-layout cache)
-  void* ptrs[] = {d->ring_info, d->ring_pairs, d->ring_nb8, d->ring_nb16, d->linv_tiles,
+  void* ptrs[] = {d->ring_info, d->ring_pairs, d->ring_nb8, d->ring_nb16, d->linv_tiles, d->pinv_tiles,
                   d->tri,       d->hinge,       d->vt_off,    d->vt_list,    d->vh_off,
                   d->vh_list,   d->G64,         d->G32,       d->A64,        d->A32,
                   d->coef64,    d->coef32,      d->rest64,    d->rest32,     d->cband64,
@@ -114,9 +114,21 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   const double ma = 1.0 + ct->h * ct->alpha;
   p.inv_h2m = ma * ct->mass / (ct->h * ct->h);
   p.h2_over_m = ct->h * ct->h / ct->mass;
-  p.pred_h = ct->h / ma;
-  p.pred_h2m = p.h2_over_m / ma;
   p.ray_k = ct->beta / ct->h;
+  if (ct->beta > 0.0) {
+    // the prediction is m M~^-1 (h v + h^2 F/m): the factor 1 / (1 + h alpha) is inside M~
+    p.pred_h = ct->h;
+    p.pred_h2m = p.h2_over_m;
+  } else {
+    p.pred_h = ct->h / ma;
+    p.pred_h2m = p.h2_over_m / ma;
+  }
+  // fused form: with d = (1 + h alpha) m/h^2 + w_v and c = (beta/h) / (1 + beta/h),
+  // (beta/h) K e = c (L e - d e), so the quasi-Newton update L^-1 grad g equals
+  // L^-1 [(inv_h2m - c d) e + rest of grad g] + c e: the gradient takes grad_mass instead of
+  // inv_h2m and the update subtracts c e
+  p.ray_c = ct->beta > 0.0 ? p.ray_k / (1.0 + p.ray_k) : 0.0;
+  p.grad_mass = p.inv_h2m - p.ray_c * (p.inv_h2m + ct->w_v);
   p.w_s = ct->w_s; p.w_a = ct->w_a; p.w_b = ct->w_b; p.w_v = ct->w_v;
   p.s_min = ct->s_min; p.s_max = ct->s_max; p.V0 = ct->V0; p.kappa = ct->kappa;
   p.v_max = ct->v_max;
@@ -152,19 +164,24 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
     // one are zero too (the kernel's look-ahead loads read them).
     const int RT = p.row_tiles, KS = p.k_steps, n = ct->n;
     const int KR = ct->npad / 4, C = kMfmaChunk, nch = (KR + C - 1) / C;
-    std::vector<float> lt((size_t)RT * KS * 64, 0.0f);
-    for (int rt = 0; rt < RT; ++rt)
-      for (int c = 0; c < nch; ++c)
-        for (int j = 0; j < C; ++j) {
-          const int s = std::min(c * C, KR - C) + j;
-          if (s < c * C) continue;   // covered by the previous chunk
-          for (int l = 0; l < 64; ++l) {
-            const int row = rt * 16 + (l & 15), col = 4 * s + (l >> 4);
-            if (row < n && col < n)
-              lt[((size_t)rt * KS + c * C + j) * 64 + l] = (float)ct->Linv[(size_t)row * n + col];
+    auto tiles = [&](const std::vector<double>& dense) {
+      std::vector<float> lt((size_t)RT * KS * 64, 0.0f);
+      for (int rt = 0; rt < RT; ++rt)
+        for (int c = 0; c < nch; ++c)
+          for (int j = 0; j < C; ++j) {
+            const int s = std::min(c * C, KR - C) + j;
+            if (s < c * C) continue;   // covered by the previous chunk
+            for (int l = 0; l < 64; ++l) {
+              const int row = rt * 16 + (l & 15), col = 4 * s + (l >> 4);
+              if (row < n && col < n)
+                lt[((size_t)rt * KS + c * C + j) * 64 + l] = (float)dense[(size_t)row * n + col];
+            }
           }
-        }
-    chk(upload(&d->linv_tiles, lt));
+      return lt;
+    };
+    chk(upload(&d->linv_tiles, tiles(ct->Linv)));
+    // Rayleigh damping with beta > 0: m M~^-1 in the same order, for the prediction
+    if (!ct->pinv.empty()) chk(upload(&d->pinv_tiles, tiles(ct->pinv)));
   }
   if (st != NPFEM_OK) {
     free_devtype(d);
@@ -516,7 +533,7 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
     b->offsets[c + 1] = b->offsets[c] + t->n;
   }
   for (npfem_celltype* t : b->types) {
-    b->fused_extras = b->fused_extras || t->kappa > 0.0 || t->v_max > 0.0;
+    b->fused_extras = b->fused_extras || t->kappa > 0.0 || t->v_max > 0.0 || t->beta > 0.0;
     if (b->dt == 0) b->dt = t->h;
     if (std::fabs(t->h - b->dt) > 1e-12 * b->dt)
       return bail(fail(NPFEM_E_DT, "cell types of one batch must share dt"));

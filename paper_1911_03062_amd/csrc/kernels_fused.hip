@@ -226,8 +226,8 @@ __device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const 
   return g * (1.0f / 6.0f);
 }
 
-// EXTRAS: some type of the batch has position-based damping or a velocity cap; without them
-// the kernel is built without those code paths.
+// EXTRAS: some type of the batch has position-based damping, a velocity cap or Rayleigh
+// damping with beta > 0; without them the kernel is built without those code paths.
 template <int NQ, bool EXTRAS>
 __global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
@@ -283,6 +283,14 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const bool damp = EXTRAS && T.p.kappa > 0.0;
     const float kappa = (float)T.p.kappa;
     const float v_max = (float)T.p.v_max;
+    // Rayleigh damping with beta > 0: delta^0 = m M~^-1 (h v + h^2 F/m) is one more product on
+    // the matrix cores (R = -(h v + h^2 F/m) first); delta^0 then waits in v for the
+    // write-back (v_n has been read by then)
+    const bool ray = EXTRAS && T.p.ray_c > 0.0;
+    // Rayleigh in the iteration: grad g takes grad_mass instead of m/h^2 and the update
+    // subtracts ray_c e (both the plain values for other types)
+    const float gmass = EXTRAS ? (float)T.p.grad_mass : ih2m;
+    const float ray_c = (float)T.p.ray_c;
     float* Dm = R + G4 * CS;
     float e[NQ][3];
 #pragma unroll
@@ -302,6 +310,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
             Xv[c] = xl;                       // x_n and v_n staged for the reductions
             Rv[c] = v[c * vt + off + vi];
             if (vi == 0) Dm[kDampWords * ITEM_C(it) + 9 + c] = x[c * vt + off];
+          } else if (ray) {
+            Xv[c] = xl;
+            Rv[c] = -(h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi]);
           } else {
             Xv[c] = xl + (h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi]);
           }
@@ -366,8 +377,13 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const float vdc[3] = {vd.x, vd.y, vd.z};
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            Xv[c] += h * vdc[c] + h2m * f[c * vt + off + vi];
-            Rv[c] = 0.0f;
+            const float b = h * vdc[c] + h2m * f[c * vt + off + vi];
+            if (ray) {
+              Rv[c] = -b;
+            } else {
+              Xv[c] += b;
+              Rv[c] = 0.0f;
+            }
           }
         }
     }
@@ -384,6 +400,97 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const int ncols = 3 * count, CT = (ncols + 15) / 16;
     const int n_units = RT * CT;
     const int u0 = (n_units * wave) / kFusedWaves, u1 = (n_units * (wave + 1)) / kFusedWaves;
+
+    // Products on the matrix cores: D = -A R for all 3 * cells columns of the group, A the
+    // type's tiles (L^-1, or m M~^-1 for the Rayleigh prediction). Column col = 3 cell + coord,
+    // row k = vertex: B(k, col) = R[cell][k][coord]. A work item is one tile or two
+    // neighbouring tiles of the wave's share: with two or more column tiles, two column
+    // tiles of one row tile (sharing every A fragment); with one column tile, two row tiles
+    // (sharing B). Each wave holds its tiles in registers until every wave has read R, then
+    // writes D over R.
+    auto global_product = [&](const float* tiles) {
+      f4 acc[kMaxTilesPerWave];
+#pragma unroll
+      for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+      int n_items = 0;
+      {
+        const gfloat* Lt = gptr(tiles) + lane;
+        const int kq = lane >> 4;
+        for (int u = u0; u < u1;) {
+          f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
+          if (CT >= 2) {
+            const int rt = u / CT, ct = u - rt * CT;
+            const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * kq);
+            if (ct + 1 < CT && u + 1 < u1) {
+              const lfloat* RbB =
+                  (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq);
+              mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
+              u += 2;
+            } else {
+              mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
+              u += 1;
+            }
+          } else {
+            const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * kq);
+            mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
+            if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
+            u += (u + 1 < u1) ? 2 : 1;
+          }
+          // keep the item's tiles at the end of the held set (indices stay compile-time)
+#pragma unroll
+          for (int i = 0; i + 2 < kMaxTilesPerWave; ++i) acc[i] = acc[i + 2];
+          acc[kMaxTilesPerWave - 2] = d0;
+          acc[kMaxTilesPerWave - 1] = d1;
+          ++n_items;
+        }
+      }
+      __syncthreads();
+      {
+        // replay the item sequence to place the held tiles
+        int u = u0;
+#pragma unroll
+        for (int q = 0; q < kMaxTilesPerWave / 2; ++q) {
+          if (q >= kMaxTilesPerWave / 2 - n_items) {
+            if (CT >= 2) {
+              const int rt = u / CT, ct = u - rt * CT;
+              write_tile(R, acc[2 * q], rt, ct, lane, n, ncols, CS);
+              if (ct + 1 < CT && u + 1 < u1) {
+                write_tile(R, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS);
+                u += 2;
+              } else {
+                u += 1;
+              }
+            } else {
+              write_tile(R, acc[2 * q], u, 0, lane, n, ncols, CS);
+              if (u + 1 < u1) write_tile(R, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS);
+              u += (u + 1 < u1) ? 2 : 1;
+            }
+          }
+        }
+      }
+    };
+
+    if (ray) {   // delta^0 = m M~^-1 (h v + h^2 F/m): R holds its negated right-hand side
+      global_product(T.pinv_tiles);
+      __syncthreads();
+      refresh_items(item);
+#pragma unroll
+      for (int it = 0; it < NQ; ++it)
+        if (ITEM_OK(it)) {
+          const int64_t off = off_lds[ITEM_C(it)];
+          const int vi = ITEM_V(it);
+          float* Rv = R + ITEM_W(it);
+          float* Xv = X + ITEM_W(it);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float d0 = Rv[c];
+            Xv[c] += d0;
+            v[c * vt + off + vi] = d0;   // kept for the write-back
+            Rv[c] = 0.0f;
+          }
+        }
+      __syncthreads();
+    }
 
     for (int k = 0; k < K; ++k) {
       // ---- volume constraint. R is zero here. Over the triangle rounds every triangle adds
@@ -460,7 +567,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           float* Rv = R + ITEM_W(it);
           const float lw = w_v * lam_lds[ITEM_C(it)];   // w_v lambda / 6
 #pragma unroll
-          for (int c = 0; c < 3; ++c) Rv[c] = ih2m * e[it][c] - lw * Rv[c];
+          for (int c = 0; c < 3; ++c) Rv[c] = gmass * e[it][c] - lw * Rv[c];
         }
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
@@ -547,12 +654,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       }
       __syncthreads();
-      // ---- global step: D = -L^-1 R on the matrix cores. Column col = 3 cell + coord,
-      // row k = vertex: B(k, col) = R[cell][k][coord]. A work item is one tile or two
-      // neighbouring tiles of the wave's share: with two or more column tiles, two column
-      // tiles of one row tile (sharing every A fragment); with one column tile, two row tiles
-      // (sharing B). Each wave holds its tiles in registers until every wave has read R, then
-      // writes D over R.
+      // ---- global step: D = -L^-1 R on the matrix cores (the product of global_product,
+      //      written out here: through the lambda the loop spills one more register)
       f4 acc[kMaxTilesPerWave];
 #pragma unroll
       for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
@@ -622,7 +725,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           float* Xv = X + ITEM_W(it);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float dd = Rv[c];
+            const float dd = EXTRAS ? Rv[c] - ray_c * e[it][c] : Rv[c];
             e[it][c] += dd;
             Xv[c] += dd;
             Rv[c] = 0.0f;   // R starts the next iteration at zero
@@ -681,7 +784,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           vin[c] = v[c * vt + off + vi];
           xin[c] = x[c * vt + off + vi];
         }
-        if (damp) {
+        if (damp && !ray) {
           const float* d = Dm + kDampWords * ITEM_C(it);
           const Vec3<float> xl = v3<float>(xin[0] - d[9], xin[1] - d[10], xin[2] - d[11]);
           const Vec3<float> vd = pbd_velocity<float>(v3<float>(vin[0], vin[1], vin[2]),
@@ -693,7 +796,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         float vn[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float dl = (h * vin[c] + h2m * f[c * vt + off + vi]) + e[it][c];
+          // with Rayleigh beta, v holds delta^0 since the start of the step
+          const float dl = ray ? vin[c] + e[it][c] : (h * vin[c] + h2m * f[c * vt + off + vi]) + e[it][c];
           const float xn = xin[c] + dl;
           vn[c] = dl * ih;
           x[c * vt + off + vi] = xn;

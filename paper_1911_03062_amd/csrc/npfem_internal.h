@@ -78,6 +78,8 @@ struct TypeParams {
                                 // (h and h^2/m over 1 + h alpha of Rayleigh damping)
   double ray_k;                 // beta / h of Rayleigh damping (0 = off): the gradient gains
                                 // ray_k K e and the prediction solves with M~
+  double ray_c;                 // fused form: c = ray_k / (1 + ray_k), the update's - c e
+  double grad_mass;             // fused form: the gradient's coefficient of e
 };
 
 // Device copy of a cell type's constants. Pointers are device pointers.
@@ -92,6 +94,7 @@ struct DevType {
   TriRec* tri_sched = nullptr;       // [tri_rounds][slots]
   HingeRec* hinge_sched = nullptr;   // [hinge_rounds][slots]
   float* linv_tiles = nullptr;       // [row_tiles][k_steps][64] MFMA A-operand order
+  float* pinv_tiles = nullptr;       // m M~^-1 in the same order (Rayleigh beta > 0)
   // plain form (both precisions)
   int32_t* tri = nullptr;            // [m][3]
   int32_t* hinge = nullptr;          // [e][4]
@@ -122,6 +125,7 @@ struct npfem_celltype {
   double alpha = 0, beta = 0;     // Rayleigh damping
   std::vector<double> mband;      // [n][bw+1] banded Cholesky factor of M~ (beta > 0)
   std::vector<double> kband;      // [n][bw+1] lower band of K (beta > 0)
+  std::vector<double> pinv;       // [n][n] m M~^-1 (beta > 0), the fused form's prediction
   std::vector<double> X;          // [n][3]
   std::vector<int32_t> tri;       // [m][3]
   std::vector<double> G;          // [m][3][2]

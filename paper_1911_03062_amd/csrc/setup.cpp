@@ -480,6 +480,7 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   // gradient's damping term (beta > 0; with alpha alone M~ is diagonal)
   ct->mband.clear();
   ct->kband.clear();
+  ct->pinv.clear();
   if (ct->beta > 0.0) {
     std::vector<double> Mt((size_t)n * n), Cm;
     for (int i = 0; i < n; ++i)
@@ -487,6 +488,24 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
         Mt[(size_t)i * n + j] = dt * ct->beta * K[(size_t)i * n + j] +
                                 (i == j ? (1.0 + dt * ct->alpha) * ct->mass : 0.0);
     if (!band_cholesky(Mt, n, bw, Cm)) return fail(NPFEM_E_NOT_SPD, "Cholesky pivot of M~ <= 0");
+    // m M~^-1 column by column through M~'s factor (fused form)
+    ct->pinv.assign((size_t)n * n, 0.0);
+    std::vector<double> col(n);
+    for (int c = 0; c < n; ++c) {
+      std::fill(col.begin(), col.end(), 0.0);
+      col[c] = ct->mass;
+      for (int i = 0; i < n; ++i) {
+        double s = col[i];
+        for (int k = std::max(0, i - bw); k < i; ++k) s -= Cm[(size_t)i * n + k] * col[k];
+        col[i] = s / Cm[(size_t)i * n + i];
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        double s = col[i];
+        for (int k = i + 1; k <= std::min(n - 1, i + bw); ++k) s -= Cm[(size_t)k * n + i] * col[k];
+        col[i] = s / Cm[(size_t)i * n + i];
+      }
+      for (int i = 0; i < n; ++i) ct->pinv[(size_t)i * n + c] = col[i];
+    }
     ct->mband.assign((size_t)n * (bw + 1), 0.0);
     ct->kband.assign((size_t)n * (bw + 1), 0.0);
     for (int i = 0; i < n; ++i)
@@ -600,11 +619,7 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     ct->fused_reason = "mesh too large for the fused kernel's LDS layout (n <= 576)";
     return NPFEM_OK;
   }
-  if (ct->beta > 0.0) {
-    ct->fused_ok = false;
-    ct->fused_reason = "Rayleigh damping with beta > 0 runs in the plain form";
-    return NPFEM_OK;
-  }
+
   std::vector<std::vector<int>> tel(m), hel(e);
   for (int t = 0; t < m; ++t) tel[t] = {ct->tri[3 * t], ct->tri[3 * t + 1], ct->tri[3 * t + 2]};
   for (int h = 0; h < e; ++h)

@@ -102,23 +102,26 @@ def test_rayleigh_plain_mixed_batch(precision, alpha, beta, kappa):
     assert sep.min() > 100 * err.max()
 
 
-def test_rayleigh_alpha_fused_and_beta_rejected():
-    """alpha alone (M~ = (1 + h alpha) M: a scaled prediction and mass term, L with that
-    mass) runs in the fused form; beta > 0 is reported as unsupported there."""
-    from paper_1911_03062_amd import npfem as N
-    lt, ot = _rayleigh_types(0.5, 0.0)
+@pytest.mark.parametrize("alpha,beta,kappa", [(0.5, 0.0, None), (0.3, 0.05, None), (0.0, 0.01, KAPPA)])
+def test_rayleigh_fused_mixed_batch(alpha, beta, kappa):
+    """The fused form: alpha alone scales the prediction and the mass term; beta adds the
+    m M~^-1 product for the prediction and the (beta/h) K e term through the L^-1 product
+    (grad_mass and - c e); also with position-based damping (the paper's beta_D = 0.01)."""
+    lt, ot = _rayleigh_types(alpha, beta, kappa)
     tids = np.array([I.RBC] * 5 + [I.PLT] * 9, dtype=np.int32)
+    tids = tids[np.random.default_rng(176).permutation(len(tids))]
     b = I.make_batch(tids, seed=173)
     rng = np.random.default_rng(174)
     v0 = rng.normal(0, 0.05, size=b.x0.shape).astype(np.float32).astype(np.float64)
     forces = list(I.force_stream(b, seed=175, sigma=20.0, n_steps=4))
-    _say("case: Rayleigh alpha 0.5 fused FP32, 5 RBC + 9 PLT, 4 steps")
-    xo, _ = run_oracle(ot, b.types, b.offsets, b.x0, v0, forces, 10)
-    xg, _ = run_gpu(lt, b.types, b.x0, v0, forces, 10)
+    _say(f"case: Rayleigh fused FP32, alpha {alpha}, beta {beta}, kappa {kappa}, 5 RBC + 9 PLT, 4 steps")
+    xo, vo = run_oracle(ot, b.types, b.offsets, b.x0, v0, forces, 10)
+    xg, vg = run_gpu(lt, b.types, b.x0, v0, forces, 10)
     err = cell_errors(b.types, b.offsets, xg, xo)
-    _say(f"Rayleigh alpha fused: max err/diam {err.max():.3e}")
+    xu, _ = run_oracle({k: O.CellType(x, t, m, I.DT) for k, (x, t, m) in I.cell_type_inputs().items()},
+                       b.types, b.offsets, b.x0, v0, forces, 10)
+    sep = cell_errors(b.types, b.offsets, xu, xo)
+    verr = np.abs(vg - vo).max() / np.abs(vo).max()
+    _say(f"Rayleigh fused: max err/diam {err.max():.3e}, v err {verr:.3e}, damped vs undamped {sep.min():.3e}")
     assert err.max() <= 1e-5
-    lb, _ = _rayleigh_types(0.0, 0.05)
-    with pytest.raises(N.NpfemError) as ei:
-        N.Batch([lb[I.RBC]], precision=32, form="fused")
-    assert ei.value.name == "NPFEM_E_UNSUPPORTED"
+    assert sep.min() > 100 * err.max()
