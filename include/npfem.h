@@ -137,7 +137,7 @@ int64_t npfem_batch_vertex_count(const npfem_batch* batch);
  *   cell_volume_area  optional device double [n_cells][2]: enclosed volume and surface
  *               area of each cell at x_{n+1} (FP64 reductions), or NULL.
  * Buffers are caller-owned and borrowed for the duration of the enqueued work.
- * n_pd_iters = 0 returns the prediction x_n + h v_n + h^2 F/m (free flight).
+ * n_pd_iters = 0 returns the prediction y_n (x_n + h v_n + h^2 F/m without damping).
  * Errors: NPFEM_E_INVALID (null buffer, n_pd_iters < 0), NPFEM_E_DT, NPFEM_E_HIP.
  * A non-finite result is flagged on the device; npfem_batch_check reports it.
  */
