@@ -32,6 +32,10 @@ w/2 ||A x - p(x)||^2 with exact projections p:
     without the mass and volume terms): M~ = M + h C enters y_n and g(x) as in the
     minimisation form (npFEM subsection), and the quasi-Newton matrix becomes
     M~/h^2 + w_v I + K; alpha in 1/us and beta in us (the solver's time unit);
+  * optional collision energies (particle-in-kernel technique, supplementary material): for a
+    vertex in contact, (w_i/2) ||x_i - p_i||^2 toward the projection point p_i of the closest
+    foreign particle, added to g and its gradient but not to L (the caller supplies p and w,
+    and zeroes F_ext at contacting vertices as the technique prescribes);
   * optional capping of the new vertex velocities at v_max (the velocity truncation for the
     stability of the immersed-boundary coupling, Fluid-structure interaction subsection);
 Everything is float64, vectorised over the cells of one type (arrays [N][n][3]).
@@ -338,8 +342,9 @@ def _mass_term(ct, d):
     return (np.einsum("ij,njd->nid", ct.Mt, d)) / ct.h ** 2
 
 
-def gradient(x, y, ct):
-    """grad g(x) [N][n][3] with projections recomputed at x (local step of the iteration)."""
+def gradient(x, y, ct, contacts=None):
+    """grad g(x) [N][n][3] with projections recomputed at x (local step of the iteration);
+    contacts = (p [N][n][3], w [N][n]) adds w (x - p)."""
     N = x.shape[0]
     F = deformation_gradients(x, ct)
     p_s, p_a = triangle_projections(F, ct)
@@ -351,6 +356,9 @@ def gradient(x, y, ct):
     g += _scatter_triangles(ct, M, N)
     g += _scatter_hinges(ct, ct.w_b * (u - p_b), N)
     g += ct.w_v * (x - p_v)
+    if contacts is not None:
+        p_c, w_c = contacts
+        g += w_c[..., None] * (x - p_c)
     return g
 
 
@@ -370,8 +378,8 @@ def pd_rhs(x, y, ct):
     return b
 
 
-def energy(x, y, ct):
-    """g(x) per cell [N] with projections at x."""
+def energy(x, y, ct, contacts=None):
+    """g(x) per cell [N] with projections at x (and the contact energies, if any)."""
     F = deformation_gradients(x, ct)
     p_s, p_a = triangle_projections(F, ct)
     u = bending_vectors(x, ct)
@@ -382,6 +390,9 @@ def energy(x, y, ct):
     e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_a, (F - p_a) ** 2)
     e += 0.5 * ct.w_b * np.einsum("ned,ned->n", u - p_b, u - p_b)
     e += 0.5 * ct.w_v * np.einsum("nid,nid->n", x - p_v, x - p_v)
+    if contacts is not None:
+        p_c, w_c = contacts
+        e += 0.5 * np.einsum("ni,nid,nid->n", w_c, x - p_c, x - p_c)
     return e
 
 
@@ -439,14 +450,16 @@ def predict(x, v, f, ct):
 
 
 def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
-         history: list | None = None):
+         history: list | None = None, contacts=None):
     """One implicit-Euler step for N cells of one type; x, v, f are [N][n][3] float64.
 
     The iteration starts at x^0 = y and performs ``n_iters`` quasi-Newton updates
     x^{k+1} = x^k - L^-1 grad g(x^k) (form "qn") or the algebraically identical
     projective-dynamics updates x^{k+1} = L^-1 rhs(x^k) (form "pd"). n_iters = 0 returns
     the prediction. Returns (x_{n+1}, v_{n+1}) with v_{n+1} = (x_{n+1} - x_n)/h, capped at
-    the type's v_max when it has one (positions are not changed by the cap).
+    the type's v_max when it has one (positions are not changed by the cap). contacts =
+    (p [N][n][3], w [N][n]) adds the collision energies (quasi-Newton form only: they enter
+    grad g, not L).
     """
     x = np.asarray(x, dtype=np.float64)
     y = predict(x, v, f, ct)
@@ -455,8 +468,10 @@ def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
         history.append(xk.copy())
     for _ in range(n_iters):
         if form == "qn":
-            xk = xk - solve(ct, gradient(xk, y, ct), method)
+            xk = xk - solve(ct, gradient(xk, y, ct, contacts), method)
         elif form == "pd":
+            if contacts is not None:
+                raise ValueError("contacts enter the quasi-Newton form only")
             xk = solve(ct, pd_rhs(xk, y, ct), method)
         else:
             raise ValueError(form)
@@ -505,11 +520,13 @@ def cap_velocities(v, v_max: float):
 # ----------------------------------------------------------------------------------------
 
 
-def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=None):
+def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=None,
+               contact_p=None, contact_w=None):
     """Advance the listed cells (default: all) of a SoA batch; returns new (x, v) copies.
 
     cell_types maps type id -> CellType; x, v, f are float64 [3][V_total].
-    Cells of the same type are stepped together (they are independent).
+    Cells of the same type are stepped together (they are independent). contact_p [3][V_total]
+    and contact_w [V_total] give the collision energies (w = 0: no contact).
     """
     types = np.asarray(types)
     offsets = np.asarray(offsets)
@@ -523,7 +540,10 @@ def step_batch(cell_types: dict, types, offsets, x, v, f, n_iters: int, cells=No
         xs = np.transpose(x[:, idx], (1, 2, 0))
         vs = np.transpose(v[:, idx], (1, 2, 0))
         fs = np.transpose(f[:, idx], (1, 2, 0))
-        xn, vn = step(ct, xs, vs, fs, n_iters)
+        contacts = None
+        if contact_w is not None:
+            contacts = (np.transpose(contact_p[:, idx], (1, 2, 0)), contact_w[idx])
+        xn, vn = step(ct, xs, vs, fs, n_iters, contacts=contacts)
         xo[:, idx] = np.transpose(xn, (2, 0, 1))
         vo[:, idx] = np.transpose(vn, (2, 0, 1))
     return xo, vo

@@ -640,3 +640,45 @@ def test_rayleigh_quasi_newton_equals_projective_dynamics():
     a, _ = O.step(ct, x, v, f, 4, form="qn")
     b, _ = O.step(ct, x, v, f, 4, form="pd")
     assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
+
+
+# ------------------------------------------------------- collision energies (PIK, f2 part)
+
+
+def _contacts(x, seed, frac=0.15, w=400.0, gap=0.3):
+    rng = np.random.default_rng(seed)
+    N, n, _ = x.shape
+    wc = np.where(rng.random((N, n)) < frac, w, 0.0)
+    pc = x + gap * rng.normal(size=x.shape)
+    return pc, wc
+
+
+def test_contacts_with_zero_weight_change_nothing():
+    x0, t, m, x = _deformed_plt(80)
+    ct = O.CellType(x0, t, m, I.DT)
+    rng = np.random.default_rng(81)
+    v, f = 0.05 * rng.normal(size=x.shape), 10.0 * rng.normal(size=x.shape)
+    pc, _ = _contacts(x, 82)
+    a, va = O.step(ct, x, v, f, 6)
+    b, vb = O.step(ct, x, v, f, 6, contacts=(pc, np.zeros(x.shape[:2])))
+    assert np.array_equal(a, b) and np.array_equal(va, vb)
+
+
+def test_converged_step_with_contacts_satisfies_newtons_law():
+    """At convergence the contact energies act as forces -w (x1 - p) in the implicit-Euler
+    equation of motion: F_int(x1) + F_ext - w (x1 - p) = M (v1 - v0)/h, with F_int from the
+    gradient at y = x (no mass term, no contacts) and the contact force written out here."""
+    x0, t, m = I.cell_type_inputs()[I.RBC]
+    x = x0[None] + 0.02 * np.random.default_rng(83).normal(size=(1,) + x0.shape)
+    ct = O.CellType(x0, t, m, I.DT)
+    rng = np.random.default_rng(84)
+    v0, f = 0.05 * rng.normal(size=x.shape), 10.0 * rng.normal(size=x.shape)
+    pc, wc = _contacts(x, 85, gap=0.1)
+    x1, v1 = O.step(ct, x, v0, f, 100, contacts=(pc, wc))
+    res = -O.gradient(x1, x1, ct) + f - wc[..., None] * (x1 - pc) - ct.mass * (v1 - v0) / I.DT
+    scale = np.abs(ct.mass * (v1 - v0) / I.DT).max() + np.abs(f).max()
+    assert np.abs(res).max() <= 1e-10 * scale, np.abs(res).max() / scale   # 5e-14 here
+    # the contacts pull: every contacting vertex ends closer to its point than without them
+    xf, _ = O.step(ct, x, v0, f, 100)
+    on = wc > 0
+    assert np.all(np.linalg.norm(x1 - pc, axis=-1)[on] < np.linalg.norm(xf - pc, axis=-1)[on])
