@@ -146,6 +146,24 @@ npfem_status npfem_step(npfem_batch* batch, void* x, void* v, const void* ext_fo
                         double* cell_volume_area);
 
 /*
+ * npfem_step with collision energies (particle-in-kernel technique, supplementary material):
+ * for every vertex i with contact_w[i] > 0, the energy (contact_w[i]/2) ||x_i - p_i||^2 toward
+ * its projection point p_i (the desired location given by the closest foreign particle) is
+ * added to g, so grad g gains contact_w[i] (x_i - p_i); the system matrix is unchanged. The
+ * caller finds the contacts and zeroes ext_forces at contacting vertices (the technique
+ * replaces the fluid force there). The iteration contracts while contact_w stays well below
+ * the diagonal of L (m/h^2 + ...: about 3.6e4 pN/um for the RBC of the workloads).
+ *   contact_p  device, in, [3][V_total] projection points (um), batch precision;
+ *   contact_w  device, in, [V_total] weights (pN/um), 0 = no contact, batch precision.
+ * Both NULL: exactly npfem_step. Errors: as npfem_step, and NPFEM_E_INVALID when only one of
+ * the two is given. Not recorded by npfem_graph_create.
+ */
+npfem_status npfem_step_contacts(npfem_batch* batch, void* x, void* v, const void* ext_forces,
+                                 double dt, int32_t n_pd_iters, void* stream,
+                                 double* cell_volume_area, const void* contact_p,
+                                 const void* contact_w);
+
+/*
  * Restrict the following npfem_step calls of a fused-form batch to a subset of its cells
  * (continuous batching: the union of the cells of the requests admitted to one tick).
  * cell_ids: host array of n distinct cell ids of the batch, read during the call; NULL or

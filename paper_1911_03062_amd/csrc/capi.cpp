@@ -609,11 +609,13 @@ struct DeviceGuard {
 
 npfem_status step_fused(npfem_batch* b, const FusedGroup* groups, const int* count, void* x,
                         void* v, const void* f, int32_t n_pd_iters, void* stream,
-                        double* cell_volume_area) {
+                        double* cell_volume_area, const void* cp = nullptr,
+                        const void* cw = nullptr) {
   hipError_t e = launch_fused_step(b->d_types, (int)b->types.size(), groups, count, b->n_groups,
                                    b->d_offsets, b->offsets.back(), (float*)x, (float*)v,
-                                   (const float*)f, n_pd_iters, cell_volume_area, b->d_flag,
-                                   b->lds_bytes, b->fused_extras, stream);
+                                   (const float*)f, (const float*)cp, (const float*)cw, n_pd_iters,
+                                   cell_volume_area, b->d_flag, b->lds_bytes, b->fused_extras,
+                                   stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
   return NPFEM_OK;
 }
@@ -624,9 +626,18 @@ extern "C" {
 
 npfem_status npfem_step(npfem_batch* b, void* x, void* v, const void* f, double dt,
                         int32_t n_pd_iters, void* stream, double* cell_volume_area) {
+  return npfem_step_contacts(b, x, v, f, dt, n_pd_iters, stream, cell_volume_area, nullptr,
+                             nullptr);
+}
+
+npfem_status npfem_step_contacts(npfem_batch* b, void* x, void* v, const void* f, double dt,
+                                 int32_t n_pd_iters, void* stream, double* cell_volume_area,
+                                 const void* contact_p, const void* contact_w) {
   if (!b) return fail(NPFEM_E_INVALID, "batch is null");
   if (b->n_cells == 0) return NPFEM_OK;
   if (!x || !v || !f) return fail(NPFEM_E_INVALID, "null state or force buffer");
+  if ((contact_p == nullptr) != (contact_w == nullptr))
+    return fail(NPFEM_E_INVALID, "contact points and weights go together");
   if (n_pd_iters < 0) return fail(NPFEM_E_INVALID, "n_pd_iters < 0");
   if (!(std::fabs(dt - b->dt) <= 1e-12 * b->dt))
     return fail(NPFEM_E_DT, "dt differs from the cell types' factorised dt");
@@ -637,7 +648,7 @@ npfem_status npfem_step(npfem_batch* b, void* x, void* v, const void* f, double 
     for (int c = 0; c < b->n_cells; ++c) {
       const int ti = b->type_of[c];
       hipError_t e = launch_plain_cell(b->precision, b->d_types + ti, b->dev_types[ti]->p, x, v, f,
-                                       vtot, b->offsets[c], n_pd_iters, b->work,
+                                       contact_p, contact_w, vtot, b->offsets[c], n_pd_iters, b->work,
                                        cell_volume_area ? cell_volume_area + 2 * (int64_t)c : nullptr,
                                        b->d_flag, stream);
       if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("plain launch: ") + hipGetErrorString(e));
@@ -646,7 +657,8 @@ npfem_status npfem_step(npfem_batch* b, void* x, void* v, const void* f, double 
   }
   const FusedGroup* groups = b->ring_cur < 0 ? b->d_groups : b->d_ring[b->ring_cur];
   const int* count = b->ring_cur < 0 ? b->d_count_all : b->d_ring_count[b->ring_cur];
-  return step_fused(b, groups, count, x, v, f, n_pd_iters, stream, cell_volume_area);
+  return step_fused(b, groups, count, x, v, f, n_pd_iters, stream, cell_volume_area, contact_p,
+                    contact_w);
 }
 
 npfem_status npfem_batch_set_active(npfem_batch* b, const int32_t* cell_ids, int32_t n,

@@ -227,12 +227,14 @@ __device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const 
 }
 
 // EXTRAS: some type of the batch has position-based damping, a velocity cap or Rayleigh
-// damping with beta > 0; without them the kernel is built without those code paths.
+// damping with beta > 0, or the step has contacts (cp, cw: collision points [3][V] and
+// weights [V]); without them the kernel is built without those code paths.
 template <int NQ, bool EXTRAS>
 __global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
              const int* __restrict__ n_groups_dev, const int64_t* __restrict__ offsets, int64_t vt,
-             float* __restrict__ x, float* __restrict__ v, const float* __restrict__ f, int K,
+             float* __restrict__ x, float* __restrict__ v, const float* __restrict__ f,
+             const float* __restrict__ cp, const float* __restrict__ cw, int K,
              double* __restrict__ vol_area, int* __restrict__ flag) {
   extern __shared__ float lds[];
   __shared__ float lam_lds[kMaxGroupCells];
@@ -568,6 +570,17 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const float lw = w_v * lam_lds[ITEM_C(it)];   // w_v lambda / 6
 #pragma unroll
           for (int c = 0; c < 3; ++c) Rv[c] = gmass * e[it][c] - lw * Rv[c];
+          if (EXTRAS && cw != nullptr) {   // collision energy: w (x - p), x = x_n[0] + X
+            const int64_t off = off_lds[ITEM_C(it)];
+            const int vi = ITEM_V(it);
+            const float wc = cw[off + vi];
+            if (wc != 0.0f) {
+              const float* Xv = X + ITEM_W(it);
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                Rv[c] += wc * ((x[c * vt + off] - cp[c * vt + off + vi]) + Xv[c]);
+            }
+          }
         }
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
@@ -822,20 +835,22 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 
 hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
                              const int* n_groups_dev, int max_groups, const int64_t* offsets,
-                             int64_t vtot, float* x, float* v, const float* f, int K,
-                             double* vol_area, int* flag, size_t lds_bytes, bool extras,
-                             void* stream) {
+                             int64_t vtot, float* x, float* v, const float* f, const float* cp,
+                             const float* cw, int K, double* vol_area, int* flag, size_t lds_bytes,
+                             bool extras, void* stream) {
   (void)n_types;
   if (max_groups == 0) return hipSuccess;
   // one workgroup per group up to a few waves of the chip; beyond that workgroups loop
   const int grid = max_groups < kMaxFusedGrid ? max_groups : kMaxFusedGrid;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (extras)
+  if (extras || cw != nullptr)
     hipLaunchKernelGGL((k_fused_step<kMaxItems, true>), dim3(grid), dim3(kFusedThreads), lds_bytes,
-                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, K, vol_area, flag);
+                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, cp, cw, K,
+                       vol_area, flag);
   else
     hipLaunchKernelGGL((k_fused_step<kMaxItems, false>), dim3(grid), dim3(kFusedThreads), lds_bytes,
-                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, K, vol_area, flag);
+                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, nullptr, nullptr,
+                       K, vol_area, flag);
   return hipGetLastError();
 }
 

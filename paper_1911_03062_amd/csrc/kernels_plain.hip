@@ -164,11 +164,12 @@ struct PlainConst<double> {
   static __device__ const double* kband(const DevType& t) { return t.kband64; }
 };
 
-// Local step: projections of every constraint at x^k and assembly of grad g(x^k) into r.
+// Local step: projections of every constraint at x^k and assembly of grad g(x^k) into r,
+// with the collision energies' w (x - p) when contacts are given (cp, cw: [3][V], [V]).
 template <typename T>
 __global__ void __launch_bounds__(kPlainThreads)
 k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t vt, int64_t off,
-              void* work) {
+              void* work, const T* __restrict__ cp, const T* __restrict__ cw) {
   const DevType& dt = *dtp;
   const TypeParams& p = dt.p;
   const int n = p.n, m = p.m, e = p.e;
@@ -246,6 +247,11 @@ k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t 
       for (int s = dt.vt_off[i]; s < dt.vt_off[i + 1]; ++s) acc += w.tcon[3 * dt.vt_list[s] + c];
       for (int s = dt.vh_off[i]; s < dt.vh_off[i + 1]; ++s) acc += w.hcon[3 * dt.vh_list[s] + c];
       acc -= lam_w * w.gv[c * n + i];
+      if (cw != nullptr) {
+        const T wc = cw[off + i];
+        if (wc != T(0))   // x - p = (x_n - p) + delta
+          acc += wc * ((x[c * vt + off + i] - cp[c * vt + off + i]) + w.d[c * n + i]);
+      }
       w.r[c * n + i] = acc;
     }
   }
@@ -348,15 +354,15 @@ k_plain_finalize(const DevType* __restrict__ dtp, T* __restrict__ x, T* __restri
 
 template <typename T>
 hipError_t plain_step_t(const DevType* dt_dev, const TypeParams& p, T* x, T* v, const T* f,
-                        int64_t vt, int64_t off, int K, void* work, double* vol_area, int* flag,
-                        hipStream_t s) {
+                        const T* cp, const T* cw, int64_t vt, int64_t off, int K, void* work,
+                        double* vol_area, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_plain_predict<T>, dim3(1), dim3(kPlainThreads), 0, s, p, x, v, f, vt,
                      off, work);
   if (p.ray_k > 0.0)
     hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, true);
   for (int k = 0; k < K; ++k) {
     hipLaunchKernelGGL(k_plain_local<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt, off,
-                       work);
+                       work, cp, cw);
     hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, false);
   }
   hipLaunchKernelGGL(k_plain_finalize<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, v, vt,
@@ -374,14 +380,16 @@ size_t plain_work_bytes(int precision, int n, int m, int e) {
 bool plain_supported(int n, int bw) { return n <= kMaxBand && bw < kMaxBand; }
 
 hipError_t launch_plain_cell(int precision, const DevType* dt_dev, const TypeParams& p, void* x,
-                             void* v, const void* f, int64_t vtot, int64_t off, int K,
-                             void* work, double* vol_area, int* flag, void* stream) {
+                             void* v, const void* f, const void* cp, const void* cw, int64_t vtot,
+                             int64_t off, int K, void* work, double* vol_area, int* flag,
+                             void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (precision == 64)
-    return plain_step_t<double>(dt_dev, p, (double*)x, (double*)v, (const double*)f, vtot, off, K,
-                                work, vol_area, flag, s);
-  return plain_step_t<float>(dt_dev, p, (float*)x, (float*)v, (const float*)f, vtot, off, K,
-                             work, vol_area, flag, s);
+    return plain_step_t<double>(dt_dev, p, (double*)x, (double*)v, (const double*)f,
+                                (const double*)cp, (const double*)cw, vtot, off, K, work, vol_area,
+                                flag, s);
+  return plain_step_t<float>(dt_dev, p, (float*)x, (float*)v, (const float*)f, (const float*)cp,
+                             (const float*)cw, vtot, off, K, work, vol_area, flag, s);
 }
 
 }  // namespace npfem

@@ -230,13 +230,14 @@ static_assert(sizeof(FilterBlock) % 16 == 0, "FilterBlock is read as whole dword
 size_t plain_work_bytes(int precision, int n, int m, int e);
 bool plain_supported(int n, int bw);
 hipError_t launch_plain_cell(int precision, const DevType* dt_dev, const TypeParams& p, void* x,
-                             void* v, const void* f, int64_t vtot, int64_t off, int K,
-                             void* work, double* vol_area, int* flag, void* stream);
+                             void* v, const void* f, const void* cp, const void* cw, int64_t vtot,
+                             int64_t off, int K, void* work, double* vol_area, int* flag,
+                             void* stream);
 hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
                              const int* n_groups_dev, int max_groups, const int64_t* offsets,
-                             int64_t vtot, float* x, float* v, const float* f, int K,
-                             double* vol_area, int* flag, size_t lds_bytes, bool extras,
-                             void* stream);
+                             int64_t vtot, float* x, float* v, const float* f, const float* cp,
+                             const float* cw, int K, double* vol_area, int* flag, size_t lds_bytes,
+                             bool extras, void* stream);
 hipError_t launch_median_filter(int precision, int net_keys, const DevType* types,
                                 const FilterBlock* blocks, int n_blocks, int64_t vt,
                                 const void* f, void* out, size_t lds_bytes, void* stream);

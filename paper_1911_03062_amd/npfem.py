@@ -81,6 +81,9 @@ def lib() -> ctypes.CDLL:
     L.npfem_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                              c_void_p, c_void_p]
     L.npfem_step.restype = c_int32
+    L.npfem_step_contacts.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
+                                      c_void_p, c_void_p, c_void_p, c_void_p]
+    L.npfem_step_contacts.restype = c_int32
     L.npfem_batch_set_active.argtypes = [c_void_p, POINTER(c_int32), c_int32, c_void_p]
     L.npfem_batch_set_active.restype = c_int32
     L.npfem_batch_check.argtypes = [c_void_p, c_void_p]
@@ -195,11 +198,20 @@ class Batch:
     def vertex_count(self) -> int:
         return int(self.offsets[-1])
 
-    def step(self, x, v, f, dt: float, n_pd_iters: int, vol_area=None, stream=None):
-        """Advance in place; x, v, f are device tensors [3][V_total] of the batch's dtype."""
+    def step(self, x, v, f, dt: float, n_pd_iters: int, vol_area=None, stream=None,
+             contacts=None):
+        """Advance in place; x, v, f are device tensors [3][V_total] of the batch's dtype.
+        contacts = (p [3][V_total], w [V_total]) adds the collision energies."""
         import torch
         dtype = torch.float64 if self.precision == 64 else torch.float32
-        for name, t in (("x", x), ("v", v), ("f", f)):
+        cp = cw = 0
+        if contacts is not None:
+            p_, w_ = contacts
+            if not (w_.is_cuda and w_.dtype == dtype and w_.is_contiguous()
+                    and tuple(w_.shape) == (self.vertex_count,)):
+                raise ValueError(f"contact weights must be a contiguous device tensor [{self.vertex_count}] of {dtype}")
+            cp, cw = p_, w_
+        for name, t in (("x", x), ("v", v), ("f", f)) + ((("contact points", cp),) if contacts is not None else ()):
             if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()
                     and tuple(t.shape) == (3, self.vertex_count)):
                 raise ValueError(f"{name} must be a contiguous device tensor [3][{self.vertex_count}] of {dtype}")
@@ -210,8 +222,14 @@ class Batch:
                 raise ValueError("vol_area must be a contiguous float64 device tensor [n_cells][2]")
             va = vol_area.data_ptr()
         s = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().npfem_step(self._h, x.data_ptr(), v.data_ptr(), f.data_ptr(), float(dt),
-                                int(n_pd_iters), c_void_p(s.cuda_stream), c_void_p(va)))
+        if contacts is None:
+            _check(lib().npfem_step(self._h, x.data_ptr(), v.data_ptr(), f.data_ptr(), float(dt),
+                                    int(n_pd_iters), c_void_p(s.cuda_stream), c_void_p(va)))
+        else:
+            _check(lib().npfem_step_contacts(self._h, x.data_ptr(), v.data_ptr(), f.data_ptr(),
+                                             float(dt), int(n_pd_iters), c_void_p(s.cuda_stream),
+                                             c_void_p(va), c_void_p(cp.data_ptr()),
+                                             c_void_p(cw.data_ptr())))
 
     def filter_forces(self, f_in, f_out=None, stream=None):
         """One-ring median filter of external forces [3][V_total] into f_out (default: in
