@@ -46,17 +46,22 @@ class Material:
     v_max: float = 0.0        # velocity cap, 0 = off
     rayleigh_alpha: float = 0.0   # Rayleigh damping C = alpha M + beta K: alpha in 1/us
     rayleigh_beta: float = 0.0    # beta in us (alpha_D, beta_D of the table)
+    membrane: str = "pd"          # "pd" constraints or the "skalak" strain energy
 
     def scaled(self, s: float) -> "Material":
         return Material(self.density, self.shear_B * s, self.area_C * s, self.skalak_D * s,
                         self.k_bend * s, self.k_vol * s, self.strain_min, self.strain_max,
-                        self.pbd_kappa, self.v_max, self.rayleigh_alpha, self.rayleigh_beta)
+                        self.pbd_kappa, self.v_max, self.rayleigh_alpha, self.rayleigh_beta,
+                        self.membrane)
 
     def with_kappa(self, kappa: float) -> "Material":
         return dataclasses.replace(self, pbd_kappa=kappa)
 
     def with_v_max(self, v_max: float) -> "Material":
         return dataclasses.replace(self, v_max=v_max)
+
+    def with_membrane(self, membrane: str) -> "Material":
+        return dataclasses.replace(self, membrane=membrane)
 
     def with_rayleigh(self, alpha: float, beta: float) -> "Material":
         return dataclasses.replace(self, rayleigh_alpha=alpha, rayleigh_beta=beta)

@@ -32,6 +32,12 @@ w/2 ||A x - p(x)||^2 with exact projections p:
     without the mass and volume terms): M~ = M + h C enters y_n and g(x) as in the
     minimisation form (npFEM subsection), and the quasi-Newton matrix becomes
     M~/h^2 + w_v I + K; alpha in 1/us and beta in us (the solver's time unit);
+  * optional Skalak membrane (material `membrane` = "skalak"): the strain and area constraints
+    are replaced by the Skalak strain energy per unit rest area
+    W = (B/4)(I1^2 + 2 I1 - 2 I2) + (C/4) I2^2, I1 = tr(F^T F) - 2, I2 = det(F^T F) - 1
+    (Skalak et al. 1973; B, C of the parameter table); the quasi-Newton direction keeps the
+    same prefactored L and the step length comes from a backtracking (Armijo) line search on
+    g, per cell;
   * optional collision energies (particle-in-kernel technique, supplementary material): for a
     vertex in contact, (w_i/2) ||x_i - p_i||^2 toward the projection point p_i of the closest
     foreign particle, added to g and its gradient but not to L (the caller supplies p and w,
@@ -81,6 +87,7 @@ class CellType:
         self.s_max = float(material.strain_max)
         self.kappa = float(getattr(material, "pbd_kappa", 0.0))
         self.v_max = float(getattr(material, "v_max", 0.0))
+        self.skalak = getattr(material, "membrane", "pd") == "skalak"
         self.alpha = float(getattr(material, "rayleigh_alpha", 0.0))
         self.beta = float(getattr(material, "rayleigh_beta", 0.0))
 
@@ -342,13 +349,32 @@ def _mass_term(ct, d):
     return (np.einsum("ij,njd->nid", ct.Mt, d)) / ct.h ** 2
 
 
+def skalak_density(F, ct):
+    """Skalak strain energy per unit rest area W [N][m] and its derivative dW/dF [N][m][3][2]:
+    with C = F^T F, I1 = tr C - 2, I2 = det C - 1, W = (B/4)(I1^2 + 2 I1 - 2 I2) + (C/4) I2^2;
+    dW/dC = (B/2)(I1 + 1) 1 + (C I2 - B)/2 adj(C) (d det C / dC = adj C), dW/dF = 2 F dW/dC."""
+    C = np.einsum("nmdk,nmdl->nmkl", F, F)
+    I1 = C[..., 0, 0] + C[..., 1, 1] - 2.0
+    I2 = C[..., 0, 0] * C[..., 1, 1] - C[..., 0, 1] * C[..., 1, 0] - 1.0
+    B, Cc = ct.w_s, ct.w_a
+    W = 0.25 * B * (I1 ** 2 + 2.0 * I1 - 2.0 * I2) + 0.25 * Cc * I2 ** 2
+    adj = np.empty_like(C)
+    adj[..., 0, 0], adj[..., 1, 1] = C[..., 1, 1], C[..., 0, 0]
+    adj[..., 0, 1], adj[..., 1, 0] = -C[..., 0, 1], -C[..., 1, 0]
+    dWdC = (0.5 * B * (I1 + 1.0))[..., None, None] * np.eye(2) + (0.5 * (Cc * I2 - B))[..., None, None] * adj
+    return W, 2.0 * np.einsum("nmdk,nmkl->nmdl", F, dWdC)
+
+
 def gradient(x, y, ct, contacts=None):
     """grad g(x) [N][n][3] with projections recomputed at x (local step of the iteration);
     contacts = (p [N][n][3], w [N][n]) adds w (x - p)."""
     N = x.shape[0]
     F = deformation_gradients(x, ct)
-    p_s, p_a = triangle_projections(F, ct)
-    M = ct.area[None, :, None, None] * (ct.w_s * (F - p_s) + ct.w_a * (F - p_a))
+    if ct.skalak:
+        M = ct.area[None, :, None, None] * skalak_density(F, ct)[1]
+    else:
+        p_s, p_a = triangle_projections(F, ct)
+        M = ct.area[None, :, None, None] * (ct.w_s * (F - p_s) + ct.w_a * (F - p_a))
     u = bending_vectors(x, ct)
     p_b = bending_projection(u, ct)
     p_v, _, _ = volume_projection(x, ct)
@@ -381,13 +407,16 @@ def pd_rhs(x, y, ct):
 def energy(x, y, ct, contacts=None):
     """g(x) per cell [N] with projections at x (and the contact energies, if any)."""
     F = deformation_gradients(x, ct)
-    p_s, p_a = triangle_projections(F, ct)
     u = bending_vectors(x, ct)
     p_b = bending_projection(u, ct)
     p_v, _, _ = volume_projection(x, ct)
     e = 0.5 * np.einsum("nid,nid->n", x - y, _mass_term(ct, x - y))
-    e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_s, (F - p_s) ** 2)
-    e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_a, (F - p_a) ** 2)
+    if ct.skalak:
+        e += np.einsum("t,nt->n", ct.area, skalak_density(F, ct)[0])
+    else:
+        p_s, p_a = triangle_projections(F, ct)
+        e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_s, (F - p_s) ** 2)
+        e += np.einsum("t,ntdk->n", 0.5 * ct.area * ct.w_a, (F - p_a) ** 2)
     e += 0.5 * ct.w_b * np.einsum("ned,ned->n", u - p_b, u - p_b)
     e += 0.5 * ct.w_v * np.einsum("nid,nid->n", x - p_v, x - p_v)
     if contacts is not None:
@@ -467,7 +496,9 @@ def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
     if history is not None:
         history.append(xk.copy())
     for _ in range(n_iters):
-        if form == "qn":
+        if ct.skalak:
+            xk = line_search_update(ct, xk, y, contacts, method)
+        elif form == "qn":
             xk = xk - solve(ct, gradient(xk, y, ct, contacts), method)
         elif form == "pd":
             if contacts is not None:
@@ -478,6 +509,29 @@ def step(ct, x, v, f, n_iters: int, form: str = "qn", method: str = "cholesky",
         if history is not None:
             history.append(xk.copy())
     return xk, cap_velocities((xk - x) / ct.h, ct.v_max)
+
+
+ARMIJO_C = 1e-4        # sufficient-decrease constant of the line search
+MAX_HALVINGS = 8       # step lengths 1, 1/2, ..., 1/256
+
+
+def line_search_update(ct, x, y, contacts=None, method: str = "cholesky"):
+    """One quasi-Newton iteration with a backtracking line search, per cell: direction
+    d = -L^-1 grad g(x); the step length a is the first of 1, 1/2, ..., 2^-MAX_HALVINGS with
+    g(x + a d) <= g(x) + ARMIJO_C a grad g(x).d (the last one when none qualifies)."""
+    gk = gradient(x, y, ct, contacts)
+    d = -solve(ct, gk, method)
+    e0 = energy(x, y, ct, contacts)
+    slope = np.einsum("nid,nid->n", gk, d)
+    a = np.ones(x.shape[0])
+    done = np.zeros(x.shape[0], dtype=bool)
+    for h in range(MAX_HALVINGS + 1):
+        et = energy(x + a[:, None, None] * d, y, ct, contacts)
+        done |= et <= e0 + ARMIJO_C * a * slope
+        if done.all() or h == MAX_HALVINGS:
+            break
+        a = np.where(done, a, 0.5 * a)
+    return x + a[:, None, None] * d
 
 
 # ----------------------------------------------------------------------------------------

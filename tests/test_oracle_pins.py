@@ -682,3 +682,93 @@ def test_converged_step_with_contacts_satisfies_newtons_law():
     xf, _ = O.step(ct, x, v0, f, 100)
     on = wc > 0
     assert np.all(np.linalg.norm(x1 - pc, axis=-1)[on] < np.linalg.norm(xf - pc, axis=-1)[on])
+
+
+# --------------------------------------------------- Skalak membrane with line search (f2)
+
+
+def _skalak_ct(kind=I.RBC):
+    x0, t, m = I.cell_type_inputs()[kind]
+    return x0, t, O.CellType(x0, t, m.with_membrane("skalak"), I.DT)
+
+
+def test_skalak_density_closed_forms():
+    """Equibiaxial stretch l (C = l^2 1): W = (B/2)(l^2 - 1)^2 + (C/4)(l^4 - 1)^2; uniaxial
+    (l, 1): W = ((B + C)/4)(l^2 - 1)^2; at rest W = 0 and dW/dF = 0 (worked by hand from the
+    invariants)."""
+    _, _, ct = _skalak_ct()
+    B, C = ct.w_s, ct.w_a
+    for lam in (0.8, 1.0, 1.03, 1.5):
+        Fe = np.zeros((1, 1, 3, 2)); Fe[0, 0, 0, 0] = Fe[0, 0, 1, 1] = lam
+        W, P = O.skalak_density(Fe, ct)
+        assert np.isclose(W[0, 0], 0.5 * B * (lam ** 2 - 1) ** 2 + 0.25 * C * (lam ** 4 - 1) ** 2, rtol=1e-13, atol=1e-300)
+        Fu = np.zeros((1, 1, 3, 2)); Fu[0, 0, 0, 0] = lam; Fu[0, 0, 1, 1] = 1.0
+        Wu, _ = O.skalak_density(Fu, ct)
+        assert np.isclose(Wu[0, 0], 0.25 * (B + C) * (lam ** 2 - 1) ** 2, rtol=1e-13, atol=1e-300)
+        if lam == 1.0:
+            assert W[0, 0] == 0.0 and np.abs(P).max() == 0.0
+
+
+def test_skalak_stress_matches_finite_differences():
+    _, _, ct = _skalak_ct()
+    rng = np.random.default_rng(90)
+    F = np.zeros((1, 5, 3, 2))
+    F[0, :, 0, 0] = F[0, :, 1, 1] = 1.0
+    F += 0.2 * rng.normal(size=F.shape)
+    _, P = O.skalak_density(F, ct)
+    h = 1e-6
+    for d in range(3):
+        for k in range(2):
+            Fp, Fm = F.copy(), F.copy()
+            Fp[..., d, k] += h
+            Fm[..., d, k] -= h
+            fd = (O.skalak_density(Fp, ct)[0] - O.skalak_density(Fm, ct)[0]) / (2 * h)
+            assert np.allclose(P[..., d, k], fd, rtol=1e-6, atol=1e-6 * np.abs(P).max())
+
+
+def test_skalak_line_search_decreases_g_every_iteration():
+    """The Armijo rule makes every iteration a descent step of g (with its projections)."""
+    x0, t, ct = _skalak_ct()
+    rng = np.random.default_rng(91)
+    x = x0[None] + 0.03 * rng.normal(size=(2,) + x0.shape)
+    v, f = 0.1 * rng.normal(size=x.shape), 200.0 * rng.normal(size=x.shape)
+    y = O.predict(x, v, f, ct)
+    xk, g_prev = y.copy(), O.energy(y, y, ct)
+    for _ in range(10):
+        xk = O.line_search_update(ct, xk, y)
+        g_now = O.energy(xk, y, ct)
+        assert np.all(g_now <= g_prev + 1e-12 * np.abs(g_prev))
+        g_prev = g_now
+    # an inflated cell (area strain ~ 1): the full step overshoots and is halved, still descent
+    xi = (1.4 * x0)[None]
+    y = xi.copy()
+    xk, g_prev, halved = y.copy(), O.energy(y, y, ct), False
+    for _ in range(4):
+        gk = O.gradient(xk, y, ct)
+        d = -O.solve(ct, gk)
+        full = O.energy(xk + d, y, ct) > g_prev + O.ARMIJO_C * np.einsum("nid,nid->n", gk, d)
+        halved |= bool(full.any())
+        xk = O.line_search_update(ct, xk, y)
+        g_now = O.energy(xk, y, ct)
+        assert np.all(g_now < g_prev)
+        g_prev = g_now
+    assert halved
+
+
+def test_skalak_rigid_invariance_and_newtons_law():
+    """A rotated and translated problem gives the rotated and translated step; a converged
+    step satisfies the equation of motion with F_int = -grad of the Skalak, bending and volume
+    energies."""
+    x0, t, ct = _skalak_ct()
+    rng = np.random.default_rng(92)
+    x = x0[None] + 0.02 * rng.normal(size=(1,) + x0.shape)
+    v, f = 0.05 * rng.normal(size=x.shape), 10.0 * rng.normal(size=x.shape)
+    R = I.random_rotations(np.random.default_rng(93), 1)[0]
+    tr = np.array([3.0, -2.0, 5.0])
+    a, _ = O.step(ct, x, v, f, 8)
+    b, _ = O.step(ct, x @ R.T + tr, v @ R.T, f @ R.T, 8)
+    assert np.abs(b - (a @ R.T + tr)).max() <= 1e-11
+    x1, v1 = O.step(ct, x, v, f, 150)
+    res = -O.gradient(x1, x1, ct) + f - ct.mass * (v1 - v) / I.DT
+    scale = np.abs(ct.mass * (v1 - v) / I.DT).max() + np.abs(f).max()
+    assert np.abs(res).max() <= 1e-9 * scale, np.abs(res).max() / scale
