@@ -73,7 +73,16 @@ typedef struct {
   double rayleigh_beta; /* us,   constant strain + area + bending stiffness: M~ = M + h C     */
                         /* enters y_n = x_n + h M~^-1 (M v_n + h F_ext) and the mass term of */
                         /* g, and L = M~/h^2 + k_vol I + K (npFEM subsection); both forms    */
+  int32_t membrane;     /* NPFEM_MEMBRANE_PD: strain + area constraint energies (default);    */
+                        /* NPFEM_MEMBRANE_SKALAK: the Skalak strain energy                   */
+                        /* W = (B/4)(I1^2 + 2 I1 - 2 I2) + (C/4) I2^2 per unit rest area      */
+                        /* (B = shear_B, C = area_C), quasi-Newton direction -L^-1 grad g     */
+                        /* with a backtracking line search on g per cell (steps 1, 1/2, ...,  */
+                        /* 1/256, Armijo constant 1e-4). Plain form only, without Rayleigh   */
+                        /* beta; other combinations report NPFEM_E_UNSUPPORTED               */
 } npfem_material;
+
+enum { NPFEM_MEMBRANE_PD = 0, NPFEM_MEMBRANE_SKALAK = 1 };
 
 typedef struct npfem_celltype npfem_celltype;   /* opaque, library-owned */
 typedef struct npfem_batch npfem_batch;         /* opaque, library-owned */

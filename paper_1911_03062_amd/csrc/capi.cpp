@@ -108,13 +108,14 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   p.row_tiles = (ct->n + 15) / 16;
   // whole chunks plus two zero chunks read by the global step's look-ahead loads
   p.k_steps = ((ct->npad / 4 + kMfmaChunk - 1) / kMfmaChunk + 2) * kMfmaChunk;
-  p.pad0 = 0;
+  p.skalak = 0;
   p.h = ct->h; p.mass = ct->mass;
   // Rayleigh damping: M~/h^2 = (1 + h alpha) m/h^2 I + (beta/h) K
   const double ma = 1.0 + ct->h * ct->alpha;
   p.inv_h2m = ma * ct->mass / (ct->h * ct->h);
   p.h2_over_m = ct->h * ct->h / ct->mass;
   p.ray_k = ct->beta / ct->h;
+  p.skalak = ct->membrane == NPFEM_MEMBRANE_SKALAK ? 1 : 0;
   if (ct->beta > 0.0) {
     // the prediction is m M~^-1 (h v + h^2 F/m): the factor 1 / (1 + h alpha) is inside M~
     p.pred_h = ct->h;

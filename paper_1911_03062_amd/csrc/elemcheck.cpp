@@ -54,6 +54,26 @@ double median_any(const double* vals, int k) {
 
 extern "C" {
 // p: [3][3] vertex positions a, b, c; g: (g_b0, g_b1, g_c0, g_c1); out: [3][3] contributions.
+// Skalak triangle (p: [3][3], g: (g_b0, g_b1, g_c0, g_c1)): contributions to out [3][3],
+// returns the energy A W.
+double npfem_check_skalak(const double* p, const double* g, double area, double B, double C,
+                          double* out, int precision) {
+  if (precision == 64) {
+    Vec3<double> r[3] = {v3<double>(0, 0, 0), v3<double>(0, 0, 0), v3<double>(0, 0, 0)};
+    const double E = skalak_residual<double>(v3<double>(p[0], p[1], p[2]), v3<double>(p[3], p[4], p[5]),
+                                             v3<double>(p[6], p[7], p[8]), g[0], g[1], g[2], g[3],
+                                             area, B, C, r[0], r[1], r[2]);
+    for (int q = 0; q < 3; ++q) { out[3 * q] = r[q].x; out[3 * q + 1] = r[q].y; out[3 * q + 2] = r[q].z; }
+    return E;
+  }
+  Vec3<float> r[3] = {v3<float>(0, 0, 0), v3<float>(0, 0, 0), v3<float>(0, 0, 0)};
+  const float E = skalak_residual<float>(v3<float>(p[0], p[1], p[2]), v3<float>(p[3], p[4], p[5]),
+                                         v3<float>(p[6], p[7], p[8]), (float)g[0], (float)g[1],
+                                         (float)g[2], (float)g[3], (float)area, (float)B, (float)C,
+                                         r[0], r[1], r[2]);
+  for (int q = 0; q < 3; ++q) { out[3 * q] = r[q].x; out[3 * q + 1] = r[q].y; out[3 * q + 2] = r[q].z; }
+  return E;
+}
 void npfem_check_triangle(const double* p, const double* g, double area, double w_s, double w_a,
                           double s_min, double s_max, double* out, int precision) {
   if (precision == 64) tri<double>(p, g, area, w_s, w_a, s_min, s_max, out);

@@ -34,6 +34,7 @@ struct PlainWork {
   T* tcon;    // [m][3][3] triangle contributions to (a, b, c)
   T* tn;      // [m][3] twice the triangle area vector
   T* hcon;    // [e][4][3] hinge contributions
+  T* dir;     // [3][n] search direction (Skalak membrane)
 };
 
 template <typename T>
@@ -46,7 +47,8 @@ __host__ __device__ inline PlainWork<T> plain_layout(void* base, int n, int m, i
   w.gv = p; p += 3 * n;
   w.tcon = p; p += 9 * m;
   w.tn = p; p += 3 * m;
-  w.hcon = p;
+  w.hcon = p; p += 12 * e;
+  w.dir = p;
   return w;
 }
 
@@ -187,8 +189,12 @@ k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t 
     const Vec3<T> pb = cell_pos(x, vt, off, w.d, n, b);
     const Vec3<T> pc = cell_pos(x, vt, off, w.d, n, c);
     Vec3<T> ra = v3<T>(0, 0, 0), rb = ra, rc = ra;   // contributions are accumulated
-    triangle_residual<T>(pa, pb, pc, G[6 * t + 2], G[6 * t + 3], G[6 * t + 4], G[6 * t + 5],
-                         A[t], T(p.w_s), T(p.w_a), T(p.s_min), T(p.s_max), ra, rb, rc);
+    if (p.skalak)
+      (void)skalak_residual<T>(pa, pb, pc, G[6 * t + 2], G[6 * t + 3], G[6 * t + 4], G[6 * t + 5],
+                               A[t], T(p.w_s), T(p.w_a), ra, rb, rc);
+    else
+      triangle_residual<T>(pa, pb, pc, G[6 * t + 2], G[6 * t + 3], G[6 * t + 4], G[6 * t + 5],
+                           A[t], T(p.w_s), T(p.w_a), T(p.s_min), T(p.s_max), ra, rb, rc);
     T* tc = w.tcon + 9 * t;
     tc[0] = ra.x; tc[1] = ra.y; tc[2] = ra.z;
     tc[3] = rb.x; tc[4] = rb.y; tc[5] = rb.z;
@@ -258,12 +264,14 @@ k_plain_local(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t 
 }
 
 // Banded solve of r (three right-hand sides, one wave per coordinate, band products reduced
-// across the wave). Global step (predict = false): L D = r with L's factor, then
-// delta -= D. Prediction (predict = true, Rayleigh damping with beta > 0): M~ D = r with
-// M~'s factor, then delta^0 = delta = D.
+// across the wave). Global step (kSolveUpdate): L D = r with L's factor, then delta -= D.
+// Prediction (kSolvePredict, Rayleigh damping with beta > 0): M~ D = r with M~'s factor,
+// then delta^0 = delta = D. Direction (kSolveDirection, Skalak membrane): dir = -L^-1 r.
+enum { kSolveUpdate = 0, kSolvePredict = 1, kSolveDirection = 2 };
 template <typename T>
 __global__ void __launch_bounds__(192)
-k_plain_solve(const DevType* __restrict__ dtp, void* work, bool predict) {
+k_plain_solve(const DevType* __restrict__ dtp, void* work, int mode) {
+  const bool predict = mode == kSolvePredict;
   const DevType& dt = *dtp;
   const int n = dt.p.n, bw = dt.p.bw, bs = bw + 1;
   PlainWork<T> w = plain_layout<T>(work, n, dt.p.m, dt.p.e);
@@ -296,9 +304,96 @@ k_plain_solve(const DevType* __restrict__ dtp, void* work, bool predict) {
       w.d0[c * n + i] = yc[i];
       w.d[c * n + i] = yc[i];
     }
+  } else if (mode == kSolveDirection) {
+    for (int i = lane; i < n; i += 64) w.dir[c * n + i] = -yc[i];
   } else {
     for (int i = lane; i < n; i += 64) w.d[c * n + i] -= yc[i];
   }
+}
+
+// Skalak membrane: backtracking line search along dir from delta, one cell. g at step length
+// a (positions x_n + delta + a dir): Skalak energies of the triangles, bending energies of the
+// hinges (projections at that point), the volume energy (w_v/2)(V0 - V)^2/|grad V|^2, the
+// inertia term (1 + h alpha)(m/2h^2)|delta + a dir - delta^0|^2 and the contact energies,
+// summed in FP64. The first a of 1, 1/2, ..., 2^-kMaxHalvings with
+// g(a) <= g(0) + kArmijoC a grad g . dir is taken (the last one when none qualifies).
+template <typename T>
+__global__ void __launch_bounds__(kPlainThreads)
+k_plain_linesearch(const DevType* __restrict__ dtp, const T* __restrict__ x, int64_t vt,
+                   int64_t off, void* work, const T* __restrict__ cp, const T* __restrict__ cw) {
+  const DevType& dt = *dtp;
+  const TypeParams& p = dt.p;
+  const int n = p.n, m = p.m, e = p.e;
+  PlainWork<T> w = plain_layout<T>(work, n, m, e);
+  const T* G = PlainConst<T>::G(dt);
+  const T* A = PlainConst<T>::A(dt);
+  const T* coef = PlainConst<T>::coef(dt);
+  const T* rest = PlainConst<T>::rest(dt);
+  __shared__ double sh[8];
+  double sl = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int c = 0; c < 3; ++c) sl += (double)w.r[c * n + i] * (double)w.dir[c * n + i];
+  const double slope = block_sum(sl, sh);
+  auto pos = [&](int i, T a) {
+    return v3<T>((x[off + i] - x[off]) + (w.d[i] + a * w.dir[i]),
+                 (x[vt + off + i] - x[vt + off]) + (w.d[n + i] + a * w.dir[n + i]),
+                 (x[2 * vt + off + i] - x[2 * vt + off]) + (w.d[2 * n + i] + a * w.dir[2 * n + i]));
+  };
+  auto energy = [&](T a) {
+    double ee = 0;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+      const Vec3<T> pa = pos(dt.tri[3 * t], a), pb = pos(dt.tri[3 * t + 1], a);
+      const Vec3<T> pc = pos(dt.tri[3 * t + 2], a);
+      Vec3<T> ra = v3<T>(0, 0, 0), rb = ra, rc = ra;
+      ee += (double)skalak_residual<T>(pa, pb, pc, G[6 * t + 2], G[6 * t + 3], G[6 * t + 4],
+                                       G[6 * t + 5], A[t], T(p.w_s), T(p.w_a), ra, rb, rc);
+      const Vec3<T> nt = cross3(pb - pa, pc - pa);
+      w.tn[3 * t] = nt.x; w.tn[3 * t + 1] = nt.y; w.tn[3 * t + 2] = nt.z;
+    }
+    for (int h = threadIdx.x; h < e; h += blockDim.x) {
+      const int* hv = dt.hinge + 4 * h;
+      ee += (double)hinge_energy<T>(pos(hv[0], a), pos(hv[1], a), pos(hv[2], a), pos(hv[3], a),
+                                    coef[4 * h + 1], coef[4 * h + 2], coef[4 * h + 3], rest[h],
+                                    T(p.w_b));
+    }
+    __syncthreads();
+    double vp = 0, gp = 0, em = 0, ec = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      T gx = 0, gy = 0, gz = 0;
+      for (int s = dt.vt_off[i]; s < dt.vt_off[i + 1]; ++s) {
+        const int t = dt.vt_list[s] / 3;
+        gx += w.tn[3 * t]; gy += w.tn[3 * t + 1]; gz += w.tn[3 * t + 2];
+      }
+      gx *= T(1.0 / 6.0); gy *= T(1.0 / 6.0); gz *= T(1.0 / 6.0);
+      const Vec3<T> pi = pos(i, a);
+      vp += (double)pi.x * (double)gx + (double)pi.y * (double)gy + (double)pi.z * (double)gz;
+      gp += (double)gx * (double)gx + (double)gy * (double)gy + (double)gz * (double)gz;
+      const T wc = cw != nullptr ? cw[off + i] : T(0);
+      for (int c = 0; c < 3; ++c) {
+        const T dl = (w.d[c * n + i] + a * w.dir[c * n + i]) - w.d0[c * n + i];
+        em += (double)dl * (double)dl;
+        if (wc != T(0)) {
+          const T g = (x[c * vt + off + i] - cp[c * vt + off + i]) + (w.d[c * n + i] + a * w.dir[c * n + i]);
+          ec += 0.5 * (double)wc * (double)g * (double)g;
+        }
+      }
+    }
+    const double E_el = block_sum(ee, sh);
+    const double V = block_sum(vp, sh) / 3.0, G2 = block_sum(gp, sh);
+    const double E_m = 0.5 * p.inv_h2m * block_sum(em, sh);
+    const double E_c = block_sum(ec, sh);
+    const double E_v = G2 > 0 ? 0.5 * p.w_v * (p.V0 - V) * (p.V0 - V) / G2 : 0.0;
+    __syncthreads();   // w.tn is rewritten by the next evaluation
+    return E_el + E_m + E_v + E_c;
+  };
+  const double e0 = energy(T(0));
+  T a = T(1);
+  for (int h = 0; h <= kMaxHalvings; ++h) {
+    if (energy(a) <= e0 + kArmijoC * (double)a * slope || h == kMaxHalvings) break;
+    a *= T(0.5);
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int c = 0; c < 3; ++c) w.d[c * n + i] += a * w.dir[c * n + i];
 }
 
 // Class test (not v - v == 0, which FMA contraction can turn into a product's rounding error).
@@ -359,11 +454,18 @@ hipError_t plain_step_t(const DevType* dt_dev, const TypeParams& p, T* x, T* v, 
   hipLaunchKernelGGL(k_plain_predict<T>, dim3(1), dim3(kPlainThreads), 0, s, p, x, v, f, vt,
                      off, work);
   if (p.ray_k > 0.0)
-    hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, true);
+    hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, (int)kSolvePredict);
   for (int k = 0; k < K; ++k) {
     hipLaunchKernelGGL(k_plain_local<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt, off,
                        work, cp, cw);
-    hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, false);
+    if (p.skalak) {
+      hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work,
+                         (int)kSolveDirection);
+      hipLaunchKernelGGL(k_plain_linesearch<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt,
+                         off, work, cp, cw);
+    } else {
+      hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, (int)kSolveUpdate);
+    }
   }
   hipLaunchKernelGGL(k_plain_finalize<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, v, vt,
                      off, work, vol_area, flag);
@@ -374,7 +476,7 @@ hipError_t plain_step_t(const DevType* dt_dev, const TypeParams& p, T* x, T* v, 
 
 size_t plain_work_bytes(int precision, int n, int m, int e) {
   const size_t el = precision == 64 ? 8 : 4;
-  return el * (12 * (size_t)n + 12 * (size_t)m + 12 * (size_t)e) + 256;
+  return el * (15 * (size_t)n + 12 * (size_t)m + 12 * (size_t)e) + 256;
 }
 
 bool plain_supported(int n, int bw) { return n <= kMaxBand && bw < kMaxBand; }

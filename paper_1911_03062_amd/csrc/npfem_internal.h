@@ -66,7 +66,7 @@ struct TypeParams {
   int32_t row_tiles;            // ceil(n / 16): MFMA row tiles of L^-1
   int32_t k_steps;              // MFMA k steps stored per L^-1 row tile: npad / 4 rounded
                                 // up to whole kMfmaChunk chunks plus two chunks (zeros)
-  int32_t pad0;
+  int32_t skalak;               // membrane: 0 = PD constraints, 1 = Skalak energy
   double h, mass, inv_h2m;      // h, m, m / h^2
   double h2_over_m;             // h^2 / m
   double w_s, w_a, w_b, w_v;
@@ -123,6 +123,7 @@ struct npfem_celltype {
   double w_s = 0, w_a = 0, w_b = 0, w_v = 0, s_min = 1, s_max = 1, kappa = 0;
   double v_max = 0;
   double alpha = 0, beta = 0;     // Rayleigh damping
+  int membrane = 0;               // NPFEM_MEMBRANE_*
   std::vector<double> mband;      // [n][bw+1] banded Cholesky factor of M~ (beta > 0)
   std::vector<double> kband;      // [n][bw+1] lower band of K (beta > 0)
   std::vector<double> pinv;       // [n][n] m M~^-1 (beta > 0), the fused form's prediction
@@ -183,6 +184,8 @@ struct FusedGroup {
 };
 
 constexpr int kMfmaChunk = 8;               // k steps per prefetched L^-1 chunk
+constexpr double kArmijoC = 1e-4;           // Skalak line search: sufficient decrease
+constexpr int kMaxHalvings = 8;             //   and step lengths 1, 1/2, ..., 1/256
 constexpr int kDampWords = 12;              // LDS floats per cell for position-based damping
 constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
 

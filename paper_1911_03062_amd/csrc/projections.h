@@ -219,6 +219,43 @@ __host__ __device__ __forceinline__ void hinge_residual(Vec3<T> pi, Vec3<T> pj, 
   rl = rl + W * a3;
 }
 
+// Bending energy of one hinge: (w_b/2) (|u| - r)^2, 0 for u = 0 (the projection is u then).
+template <typename T>
+__host__ __device__ __forceinline__ T hinge_energy(Vec3<T> pi, Vec3<T> pj, Vec3<T> pk, Vec3<T> pl,
+                                                   T a1, T a2, T a3, T rest, T w_b) {
+  const Vec3<T> u = (pj - pi) * a1 + (pk - pi) * a2 + (pl - pi) * a3;
+  const T nu2 = dot3(u, u);
+  if (!(nu2 > T(0))) return T(0);
+  const T dd = dsqrt(nu2) - rest;
+  return T(0.5) * w_b * dd * dd;
+}
+
+// Skalak membrane (Skalak et al. 1973) of one triangle: with F = [f0 f1] = sum_j x_j g_j^T,
+// C = F^T F, I1 = tr C - 2, I2 = det C - 1, the energy A W with
+// W = (B/4)(I1^2 + 2 I1 - 2 I2) + (C/4) I2^2 and the first Piola stress
+// P = dW/dF = 2 F S, S = dW/dC = (B/2)(I1 + 1) 1 + (C I2 - B)/2 adj(C). Adds A P g_j to the
+// vertex contributions (g_a = -g_b - g_c) and returns A W.
+template <typename T>
+__host__ __device__ __forceinline__ T skalak_residual(Vec3<T> pa, Vec3<T> pb, Vec3<T> pc, T gb0,
+                                                      T gb1, T gc0, T gc1, T area, T B, T Cm,
+                                                      Vec3<T>& ra, Vec3<T>& rb, Vec3<T>& rc) {
+  const Vec3<T> e1 = pb - pa, e2 = pc - pa;
+  const Vec3<T> f0 = e1 * gb0 + e2 * gc0, f1 = e1 * gb1 + e2 * gc1;
+  const T c00 = dot3(f0, f0), c01 = dot3(f0, f1), c11 = dot3(f1, f1);
+  const T I1 = (c00 - T(1)) + (c11 - T(1));
+  const T I2 = c00 * c11 - c01 * c01 - T(1);
+  const T W = T(0.25) * B * (I1 * I1 + T(2) * I1 - T(2) * I2) + T(0.25) * Cm * I2 * I2;
+  const T sa = T(0.5) * B * (I1 + T(1)), sb = T(0.5) * (Cm * I2 - B);
+  const T s00 = sa + sb * c11, s01 = -sb * c01, s11 = sa + sb * c00;
+  const Vec3<T> p0 = (f0 * s00 + f1 * s01) * (T(2) * area);
+  const Vec3<T> p1 = (f0 * s01 + f1 * s11) * (T(2) * area);
+  const Vec3<T> kb = p0 * gb0 + p1 * gb1, kc = p0 * gc0 + p1 * gc1;
+  rb = rb + kb;
+  rc = rc + kc;
+  ra = ra - kb - kc;
+  return area * W;
+}
+
 // Position-based damping (Mueller et al. 2007): the angular velocity of a cell's rigid motion
 // solves I w = L with the inertia tensor I = sum (|r|^2 1 - r r^T) and angular momentum
 // L = sum r x v about the centre of mass (equal masses cancel). Isym = (xx, yy, zz, xy, xz, yz).

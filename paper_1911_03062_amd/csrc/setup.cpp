@@ -309,7 +309,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
       !(mat->pbd_kappa >= 0.0 && mat->pbd_kappa <= 1.0) ||
       !(mat->v_max >= 0.0 && std::isfinite(mat->v_max)) ||
       !(mat->rayleigh_alpha >= 0.0 && std::isfinite(mat->rayleigh_alpha)) ||
-      !(mat->rayleigh_beta >= 0.0 && std::isfinite(mat->rayleigh_beta)))
+      !(mat->rayleigh_beta >= 0.0 && std::isfinite(mat->rayleigh_beta)) ||
+      (mat->membrane != NPFEM_MEMBRANE_PD && mat->membrane != NPFEM_MEMBRANE_SKALAK))
     return fail(NPFEM_E_INVALID, "material constants out of range");
 
   ct->n = n;
@@ -325,6 +326,9 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   ct->v_max = mat->v_max;
   ct->alpha = mat->rayleigh_alpha;
   ct->beta = mat->rayleigh_beta;
+  ct->membrane = mat->membrane;
+  if (ct->membrane == NPFEM_MEMBRANE_SKALAK && ct->beta > 0.0)
+    return fail(NPFEM_E_UNSUPPORTED, "the Skalak membrane with Rayleigh beta damping");
   ct->X.assign(mesh->rest_xyz, mesh->rest_xyz + 3 * (size_t)n);
   ct->tri.assign(mesh->tri, mesh->tri + 3 * (size_t)m);
   for (double c : ct->X)
@@ -617,6 +621,11 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   ct->fused_ok = !feasible.empty();
   if (!ct->fused_ok) {
     ct->fused_reason = "mesh too large for the fused kernel's LDS layout (n <= 576)";
+    return NPFEM_OK;
+  }
+  if (ct->membrane == NPFEM_MEMBRANE_SKALAK) {
+    ct->fused_ok = false;
+    ct->fused_reason = "the Skalak membrane runs in the plain form";
     return NPFEM_OK;
   }
 

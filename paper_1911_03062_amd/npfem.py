@@ -39,7 +39,10 @@ class _Material(ctypes.Structure):
     _fields_ = [("density", c_double), ("shear_B", c_double), ("area_C", c_double),
                 ("skalak_D", c_double), ("k_bend", c_double), ("k_vol", c_double),
                 ("strain_min", c_double), ("strain_max", c_double), ("pbd_kappa", c_double),
-                ("v_max", c_double), ("rayleigh_alpha", c_double), ("rayleigh_beta", c_double)]
+                ("v_max", c_double), ("rayleigh_alpha", c_double), ("rayleigh_beta", c_double),
+                ("membrane", c_int32)]
+
+MEMBRANES = {"pd": 0, "skalak": 1}
 
 
 class _Info(ctypes.Structure):
@@ -139,7 +142,8 @@ class CellType:
                         float(getattr(material, "pbd_kappa", 0.0)),
                         float(getattr(material, "v_max", 0.0)),
                         float(getattr(material, "rayleigh_alpha", 0.0)),
-                        float(getattr(material, "rayleigh_beta", 0.0)))
+                        float(getattr(material, "rayleigh_beta", 0.0)),
+                        MEMBRANES[getattr(material, "membrane", "pd")])
         h = c_void_p()
         _check(lib().npfem_create_celltype(ctypes.byref(mesh), ctypes.byref(mat), float(dt),
                                            ctypes.byref(h)))

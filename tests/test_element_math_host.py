@@ -212,3 +212,29 @@ def test_velocity_cap_helper_matches_oracle(lib):
                 w = np.ascontiguousarray(v[i].copy())
                 lib.npfem_check_cap(_ptr(w), vmax, prec)
                 assert np.abs(w - ref[i]).max() <= tol * (1 + np.abs(ref[i]).max()), (prec, vmax, i)
+
+
+@pytest.mark.parametrize("kind", [I.RBC, I.PLT])
+def test_skalak_element_matches_oracle(lib, kind):
+    """The kernels' Skalak triangle (energy A W and contributions A P g_j) against the
+    oracle's Skalak density and triangle scatter, in FP64 and FP32."""
+    lib.npfem_check_skalak.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, dp, ctypes.c_int]
+    lib.npfem_check_skalak.restype = ctypes.c_double
+    x0, t, m = I.cell_type_inputs()[kind]
+    ct = O.CellType(x0, t, m.with_membrane("skalak"), I.DT)
+    rng = np.random.default_rng(95)
+    x = x0[None] + 0.05 * rng.normal(size=(1,) + x0.shape)
+    F = O.deformation_gradients(x, ct)
+    W, P = O.skalak_density(F, ct)
+    for tt in range(0, ct.m, 37):
+        a, b, c = ct.tri[tt]
+        pts = np.ascontiguousarray(x[0, [a, b, c]].reshape(-1))
+        g = np.ascontiguousarray([ct.G[tt, 1, 0], ct.G[tt, 1, 1], ct.G[tt, 2, 0], ct.G[tt, 2, 1]])
+        ref = np.stack([ct.area[tt] * P[0, tt] @ ct.G[tt, j] for j in range(3)])
+        for prec, tol in ((64, 1e-10), (32, 2e-3)):
+            out = np.zeros(9)
+            E = lib.npfem_check_skalak(_ptr(pts), _ptr(g), ct.area[tt], ct.w_s, ct.w_a, _ptr(out), prec)
+            scale = np.abs(ref).max() + 1e-3 * ct.w_s * ct.area[tt]
+            assert np.abs(out.reshape(3, 3) - ref).max() <= tol * scale, (prec, tt)
+            assert abs(E - ct.area[tt] * W[0, tt]) <= tol * (abs(ct.area[tt] * W[0, tt]) + 1e-3 * ct.w_s * ct.area[tt]), (prec, tt)

@@ -110,3 +110,12 @@ def test_rayleigh_system_matrix_matches_oracle(alpha, beta):
     oc = O.CellType(x, t, mat, I.DT)
     assert np.abs(ct.matrix() - oc.L).max() <= 1e-13 * np.abs(oc.L).max()
     assert ct.cells_per_wave() != []
+
+
+def test_skalak_membrane_is_plain_form_only_and_excludes_rayleigh_beta():
+    x, t, m = I.cell_type_inputs()[I.RBC]
+    ct = N.CellType(x, t, m.with_membrane("skalak"), I.DT)
+    assert ct.cells_per_wave() == []
+    oc = O.CellType(x, t, m.with_membrane("skalak"), I.DT)
+    assert np.abs(ct.matrix() - oc.L).max() <= 1e-13 * np.abs(oc.L).max()
+    _expect("NPFEM_E_UNSUPPORTED", lambda: N.CellType(x, t, m.with_membrane("skalak").with_rayleigh(0.0, 0.01), I.DT))
