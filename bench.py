@@ -253,6 +253,45 @@ def main():
     visco_ms = ve0.elapsed_time(ve1) / v_steps
     del vgraphs, vbatch, vx, vv
 
+    # collision energies on the same batch: 5 % of the vertices in contact (projection points
+    # within 0.1 um, w = 400 pN/um, their forces zeroed), fused form, eager steps
+    crng = np.random.default_rng(13)
+    cw_np = np.where(crng.random(b.v_total) < 0.05, 400.0, 0.0)
+    cw = torch.tensor(cw_np, dtype=torch.float32, device="cuda")
+    cpt = (x + 0.1 * torch.randn(x.shape, generator=torch.Generator(device="cuda").manual_seed(13),
+                                 device="cuda")).contiguous()
+    cf = torch.where(cw > 0, torch.zeros_like(pool[0]), pool[0]).contiguous()
+    xc2, vc2 = x.clone(), v.clone()
+    batch.step(xc2, vc2, cf, I.DT, K, contacts=(cpt, cw))
+    torch.cuda.synchronize()
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c_steps = 5
+    ce0.record(stream)
+    for _ in range(c_steps):
+        batch.step(xc2, vc2, cf, I.DT, K, contacts=(cpt, cw))
+    ce1.record(stream)
+    torch.cuda.synchronize()
+    batch.check()
+    contacts_ms = ce0.elapsed_time(ce1) / c_steps
+    del xc2, vc2, cpt, cw, cf
+
+    # Skalak membrane with line search (plain form) on the plain comparator's cells
+    stypes = {k: N.CellType(x_, t_, m_.with_membrane("skalak"), I.DT)
+              for k, (x_, t_, m_) in I.cell_type_inputs().items()}
+    sbatch = N.Batch([stypes[int(b.types[c])] for c in pcells], precision=32, form="plain")
+    sx, sv = px.clone(), pv.clone()
+    sbatch.step(sx, sv, pf, I.DT, K)
+    torch.cuda.synchronize()
+    se0, se1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    se0.record(stream)
+    for _ in range(p_steps):
+        sbatch.step(sx, sv, pf, I.DT, K)
+    se1.record(stream)
+    torch.cuda.synchronize()
+    sbatch.check()
+    skalak_ms = se0.elapsed_time(se1) / p_steps
+    del sbatch, sx, sv
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -307,6 +346,18 @@ def main():
             "ms_per_step": visco_ms, "value": n_cells * K / (visco_ms * 1e-3),
             "unit": "cell-PD-iterations/s", "cells_per_wave": vlayouts,
             "cost_vs_undamped": visco_ms / (elapsed_s * 1e3 / args.steps),
+        },
+        "contacts": {
+            "config": "5 % of the vertices in contact (w = 400 pN/um, projection points within "
+                      "0.1 um, forces zeroed there); same batch and K, eager steps",
+            "ms_per_step": contacts_ms, "value": n_cells * K / (contacts_ms * 1e-3),
+            "unit": "cell-PD-iterations/s",
+        },
+        "skalak_plain": {
+            "config": f"Skalak membrane with line search, plain form, the same {len(pcells)} cells",
+            "ms_per_step": skalak_ms, "value": len(pcells) * K / (skalak_ms * 1e-3),
+            "unit": "cell-PD-iterations/s", "launches_per_cell_step": 3 * K + 2,
+            "cost_vs_plain_pd": skalak_ms / plain_ms,
         },
         "kernel_source_hash": kernel_source_hash(),
     }
