@@ -58,6 +58,55 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+# All-cores oracle baseline: forked workers (before anything touches the GPU) step disjoint
+# sampled cells with one BLAS thread each, as many cells per worker as the one-core baseline
+# steps (the oracle vectorises over the cells of a type); the workload arrays are shared by
+# the fork.
+_ORACLE_JOB = {}
+
+
+def _oracle_worker(cells):
+    import contextlib
+    import oracle as O
+    import npfem_inputs as I
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:                      # pragma: no cover
+        limiter = contextlib.nullcontext()
+    j = _ORACLE_JOB
+    b, pool, K, steps = j["batch"], j["pool"], j["K"], j["steps"]
+    ot = {k: O.CellType(x_, t_, m_, I.DT) for k, (x_, t_, m_) in I.cell_type_inputs().items()}
+    xo, vo = b.x0.copy(), b.v0.copy()
+    with limiter:
+        c0 = time.perf_counter()
+        for s in range(steps):
+            xo, vo = O.step_batch(ot, b.types, b.offsets, xo, vo, pool[s % len(pool)], K,
+                                  cells=np.asarray(cells))
+        return time.perf_counter() - c0
+
+
+def oracle_all_cores(w, K, steps, pool_n, cells_per_proc=3):
+    import multiprocessing as mp
+    n_procs = max(1, min(16, os.cpu_count() or 1))
+    b = w.batch()
+    _ORACLE_JOB.update(batch=b, pool=list(w.forces(b, n_steps=pool_n)), K=K, steps=steps)
+    rng = np.random.default_rng(14)
+    cells = rng.choice(b.n_cells, n_procs * cells_per_proc, replace=False)
+    parts = [cells[i::n_procs].tolist() for i in range(n_procs)]
+    with mp.get_context("fork").Pool(n_procs) as pool:
+        times = pool.map(_oracle_worker, parts)
+    _ORACLE_JOB.clear()
+    wall = max(times)
+    return {
+        "value": len(cells) * K * steps / wall, "unit": "cell-PD-iterations/s", "cores": n_procs,
+        "kind": "oracle",
+        "sample": f"{len(cells)} sampled cells of {w.name}, {cells_per_proc} per forked worker, "
+                  f"{steps} steps x {K} PD iterations, NumPy FP64, 1 BLAS thread per worker; "
+                  f"slowest worker {wall:.1f} s",
+    }
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -91,8 +140,17 @@ def main():
               "own batch of cells, which this build does not do)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import npfem_inputs as I
+    cpu_all = None
+    if not args.no_cpu_baseline:
+        # before torch and the library are loaded: the workers are plain forks
+        log("oracle on all host cores")
+        w0 = I.WORKLOADS[args.workload]
+        cpu_all = oracle_all_cores(w0, w0.n_pd_iters, args.warmup + args.steps,
+                                   max(1, min(args.force_pool, args.warmup + args.steps)),
+                                   cells_per_proc=args.sample_cells)
+
+    import torch
     from paper_1911_03062_amd import npfem as N
 
     torch.cuda.set_device(0)
@@ -423,6 +481,8 @@ def main():
                       f"{n_steps_total} steps x {K} PD iterations, NumPy FP64, 1 BLAS thread, "
                       f"{cpu_s:.1f} s",
         }
+        if cpu_all is not None:
+            out["cpu_baseline_all_cores"] = cpu_all
         if not out["accuracy"]["passes"]:
             out["value_invalid_reason"] = "accuracy gate failed"
     print(json.dumps(out))
