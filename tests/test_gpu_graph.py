@@ -97,3 +97,32 @@ def test_graph_argument_errors():
     assert ei.value.name == "NPFEM_E_DT"
     with pytest.raises(ValueError):
         batch.graph(x0.clone(), v0.clone(), [forces[0].double()], I.DT, 10)
+
+
+def test_graph_replays_of_the_viscoelastic_kernel_variant():
+    """Types with position-based and Rayleigh damping and a velocity cap run the kernel variant
+    with those paths (and the extra m M~^-1 product); its replays also equal eager steps."""
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    inp = I.cell_type_inputs()
+    types = {k: N.CellType(x, t, m.with_rayleigh(0.0, 0.01).with_kappa(0.8).with_v_max(0.08), I.DT)
+             for k, (x, t, m) in inp.items()}
+    tids = np.array([I.RBC] * 5 + [I.PLT] * 11, dtype=np.int32)
+    b = I.make_batch(tids, seed=86)
+    batch = N.Batch([types[int(t)] for t in tids], 32, "fused")
+    forces = [torch.tensor(f, dtype=torch.float32, device="cuda")
+              for f in I.force_stream(b, seed=87, sigma=30.0, n_steps=3)]
+    x0 = torch.tensor(b.x0, dtype=torch.float32, device="cuda")
+    v0 = torch.tensor(np.random.default_rng(88).normal(0, 0.05, b.x0.shape), dtype=torch.float32,
+                      device="cuda")
+    xe, ve = _eager(batch, forces, x0, v0, 10)
+    xg, vg = x0.clone(), v0.clone()
+    g = batch.graph(xg, vg, forces, I.DT, 10)
+    for rep in range(3):
+        _say(f"case: viscoelastic graph of 3 steps, replay {rep}")
+        xg.copy_(x0)
+        vg.copy_(v0)
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe) and torch.equal(vg, ve), rep
+        _eager(batch, forces[:1], x0, v0, 2)   # eager work between replays
