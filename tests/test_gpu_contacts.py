@@ -92,3 +92,29 @@ def test_zero_weights_and_argument_errors():
         N._check(N.lib().npfem_step_contacts(batch._h, x.data_ptr(), x.data_ptr(), x.data_ptr(),
                                              I.DT, 1, None, None, x.data_ptr(), None))
     assert ei.value.name == "NPFEM_E_INVALID"
+
+
+def test_contacts_full_size_sampled():
+    """The benchmark's contacts leg at full size: 5 % of the 5.4 M vertices in contact
+    (w = 400 pN/um within 0.1 um, their forces zeroed), 2 steps of K = 20, sampled cells."""
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    w = I.WORKLOADS["large_24000"]
+    b = w.batch()
+    rng = np.random.default_rng(13)
+    cw = np.where(rng.random(b.v_total) < 0.05, 400.0, 0.0).astype(np.float32).astype(np.float64)
+    cp = (b.x0 + 0.1 * rng.normal(size=b.x0.shape)).astype(np.float32).astype(np.float64)
+    forces = [np.where(cw > 0, 0.0, f) for f in w.forces(b, n_steps=2)]
+    _say(f"case: contacts fused, {w.name} ({b.n_cells} cells), 2 steps x K = {w.n_pd_iters}")
+    xg, _ = _run_gpu(lib_types(), b, b.v0, forces, w.n_pd_iters, "fused", 32, (cp, cw))
+    srng = np.random.default_rng(10)
+    cells = np.unique(np.concatenate([srng.choice(b.n_cells, 20, replace=False),
+                                      [0, b.n_cells - 1]])).astype(np.int64)
+    ot = oracle_types()
+    x, v = b.x0.copy(), b.v0.copy()
+    for f in forces:
+        x, v = O.step_batch(ot, b.types, b.offsets, x, v, f, w.n_pd_iters, cells=cells,
+                            contact_p=cp, contact_w=cw)
+    err = cell_errors(b.types, b.offsets, xg, x, cells)
+    _say(f"contacts full size: sampled {len(cells)} cells, max err/diam {err.max():.3e}")
+    assert err.max() <= 1e-5

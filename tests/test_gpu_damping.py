@@ -125,3 +125,23 @@ def test_rayleigh_fused_mixed_batch(alpha, beta, kappa):
     _say(f"Rayleigh fused: max err/diam {err.max():.3e}, v err {verr:.3e}, damped vs undamped {sep.min():.3e}")
     assert err.max() <= 1e-5
     assert sep.min() > 100 * err.max()
+
+
+def test_viscoelastic_full_size_sampled():
+    """The benchmark's viscoelastic leg at full size: 20 000 RBC + 4 000 PLT with Rayleigh
+    beta_D = 0.01 and kappa = 0.8 on every cell, autotuned layouts, 2 steps of K = 20; the
+    oracle steps sampled cells (including strongly forced ones)."""
+    w = I.WORKLOADS["large_24000"]
+    b = w.batch()
+    forces = list(w.forces(b, n_steps=2))
+    lt, ot = _rayleigh_types(0.0, 0.01, {I.RBC: 0.8, I.PLT: 0.8})
+    _say(f"case: viscoelastic fused, {w.name} ({b.n_cells} cells), 2 steps x K = {w.n_pd_iters}")
+    xg, _ = run_gpu(lt, b.types, b.x0, b.v0, forces, w.n_pd_iters)
+    rng = np.random.default_rng(9)
+    strong = I.strong_cells(b, w.seed, w.strong_fraction)
+    cells = np.unique(np.concatenate([rng.choice(b.n_cells, 20, replace=False), strong[:6],
+                                      [0, b.n_cells - 1]])).astype(np.int64)
+    xo, _ = run_oracle(ot, b.types, b.offsets, b.x0, b.v0, forces, w.n_pd_iters, cells=cells)
+    err = cell_errors(b.types, b.offsets, xg, xo, cells)
+    _say(f"viscoelastic full size: sampled {len(cells)} cells, max err/diam {err.max():.3e}")
+    assert err.max() <= 1e-5
