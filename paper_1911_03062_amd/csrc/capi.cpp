@@ -103,7 +103,7 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   if (!d) return fail(NPFEM_E_NOMEM, "host allocation");
   TypeParams& p = d->p;
   p.n = ct->n; p.m = ct->m; p.e = ct->e; p.bw = ct->bw;
-  p.npad = ct->npad; p.gw = ct->gw; p.slots = ct->slots;
+  p.npad = ct->npad; p.cs = ct->cs; p.gw = ct->gw; p.slots = ct->slots;
   p.tri_rounds = ct->tri_rounds; p.hinge_rounds = ct->hinge_rounds;
   p.row_tiles = (ct->n + 15) / 16;
   // whole chunks plus two zero chunks read by the global step's look-ahead loads
@@ -159,25 +159,27 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   if (ct->fused_ok) {
     chk(layout_schedules_locked(ct, dev, 0, &d->tri_sched, &d->hinge_sched));
     // L^-1 in MFMA A-operand order: row tile rt, chunk c, step j, lane l -> (row rt*16 + l%16,
-    // col 4 s + l/16) with s = s0(c) + j. Chunk c starts at s0(c) = min(c C, KR - C) (C =
-    // kMfmaChunk, KR = npad / 4 >= C): the last chunk ends at the last step and overlaps the
-    // one before it, so its overlapping steps are stored as zeros; the two chunks after the last
-    // one are zero too (the kernel's look-ahead loads read them).
+    // k row kr). Chunk c covers the 32 k rows from 4 s0(c), s0(c) = min(c C, KR - C) (C =
+    // kMfmaChunk, KR = npad / 4 >= C), in the order that keeps the global step's LDS reads free
+    // of bank conflicts: lane group g = l/16 reads kr = 4 s0 + k_row_in_chunk(g, j). The last chunk
+    // ends at the last row and overlaps the one before it, so its rows below 4 c C are stored as
+    // zeros; the two chunks after the last one are zero too (the kernel's look-ahead loads read
+    // them).
     const int RT = p.row_tiles, KS = p.k_steps, n = ct->n;
     const int KR = ct->npad / 4, C = kMfmaChunk, nch = (KR + C - 1) / C;
     auto tiles = [&](const std::vector<double>& dense) {
       std::vector<float> lt((size_t)RT * KS * 64, 0.0f);
       for (int rt = 0; rt < RT; ++rt)
-        for (int c = 0; c < nch; ++c)
-          for (int j = 0; j < C; ++j) {
-            const int s = std::min(c * C, KR - C) + j;
-            if (s < c * C) continue;   // covered by the previous chunk
+        for (int c = 0; c < nch; ++c) {
+          const int s0 = std::min(c * C, KR - C);
+          for (int j = 0; j < C; ++j)
             for (int l = 0; l < 64; ++l) {
-              const int row = rt * 16 + (l & 15), col = 4 * s + (l >> 4);
-              if (row < n && col < n)
-                lt[((size_t)rt * KS + c * C + j) * 64 + l] = (float)dense[(size_t)row * n + col];
+              const int row = rt * 16 + (l & 15), kr = 4 * s0 + k_row_in_chunk(l >> 4, j);
+              if (kr < 4 * c * C) continue;   // covered by the previous chunk
+              if (row < n && kr < n)
+                lt[((size_t)rt * KS + c * C + j) * 64 + l] = (float)dense[(size_t)row * n + kr];
             }
-          }
+        }
       return lt;
     };
     chk(upload(&d->linv_tiles, tiles(ct->Linv)));
@@ -369,7 +371,7 @@ npfem_status relayout(npfem_batch* b) {
     if (st != NPFEM_OK) return st;
     HIP_TRY(hipMemcpy(b->d_types + ti, &v, sizeof(DevType), hipMemcpyHostToDevice));
     const int cap = kFusedWaves * t->layouts[b->layout_of[ti]].gw;
-    const size_t per_cell = (2 * 3 * (size_t)t->npad + (t->kappa > 0.0 ? kDampWords : 0)) * sizeof(float);
+    const size_t per_cell = (2 * (size_t)t->cs + (t->kappa > 0.0 ? kDampWords : 0)) * sizeof(float);
     b->lds_bytes = std::max(b->lds_bytes, (size_t)cap * per_cell);
   }
   std::vector<FusedGroup> groups;

@@ -2,9 +2,9 @@
 //
 // One workgroup (4 waves) takes a group of up to 4*gw cells of one type. Per cell, LDS holds
 // the current positions X and the gradient/update R, FP32, vertex-interleaved
-// [cell][vertex][xyz] with a cell stride of 3*npad words (npad >= n, a multiple of 4 whose
-// quarter is odd, so 3*npad = 12 mod 64 and an MFMA B tile of 16 columns x 4 rows spreads
-// over distinct banks).
+// [cell][vertex][xyz] with a cell stride of cs = 3 (mod 16) words (3 npad, npad >= n a
+// multiple of 4, plus pad words); with the global step's k-row order each half-wave of an MFMA
+// B-tile read then touches 32 distinct LDS banks.
 // Each wave owns gw cells for everything except the global step:
 //   prediction      delta^0 = h v + h^2 F/m, kept with delta and the cell-local rest of x_n
 //                   in the owning lanes' registers (supplementary material, npFEM
@@ -120,9 +120,10 @@ typedef const __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(3))) float lfloat;
 
 // Word offset of MFMA column col (3 cell + coord) of row 0; columns past the group's last
-// read column 0 (their results are discarded).
+// read the first column of their tile (the same words as its lanes: no further LDS banks;
+// their results are discarded).
 __device__ __forceinline__ int col_base(int col, int ncols, int CS) {
-  col = col < ncols ? col : 0;
+  col = col < ncols ? col : (col & ~15);
   const int cell = col / 3;
   return cell * CS + (col - 3 * cell);
 }
@@ -134,10 +135,11 @@ __device__ __forceinline__ void load_a(float (&a)[kMfmaChunk], gfloat* La, int c
   for (int j = 0; j < kMfmaChunk; ++j) a[j] = La[(c * kMfmaChunk + j) * 64];
 }
 
-// B values of chunk c: row 4 s + lane / 16 of the lane's column for the chunk's k steps
-// s = s0 + j, read at Rb[12 s]. Chunks start at s0 = min(c kMfmaChunk, KR - kMfmaChunk): the
-// last chunk is shifted back to end at the last step and overlaps its predecessor, whose
-// overlapping steps hold zero A fragments in that chunk (as do the zero chunks after it).
+// B values of chunk c: k row 4 s0 + k_row_in_chunk(lane / 16, j) of the lane's column at step
+// j, read at Rb[12 s0 + 6 j] (Rb includes the lane group's row offset). Chunks start at
+// s0 = min(c kMfmaChunk, KR - kMfmaChunk): the last chunk is shifted back to end at the last
+// row and overlaps its predecessor, whose rows hold zero A fragments in that chunk (as do the
+// zero chunks after it).
 template <bool TWO>
 __device__ __forceinline__ void load_b(float (&b0)[kMfmaChunk], float (&b1)[kMfmaChunk],
                                        const lfloat* RbA, const lfloat* RbB, int c, int KR) {
@@ -146,8 +148,8 @@ __device__ __forceinline__ void load_b(float (&b0)[kMfmaChunk], float (&b1)[kMfm
   const lfloat* pb = RbB + 12 * s0;
 #pragma unroll
   for (int j = 0; j < kMfmaChunk; ++j) {
-    b0[j] = pa[12 * j];
-    if (TWO) b1[j] = pb[12 * j];
+    b0[j] = pa[3 * k_row_in_chunk(0, j)];
+    if (TWO) b1[j] = pb[3 * k_row_in_chunk(0, j)];
   }
 }
 
@@ -248,7 +250,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const DevType& T = types[grp.type];
     const int n = T.p.n, npad = T.p.npad, gw = T.p.gw, S = T.p.slots;
     const int G4 = kFusedWaves * gw;
-    const int CS = 3 * npad;                 // words per cell block
+    const int CS = T.p.cs;                   // words per cell block (3 npad + pad)
     float* X = lds;
     float* R = lds + G4 * CS;
 
@@ -422,10 +424,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
           if (CT >= 2) {
             const int rt = u / CT, ct = u - rt * CT;
-            const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * kq);
+            const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
             if (ct + 1 < CT && u + 1 < u1) {
               const lfloat* RbB =
-                  (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq);
+                  (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
               mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
               u += 2;
             } else {
@@ -433,7 +435,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               u += 1;
             }
           } else {
-            const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * kq);
+            const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
             mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
             if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
             u += (u + 1 < u1) ? 2 : 1;
@@ -680,10 +682,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
           if (CT >= 2) {
             const int rt = u / CT, ct = u - rt * CT;
-            const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * kq);
+            const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
             if (ct + 1 < CT && u + 1 < u1) {
               const lfloat* RbB =
-                  (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * kq);
+                  (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
               mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
               u += 2;
             } else {
@@ -691,7 +693,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               u += 1;
             }
           } else {
-            const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * kq);
+            const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
             mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
             if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
             u += (u + 1 < u1) ? 2 : 1;

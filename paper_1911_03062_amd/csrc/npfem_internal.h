@@ -59,7 +59,8 @@ struct FusedLayout {
 // Scalar parameters of a cell type as seen by the kernels.
 struct TypeParams {
   int32_t n, m, e, bw;          // vertices, triangles, hinges, band width of L
-  int32_t npad;                 // LDS row stride of one (cell, coordinate) column (fused)
+  int32_t npad;                 // MFMA k rows per cell (fused): n rounded up to whole k steps
+  int32_t cs;                   // LDS words per cell block (fused): 3 npad plus 3-15 pad words
   int32_t gw;                   // cells owned by one wave in a fused group
   int32_t slots;                // element slots per cell in a wave (64 / gw)
   int32_t tri_rounds, hinge_rounds;
@@ -144,7 +145,7 @@ struct npfem_celltype {
   // fused form: LDS column length and one element-schedule layout per feasible number of
   // cells per wave (largest first; layouts[0] is the default). gw, slots and the rounds
   // below describe layouts[0].
-  int gw = 0, slots = 0, npad = 0, tri_rounds = 0, hinge_rounds = 0;
+  int gw = 0, slots = 0, npad = 0, cs = 0, tri_rounds = 0, hinge_rounds = 0;
   std::vector<npfem::FusedLayout> layouts;
   bool fused_ok = false;
   std::string fused_reason;
@@ -197,6 +198,11 @@ constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per 
 #else
 #define NPFEM_HD
 #endif
+// k row, within a chunk's 32 rows, of MFMA lane group g = lane / 16 at step j of the chunk:
+// 2 j + {0, 16, 1, 17}[g]. The two groups of a half-wave read rows 16 apart (48 words: the
+// other 16 banks).
+inline NPFEM_HD constexpr int k_row_in_chunk(int g, int j) { return 2 * j + (g & 1) * 16 + (g >> 1); }
+static_assert(kMfmaChunk == 8, "a chunk covers the 32 k rows of k_row_in_chunk's order");
 // Number of work items the global step forms from the share [u0, u1) of the row-major tiles
 // of a group with col_tiles column tiles (the kernel's pairing rule: two column tiles of one
 // row tile, or two row tiles when there is one column tile).

@@ -593,14 +593,17 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   }
 
   // ---- fused-form layout and element schedules
-  // LDS column stride: a multiple of 4 (MFMA k step) whose quarter is odd, so that the 16
-  // columns x 4 rows of an MFMA B tile fall in 64 distinct LDS banks.
-  // (at least 36: the global step's k chunks of kMfmaChunk steps need npad / 4 >= kMfmaChunk)
-  int npad = std::max((n + 3) / 4 * 4, 4 * kMfmaChunk);
-  if ((npad / 4) % 2 == 0) npad += 4;
+  // k rows per cell: whole MFMA k steps of 4 rows, at least one chunk of kMfmaChunk steps
+  // (the global step's loads read whole chunks). A cell block of X or R holds 3 npad words
+  // [vertex][xyz] plus pad words up to a stride cs = 3 (mod 16): with the k-row order of the
+  // global step (in each chunk of 32 rows, the two lane groups of a half-wave read rows 16
+  // apart) every 16-column B tile then reads 32 distinct LDS banks per half-wave, for any
+  // number of cells in the group (32 banks of 4 bytes, served a half-wave at a time).
+  const int npad = std::max((n + 3) / 4 * 4, 4 * kMfmaChunk);
   ct->npad = npad;
-  // X and R columns (FP32), plus the per-cell damping data when the type is damped
-  const int per_cell = 2 * 3 * npad * 4 + (ct->kappa > 0.0 ? kDampWords * 4 : 0);
+  ct->cs = 3 * npad + (((3 - 3 * npad) % 16) + 16) % 16;
+  // X and R blocks (FP32), plus the per-cell damping data when the type is damped
+  const int per_cell = 2 * ct->cs * 4 + (ct->kappa > 0.0 ? kDampWords * 4 : 0);
   std::vector<int> feasible;
   for (int cand : {16, 8, 4, 2, 1}) {
     if (kFusedWaves * cand * per_cell > kFusedLdsBudget) continue;
@@ -640,8 +643,8 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     FusedLayout lay;
     lay.gw = gw;
     lay.slots = 64 / gw;
-    const Schedule tr = best_schedule(tel, n, gw, lay.slots, 3 * npad, kTriRoundValu);
-    const Schedule hr = best_schedule(hel, n, gw, lay.slots, 3 * npad, kHingeRoundValu);
+    const Schedule tr = best_schedule(tel, n, gw, lay.slots, ct->cs, kTriRoundValu);
+    const Schedule hr = best_schedule(hel, n, gw, lay.slots, ct->cs, kHingeRoundValu);
     lay.tri_rounds = (int)tr.rounds.size();
     lay.hinge_rounds = (int)hr.rounds.size();
     TriRec empty_tri{};

@@ -32,7 +32,7 @@ def _run(batch, b, forces, K):
     return x.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("rbc_gw,plt_gw", [(1, 8), (2, 4), (2, 2), (1, 1)])
+@pytest.mark.parametrize("rbc_gw,plt_gw", [(1, 4), (2, 4), (2, 2), (1, 1)])
 def test_layout_parity(rbc_gw, plt_gw):
     from paper_1911_03062_amd import npfem as N
     types = lib_types()
@@ -59,8 +59,12 @@ def test_layout_errors():
         batch.set_cells_per_wave(types[I.RBC], 4)           # not feasible for 258 vertices
     assert ei.value.name == "NPFEM_E_UNSUPPORTED"
     with pytest.raises(N.NpfemError) as ei:
-        batch.set_cells_per_wave(types[I.PLT], 8)           # type not in the batch
+        batch.set_cells_per_wave(types[I.PLT], 4)           # type not in the batch
     assert ei.value.name == "NPFEM_E_INVALID"
+    mixed = N.Batch([types[I.PLT], types[I.RBC]], 32, "fused")
+    with pytest.raises(N.NpfemError) as ei:
+        mixed.set_cells_per_wave(types[I.PLT], 8)           # 32 platelets exceed the LDS budget
+    assert ei.value.name == "NPFEM_E_UNSUPPORTED"
     plain = N.Batch([types[I.RBC]], 32, "plain")
     with pytest.raises(N.NpfemError) as ei:
         plain.autotune(10)
