@@ -350,6 +350,50 @@ def main():
     skalak_ms = se0.elapsed_time(se1) / p_steps
     del sbatch, sx, sv
 
+    # cell packing: the workload's cells placed at random at hematocrit 0.4, interpenetrating;
+    # each step finds the particle-in-kernel contacts of the current positions and then steps
+    # with their collision energies and no external force (eager, the main run's layouts)
+    log("packing run")
+    PK = I.PACKING
+    pk = I.packing_batch(b.types, seed=w.seed)
+    kbatch = N.Batch([types[int(t)] for t in pk.types], precision=32, form="fused")
+    for name, k in present.items():
+        kbatch.set_cells_per_wave(types[k], layouts[name])
+    kx = torch.tensor(pk.x0, dtype=torch.float32, device="cuda")
+    kv = torch.zeros_like(kx)
+    kf = torch.zeros_like(kx)
+    kp = torch.empty_like(kx)
+    kw = torch.empty((pk.v_total,), dtype=torch.float32, device="cuda")
+    Kp = PK["n_pd_iters"]
+
+    def pack_step():
+        kbatch.detect_contacts(kx, PK["radius"], PK["separation"], PK["weight"], kp, kw, stream)
+        kbatch.step(kx, kv, kf, I.DT, Kp, contacts=(kp, kw), stream=stream)
+
+    kbatch.detect_contacts(kx, PK["radius"], PK["separation"], PK["weight"], kp, kw, stream)
+    torch.cuda.synchronize()
+    pack_frac0 = float((kw > 0).float().mean())
+    de0, de1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    d_reps = 10
+    de0.record(stream)
+    for _ in range(d_reps):
+        kbatch.detect_contacts(kx, PK["radius"], PK["separation"], PK["weight"], kp, kw, stream)
+    de1.record(stream)
+    pack_step()
+    torch.cuda.synchronize()
+    detect_ms = de0.elapsed_time(de1) / d_reps
+    pk_steps = 200
+    pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pe0.record(stream)
+    for _ in range(pk_steps):
+        pack_step()
+    pe1.record(stream)
+    torch.cuda.synchronize()
+    kbatch.check()
+    packing_ms = pe0.elapsed_time(pe1) / pk_steps
+    pack_frac1 = float((kw > 0).float().mean())
+    del kbatch, kx, kv, kf, kp, kw
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -416,6 +460,17 @@ def main():
             "ms_per_step": skalak_ms, "value": len(pcells) * K / (skalak_ms * 1e-3),
             "unit": "cell-PD-iterations/s", "launches_per_cell_step": 3 * K + 2,
             "cost_vs_plain_pd": skalak_ms / plain_ms,
+        },
+        "packing": {
+            "config": f"the workload's cells at random rigid motions at hematocrit {PK['hematocrit']} "
+                      f"(interpenetrating), no external force, K = {Kp}; per step: contact "
+                      f"detection (kernel radius {PK['radius']} um, separation {PK['separation']} "
+                      f"um, w = {PK['weight']} pN/um) then the step with the collision energies; "
+                      f"{pk_steps + 1} steps, eager",
+            "ms_per_step": packing_ms, "detect_ms": detect_ms,
+            "value": n_cells * Kp / (packing_ms * 1e-3), "unit": "cell-PD-iterations/s",
+            "contact_fraction_first_step": pack_frac0,
+            "contact_fraction_last_step": pack_frac1,
         },
         "kernel_source_hash": kernel_source_hash(),
     }

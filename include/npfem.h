@@ -262,6 +262,34 @@ void npfem_graph_destroy(npfem_graph* graph);
 npfem_status npfem_filter_forces(npfem_batch* batch, const void* f_in, void* f_out, void* stream);
 
 /*
+ * Particle-in-kernel (PIK) contact detection (main text, near-contact handling; supplementary
+ * material, particle-in-kernel technique): produces the contact_p / contact_w inputs of
+ * npfem_step_contacts from the positions alone. For every vertex i of the batch, the colliding
+ * neighbour is the closest vertex j of ANOTHER cell with |x_i - x_j| < radius (the kernel
+ * sphere); distances are compared as squared distances ((dx dx + dy dy) + dz dz), every
+ * operation rounded in the batch precision (no fused multiply-add), strictly below
+ * radius^2, and among equal distances the smallest vertex index j wins. With a neighbour:
+ * contact_p[:, i] = x_j + separation * n_j, n_j the unit outward normal of j's cell at j
+ * (the normalised sum of its incident triangles' doubled area vectors), and
+ * contact_w[i] = weight. Without: contact_p[:, i] = x_i and contact_w[i] = 0. Asynchronous
+ * on `stream`; every cell of the batch takes part, whatever npfem_batch_set_active selected.
+ *   x          device, in, [3][V_total] positions (um), batch precision;
+ *   radius     kernel radius (um), finite, > 0; positions should stay within 1e4 radii of the
+ *              origin (the grid's cell coordinates are rounded products x / (1.001 radius));
+ *   separation distance (um) of the projection point from the neighbour, finite, >= 0;
+ *   weight     contact weight (pN/um) written for contacting vertices, finite, >= 0;
+ *   contact_p  device, out, [3][V_total], batch precision (may not overlap x);
+ *   contact_w  device, out, [V_total], batch precision.
+ * The first call allocates the batch's search workspace (a hash table of 2^k >= 2 V_total
+ * buckets and about 40 bytes per vertex); calls on one batch must not overlap in time.
+ * Errors: NPFEM_E_INVALID (null batch or buffer, radius / separation / weight out of range),
+ * NPFEM_E_NOMEM, NPFEM_E_HIP.
+ */
+npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double radius,
+                                   double separation, double weight, void* contact_p,
+                                   void* contact_w, void* stream);
+
+/*
  * Synchronise `stream` and report NPFEM_E_NONFINITE if any step since the last check
  * produced a non-finite position or velocity (the flag is then cleared), NPFEM_E_HIP on a
  * device error, NPFEM_OK otherwise.

@@ -4,4 +4,5 @@ from .meshes import (rbc_mesh, platelet_mesh, tetrahedron, octahedron, icosahedr
                      uv_sphere_topology, mesh_summary, RBC_DIAMETER, PLT_DIAMETER)
 from .workloads import (DT, RBC, PLT, DIAMETER, Material, RBC_MATERIAL, PLT_MATERIAL,
                         cell_type_inputs, make_batch, force_stream, strong_cells, Batch,
-                        Workload, WORKLOADS, random_rotations)
+                        Workload, WORKLOADS, random_rotations, NOMINAL_VOLUME, PACKING,
+                        packing_batch)

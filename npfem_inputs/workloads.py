@@ -139,6 +139,28 @@ def make_batch(types, seed: int, translate: float = 200.0, identity: bool = Fals
     return Batch(types, offsets, x0, np.zeros_like(x0), meshes)
 
 
+# Nominal cell volumes (fL = um^3) that size a packing box: the RBC mesh's own volume (about a
+# normal RBC) and the paper's platelet volume (6.8 fL).
+NOMINAL_VOLUME = {RBC: 90.0, PLT: 6.8}
+
+# Cell-packing run (main text: cells placed at random without avoiding interpenetration, then
+# advanced for a few thousand steps with the fluid switched off): hematocrit of the box, and
+# the collision parameters. The kernel sphere has a diameter of 4 dx (dx = 0.5 um, the fluid
+# lattice spacing of the workloads), so a radius of 1 um; the projection point lies one
+# kernel radius from the colliding neighbour along its cell's outward normal.
+PACKING = {"hematocrit": 0.40, "dx": 0.5, "radius": 1.0, "separation": 1.0, "weight": 400.0,
+           "n_pd_iters": 10}
+
+
+def packing_batch(types, seed: int, hematocrit: float = PACKING["hematocrit"]) -> Batch:
+    """Cells at random rigid motions with centres uniform in a cube whose volume is the cells'
+    nominal volume over the hematocrit; overlaps are not avoided."""
+    types = np.asarray(types, dtype=np.int32)
+    vol = float(sum(NOMINAL_VOLUME[int(t)] for t in types))
+    edge = (vol / hematocrit) ** (1.0 / 3.0)
+    return make_batch(types, seed, translate=edge)
+
+
 def force_stream(batch: Batch, seed: int, sigma: float, n_steps: int,
                  strong_fraction: float = 0.0, strong_factor: float = 10.0):
     """Yield one fresh external-force array float64 [3][V_total] (float32-rounded) per step.

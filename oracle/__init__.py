@@ -8,4 +8,5 @@ from .npfem_oracle import (ARMIJO_C, MAX_HALVINGS, CellType, step, step_batch, p
                            cell_volume_area, pbd_damp, rigid_velocity_fit,
                            one_ring_neighbours, median_filter_forces, median_filter_batch,
                            cap_velocities, stiffness_matrix,
-                           skalak_density, line_search_update)
+                           skalak_density, line_search_update, vertex_normals,
+                           closest_foreign_vertex, pik_contacts, packing_step)

@@ -42,6 +42,11 @@ w/2 ||A x - p(x)||^2 with exact projections p:
     vertex in contact, (w_i/2) ||x_i - p_i||^2 toward the projection point p_i of the closest
     foreign particle, added to g and its gradient but not to L (the caller supplies p and w,
     and zeroes F_ext at contacting vertices as the technique prescribes);
+  * contact detection of the technique (pik_contacts): the colliding neighbour of a vertex is
+    the closest vertex of another cell inside the kernel sphere, and its projection point
+    lies at a given separation from that neighbour along the neighbour cell's outward vertex
+    normal; the packing step (packing_step) is one step with these contacts and no external
+    force (main text: cells placed at random and advanced with the fluid switched off);
   * optional capping of the new vertex velocities at v_max (the velocity truncation for the
     stability of the immersed-boundary coupling, Fluid-structure interaction subsection);
 Everything is float64, vectorised over the cells of one type (arrays [N][n][3]).
@@ -633,3 +638,91 @@ def cell_volume_area(cell_types: dict, types, offsets, x, cells=None):
         out[pos, 0] = volume(xs, ct.tri)
         out[pos, 1] = surface_area(xs, ct.tri)
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# Particle-in-kernel contact detection and the packing step (supplementary material,
+# particle-in-kernel technique; main text, near-contact handling and cell packing).
+# ----------------------------------------------------------------------------------------
+
+
+def vertex_normals(x, tri):
+    """Unit outward vertex normals of closed meshes x [N][n][3]: for every vertex, the
+    normalised sum over its triangles (a, b, c), counter-clockwise seen from outside, of
+    (x_b - x_a) x (x_c - x_a) (the area-weighted normal). Float64."""
+    tri = np.asarray(tri)
+    a, b, c = x[:, tri[:, 0]], x[:, tri[:, 1]], x[:, tri[:, 2]]
+    nt = np.cross(b - a, c - a)
+    n = np.zeros_like(x, dtype=np.float64)
+    for k in range(3):
+        np.add.at(n, (slice(None), tri[:, k]), nt)
+    return n / np.linalg.norm(n, axis=-1, keepdims=True)
+
+
+def closest_foreign_vertex(x, cell_of, radius: float, dtype=np.float64, rows=None):
+    """The colliding neighbour of the technique: for every vertex i (or the listed rows) of
+    x [3][V], the vertex j of another cell (cell_of [V]) with the smallest squared distance
+    ((dx dx + dy dy) + dz dz), computed with every operation rounded in `dtype`, among those
+    strictly below radius^2 (radius rounded to dtype, squared in dtype); the smallest j among
+    equal distances; -1 where no foreign vertex lies inside the kernel. Brute force over all
+    pairs, in blocks of rows."""
+    xd = np.asarray(x).astype(dtype)
+    cell_of = np.asarray(cell_of)
+    r = dtype(radius)
+    r2 = dtype(r * r)
+    V = xd.shape[1]
+    rows = np.arange(V) if rows is None else np.asarray(rows)
+    out = np.full(len(rows), -1, dtype=np.int64)
+    block = max(1, 4_000_000 // max(V, 1))
+    for s in range(0, len(rows), block):
+        ri = rows[s:s + block]
+        dx = xd[0][None, :] - xd[0][ri][:, None]
+        dy = xd[1][None, :] - xd[1][ri][:, None]
+        dz = xd[2][None, :] - xd[2][ri][:, None]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        d2[cell_of[None, :] == cell_of[ri][:, None]] = np.inf
+        j = np.argmin(d2, axis=1)                       # first (smallest) j among equal minima
+        hit = d2[np.arange(len(ri)), j] < r2
+        out[s:s + block] = np.where(hit, j, -1)
+    return out
+
+
+def pik_contacts(cell_types: dict, types, offsets, x, radius: float, separation: float,
+                 weight: float, dtype=np.float64, rows=None):
+    """Collision inputs of the technique from positions x [3][V_total]: for a vertex i with a
+    colliding neighbour j (closest_foreign_vertex), the projection point
+    p_i = x_j + separation * n_j (n_j the unit outward vertex normal of j's cell at j) and the
+    weight w_i = weight; otherwise p_i = x_i and w_i = 0. Returns (p [3][R], w [R], j [R]) in
+    float64 for the listed rows (default: every vertex)."""
+    types = np.asarray(types)
+    offsets = np.asarray(offsets)
+    V = int(offsets[-1])
+    cell_of = np.repeat(np.arange(len(types)), np.diff(offsets))
+    rows = np.arange(V) if rows is None else np.asarray(rows)
+    j = closest_foreign_vertex(x, cell_of, radius, dtype, rows)
+    xf = np.asarray(x, dtype=np.float64)
+    p = xf[:, rows].copy()
+    w = np.zeros(len(rows))
+    hit = np.nonzero(j >= 0)[0]
+    for k in hit:
+        jj = int(j[k])
+        c = int(cell_of[jj])
+        ct = cell_types[int(types[c])]
+        xs = xf[:, offsets[c]:offsets[c + 1]].T[None]
+        n = vertex_normals(xs, ct.tri)[0, jj - offsets[c]]
+        p[:, k] = xf[:, jj] + separation * n
+        w[k] = weight
+    return p, w, j
+
+
+def packing_step(cell_types: dict, types, offsets, x, v, n_iters: int, radius: float,
+                 separation: float, weight: float, dtype=np.float64):
+    """One step of the cell-packing run (main text: cells placed at random, interpenetrating,
+    then advanced with the fluid and the coupling switched off): contacts from the current
+    positions, no external force, and the collision energies in the step. Returns
+    (x, v, w) with w the contact weights the step used."""
+    p, w, _ = pik_contacts(cell_types, types, offsets, x, radius, separation, weight, dtype)
+    f = np.zeros_like(np.asarray(x, dtype=np.float64))
+    xn, vn = step_batch(cell_types, types, offsets, np.asarray(x, np.float64),
+                        np.asarray(v, np.float64), f, n_iters, contact_p=p, contact_w=w)
+    return xn, vn, w

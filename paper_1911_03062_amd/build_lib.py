@@ -18,7 +18,8 @@ CHECK_LIB = os.path.join(HERE, "libnpfem_elemcheck.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["setup.cpp", "capi.cpp", "kernels_plain.hip", "kernels_fused.hip", "kernels_filter.hip"]
+SOURCES = ["setup.cpp", "capi.cpp", "kernels_plain.hip", "kernels_fused.hip", "kernels_filter.hip",
+           "kernels_contacts.hip"]
 
 # Device code is compiled without packed-FP32 instructions (v_pk_*_f32).
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "npfem_internal.h"
+#include "contacts.h"
 
 namespace npfem {
 
@@ -294,6 +295,7 @@ struct npfem_batch {
   bool fused_extras = false;                // a type damps or caps velocities (kernel variant)
   void* work = nullptr;                     // plain-form workspace
   int* d_flag = nullptr;
+  npfem::ContactWork contacts;              // contact detection workspace (first use)
   ~npfem_batch() {
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -317,6 +319,7 @@ struct npfem_batch {
     if (d_filter_blocks) (void)hipFree(d_filter_blocks);
     if (work) (void)hipFree(work);
     if (d_flag) (void)hipFree(d_flag);
+    npfem::contact_work_free(contacts);
     (void)hipSetDevice(cur);
   }
 };
@@ -913,6 +916,46 @@ npfem_status npfem_filter_forces(npfem_batch* b, const void* f_in, void* f_out, 
                                             b->d_filter_blocks, b->n_filter_blocks,
                                             b->offsets.back(), f_in, f_out, b->filter_lds, stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("median filter launch: ") + hipGetErrorString(e));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_detect_contacts(npfem_batch* b, const void* x, double radius,
+                                   double separation, double weight, void* contact_p,
+                                   void* contact_w, void* stream) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  if (!(radius > 0.0) || !std::isfinite(radius))
+    return fail(NPFEM_E_INVALID, "radius must be finite and > 0");
+  if (!(separation >= 0.0) || !std::isfinite(separation))
+    return fail(NPFEM_E_INVALID, "separation must be finite and >= 0");
+  if (!(weight >= 0.0) || !std::isfinite(weight))
+    return fail(NPFEM_E_INVALID, "weight must be finite and >= 0");
+  if (b->n_cells == 0) return NPFEM_OK;
+  if (!x || !contact_p || !contact_w) return fail(NPFEM_E_INVALID, "null buffer");
+  DeviceGuard guard(b->device);
+  npfem::ContactWork& w = b->contacts;
+  if (w.n_vertices == 0) {
+    const int64_t V = b->offsets.back();
+    if (npfem::contact_work_alloc(w, V, b->n_cells) != hipSuccess)
+      return fail(NPFEM_E_NOMEM, "contact detection workspace");
+    std::vector<int32_t> cell_of((size_t)V), type_of((size_t)b->n_cells);
+    for (int c = 0; c < b->n_cells; ++c) {
+      type_of[c] = b->type_of[c];
+      for (int64_t i = b->offsets[c]; i < b->offsets[c + 1]; ++i) cell_of[(size_t)i] = c;
+    }
+    hipError_t e = hipMemcpy(w.cell_of, cell_of.data(), sizeof(int32_t) * cell_of.size(),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(w.type_of, type_of.data(), sizeof(int32_t) * type_of.size(),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      npfem::contact_work_free(w);
+      return fail(NPFEM_E_HIP, std::string("contact tables: ") + hipGetErrorString(e));
+    }
+  }
+  const hipError_t e = npfem::launch_detect_contacts(b->precision, b->d_types, b->d_offsets, w, x,
+                                                     radius, separation, weight, contact_p,
+                                                     contact_w, stream);
+  if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("contact detection: ") + hipGetErrorString(e));
   return NPFEM_OK;
 }
 

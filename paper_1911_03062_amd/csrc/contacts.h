@@ -1,0 +1,36 @@
+// Launchers of the particle-in-kernel (PIK) contact detection kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include <hip/hip_runtime_api.h>
+
+#include "npfem_internal.h"
+
+namespace npfem {
+
+// Device workspace of one batch's contact detection, sized for V vertices.
+struct ContactWork {
+  int64_t n_vertices = 0;
+  uint32_t n_buckets = 0;         // hash table size: a power of two >= 2 V
+  int32_t* cell_of = nullptr;     // [V] cell of each vertex
+  int32_t* type_of = nullptr;     // [n_cells] type index of each cell
+  int32_t* bucket = nullptr;      // [V] bucket of each vertex
+  uint32_t* count = nullptr;      // [n_buckets] vertices per bucket (scatter cursor)
+  uint32_t* start = nullptr;      // [n_buckets + 1] exclusive prefix sum of count
+  void* entries = nullptr;        // [V] positions and vertex index, sorted by bucket
+  void* scan_tmp = nullptr;       // hipcub scan scratch
+  size_t scan_bytes = 0;
+};
+
+// Allocates w for V vertices (cell_of / type_of filled by the caller afterwards).
+hipError_t contact_work_alloc(ContactWork& w, int64_t n_vertices, int n_cells);
+void contact_work_free(ContactWork& w);
+
+// One detection pass: fills contact_p [3][V] and contact_w [V] (precision 32 or 64).
+hipError_t launch_detect_contacts(int precision, const DevType* types, const int64_t* offsets,
+                                  ContactWork& w, const void* x, double radius, double separation,
+                                  double weight, void* contact_p, void* contact_w, void* stream);
+
+}  // namespace npfem

@@ -1,0 +1,221 @@
+// Particle-in-kernel (PIK) contact detection: for every vertex of the batch, the closest
+// vertex of another cell inside the interpolation kernel's sphere, and the projection point
+// that the collision energy pulls the vertex towards (main text, near-contact handling;
+// supplementary material, particle-in-kernel technique).
+//
+// A uniform grid of cell size c (slightly above the kernel radius r) is hashed into a table
+// of 2^k buckets (spatial hashing of Teschner et al., 2003: XOR of the integer cell
+// coordinates times three large primes); a counting sort places every vertex's position and
+// index in its bucket's range. A vertex then scans the 27 buckets around its own grid cell:
+// every vertex within r lies in one of them, since |x_i - x_j| < r < c keeps the cell
+// coordinates within one of each other. Buckets shared by distant grid cells only add
+// candidates that the distance test rejects.
+//
+// The choice of the neighbour is exact and independent of the order of the scan: squared
+// distances in the batch precision, ((dx dx + dy dy) + dz dz) with every operation rounded
+// (no fused multiply-add), strictly below r^2, smallest distance first and the smallest
+// vertex index among equal distances.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "contacts.h"
+
+namespace npfem {
+
+namespace {
+
+constexpr int kContactThreads = 256;
+constexpr double kCellOverRadius = 1.001;   // grid cell size / kernel radius
+
+template <typename T>
+struct Entry {
+  T x, y, z;
+  int32_t j;
+};
+
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
+__device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(a, b); }
+
+__device__ __forceinline__ uint32_t bucket_of(int ix, int iy, int iz, uint32_t mask) {
+  return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) &
+         mask;
+}
+
+template <typename T>
+__device__ __forceinline__ int grid_coord(T v, T inv_c) {
+  return (int)floor(v * inv_c);
+}
+
+__global__ void __launch_bounds__(kContactThreads) k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kContactThreads)
+    k_contact_count(const T* __restrict__ x, int64_t V, T inv_c, uint32_t mask,
+                    int32_t* __restrict__ bucket, uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  if (i >= V) return;
+  const uint32_t b = bucket_of(grid_coord(x[i], inv_c), grid_coord(x[V + i], inv_c),
+                               grid_coord(x[2 * V + i], inv_c), mask);
+  bucket[i] = (int32_t)b;
+  atomicAdd(&count[b], 1u);
+}
+
+// Counting-sort scatter: count[b] runs down to zero, so the table is clear for the next pass.
+template <typename T>
+__global__ void __launch_bounds__(kContactThreads)
+    k_contact_scatter(const T* __restrict__ x, int64_t V, const int32_t* __restrict__ bucket,
+                      const uint32_t* __restrict__ start, uint32_t* __restrict__ count,
+                      Entry<T>* __restrict__ entries) {
+  const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  if (i >= V) return;
+  const uint32_t b = (uint32_t)bucket[i];
+  const uint32_t pos = start[b] + atomicSub(&count[b], 1u) - 1u;
+  Entry<T> e;
+  e.x = x[i];
+  e.y = x[V + i];
+  e.z = x[2 * V + i];
+  e.j = (int32_t)i;
+  entries[pos] = e;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kContactThreads)
+    k_contact_query(const DevType* __restrict__ types, const int64_t* __restrict__ offsets,
+                    const int32_t* __restrict__ cell_of, const int32_t* __restrict__ type_of,
+                    const T* __restrict__ x, int64_t V, T inv_c, uint32_t mask,
+                    const uint32_t* __restrict__ start, const Entry<T>* __restrict__ entries,
+                    T r2, T sep, T weight, T* __restrict__ cp, T* __restrict__ cw) {
+  const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  if (i >= V) return;
+  const T xi = x[i], yi = x[V + i], zi = x[2 * V + i];
+  const int ci = cell_of[i];
+  const int gx = grid_coord(xi, inv_c), gy = grid_coord(yi, inv_c), gz = grid_coord(zi, inv_c);
+  T best = r2;
+  int32_t bj = -1;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const uint32_t b = bucket_of(gx + dx, gy + dy, gz + dz, mask);
+        const uint32_t k1 = start[b + 1];
+        for (uint32_t k = start[b]; k < k1; ++k) {
+          const Entry<T> e = entries[k];
+          const T ex = sub_rn(e.x, xi), ey = sub_rn(e.y, yi), ez = sub_rn(e.z, zi);
+          const T d2 = add_rn(add_rn(mul_rn(ex, ex), mul_rn(ey, ey)), mul_rn(ez, ez));
+          if (d2 < r2 && (d2 < best || (d2 == best && e.j < bj)) && cell_of[e.j] != ci) {
+            best = d2;
+            bj = e.j;
+          }
+        }
+      }
+  if (bj < 0) {
+    cp[i] = xi;
+    cp[V + i] = yi;
+    cp[2 * V + i] = zi;
+    cw[i] = T(0);
+    return;
+  }
+  // unit outward normal of the neighbour's cell at the neighbour: the sum of its incident
+  // triangles' doubled area vectors (x_b - x_j) x (x_c - x_j), (j, b, c) counter-clockwise
+  const int cj = cell_of[bj];
+  const DevType& D = types[type_of[cj]];
+  const int64_t off = offsets[cj];
+  const int vj = (int)(bj - off);
+  const T xj = x[bj], yj = x[V + bj], zj = x[2 * V + bj];
+  const uint32_t info = D.ring_info[vj];
+  const int roff = (int)(info >> 8), deg = (int)(info & 255u);
+  T nx = T(0), ny = T(0), nz = T(0);
+  for (int s = 0; s < deg; ++s) {
+    const uint32_t pr = D.ring_pairs[roff + s];
+    const int64_t b = off + (int64_t)(pr & 0xffffu), c = off + (int64_t)(pr >> 16);
+    const T bx = x[b] - xj, by = x[V + b] - yj, bz = x[2 * V + b] - zj;
+    const T cx = x[c] - xj, cy = x[V + c] - yj, cz = x[2 * V + c] - zj;
+    nx += by * cz - bz * cy;
+    ny += bz * cx - bx * cz;
+    nz += bx * cy - by * cx;
+  }
+  const T s = sep / sqrt(nx * nx + ny * ny + nz * nz);
+  cp[i] = xj + s * nx;
+  cp[V + i] = yj + s * ny;
+  cp[2 * V + i] = zj + s * nz;
+  cw[i] = weight;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kContactThreads - 1) / kContactThreads); }
+
+template <typename T>
+hipError_t detect(const DevType* types, const int64_t* offsets, ContactWork& w, const T* x,
+                  double radius, double separation, double weight, T* cp, T* cw, hipStream_t s) {
+  const int64_t V = w.n_vertices;
+  const T inv_c = (T)(1.0 / (radius * kCellOverRadius));
+  const T r = (T)radius;
+  const T r2 = r * r;
+  const uint32_t mask = w.n_buckets - 1u;
+  Entry<T>* entries = static_cast<Entry<T>*>(w.entries);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(w.n_buckets + 1)), dim3(kContactThreads), 0, s,
+                     w.count, (int64_t)w.n_buckets + 1, 0u);
+  hipLaunchKernelGGL(k_contact_count<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, x, V,
+                     inv_c, mask, w.bucket, w.count);
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(w.scan_tmp, w.scan_bytes, w.count, w.start,
+                                                  (int)w.n_buckets + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_contact_scatter<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, x, V,
+                     w.bucket, w.start, w.count, entries);
+  hipLaunchKernelGGL(k_contact_query<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, types,
+                     offsets, w.cell_of, w.type_of, x, V, inv_c, mask, w.start, entries, r2,
+                     (T)separation, (T)weight, cp, cw);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t contact_work_alloc(ContactWork& w, int64_t n_vertices, int n_cells) {
+  contact_work_free(w);
+  uint32_t nb = 1024;
+  while ((int64_t)nb < 2 * n_vertices) nb <<= 1;
+  w.n_vertices = n_vertices;
+  w.n_buckets = nb;
+  const size_t entry_bytes = sizeof(Entry<double>);   // large enough for either precision
+  hipError_t e = hipSuccess;
+  if ((e = hipMalloc(&w.cell_of, sizeof(int32_t) * (size_t)n_vertices)) != hipSuccess ||
+      (e = hipMalloc(&w.type_of, sizeof(int32_t) * (size_t)n_cells)) != hipSuccess ||
+      (e = hipMalloc(&w.bucket, sizeof(int32_t) * (size_t)n_vertices)) != hipSuccess ||
+      (e = hipMalloc(&w.count, sizeof(uint32_t) * ((size_t)nb + 1))) != hipSuccess ||
+      (e = hipMalloc(&w.start, sizeof(uint32_t) * ((size_t)nb + 1))) != hipSuccess ||
+      (e = hipMalloc(&w.entries, entry_bytes * (size_t)n_vertices)) != hipSuccess) {
+    contact_work_free(w);
+    return e;
+  }
+  e = hipcub::DeviceScan::ExclusiveSum(nullptr, w.scan_bytes, w.count, w.start, (int)nb + 1);
+  if (e == hipSuccess) e = hipMalloc(&w.scan_tmp, w.scan_bytes > 0 ? w.scan_bytes : 1);
+  if (e != hipSuccess) contact_work_free(w);
+  return e;
+}
+
+void contact_work_free(ContactWork& w) {
+  for (void* p : {(void*)w.cell_of, (void*)w.type_of, (void*)w.bucket, (void*)w.count,
+                  (void*)w.start, w.entries, w.scan_tmp})
+    if (p) (void)hipFree(p);
+  w = ContactWork{};
+}
+
+hipError_t launch_detect_contacts(int precision, const DevType* types, const int64_t* offsets,
+                                  ContactWork& w, const void* x, double radius, double separation,
+                                  double weight, void* contact_p, void* contact_w, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (w.n_vertices == 0) return hipSuccess;
+  if (precision == 64)
+    return detect<double>(types, offsets, w, static_cast<const double*>(x), radius, separation,
+                          weight, static_cast<double*>(contact_p), static_cast<double*>(contact_w),
+                          s);
+  return detect<float>(types, offsets, w, static_cast<const float*>(x), radius, separation, weight,
+                       static_cast<float*>(contact_p), static_cast<float*>(contact_w), s);
+}
+
+}  // namespace npfem

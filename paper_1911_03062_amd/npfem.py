@@ -92,6 +92,9 @@ def lib() -> ctypes.CDLL:
     L.npfem_batch_check.argtypes = [c_void_p, c_void_p]
     L.npfem_filter_forces.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     L.npfem_filter_forces.restype = c_int32
+    L.npfem_detect_contacts.argtypes = [c_void_p, c_void_p, c_double, c_double, c_double,
+                                        c_void_p, c_void_p, c_void_p]
+    L.npfem_detect_contacts.restype = c_int32
     L.npfem_batch_check.restype = c_int32
     L.npfem_celltype_cells_per_wave.argtypes = [c_void_p, POINTER(c_int32), c_int32]
     L.npfem_celltype_cells_per_wave.restype = c_int32
@@ -249,6 +252,28 @@ class Batch:
         _check(lib().npfem_filter_forces(self._h, f_in.data_ptr(), f_out.data_ptr(),
                                          c_void_p(s.cuda_stream)))
         return f_out
+
+    def detect_contacts(self, x, radius: float, separation: float, weight: float,
+                        contact_p=None, contact_w=None, stream=None):
+        """Particle-in-kernel contacts from positions x [3][V_total]: returns (contact_p
+        [3][V_total], contact_w [V_total]) for step(..., contacts=...), allocated when not
+        given."""
+        import torch
+        dtype = torch.float64 if self.precision == 64 else torch.float32
+        if contact_p is None:
+            contact_p = torch.empty_like(x)
+        if contact_w is None:
+            contact_w = torch.empty((self.vertex_count,), dtype=dtype, device=x.device)
+        for name, t, shape in (("x", x, (3, self.vertex_count)),
+                               ("contact_p", contact_p, (3, self.vertex_count)),
+                               ("contact_w", contact_w, (self.vertex_count,))):
+            if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == shape):
+                raise ValueError(f"{name} must be a contiguous device tensor {list(shape)} of {dtype}")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_detect_contacts(self._h, x.data_ptr(), float(radius), float(separation),
+                                           float(weight), contact_p.data_ptr(),
+                                           contact_w.data_ptr(), c_void_p(s.cuda_stream)))
+        return contact_p, contact_w
 
     def _check_state(self, x, v, forces, vol_area):
         import torch
