@@ -131,6 +131,8 @@ def main():
                     help="keep the default fused layouts instead of timing them first")
     ap.add_argument("--cells-per-wave", default=None,
                     help="fused layouts as 'RBC,PLT' cells per wave (skips the autotuner)")
+    ap.add_argument("--packing-steps", type=int, default=200,
+                    help="timed steps of the packing leg (detection + step)")
     ap.add_argument("--eager", action="store_true",
                     help="time plain npfem_step calls instead of HIP-graph replays")
     args = ap.parse_args()
@@ -382,7 +384,7 @@ def main():
     pack_step()
     torch.cuda.synchronize()
     detect_ms = de0.elapsed_time(de1) / d_reps
-    pk_steps = 200
+    pk_steps = max(1, args.packing_steps)
     pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     pe0.record(stream)
     for _ in range(pk_steps):
