@@ -13,7 +13,7 @@ namespace npfem {
 // Device workspace of one batch's contact detection, sized for V vertices.
 struct ContactWork {
   int64_t n_vertices = 0;
-  uint32_t n_buckets = 0;         // hash table size: a power of two >= 2 V
+  uint32_t n_buckets = 0;         // bucket table size: a power of two >= 2 V
   int32_t* cell_of = nullptr;     // [V] cell of each vertex
   int32_t* type_of = nullptr;     // [n_cells] type index of each cell
   int32_t* bucket = nullptr;      // [V] bucket of each vertex

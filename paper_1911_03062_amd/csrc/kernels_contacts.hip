@@ -3,14 +3,17 @@
 // that the collision energy pulls the vertex towards (main text, near-contact handling;
 // supplementary material, particle-in-kernel technique).
 //
-// A uniform grid of cell size c (slightly above the kernel radius r) is hashed into a table
-// of 2^k buckets (spatial hashing of Teschner et al., 2003: XOR of the integer cell
-// coordinates times three large primes); a counting sort places every vertex's position and
-// index in its bucket's range. A vertex then scans the buckets of the 27 grid cells around
-// its own: every vertex within r lies in one of them, since |x_i - x_j| < r < c keeps the
-// cell coordinates within one of each other; cells whose box is a full cell size or more
-// from the vertex are skipped (on average about 6 of the 27). Buckets shared by distant grid
-// cells only add candidates that the distance test rejects.
+// A uniform grid of cell size c (slightly above the kernel radius r) is folded into a table
+// of 2^k buckets by a periodic linear index, bucket = (ix mod 2^kx) + 2^kx ((iy mod 2^ky) +
+// 2^ky (iz mod 2^kz)) with kx + ky + kz = k, so that neighbouring grid cells along x are
+// consecutive buckets; a counting sort places every vertex's position and index in its
+// bucket's range. Queries run in that bucket order (neighbouring lanes read nearly the same
+// records). A vertex scans the grid cells around its own, one row along x at a time (one
+// contiguous range of records unless the row wraps around the fold): every vertex within r
+// lies in one of the 27, since |x_i - x_j| < r < c keeps the cell coordinates within one of
+// each other, and cells whose box is a full cell size or more from the vertex are skipped
+// (on average about 6 of the 27). Grid cells one fold period or more apart share buckets;
+// their records only add candidates that the distance test rejects.
 //
 // The choice of the neighbour is exact and independent of the order of the scan: squared
 // distances in the batch precision, ((dx dx + dy dy) + dz dz) with every operation rounded
@@ -41,9 +44,16 @@ __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(
 __device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
 __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(a, b); }
 
-__device__ __forceinline__ uint32_t bucket_of(int ix, int iy, int iz, uint32_t mask) {
-  return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) &
-         mask;
+// Periodic linear index of grid cell (ix, iy, iz); g = (kx, ky, kz) bit widths.
+struct GridFold {
+  uint32_t kx, ky, kz;
+};
+
+__device__ __forceinline__ uint32_t bucket_of(int ix, int iy, int iz, GridFold g) {
+  const uint32_t bx = (uint32_t)ix & ((1u << g.kx) - 1u);
+  const uint32_t by = (uint32_t)iy & ((1u << g.ky) - 1u);
+  const uint32_t bz = (uint32_t)iz & ((1u << g.kz) - 1u);
+  return bx | (by << g.kx) | (bz << (g.kx + g.ky));
 }
 
 template <typename T>
@@ -58,12 +68,12 @@ __global__ void __launch_bounds__(kContactThreads) k_fill_u32(uint32_t* p, int64
 
 template <typename T>
 __global__ void __launch_bounds__(kContactThreads)
-    k_contact_count(const T* __restrict__ x, int64_t V, T inv_c, uint32_t mask,
+    k_contact_count(const T* __restrict__ x, int64_t V, T inv_c, GridFold fold,
                     int32_t* __restrict__ bucket, uint32_t* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
   if (i >= V) return;
   const uint32_t b = bucket_of(grid_coord(x[i], inv_c), grid_coord(x[V + i], inv_c),
-                               grid_coord(x[2 * V + i], inv_c), mask);
+                               grid_coord(x[2 * V + i], inv_c), fold);
   bucket[i] = (int32_t)b;
   atomicAdd(&count[b], 1u);
 }
@@ -90,12 +100,15 @@ template <typename T>
 __global__ void __launch_bounds__(kContactThreads)
     k_contact_query(const DevType* __restrict__ types, const int64_t* __restrict__ offsets,
                     const int32_t* __restrict__ cell_of, const int32_t* __restrict__ type_of,
-                    const T* __restrict__ x, int64_t V, T inv_c, uint32_t mask,
+                    const T* __restrict__ x, int64_t V, T inv_c, GridFold fold,
                     const uint32_t* __restrict__ start, const Entry<T>* __restrict__ entries,
                     T r2, T sep, T weight, T* __restrict__ cp, T* __restrict__ cw) {
-  const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
-  if (i >= V) return;
-  const T xi = x[i], yi = x[V + i], zi = x[2 * V + i];
+  const int64_t q = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  if (q >= V) return;
+  // queries in bucket order: neighbouring lanes scan nearly the same rows of records
+  const Entry<T> me = entries[q];
+  const int64_t i = me.j;
+  const T xi = me.x, yi = me.y, zi = me.z;
   const int ci = cell_of[i];
   const int64_t own0 = offsets[ci], own1 = offsets[ci + 1];   // the vertex's own cell
   const T ux = xi * inv_c, uy = yi * inv_c, uz = zi * inv_c;   // grid units
@@ -103,25 +116,36 @@ __global__ void __launch_bounds__(kContactThreads)
   const T fx = ux - (T)gx, fy = uy - (T)gy, fz = uz - (T)gz;
   T best = r2;
   int32_t bj = -1;
+  auto scan = [&](uint32_t k0, uint32_t k1) {
+    for (uint32_t k = k0; k < k1; ++k) {
+      const Entry<T> e = entries[k];
+      const T ex = sub_rn(e.x, xi), ey = sub_rn(e.y, yi), ez = sub_rn(e.z, zi);
+      const T d2 = add_rn(add_rn(mul_rn(ex, ex), mul_rn(ey, ey)), mul_rn(ez, ez));
+      if (d2 < r2 && (e.j < own0 || e.j >= own1) && (d2 < best || (d2 == best && e.j < bj))) {
+        best = d2;
+        bj = e.j;
+      }
+    }
+  };
+  // grid cells whose box lies a full cell (1.001 r) or more away hold no vertex within r
+  // (the margin covers the rounding of the grid units); the cells of one row along x that
+  // remain are consecutive buckets unless the row wraps around the fold
   for (int dz = -1; dz <= 1; ++dz) {
     const T cz = dz < 0 ? fz : (dz > 0 ? T(1) - fz : T(0));
     for (int dy = -1; dy <= 1; ++dy) {
       const T cy = dy < 0 ? fy : (dy > 0 ? T(1) - fy : T(0));
-      for (int dx = -1; dx <= 1; ++dx) {
-        // grid cells whose box lies a full cell (1.001 r) or more away hold no vertex
-        // within r (the margin covers the rounding of the grid units)
-        const T cx = dx < 0 ? fx : (dx > 0 ? T(1) - fx : T(0));
-        if (cx * cx + cy * cy + cz * cz >= T(1)) continue;
-        const uint32_t b = bucket_of(gx + dx, gy + dy, gz + dz, mask);
-        const uint32_t k1 = start[b + 1];
-        for (uint32_t k = start[b]; k < k1; ++k) {
-          const Entry<T> e = entries[k];
-          const T ex = sub_rn(e.x, xi), ey = sub_rn(e.y, yi), ez = sub_rn(e.z, zi);
-          const T d2 = add_rn(add_rn(mul_rn(ex, ex), mul_rn(ey, ey)), mul_rn(ez, ez));
-          if (d2 < r2 && (e.j < own0 || e.j >= own1) && (d2 < best || (d2 == best && e.j < bj))) {
-            best = d2;
-            bj = e.j;
-          }
+      const T row = cy * cy + cz * cz;
+      if (row >= T(1)) continue;
+      const int lo = (fx * fx + row < T(1)) ? -1 : 0;
+      const int hi = ((T(1) - fx) * (T(1) - fx) + row < T(1)) ? 1 : 0;
+      const uint32_t b_lo = bucket_of(gx + lo, gy + dy, gz + dz, fold);
+      const uint32_t b_hi = bucket_of(gx + hi, gy + dy, gz + dz, fold);
+      if (b_hi - b_lo == (uint32_t)(hi - lo)) {
+        scan(start[b_lo], start[b_hi + 1]);
+      } else {
+        for (int dx = lo; dx <= hi; ++dx) {
+          const uint32_t b = bucket_of(gx + dx, gy + dy, gz + dz, fold);
+          scan(start[b], start[b + 1]);
         }
       }
     }
@@ -168,19 +192,24 @@ hipError_t detect(const DevType* types, const int64_t* offsets, ContactWork& w, 
   const T inv_c = (T)(1.0 / (radius * kCellOverRadius));
   const T r = (T)radius;
   const T r2 = r * r;
-  const uint32_t mask = w.n_buckets - 1u;
+  uint32_t k = 0;
+  while ((1u << k) < w.n_buckets) ++k;
+  GridFold fold;
+  fold.kx = (k + 2) / 3;
+  fold.ky = (k - fold.kx + 1) / 2;
+  fold.kz = k - fold.kx - fold.ky;
   Entry<T>* entries = static_cast<Entry<T>*>(w.entries);
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(w.n_buckets + 1)), dim3(kContactThreads), 0, s,
                      w.count, (int64_t)w.n_buckets + 1, 0u);
   hipLaunchKernelGGL(k_contact_count<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, x, V,
-                     inv_c, mask, w.bucket, w.count);
+                     inv_c, fold, w.bucket, w.count);
   hipError_t e = hipcub::DeviceScan::ExclusiveSum(w.scan_tmp, w.scan_bytes, w.count, w.start,
                                                   (int)w.n_buckets + 1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_contact_scatter<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, x, V,
                      w.bucket, w.start, w.count, entries);
   hipLaunchKernelGGL(k_contact_query<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, types,
-                     offsets, w.cell_of, w.type_of, x, V, inv_c, mask, w.start, entries, r2,
+                     offsets, w.cell_of, w.type_of, x, V, inv_c, fold, w.start, entries, r2,
                      (T)separation, (T)weight, cp, cw);
   return hipGetLastError();
 }
