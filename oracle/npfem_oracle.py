@@ -664,26 +664,40 @@ def closest_foreign_vertex(x, cell_of, radius: float, dtype=np.float64, rows=Non
     x [3][V], the vertex j of another cell (cell_of [V]) with the smallest squared distance
     ((dx dx + dy dy) + dz dz), computed with every operation rounded in `dtype`, among those
     strictly below radius^2 (radius rounded to dtype, squared in dtype); the smallest j among
-    equal distances; -1 where no foreign vertex lies inside the kernel. Brute force over all
-    pairs, in blocks of rows."""
+    equal distances; -1 where no foreign vertex lies inside the kernel.
+
+    Brute force over pairs. For the rows of one cell, the candidates are the other cells'
+    vertices inside that cell's bounding box grown by the radius (plus 0.1 %): every vertex
+    within the radius of one of the rows lies there, so the result is the full search's."""
     xd = np.asarray(x).astype(dtype)
+    x64 = xd.astype(np.float64)
     cell_of = np.asarray(cell_of)
     r = dtype(radius)
     r2 = dtype(r * r)
     V = xd.shape[1]
     rows = np.arange(V) if rows is None else np.asarray(rows)
     out = np.full(len(rows), -1, dtype=np.int64)
-    block = max(1, 4_000_000 // max(V, 1))
-    for s in range(0, len(rows), block):
-        ri = rows[s:s + block]
-        dx = xd[0][None, :] - xd[0][ri][:, None]
-        dy = xd[1][None, :] - xd[1][ri][:, None]
-        dz = xd[2][None, :] - xd[2][ri][:, None]
+    grow = float(radius) * 1.001
+    order = np.argsort(x64[0], kind="stable")
+    xs = x64[0][order]
+    for c in np.unique(cell_of[rows]):
+        sel = np.nonzero(cell_of[rows] == c)[0]
+        ri = rows[sel]
+        lo = x64[:, ri].min(axis=1) - grow
+        hi = x64[:, ri].max(axis=1) + grow
+        sub = order[np.searchsorted(xs, lo[0], "left"):np.searchsorted(xs, hi[0], "right")]
+        keep = ((x64[1][sub] >= lo[1]) & (x64[1][sub] <= hi[1]) & (x64[2][sub] >= lo[2])
+                & (x64[2][sub] <= hi[2]) & (cell_of[sub] != c))
+        cand = np.sort(sub[keep])                       # ascending: argmin takes the smallest j
+        if cand.size == 0:
+            continue
+        dx = xd[0][cand][None, :] - xd[0][ri][:, None]
+        dy = xd[1][cand][None, :] - xd[1][ri][:, None]
+        dz = xd[2][cand][None, :] - xd[2][ri][:, None]
         d2 = (dx * dx + dy * dy) + dz * dz
-        d2[cell_of[None, :] == cell_of[ri][:, None]] = np.inf
         j = np.argmin(d2, axis=1)                       # first (smallest) j among equal minima
         hit = d2[np.arange(len(ri)), j] < r2
-        out[s:s + block] = np.where(hit, j, -1)
+        out[sel] = np.where(hit, cand[j], -1)
     return out
 
 

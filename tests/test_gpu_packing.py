@@ -154,3 +154,45 @@ def test_full_size_detection_sampled():
     _compare(pg[:, rows], wg[rows], po, wo, b.x0[:, rows], 32)
     _say(f"full size: {np.mean(wg > 0):.3f} of the vertices in contact; {len(rows)} sampled")
     assert 0.1 < np.mean(wg > 0) < 0.9
+
+
+def test_full_size_packing_step_sampled():
+    """One packing step of the full-size placement (24 000 cells, the bench's layout and K):
+    the oracle finds the contacts of 2 RBC and 2 platelets by brute force over all 5.42 M
+    vertices and steps those cells; positions within the fused form's tolerance and the
+    contact decisions bit for bit."""
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    lt, ot = _types()
+    w = I.WORKLOADS["large_24000"]
+    b = I.packing_batch(w.types(), seed=w.seed)
+    batch = N.Batch([lt[int(t)] for t in b.types], precision=32, form="fused")
+    batch.set_cells_per_wave(lt[I.RBC], 2)
+    batch.set_cells_per_wave(lt[I.PLT], 4)
+    K = P["n_pd_iters"]
+    _say(f"case: packing step at full size ({b.n_cells} cells), K = {K}, 4 sampled cells")
+    x = torch.tensor(b.x0, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(x)
+    cp, cw = batch.detect_contacts(x, P["radius"], P["separation"], P["weight"])
+    batch.step(x, v, torch.zeros_like(x), I.DT, K, contacts=(cp, cw))
+    batch.check()
+    xg = x.double().cpu().numpy()
+    wg = cw.double().cpu().numpy()
+    rng = np.random.default_rng(331)
+    cells = np.concatenate([rng.choice(np.nonzero(b.types == I.RBC)[0], 2, replace=False),
+                            rng.choice(np.nonzero(b.types == I.PLT)[0], 2, replace=False)])
+    rows = np.concatenate([np.arange(b.offsets[c], b.offsets[c + 1]) for c in cells])
+    po, wo, _ = O.pik_contacts(ot, b.types, b.offsets, b.x0, P["radius"], P["separation"],
+                               P["weight"], np.float32, rows=rows)
+    assert np.array_equal(wg[rows], wo)
+    p_full = b.x0.copy()
+    w_full = np.zeros(b.v_total)
+    p_full[:, rows] = po
+    w_full[rows] = wo
+    xo, _ = O.step_batch(ot, b.types, b.offsets, b.x0, np.zeros_like(b.x0), np.zeros_like(b.x0),
+                         K, cells=cells, contact_p=p_full, contact_w=w_full)
+    err = cell_errors(b.types, b.offsets, xg, xo, cells)
+    _say(f"full-size packing step: {np.mean(wo > 0):.3f} of the sampled vertices in contact, "
+         f"max err/diam {err.max():.3e}")
+    assert np.mean(wo > 0) > 0.1
+    assert err.max() <= 1e-5
