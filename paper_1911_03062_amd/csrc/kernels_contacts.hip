@@ -66,28 +66,60 @@ __global__ void __launch_bounds__(kContactThreads) k_fill_u32(uint32_t* p, int64
   if (i < n) p[i] = v;
 }
 
+// Runs of equal buckets among the lanes of a wave (consecutive vertices of a cell often share
+// a grid cell): a lane learns the first lane of its run and the run's length, so that one
+// atomic serves the run. Every lane of the wave takes part (inactive lanes carry b = ~0u).
+struct Run {
+  int head;    // first lane of the run
+  int len;     // lanes in the run
+};
+
+__device__ __forceinline__ Run bucket_run(uint32_t b) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const uint32_t prev = __shfl_up(b, 1, 64);
+  const bool is_head = lane == 0 || prev != b;
+  const uint64_t heads = __ballot(is_head);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
+  Run r;
+  r.head = 63 - __clzll((long long)(heads & upto));
+  const uint64_t after = heads & ~upto;
+  r.len = (after ? (__ffsll((long long)after) - 1) : 64) - r.head;
+  return r;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kContactThreads)
     k_contact_count(const T* __restrict__ x, int64_t V, T inv_c, GridFold fold,
                     int32_t* __restrict__ bucket, uint32_t* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
-  if (i >= V) return;
-  const uint32_t b = bucket_of(grid_coord(x[i], inv_c), grid_coord(x[V + i], inv_c),
-                               grid_coord(x[2 * V + i], inv_c), fold);
-  bucket[i] = (int32_t)b;
-  atomicAdd(&count[b], 1u);
+  const bool active = i < V;
+  uint32_t b = ~0u;
+  if (active) {
+    b = bucket_of(grid_coord(x[i], inv_c), grid_coord(x[V + i], inv_c),
+                  grid_coord(x[2 * V + i], inv_c), fold);
+    bucket[i] = (int32_t)b;
+  }
+  const Run r = bucket_run(b);
+  if (active && (int)(threadIdx.x & 63u) == r.head) atomicAdd(&count[b], (uint32_t)r.len);
 }
 
 // Counting-sort scatter: count[b] runs down to zero, so the table is clear for the next pass.
+// The head of a run of equal buckets claims the run's slots with one atomic.
 template <typename T>
 __global__ void __launch_bounds__(kContactThreads)
     k_contact_scatter(const T* __restrict__ x, int64_t V, const int32_t* __restrict__ bucket,
                       const uint32_t* __restrict__ start, uint32_t* __restrict__ count,
                       Entry<T>* __restrict__ entries) {
   const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
-  if (i >= V) return;
-  const uint32_t b = (uint32_t)bucket[i];
-  const uint32_t pos = start[b] + atomicSub(&count[b], 1u) - 1u;
+  const bool active = i < V;
+  const uint32_t b = active ? (uint32_t)bucket[i] : ~0u;
+  const Run r = bucket_run(b);
+  const int lane = (int)(threadIdx.x & 63u);
+  uint32_t top = 0;   // count[b] before the run's claim: slots [top - len, top) are the run's
+  if (active && lane == r.head) top = atomicSub(&count[b], (uint32_t)r.len);
+  top = __shfl(top, r.head, 64);
+  if (!active) return;
+  const uint32_t pos = start[b] + top - (uint32_t)r.len + (uint32_t)(lane - r.head);
   Entry<T> e;
   e.x = x[i];
   e.y = x[V + i];
