@@ -30,6 +30,7 @@ namespace {
 
 constexpr int kContactThreads = 256;
 constexpr double kCellOverRadius = 1.001;   // grid cell size / kernel radius
+constexpr uint32_t kXcds = 8;               // accelerator complex dies (one L2 each)
 
 template <typename T>
 struct Entry {
@@ -135,7 +136,12 @@ __global__ void __launch_bounds__(kContactThreads)
                     const T* __restrict__ x, int64_t V, T inv_c, GridFold fold,
                     const uint32_t* __restrict__ start, const Entry<T>* __restrict__ entries,
                     T r2, T sep, T weight, T* __restrict__ cp, T* __restrict__ cw) {
-  const int64_t q = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); XCD x takes the x-th
+  // contiguous eighth of the records, so that queries sharing rows of records share an L2.
+  const uint32_t nb = gridDim.x, xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
+  const uint32_t per = nb / kXcds, rem = nb % kXcds;
+  const uint32_t block = xcd * per + (xcd < rem ? xcd : rem) + idx;
+  const int64_t q = (int64_t)block * kContactThreads + threadIdx.x;
   if (q >= V) return;
   // queries in bucket order: neighbouring lanes scan nearly the same rows of records
   const Entry<T> me = entries[q];
