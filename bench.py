@@ -38,6 +38,10 @@ FUSED_SRC = os.path.join(ROOT, "paper_1911_03062_amd", "csrc", "kernels_fused.hi
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_large_24000_traffic.json")
 
 
+# algorithmic HBM bytes of one contact-detection pass per vertex (FP32; see the packing leg)
+DETECT_BYTES_PER_VERTEX = 36 + 8 + 32 + 16 + 4
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for name in ("kernels_fused.hip", "projections.h", "filters.h", "npfem_internal.h"):
@@ -470,6 +474,16 @@ def main():
                       f"um, w = {PK['weight']} pN/um) then the step with the collision energies; "
                       f"{pk_steps + 1} steps, eager",
             "ms_per_step": packing_ms, "detect_ms": detect_ms,
+            "detect_roofline": {
+                "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                "algorithmic_bytes_per_pass": DETECT_BYTES_PER_VERTEX * pk.v_total,
+                "achieved": DETECT_BYTES_PER_VERTEX * pk.v_total / (detect_ms * 1e-3) / 1e9,
+                "frac": DETECT_BYTES_PER_VERTEX * pk.v_total / (detect_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "note": "one detection pass (fill, count, scan, scatter, query): positions read "
+                        "three times (36 B), bucket written and read (8 B), record written and "
+                        "read (32 B), projection point and weight written (16 B), the vertex's "
+                        "cell read (4 B), per vertex; candidate gathers are not algorithmic",
+            },
             "value": n_cells * Kp / (packing_ms * 1e-3), "unit": "cell-PD-iterations/s",
             "contact_fraction_first_step": pack_frac0,
             "contact_fraction_last_step": pack_frac1,
