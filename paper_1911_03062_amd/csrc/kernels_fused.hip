@@ -172,6 +172,9 @@ template <bool TWO>
 __device__ __forceinline__ void mfma_rows(gfloat* La, const lfloat* RbA, const lfloat* RbB,
                                           int KR, f4& acc0, f4& acc1) {
   const int nch = (KR + kMfmaChunk - 1) / kMfmaChunk;
+  // raised wave priority while the matrix cores work: the CU's other workgroups are in their
+  // VALU-bound element rounds, and issuing this wave's loads and MFMAs first keeps both busy
+  __builtin_amdgcn_s_setprio(1);
   float aP[kMfmaChunk], aQ[kMfmaChunk], bP0[kMfmaChunk], bP1[kMfmaChunk], bQ0[kMfmaChunk],
       bQ1[kMfmaChunk];
   load_a(aP, La, 0);
@@ -190,6 +193,7 @@ __device__ __forceinline__ void mfma_rows(gfloat* La, const lfloat* RbA, const l
     __builtin_amdgcn_sched_barrier(0);
   }
   if (c < nch) mma_chunk<TWO>(aP, bP0, bP1, acc0, acc1);
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // D = -acc for output tile (rt, ct) into R: lane holds rows rt*16 + 4 (lane/16) + r of
