@@ -283,7 +283,7 @@ npfem_status npfem_filter_forces(npfem_batch* batch, const void* f_in, void* f_o
  * The first call allocates the batch's search workspace (a grid-bucket table of 2^k >= 2 V_total
  * buckets and about 40 bytes per vertex); calls on one batch must not overlap in time.
  * Errors: NPFEM_E_INVALID (null batch or buffer, radius / separation / weight out of range),
- * NPFEM_E_NOMEM, NPFEM_E_HIP.
+ * NPFEM_E_UNSUPPORTED (more than 2^29 vertices in the batch), NPFEM_E_NOMEM, NPFEM_E_HIP.
  */
 npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double radius,
                                    double separation, double weight, void* contact_p,

@@ -919,6 +919,10 @@ npfem_status npfem_filter_forces(npfem_batch* b, const void* f_in, void* f_out, 
   return NPFEM_OK;
 }
 
+// Vertex indices of the detection records are int32 and its bucket table (2^k >= 2 V
+// buckets, uint32 counts) is scanned as one int-sized range.
+constexpr int64_t kMaxContactVertices = int64_t(1) << 29;
+
 npfem_status npfem_detect_contacts(npfem_batch* b, const void* x, double radius,
                                    double separation, double weight, void* contact_p,
                                    void* contact_w, void* stream) {
@@ -931,6 +935,8 @@ npfem_status npfem_detect_contacts(npfem_batch* b, const void* x, double radius,
     return fail(NPFEM_E_INVALID, "weight must be finite and >= 0");
   if (b->n_cells == 0) return NPFEM_OK;
   if (!x || !contact_p || !contact_w) return fail(NPFEM_E_INVALID, "null buffer");
+  if (b->offsets.back() > kMaxContactVertices)
+    return fail(NPFEM_E_UNSUPPORTED, "contact detection handles at most 2^29 vertices per batch");
   DeviceGuard guard(b->device);
   npfem::ContactWork& w = b->contacts;
   if (w.n_vertices == 0) {
