@@ -196,3 +196,19 @@ def test_full_size_packing_step_sampled():
          f"max err/diam {err.max():.3e}")
     assert np.mean(wo > 0) > 0.1
     assert err.max() <= 1e-5
+
+
+def test_detection_ignores_the_active_subset():
+    """npfem_batch_set_active restricts steps, not detection: every cell takes part."""
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    lt, _ = _types()
+    tids = np.array([I.RBC] * 3 + [I.PLT] * 6, dtype=np.int32)
+    b = I.packing_batch(tids, seed=341)
+    batch = N.Batch([lt[int(t)] for t in b.types], precision=32, form="fused")
+    _say("case: contact detection with an active subset of 2 of 9 cells")
+    p_all, w_all = _detect(batch, b.x0, 32)
+    batch.set_active([1, 7])
+    p_sub, w_sub = _detect(batch, b.x0, 32)
+    assert (w_all > 0).any()
+    assert np.array_equal(w_all, w_sub) and np.array_equal(p_all, p_sub)
