@@ -281,7 +281,7 @@ npfem_status npfem_filter_forces(npfem_batch* batch, const void* f_in, void* f_o
  *   contact_p  device, out, [3][V_total], batch precision (may not overlap x);
  *   contact_w  device, out, [V_total], batch precision.
  * The first call allocates the batch's search workspace (a grid-bucket table of 2^k >= 2 V_total
- * buckets and about 40 bytes per vertex); calls on one batch must not overlap in time.
+ * buckets and about 80 bytes per vertex); calls on one batch must not overlap in time.
  * Errors: NPFEM_E_INVALID (null batch or buffer, radius / separation / weight out of range),
  * NPFEM_E_UNSUPPORTED (more than 2^29 vertices in the batch), NPFEM_E_NOMEM, NPFEM_E_HIP.
  */

@@ -20,6 +20,8 @@ struct ContactWork {
   uint32_t* count = nullptr;      // [n_buckets] vertices per bucket (scatter cursor)
   uint32_t* start = nullptr;      // [n_buckets + 1] exclusive prefix sum of count
   void* entries = nullptr;        // [V] positions and vertex index, sorted by bucket
+  int32_t* slot = nullptr;        // [V] sorted position of each vertex
+  void* results = nullptr;        // [V] (p, w) of each record, in sorted order
   void* scan_tmp = nullptr;       // hipcub scan scratch
   size_t scan_bytes = 0;
 };

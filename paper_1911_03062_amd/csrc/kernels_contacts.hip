@@ -13,7 +13,8 @@
 // lies in one of the 27, since |x_i - x_j| < r < c keeps the cell coordinates within one of
 // each other, and cells whose box is a full cell size or more from the vertex are skipped
 // (on average about 6 of the 27). Grid cells one fold period or more apart share buckets;
-// their records only add candidates that the distance test rejects.
+// their records only add candidates that the distance test rejects. The query writes its
+// results in bucket order; a last pass puts them back in vertex order with coalesced writes.
 //
 // The choice of the neighbour is exact and independent of the order of the scan: squared
 // distances in the batch precision, ((dx dx + dy dy) + dz dz) with every operation rounded
@@ -36,6 +37,11 @@ template <typename T>
 struct Entry {
   T x, y, z;
   int32_t j;
+};
+
+template <typename T>
+struct Result {
+  T px, py, pz, w;
 };
 
 __device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
@@ -110,7 +116,7 @@ template <typename T>
 __global__ void __launch_bounds__(kContactThreads)
     k_contact_scatter(const T* __restrict__ x, int64_t V, const int32_t* __restrict__ bucket,
                       const uint32_t* __restrict__ start, uint32_t* __restrict__ count,
-                      Entry<T>* __restrict__ entries) {
+                      Entry<T>* __restrict__ entries, int32_t* __restrict__ slot) {
   const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
   const bool active = i < V;
   const uint32_t b = active ? (uint32_t)bucket[i] : ~0u;
@@ -127,6 +133,7 @@ __global__ void __launch_bounds__(kContactThreads)
   e.z = x[2 * V + i];
   e.j = (int32_t)i;
   entries[pos] = e;
+  slot[i] = (int32_t)pos;
 }
 
 template <typename T>
@@ -135,7 +142,7 @@ __global__ void __launch_bounds__(kContactThreads)
                     const int32_t* __restrict__ cell_of, const int32_t* __restrict__ type_of,
                     const T* __restrict__ x, int64_t V, T inv_c, GridFold fold,
                     const uint32_t* __restrict__ start, const Entry<T>* __restrict__ entries,
-                    T r2, T sep, T weight, T* __restrict__ cp, T* __restrict__ cw) {
+                    T r2, T sep, T weight, Result<T>* __restrict__ res) {
   // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); XCD x takes the x-th
   // contiguous eighth of the records, so that queries sharing rows of records share an L2.
   const uint32_t nb = gridDim.x, xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
@@ -189,10 +196,7 @@ __global__ void __launch_bounds__(kContactThreads)
     }
   }
   if (bj < 0) {
-    cp[i] = xi;
-    cp[V + i] = yi;
-    cp[2 * V + i] = zi;
-    cw[i] = T(0);
+    res[q] = Result<T>{xi, yi, zi, T(0)};
     return;
   }
   // unit outward normal of the neighbour's cell at the neighbour: the sum of its incident
@@ -215,10 +219,21 @@ __global__ void __launch_bounds__(kContactThreads)
     nz += bx * cy - by * cx;
   }
   const T s = sep / sqrt(nx * nx + ny * ny + nz * nz);
-  cp[i] = xj + s * nx;
-  cp[V + i] = yj + s * ny;
-  cp[2 * V + i] = zj + s * nz;
-  cw[i] = weight;
+  res[q] = Result<T>{xj + s * nx, yj + s * ny, zj + s * nz, weight};
+}
+
+// Results back in vertex order: coalesced writes of contact_p [3][V] and contact_w [V].
+template <typename T>
+__global__ void __launch_bounds__(kContactThreads)
+    k_contact_unpermute(int64_t V, const int32_t* __restrict__ slot,
+                        const Result<T>* __restrict__ res, T* __restrict__ cp, T* __restrict__ cw) {
+  const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  if (i >= V) return;
+  const Result<T> r = res[slot[i]];
+  cp[i] = r.px;
+  cp[V + i] = r.py;
+  cp[2 * V + i] = r.pz;
+  cw[i] = r.w;
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kContactThreads - 1) / kContactThreads); }
@@ -245,10 +260,12 @@ hipError_t detect(const DevType* types, const int64_t* offsets, ContactWork& w, 
                                                   (int)w.n_buckets + 1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_contact_scatter<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, x, V,
-                     w.bucket, w.start, w.count, entries);
+                     w.bucket, w.start, w.count, entries, w.slot);
   hipLaunchKernelGGL(k_contact_query<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, types,
                      offsets, w.cell_of, w.type_of, x, V, inv_c, fold, w.start, entries, r2,
-                     (T)separation, (T)weight, cp, cw);
+                     (T)separation, (T)weight, static_cast<Result<T>*>(w.results));
+  hipLaunchKernelGGL(k_contact_unpermute<T>, dim3(blocks_for(V)), dim3(kContactThreads), 0, s, V,
+                     w.slot, static_cast<const Result<T>*>(w.results), cp, cw);
   return hipGetLastError();
 }
 
@@ -267,7 +284,9 @@ hipError_t contact_work_alloc(ContactWork& w, int64_t n_vertices, int n_cells) {
       (e = hipMalloc(&w.bucket, sizeof(int32_t) * (size_t)n_vertices)) != hipSuccess ||
       (e = hipMalloc(&w.count, sizeof(uint32_t) * ((size_t)nb + 1))) != hipSuccess ||
       (e = hipMalloc(&w.start, sizeof(uint32_t) * ((size_t)nb + 1))) != hipSuccess ||
-      (e = hipMalloc(&w.entries, entry_bytes * (size_t)n_vertices)) != hipSuccess) {
+      (e = hipMalloc(&w.entries, entry_bytes * (size_t)n_vertices)) != hipSuccess ||
+      (e = hipMalloc(&w.slot, sizeof(int32_t) * (size_t)n_vertices)) != hipSuccess ||
+      (e = hipMalloc(&w.results, sizeof(Result<double>) * (size_t)n_vertices)) != hipSuccess) {
     contact_work_free(w);
     return e;
   }
@@ -279,7 +298,7 @@ hipError_t contact_work_alloc(ContactWork& w, int64_t n_vertices, int n_cells) {
 
 void contact_work_free(ContactWork& w) {
   for (void* p : {(void*)w.cell_of, (void*)w.type_of, (void*)w.bucket, (void*)w.count,
-                  (void*)w.start, w.entries, w.scan_tmp})
+                  (void*)w.start, w.entries, (void*)w.slot, w.results, w.scan_tmp})
     if (p) (void)hipFree(p);
   w = ContactWork{};
 }
