@@ -772,3 +772,102 @@ def test_skalak_rigid_invariance_and_newtons_law():
     res = -O.gradient(x1, x1, ct) + f - ct.mass * (v1 - v) / I.DT
     scale = np.abs(ct.mass * (v1 - v) / I.DT).max() + np.abs(f).max()
     assert np.abs(res).max() <= 1e-9 * scale, np.abs(res).max() / scale
+
+
+# ---------------------------------------------------------------- objective g, area, line search
+
+def _fd_energy_gradient(x, y, ct, contacts, eps):
+    fd = np.zeros_like(x)
+    for i in range(x.shape[1]):
+        for d in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[0, i, d] += eps
+            xm[0, i, d] -= eps
+            fd[0, i, d] = (O.energy(xp, y, ct, contacts)[0] - O.energy(xm, y, ct, contacts)[0]) / (2 * eps)
+    return fd
+
+
+@pytest.mark.parametrize("membrane", ["pd", "skalak"])
+@pytest.mark.parametrize("rayleigh", [False, True])
+def test_energy_is_the_potential_of_the_pinned_gradient(membrane, rayleigh):
+    """g(x) of the minimisation form (npFEM subsection) against the gradient, which is pinned by
+    finite differences of an independently written energy: with the volume weight at zero every
+    remaining term of g (inertia with M or the Rayleigh M~, strain + area or the Skalak
+    membrane, bending, collision energies) is exactly the potential of its gradient term, so
+    the central difference of energy() must reproduce gradient() (a wrong factor on any term of
+    either side fails)."""
+    mat = I.Material(shear_B=3.0, area_C=40.0, k_bend=2.0, k_vol=0.0, membrane=membrane)
+    if rayleigh:
+        mat = mat.with_rayleigh(0.3, 0.05)
+    ct = _small(I.icosahedron, material=mat)
+    rng = np.random.default_rng(301)
+    x = (ct.X + 0.05 * rng.normal(size=ct.X.shape))[None]
+    y = (ct.X + 0.04 * rng.normal(size=ct.X.shape))[None]
+    w = np.where(rng.random(ct.n) < 0.4, 60.0, 0.0)[None]
+    p = x + 0.1 * rng.normal(size=x.shape)
+    g = O.gradient(x, y, ct, (p, w))
+    fd = _fd_energy_gradient(x, y, ct, (p, w), 1e-6)
+    rel = np.abs(fd - g).max() / np.abs(g).max()
+    assert rel <= 1e-6, rel
+    # the collision term alone: w (x - p) is the gradient of (w/2)|x - p|^2
+    e_c = O.energy(x, y, ct, (p, w))[0] - O.energy(x, y, ct)[0]
+    assert np.isclose(e_c, 0.5 * np.sum(w[0] * np.sum((x[0] - p[0]) ** 2, axis=1)), rtol=1e-12)
+
+
+def test_energy_volume_term_is_the_linearised_projection_distance():
+    """The volume term of g is (k_vol/2)|x - p_vol|^2 with p_vol = x + lambda grad V, i.e.
+    (k_vol/2)(V0 - V)^2/|grad V|^2, with V and grad V from the closed-form-pinned volume and
+    volume_gradient (the term is not the potential of its gradient term, so it is pinned on its
+    own)."""
+    base = dict(shear_B=3.0, area_C=40.0, k_bend=2.0)
+    ct0 = _small(I.icosahedron, material=I.Material(k_vol=0.0, **base))
+    ct1 = _small(I.icosahedron, material=I.Material(k_vol=7.0, **base))
+    rng = np.random.default_rng(302)
+    x = (ct0.X * 1.05 + 0.05 * rng.normal(size=ct0.X.shape))[None]
+    y = ct0.X[None]
+    dV = ct1.V0 - O.volume(x, ct1.tri)[0]
+    gV = O.volume_gradient(x, ct1.tri)[0]
+    expect = 0.5 * 7.0 * dV ** 2 / np.sum(gV * gV)
+    got = O.energy(x, y, ct1)[0] - O.energy(x, y, ct0)[0]
+    assert abs(dV) > 1e-3 * ct1.V0
+    assert np.isclose(got, expect, rtol=1e-12), (got, expect)
+
+
+def test_surface_area_closed_forms():
+    """Total area of the platonic meshes from their edge length a: tetrahedron corner (three
+    right isosceles faces of legs 1 plus an equilateral face of side sqrt 2), regular
+    octahedron 2 sqrt(3) a^2, regular icosahedron 5 sqrt(3) a^2; a scaled mesh scales as s^2;
+    a rigid motion keeps it."""
+    xt, tt = I.tetrahedron()
+    assert np.isclose(O.surface_area(xt[None], tt)[0], 1.5 + 3 ** 0.5 / 2, rtol=1e-14)
+    xo, to = I.octahedron(1.7)
+    a = np.linalg.norm(xo[0] - xo[1])
+    assert np.isclose(O.surface_area(xo[None], to)[0], 2 * 3 ** 0.5 * a * a, rtol=1e-14)
+    xi, ti = I.icosahedron(1.3)
+    a = min(np.linalg.norm(xi[0] - xi[j]) for j in range(1, 12))
+    assert np.isclose(O.surface_area(xi[None], ti)[0], 5 * 3 ** 0.5 * a * a, rtol=1e-13)
+    R = I.random_rotations(np.random.default_rng(303), 1)[0]
+    moved = (2.5 * xi) @ R.T + np.array([10.0, -4.0, 7.0])
+    assert np.isclose(O.surface_area(moved[None], ti)[0], 2.5 ** 2 * 5 * 3 ** 0.5 * a * a, rtol=1e-13)
+
+
+def test_line_search_step_lengths_closed_form():
+    """One line-searched iteration where g along the direction is a known quadratic: elastic
+    weights zero and every vertex in contact with weight w, started at x = y. Then L = (m/h^2) I,
+    the direction is d = -c (y - p) with c = w h^2/m, and
+    g(y + a d) = (w S/2)(1 - 2 a c + a^2 c (1 + c)), S = sum |y - p|^2, with slope -c w S, so
+    the Armijo test (constant 1e-4) holds exactly for a <= 2 (1 - 1e-4)/(1 + c). Cells with
+    c = 0.5, 1.5, 3, 5 and 1000 must take 1, 1/2, 1/4 (1/2 misses the bound 0.49995 by the
+    Armijo constant alone), 1/4 and the smallest step 1/256 (none qualifies)."""
+    mat = I.Material(shear_B=0.0, area_C=0.0, k_bend=0.0, k_vol=0.0, membrane="skalak")
+    ct = _small(I.icosahedron, material=mat)
+    cs = np.array([0.5, 1.5, 3.0, 5.0, 1000.0])
+    expect = np.array([1.0, 0.5, 0.25, 0.25, 1.0 / 256])
+    rng = np.random.default_rng(304)
+    N = len(cs)
+    y = np.broadcast_to(ct.X, (N, ct.n, 3)) + 0.01 * rng.normal(size=(N, ct.n, 3))
+    p = y + 0.2 * rng.normal(size=y.shape)
+    w = np.broadcast_to((cs * ct.mass / ct.h ** 2)[:, None], (N, ct.n)).copy()
+    x1 = O.line_search_update(ct, y.copy(), y, (p, w))
+    a = (x1 - y) / (-cs[:, None, None] * (y - p))
+    assert np.allclose(a, expect[:, None, None], rtol=1e-9, atol=0), a[:, 0, 0]
