@@ -34,12 +34,6 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // Class test (not v - v == 0, which FMA contraction can turn into a product's rounding error).
 __device__ __forceinline__ bool finite_f(float v) { return __builtin_isfinite(v); }
 
@@ -105,6 +99,7 @@ __device__ __forceinline__ void refresh_items(int (&item)[NQ]) {
 }
 
 __device__ __forceinline__ Vec3<float> ld3(const float* p) { return v3<float>(p[0], p[1], p[2]); }
+__device__ __forceinline__ Vec3<double> to_d(Vec3<float> a) { return v3<double>(a.x, a.y, a.z); }
 __device__ __forceinline__ void st3(float* p, Vec3<float> v) {
   p[0] = v.x;
   p[1] = v.y;
@@ -209,27 +204,6 @@ __device__ __forceinline__ void write_tile(float* R, f4 acc, int rt, int ct, int
     for (int r = 0; r < 4; ++r)
       if (row0 + r < n) Rw[3 * (row0 + r)] = -acc[r];
   }
-}
-
-// Volume gradient of vertex vi of the cell whose X block starts at Xc, from its one ring.
-// Also returns the vertex's third of the incident triangles' area (sum |N_t| / 6).
-__device__ __forceinline__ Vec3<float> ring_volume_grad(const DevType& T, const float* Xc, int vi,
-                                                        Vec3<float> pi, float& area_third) {
-  const uint32_t info = gptr(T.ring_info)[vi];
-  const int off = (int)(info >> 8), deg = (int)(info & 255u);
-  Vec3<float> g = v3<float>(0.f, 0.f, 0.f);
-  float ar = 0.f;
-  for (int s = 0; s < deg; ++s) {
-    const uint32_t pr = gptr(T.ring_pairs)[off + s];
-    const int b = (int)(pr & 0xffffu), c = (int)(pr >> 16);
-    const Vec3<float> pb = ld3(Xc + 3 * b) - pi;
-    const Vec3<float> pc = ld3(Xc + 3 * c) - pi;
-    const Vec3<float> nt = cross3(pb, pc);
-    g = g + nt;
-    ar += dsqrt(dot3(nt, nt));
-  }
-  area_third = ar * (1.0f / 6.0f);
-  return g * (1.0f / 6.0f);
 }
 
 // EXTRAS: some type of the batch has position-based damping, a velocity cap or Rayleigh
@@ -505,7 +479,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       // its outward doubled area vector N_t = (x_b - x_a) x (x_c - x_a) (sign-corrected when
       // the schedule lists its vertices in reversed order) to R at its three vertices,
       // so that R_i = 6 grad_i V, and x_a . N_t (= 6 x its signed volume) to the lane's sum.
-      float v6 = 0.0f;
+      double v6 = 0.0;
       {
         // software-pipelined rounds: while round r computes, the positions of round r + 1
         // and the record of round r + 2 are in flight, and round r's residual reads were
@@ -527,12 +501,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const int a = (int)(rc.ab & 0xffffu), b = (int)(rc.ab >> 16), c = (int)rc.c;
           const Vec3<float> oa = ld3(Re + 3 * a), ob = ld3(Re + 3 * b), oc = ld3(Re + 3 * c);
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
-          const Vec3<float> nt = cross3(xb - xa, xc - xa) * rc.orient;
+          // N_t and x_a . N_t in FP64 from the FP32 positions (differences of FP32 values are
+          // exact in FP64); N_t enters the FP32 residual rounded once
+          const Vec3<double> da = to_d(xa);
+          const Vec3<double> ntd = cross3(to_d(xb) - da, to_d(xc) - da) * (double)rc.orient;
+          const Vec3<float> nt = v3<float>((float)ntd.x, (float)ntd.y, (float)ntd.z);
           if (e_ok && rc.area > 0.0f) {
             st3(Re + 3 * a, oa + nt);
             st3(Re + 3 * b, ob + nt);
             st3(Re + 3 * c, oc + nt);
-            v6 += dot3(xa, nt);
+            v6 += dot3(da, ntd);
           }
           __builtin_amdgcn_wave_barrier();
           rc = rnn;
@@ -548,15 +526,15 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       }
       // |6 grad V|^2 of the cell: lane (cell, slot s) takes its vertices s, s + S, ...
-      float g36 = 0.0f;
+      double g36 = 0.0;
       if (e_ok)
         for (int vv = e_s; vv < n; vv += S) {
-          const Vec3<float> gv = ld3(Re + 3 * vv);
+          const Vec3<double> gv = to_d(ld3(Re + 3 * vv));
           g36 += dot3(gv, gv);
         }
       {
         // FP64 sums over the S lanes of each cell (all cells of the wave at once)
-        double vs = (double)v6, gs = (double)g36;
+        double vs = v6, gs = g36;
         for (int o = S >> 1; o > 0; o >>= 1) {
           vs += __shfl_xor(vs, o, 64);
           gs += __shfl_xor(gs, o, 64);
@@ -753,38 +731,30 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       __builtin_amdgcn_wave_barrier();
     }
 
-    // ---- per-cell volume and area at x_{n+1} (FP64 reductions)
-    refresh_items(item);
+    // ---- per-cell volume and area at x_{n+1}: over the triangle schedule, each lane sums
+    //      x_a . N_t and |N_t| of its triangles in FP64 (N_t formed in FP64 from the FP32
+    //      cell-local positions), then the S lanes of each cell are summed in FP64
     if (vol_area) {
-      float vpart[NQ], apart[NQ];
-#pragma unroll
-      for (int it = 0; it < NQ; ++it) {
-        vpart[it] = 0.0f;
-        apart[it] = 0.0f;
-        if (ITEM_OK(it)) {
-          const float* Xc = X + ITEM_C(it) * CS;
-          const Vec3<float> pi = ld3(X + ITEM_W(it));
-          float at;
-          const Vec3<float> gg = ring_volume_grad(T, Xc, ITEM_V(it), pi, at);
-          vpart[it] = dot3(pi, gg);
-          apart[it] = at;
-        }
-      }
-      for (int cw = 0; cw < gw; ++cw) {
-        const int gc = wave * gw + cw;
-        double vs = 0.0, as = 0.0;
-#pragma unroll
-        for (int it = 0; it < NQ; ++it)
-          if (ITEM_C(it) == gc) {
-            vs += (double)vpart[it];
-            as += (double)apart[it];
+      double vs = 0.0, as = 0.0;
+      if (e_ok)
+        for (int r = 0; r < T.p.tri_rounds; ++r) {
+          const TriHead rc = load_tri_head(T.tri_sched, r * S + e_s);
+          if (rc.area > 0.0f) {
+            const Vec3<double> da = to_d(ld3(Xe + 3 * (int)(rc.ab & 0xffffu)));
+            const Vec3<double> db = to_d(ld3(Xe + 3 * (int)(rc.ab >> 16)));
+            const Vec3<double> dc = to_d(ld3(Xe + 3 * (int)rc.c));
+            const Vec3<double> ntd = cross3(db - da, dc - da);
+            vs += (double)rc.orient * dot3(da, ntd);
+            as += __builtin_sqrt(dot3(ntd, ntd));
           }
-        vs = wave_sum_d(vs);
-        as = wave_sum_d(as);
-        if (lane == 0 && gc < count) {
-          vol_area[2 * (int64_t)grp.cells[gc]] = vs / 3.0;
-          vol_area[2 * (int64_t)grp.cells[gc] + 1] = as;
         }
+      for (int o = S >> 1; o > 0; o >>= 1) {
+        vs += __shfl_xor(vs, o, 64);
+        as += __shfl_xor(as, o, 64);
+      }
+      if (e_ok && e_s == 0) {
+        vol_area[2 * (int64_t)grp.cells[e_gc]] = vs / 6.0;
+        vol_area[2 * (int64_t)grp.cells[e_gc] + 1] = 0.5 * as;
       }
     }
     // ---- x_{n+1} = x_n + delta, v_{n+1} = delta / h capped at v_max, with delta = delta^0 + e
