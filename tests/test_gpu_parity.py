@@ -1,7 +1,10 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded
-inputs. Tolerances: FP64 plain form 1e-10 of the cell diameter after 100 steps; FP32 forms
-1e-4 of the diameter after 100 steps (the workload's accuracy bar) and 1e-7 of the diameter
-after one strongly kicked step, where an iteration count off by one shows."""
+inputs. Tolerances: FP64 plain form 1e-12 of the cell diameter after 100 steps; FP32 forms
+1e-6 of the diameter after 100 steps of a cell at the origin (where FP32 storage of the
+positions costs nothing measurable) and 1e-7 after one strongly kicked step, where an
+iteration count off by one shows; batches placed up to ~350 um from the origin are held to
+the workload's accuracy bar, 1e-4 of the diameter, which leaves room for the rounding of the
+stored FP32 positions (about ulp(200 um) / 2 = 7.6e-6 um per coordinate and step)."""
 import functools
 import sys
 
@@ -52,7 +55,7 @@ def test_plain_fp64_single_rbc_100_steps():
     err = cell_errors(b.types, b.offsets, xg, xo)[0]
     disp = cell_displacement(b.types, b.offsets, b.x0, xo, [0])[0]
     _say(f"plain fp64: max err/diam {err:.3e}, oracle displacement {disp:.3e} um")
-    assert err <= 1e-10
+    assert err <= 1e-12
     assert np.abs(vg - vo).max() <= 1e-8 * np.abs(vo).max()
 
 
@@ -73,7 +76,7 @@ def test_fp32_single_rbc_100_steps(form):
     err = cell_errors(b.types, b.offsets, xg, xo)[0]
     disp = cell_displacement(b.types, b.offsets, b.x0, xo, [0])[0]
     _say(f"{form} fp32: max err/diam {err:.3e}, oracle displacement/diam {disp / I.RBC_DIAMETER:.3e}")
-    assert err <= 1e-4
+    assert err <= 1e-6
 
 
 @pytest.mark.parametrize("form", ["plain", "fused"])
@@ -167,8 +170,14 @@ def test_fused_same_result_alone_and_in_a_mix():
     assert err.max() <= 1e-6
 
 
-@pytest.mark.parametrize("name,steps,n_sample", [("batch_1300", 5, 24), ("large_24000", 2, 24)])
-def test_fused_full_size_sampled(name, steps, n_sample):
+def _farthest_cells(b, n):
+    """The n cells whose vertices reach farthest from the origin (largest FP32 ulp)."""
+    reach = np.array([np.abs(b.x0[:, int(b.offsets[c]):int(b.offsets[c + 1])]).max()
+                      for c in range(b.n_cells)])
+    return np.argsort(reach)[-n:]
+
+
+def _sampled_run(name, steps, n_random, n_strong, n_far):
     w = I.WORKLOADS[name]
     b = w.batch()
     forces = list(w.forces(b, n_steps=steps))
@@ -176,13 +185,30 @@ def test_fused_full_size_sampled(name, steps, n_sample):
     xg, vg = run_gpu(_ltypes(), b.types, b.x0, b.v0, forces, w.n_pd_iters)
     rng = np.random.default_rng(7)
     strong = I.strong_cells(b, w.seed, w.strong_fraction)
-    cells = np.unique(np.concatenate([rng.choice(b.n_cells, n_sample, replace=False), strong[:8],
-                                      [0, b.n_cells - 1]])).astype(np.int64)
+    far = _farthest_cells(b, n_far)
+    cells = np.unique(np.concatenate([rng.choice(b.n_cells, n_random, replace=False),
+                                      strong[:n_strong], far, [0, b.n_cells - 1]])).astype(np.int64)
     xo, vo = run_oracle(_otypes(), b.types, b.offsets, b.x0, b.v0, forces, w.n_pd_iters, cells=cells)
     err = cell_errors(b.types, b.offsets, xg, xo, cells)
     disp = cell_displacement(b.types, b.offsets, b.x0, xo, cells)
-    _say(f"{name}: sampled {len(cells)} cells, max err/diam {err.max():.3e}, "
+    ferr = cell_errors(b.types, b.offsets, xg, xo, far)
+    _say(f"{name}: sampled {len(cells)} cells ({len(far)} farthest from the origin), max err/diam "
+         f"{err.max():.3e} (farthest cells {ferr.max():.3e}, median {np.median(err):.3e}), "
          f"max displacement {disp.max():.3e} um")
+    return err
+
+
+def test_fused_batch_1300_100_steps_sampled():
+    """The batched configuration over its full length: 1 000 RBC + 300 platelets at random
+    placements in [0, 200]^3 um, 100 steps x K = 10, sampled cells including those reaching
+    farthest from the origin, where the FP32 storage of the positions rounds most."""
+    err = _sampled_run("batch_1300", 100, 20, 0, 8)
+    assert err.max() <= 1e-4
+    assert np.median(err) <= 2e-5
+
+
+def test_fused_large_24000_sampled():
+    err = _sampled_run("large_24000", 3, 24, 16, 4)
     assert err.max() <= 1e-5
 
 
