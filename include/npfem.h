@@ -290,6 +290,23 @@ npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double rad
                                    void* contact_w, void* stream);
 
 /*
+ * Allocation-free variant of npfem_detect_contacts, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as npfem_detect_contacts (bitwise the same outputs), but
+ * the search workspace lives in a static device array of 64 MiB that the library holds on each
+ * GPU it runs on until the process ends, instead of memory allocated for the batch. The call
+ * makes no device allocation and no host-device copy; the first call on a GPU looks up the
+ * array's device address. It serves batches of at most 524 288 (2^19) vertices (about 2 000
+ * red cells); larger batches fail with NPFEM_E_UNSUPPORTED before any device work.
+ * Every call on one GPU, from any batch, thread or stream, shares the one workspace, and each
+ * call rewrites it from scratch: calls that overlap in time on one GPU race and give
+ * undefined results. Serialise them (one stream, or events between streams).
+ */
+npfem_status npfem_detect_contacts_noalloc(npfem_batch* batch, const void* x, double radius,
+                                           double separation, double weight, void* contact_p,
+                                           void* contact_w, void* stream);
+
+/*
  * Synchronise `stream` and report NPFEM_E_NONFINITE if any step since the last check
  * produced a non-finite position or velocity (the flag is then cleared), NPFEM_E_HIP on a
  * device error, NPFEM_OK otherwise.

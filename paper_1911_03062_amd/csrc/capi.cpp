@@ -285,6 +285,7 @@ struct npfem_batch {
   int ring_cur = -1;                        // -1: the all-cells list is active
   std::vector<char> mark;
   int64_t* d_offsets = nullptr;
+  int32_t* d_type_of = nullptr;             // per cell, index into types (device copy)
   // median filter of the external forces: blocks of consecutive whole cells
   FilterBlock* d_filter_blocks = nullptr;
   int n_filter_blocks = 0;
@@ -316,6 +317,7 @@ struct npfem_batch {
       if (h_stage_count[i]) (void)hipHostFree(h_stage_count[i]);
     }
     if (d_offsets) (void)hipFree(d_offsets);
+    if (d_type_of) (void)hipFree(d_type_of);
     if (d_filter_blocks) (void)hipFree(d_filter_blocks);
     if (work) (void)hipFree(work);
     if (d_flag) (void)hipFree(d_flag);
@@ -569,6 +571,13 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
       hipMemcpy(b->d_offsets, b->offsets.data(), (n_cells + 1) * sizeof(int64_t),
                 hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(NPFEM_E_NOMEM, "device offsets"));
+  {
+    std::vector<int32_t> type_of(b->type_of.begin(), b->type_of.end());
+    if (hipMalloc((void**)&b->d_type_of, std::max<size_t>(type_of.size(), 1) * sizeof(int32_t)) != hipSuccess ||
+        (n_cells > 0 && hipMemcpy(b->d_type_of, type_of.data(), type_of.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice) != hipSuccess))
+      return bail(fail(NPFEM_E_NOMEM, "device cell types"));
+  }
   {
     const npfem_status st = build_filter_blocks(b);
     if (st != NPFEM_OK) return bail(st);
@@ -961,6 +970,35 @@ npfem_status npfem_detect_contacts(npfem_batch* b, const void* x, double radius,
   const hipError_t e = npfem::launch_detect_contacts(b->precision, b->d_types, b->d_offsets, w, x,
                                                      radius, separation, weight, contact_p,
                                                      contact_w, stream);
+  if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("contact detection: ") + hipGetErrorString(e));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_detect_contacts_noalloc(npfem_batch* b, const void* x, double radius,
+                                           double separation, double weight, void* contact_p,
+                                           void* contact_w, void* stream) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  if (!(radius > 0.0) || !std::isfinite(radius))
+    return fail(NPFEM_E_INVALID, "radius must be finite and > 0");
+  if (!(separation >= 0.0) || !std::isfinite(separation))
+    return fail(NPFEM_E_INVALID, "separation must be finite and >= 0");
+  if (!(weight >= 0.0) || !std::isfinite(weight))
+    return fail(NPFEM_E_INVALID, "weight must be finite and >= 0");
+  if (b->n_cells == 0) return NPFEM_OK;
+  if (!x || !contact_p || !contact_w) return fail(NPFEM_E_INVALID, "null buffer");
+  const int64_t V = b->offsets.back();
+  if (V > npfem::kNoAllocMaxVertices)
+    return fail(NPFEM_E_UNSUPPORTED, "npfem_detect_contacts_noalloc handles at most " +
+                                         std::to_string(npfem::kNoAllocMaxVertices) +
+                                         " vertices per batch (its static workspace is " +
+                                         std::to_string(npfem::kContactScratchBytes >> 20) + " MiB)");
+  const size_t need = npfem::contact_noalloc_bytes(V);
+  if (need == 0 || need > npfem::kContactScratchBytes)
+    return fail(NPFEM_E_UNSUPPORTED, "the static contact workspace is too small for this batch");
+  DeviceGuard guard(b->device);
+  const hipError_t e = npfem::launch_detect_contacts_noalloc(
+      b->precision, b->d_types, b->d_offsets, b->n_cells, b->d_type_of, V, x, radius, separation,
+      weight, contact_p, contact_w, stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("contact detection: ") + hipGetErrorString(e));
   return NPFEM_OK;
 }

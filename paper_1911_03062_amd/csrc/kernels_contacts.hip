@@ -23,9 +23,17 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <map>
+#include <mutex>
+
 #include "contacts.h"
 
 namespace npfem {
+
+// Workspace of the allocation-free detection. Each GPU that runs it holds its own copy of the
+// array until the process ends; host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device (the name is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[kContactScratchBytes];
 
 namespace {
 
@@ -236,7 +244,72 @@ __global__ void __launch_bounds__(kContactThreads)
   cw[i] = r.w;
 }
 
+// Cell of every vertex from the batch's vertex offsets (offsets[0] = 0 <= i < offsets[n_cells]
+// = V): the last cell whose first vertex is at or before i.
+__global__ void __launch_bounds__(kContactThreads)
+    k_cell_of(const int64_t* __restrict__ offsets, int n_cells, int64_t V,
+              int32_t* __restrict__ cell_of) {
+  const int64_t i = (int64_t)blockIdx.x * kContactThreads + threadIdx.x;
+  if (i >= V) return;
+  int lo = 0, hi = n_cells;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offsets[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  cell_of[i] = lo;
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kContactThreads - 1) / kContactThreads); }
+
+// Places the pieces of a workspace for V vertices at 256-byte aligned offsets from base (a
+// null base only measures) and returns the bytes they span, 0 if the scan's size query fails.
+// type_of is not placed: the caller supplies it.
+size_t carve(ContactWork& w, char* base, int64_t V) {
+  uint32_t nb = 1024;
+  while ((int64_t)nb < 2 * V) nb <<= 1;
+  size_t used = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + used : nullptr;
+    used += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  w.n_vertices = V;
+  w.n_buckets = nb;
+  w.cell_of = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)V));
+  w.bucket = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)V));
+  w.count = static_cast<uint32_t*>(take(sizeof(uint32_t) * ((size_t)nb + 1)));
+  w.start = static_cast<uint32_t*>(take(sizeof(uint32_t) * ((size_t)nb + 1)));
+  w.entries = take(sizeof(Entry<double>) * (size_t)V);   // large enough for either precision
+  w.slot = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)V));
+  w.results = take(sizeof(Result<double>) * (size_t)V);
+  size_t scan = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan, w.count, w.start, (int)nb + 1) != hipSuccess)
+    return 0;
+  w.scan_bytes = scan;
+  w.scan_tmp = take(scan > 0 ? scan : 1);
+  return used;
+}
+
+// Device address of the scratch on the current device, looked up once per device.
+hipError_t scratch_address(void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> by_device;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = by_device.find(dev);
+  if (it == by_device.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    it = by_device.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
 
 template <typename T>
 hipError_t detect(const DevType* types, const int64_t* offsets, ContactWork& w, const T* x,
@@ -294,6 +367,36 @@ hipError_t contact_work_alloc(ContactWork& w, int64_t n_vertices, int n_cells) {
   if (e == hipSuccess) e = hipMalloc(&w.scan_tmp, w.scan_bytes > 0 ? w.scan_bytes : 1);
   if (e != hipSuccess) contact_work_free(w);
   return e;
+}
+
+size_t contact_noalloc_bytes(int64_t n_vertices) {
+  ContactWork w;
+  return carve(w, nullptr, n_vertices);
+}
+
+hipError_t launch_detect_contacts_noalloc(int precision, const DevType* types,
+                                          const int64_t* offsets, int n_cells,
+                                          const int32_t* type_of, int64_t n_vertices,
+                                          const void* x, double radius, double separation,
+                                          double weight, void* contact_p, void* contact_w,
+                                          void* stream) {
+  if (n_vertices == 0) return hipSuccess;
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  ContactWork w;   // a view of the scratch, never freed
+  const size_t used = carve(w, static_cast<char*>(base), n_vertices);
+  if (used == 0 || used > kContactScratchBytes) return hipErrorInvalidValue;
+  w.type_of = const_cast<int32_t*>(type_of);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_cell_of, dim3(blocks_for(n_vertices)), dim3(kContactThreads), 0, s, offsets,
+                     n_cells, n_vertices, w.cell_of);
+  if (precision == 64)
+    return detect<double>(types, offsets, w, static_cast<const double*>(x), radius, separation,
+                          weight, static_cast<double*>(contact_p), static_cast<double*>(contact_w),
+                          s);
+  return detect<float>(types, offsets, w, static_cast<const float*>(x), radius, separation, weight,
+                       static_cast<float*>(contact_p), static_cast<float*>(contact_w), s);
 }
 
 void contact_work_free(ContactWork& w) {

@@ -95,6 +95,9 @@ def lib() -> ctypes.CDLL:
     L.npfem_detect_contacts.argtypes = [c_void_p, c_void_p, c_double, c_double, c_double,
                                         c_void_p, c_void_p, c_void_p]
     L.npfem_detect_contacts.restype = c_int32
+    L.npfem_detect_contacts_noalloc.argtypes = [c_void_p, c_void_p, c_double, c_double, c_double,
+                                                c_void_p, c_void_p, c_void_p]
+    L.npfem_detect_contacts_noalloc.restype = c_int32
     L.npfem_batch_check.restype = c_int32
     L.npfem_celltype_cells_per_wave.argtypes = [c_void_p, POINTER(c_int32), c_int32]
     L.npfem_celltype_cells_per_wave.restype = c_int32
@@ -273,6 +276,25 @@ class Batch:
         _check(lib().npfem_detect_contacts(self._h, x.data_ptr(), float(radius), float(separation),
                                            float(weight), contact_p.data_ptr(),
                                            contact_w.data_ptr(), c_void_p(s.cuda_stream)))
+        return contact_p, contact_w
+
+    def detect_contacts_noalloc(self, x, radius: float, separation: float, weight: float,
+                                contact_p, contact_w, stream=None):
+        """detect_contacts on the library's static per-GPU workspace (no device allocation;
+        batches of at most 2^19 vertices; overlapping calls on one GPU race). The caller
+        provides contact_p [3][V_total] and contact_w [V_total]."""
+        import torch
+        dtype = torch.float64 if self.precision == 64 else torch.float32
+        for name, t, shape in (("x", x, (3, self.vertex_count)),
+                               ("contact_p", contact_p, (3, self.vertex_count)),
+                               ("contact_w", contact_w, (self.vertex_count,))):
+            if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == shape):
+                raise ValueError(f"{name} must be a contiguous device tensor {list(shape)} of {dtype}")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_detect_contacts_noalloc(self._h, x.data_ptr(), float(radius),
+                                                   float(separation), float(weight),
+                                                   contact_p.data_ptr(), contact_w.data_ptr(),
+                                                   c_void_p(s.cuda_stream)))
         return contact_p, contact_w
 
     def _check_state(self, x, v, forces, vol_area):
