@@ -871,3 +871,80 @@ def test_line_search_step_lengths_closed_form():
     x1 = O.line_search_update(ct, y.copy(), y, (p, w))
     a = (x1 - y) / (-cs[:, None, None] * (y - p))
     assert np.allclose(a, expect[:, None, None], rtol=1e-9, atol=0), a[:, 0, 0]
+
+
+# ---------------------------------------------------------------- planted mistakes
+# Each case plants a mistake in the oracle (a helper or constant of its module, patched for the
+# test only) and checks that the pin above that covers it fails.
+
+import oracle.npfem_oracle as OM   # noqa: E402  (the module whose globals the oracle reads)
+
+def _energy_gradient_mismatch(membrane="skalak"):
+    mat = I.Material(shear_B=3.0, area_C=40.0, k_bend=2.0, k_vol=0.0, membrane=membrane)
+    ct = _small(I.icosahedron, material=mat)
+    rng = np.random.default_rng(301)
+    x = (ct.X + 0.05 * rng.normal(size=ct.X.shape))[None]
+    y = (ct.X + 0.04 * rng.normal(size=ct.X.shape))[None]
+    g = O.gradient(x, y, ct)
+    fd = _fd_energy_gradient(x, y, ct, None, 1e-6)
+    return np.abs(fd - g).max() / np.abs(g).max()
+
+
+def test_planted_skalak_energy_factor_fails_the_potential_pin(monkeypatch):
+    """W halved in the energy only (its derivative untouched)."""
+    assert _energy_gradient_mismatch() <= 1e-6
+    real = OM.skalak_density
+
+    def planted(F, ct):
+        W, dW = real(F, ct)
+        return 0.5 * W, dW
+    monkeypatch.setattr(OM, "skalak_density", planted)
+    assert _energy_gradient_mismatch() > 1e-3
+
+
+def _volume_term_error():
+    base = dict(shear_B=3.0, area_C=40.0, k_bend=2.0)
+    ct0 = _small(I.icosahedron, material=I.Material(k_vol=0.0, **base))
+    ct1 = _small(I.icosahedron, material=I.Material(k_vol=7.0, **base))
+    rng = np.random.default_rng(302)
+    x = (ct0.X * 1.05 + 0.05 * rng.normal(size=ct0.X.shape))[None]
+    y = ct0.X[None]
+    dV = ct1.V0 - O.volume(x, ct1.tri)[0]
+    gV = O.volume_gradient(x, ct1.tri)[0]
+    expect = 0.5 * 7.0 * dV ** 2 / np.sum(gV * gV)
+    got = O.energy(x, y, ct1)[0] - O.energy(x, y, ct0)[0]
+    return abs(got - expect) / abs(expect)
+
+
+def test_planted_volume_projection_step_fails_the_volume_term_pin(monkeypatch):
+    """The linearised volume projection moved twice as far (lambda doubled)."""
+    assert _volume_term_error() <= 1e-10
+    real = OM.volume_projection
+
+    def planted(x, ct):
+        p, lam, V = real(x, ct)
+        return x + 2.0 * (p - x), lam, V
+    monkeypatch.setattr(OM, "volume_projection", planted)
+    assert _volume_term_error() > 0.5
+
+
+def _line_search_steps():
+    mat = I.Material(shear_B=0.0, area_C=0.0, k_bend=0.0, k_vol=0.0, membrane="skalak")
+    ct = _small(I.icosahedron, material=mat)
+    cs = np.array([0.5, 1.5, 3.0, 5.0, 1000.0])
+    rng = np.random.default_rng(304)
+    N = len(cs)
+    y = np.broadcast_to(ct.X, (N, ct.n, 3)) + 0.01 * rng.normal(size=(N, ct.n, 3))
+    p = y + 0.2 * rng.normal(size=y.shape)
+    w = np.broadcast_to((cs * ct.mass / ct.h ** 2)[:, None], (N, ct.n)).copy()
+    x1 = O.line_search_update(ct, y.copy(), y, (p, w))
+    return ((x1 - y) / (-cs[:, None, None] * (y - p)))[:, 0, 0]
+
+
+@pytest.mark.parametrize("name,value", [("ARMIJO_C", -1e-4), ("MAX_HALVINGS", 7)])
+def test_planted_line_search_constant_fails_the_step_length_pin(monkeypatch, name, value):
+    """The sufficient-decrease test with the constant's sign flipped, or one halving fewer."""
+    expect = np.array([1.0, 0.5, 0.25, 0.25, 1.0 / 256])
+    assert np.allclose(_line_search_steps(), expect, rtol=1e-9, atol=0)
+    monkeypatch.setattr(OM, name, value)
+    assert not np.allclose(_line_search_steps(), expect, rtol=1e-9, atol=0)
