@@ -290,6 +290,26 @@ npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double rad
                                    void* contact_w, void* stream);
 
 /*
+ * The global step alone: out[:, cell] = L^-1 rhs[:, cell] for every cell of the batch and each
+ * of its 3 coordinate columns, L the cell type's constant system matrix (supplementary
+ * material, npFEM subsection: the prefactored Hessian approximation H~ of the quasi-Newton
+ * update x - H~ grad g, shared by every cell of a type). Two ways of applying it:
+ *   NPFEM_SOLVE_DENSE   the dense precomputed L^-1 (FP64-derived, stored FP32) times the
+ *                       right-hand sides of each group of same-type cells on the FP32 matrix
+ *                       cores, as the fused step does; fused-form (FP32) batches only;
+ *   NPFEM_SOLVE_BANDED  forward and back substitution with the banded Cholesky factor
+ *                       (FP64-computed, used in the batch precision), one lane per column;
+ *                       either form and precision, band widths up to 65.
+ *   rhs, out  device, [3][V_total] in the batch precision (may be the same buffer);
+ * every cell takes part, whatever npfem_batch_set_active selected. Asynchronous on `stream`.
+ * Errors: NPFEM_E_INVALID (null batch or buffer, unknown variant), NPFEM_E_UNSUPPORTED (dense on
+ * a plain-form batch; a band wider than 65), NPFEM_E_HIP.
+ */
+enum { NPFEM_SOLVE_DENSE = 0, NPFEM_SOLVE_BANDED = 1 };
+npfem_status npfem_global_solve(npfem_batch* batch, int32_t solve, const void* rhs, void* out,
+                                void* stream);
+
+/*
  * Allocation-free variant of npfem_detect_contacts, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same arguments, results and errors as npfem_detect_contacts (bitwise the same outputs), but

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["setup.cpp", "capi.cpp", "kernels_plain.hip", "kernels_fused.hip", "kernels_filter.hip",
-           "kernels_contacts.hip"]
+           "kernels_contacts.hip", "kernels_global.hip"]
 
 # Device code is compiled without packed-FP32 instructions (v_pk_*_f32).
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

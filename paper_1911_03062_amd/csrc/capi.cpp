@@ -61,7 +61,8 @@ void free_devtype(DevType* d) {
                   d->tri,       d->hinge,       d->vt_off,    d->vt_list,    d->vh_off,
                   d->vh_list,   d->G64,         d->G32,       d->A64,        d->A32,
                   d->coef64,    d->coef32,      d->rest64,    d->rest32,     d->cband64,
-                  d->cband32,   d->mband64,     d->mband32,   d->kband64,    d->kband32};
+                  d->cband32,   d->mband64,     d->mband32,   d->kband64,    d->kband32,
+                  d->sband_rows64, d->sband_rows32, d->sband_cols64, d->sband_cols32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete d;
@@ -148,6 +149,28 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   chk(upload(&d->coef64, ct->coef)); chk(upload(&d->coef32, ct->coef));
   chk(upload(&d->rest64, ct->rest_norm)); chk(upload(&d->rest32, ct->rest_norm));
   chk(upload(&d->cband64, ct->cband)); chk(upload(&d->cband32, ct->cband));
+  // the standalone banded substitution's layouts of the factor, padded to its window
+  p.band_w = 0;
+  for (int w = 9; w <= 65; w += 8)
+    if (ct->bw <= w) {
+      p.band_w = w;
+      break;
+    }
+  if (p.band_w > 0) {
+    const int n = ct->n, bw = ct->bw, W = p.band_w;
+    std::vector<double> rows((size_t)n * (W + 1), 0.0), cols((size_t)n * (W + 1), 0.0);
+    for (int i = 0; i < n; ++i) {
+      const double diag = ct->cband[(size_t)i * (bw + 1)];
+      cols[(size_t)i * (W + 1)] = 1.0 / diag;
+      rows[(size_t)i * (W + 1)] = diag;
+      for (int k = 1; k <= bw; ++k) {
+        if (i - k >= 0) rows[(size_t)i * (W + 1) + k] = ct->cband[(size_t)i * (bw + 1) + k];
+        if (i + k < n) cols[(size_t)i * (W + 1) + k] = ct->cband[(size_t)(i + k) * (bw + 1) + k];
+      }
+    }
+    chk(upload(&d->sband_rows64, rows)); chk(upload(&d->sband_rows32, rows));
+    chk(upload(&d->sband_cols64, cols)); chk(upload(&d->sband_cols32, cols));
+  }
   if (!ct->mband.empty()) {
     chk(upload(&d->mband64, ct->mband)); chk(upload(&d->mband32, ct->mband));
     chk(upload(&d->kband64, ct->kband)); chk(upload(&d->kband32, ct->kband));
@@ -286,6 +309,8 @@ struct npfem_batch {
   std::vector<char> mark;
   int64_t* d_offsets = nullptr;
   int32_t* d_type_of = nullptr;             // per cell, index into types (device copy)
+  int32_t* d_cells_by_type = nullptr;       // cell ids grouped by type (device)
+  std::vector<int> type_first, type_count;  // each type's range in d_cells_by_type
   // median filter of the external forces: blocks of consecutive whole cells
   FilterBlock* d_filter_blocks = nullptr;
   int n_filter_blocks = 0;
@@ -294,6 +319,7 @@ struct npfem_batch {
   std::string filter_reason;                // non-empty: the filter is unavailable
   size_t lds_bytes = 0;
   bool fused_extras = false;                // a type damps or caps velocities (kernel variant)
+  bool fused_skalak = false;                // a type has the Skalak membrane (kernel variant)
   void* work = nullptr;                     // plain-form workspace
   int* d_flag = nullptr;
   npfem::ContactWork contacts;              // contact detection workspace (first use)
@@ -318,6 +344,7 @@ struct npfem_batch {
     }
     if (d_offsets) (void)hipFree(d_offsets);
     if (d_type_of) (void)hipFree(d_type_of);
+    if (d_cells_by_type) (void)hipFree(d_cells_by_type);
     if (d_filter_blocks) (void)hipFree(d_filter_blocks);
     if (work) (void)hipFree(work);
     if (d_flag) (void)hipFree(d_flag);
@@ -376,8 +403,11 @@ npfem_status relayout(npfem_batch* b) {
     if (st != NPFEM_OK) return st;
     HIP_TRY(hipMemcpy(b->d_types + ti, &v, sizeof(DevType), hipMemcpyHostToDevice));
     const int cap = kFusedWaves * t->layouts[b->layout_of[ti]].gw;
-    const size_t per_cell = (2 * (size_t)t->cs + (t->kappa > 0.0 ? kDampWords : 0)) * sizeof(float);
-    b->lds_bytes = std::max(b->lds_bytes, (size_t)cap * per_cell);
+    // X blocks below kFusedRWords, R blocks from there (for a Skalak type followed by its
+    // grad g / trial blocks), then the damping words
+    const int blocks = t->membrane == NPFEM_MEMBRANE_SKALAK ? 2 : 1;
+    const size_t per_cell = (blocks * (size_t)t->cs + (t->kappa > 0.0 ? kDampWords : 0)) * sizeof(float);
+    b->lds_bytes = std::max(b->lds_bytes, kFusedRWords * sizeof(float) + (size_t)cap * per_cell);
   }
   std::vector<FusedGroup> groups;
   build_groups(b, nullptr, b->n_cells, groups);
@@ -542,6 +572,7 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
   }
   for (npfem_celltype* t : b->types) {
     b->fused_extras = b->fused_extras || t->kappa > 0.0 || t->v_max > 0.0 || t->beta > 0.0;
+    b->fused_skalak = b->fused_skalak || t->membrane == NPFEM_MEMBRANE_SKALAK;
     if (b->dt == 0) b->dt = t->h;
     if (std::fabs(t->h - b->dt) > 1e-12 * b->dt)
       return bail(fail(NPFEM_E_DT, "cell types of one batch must share dt"));
@@ -573,9 +604,21 @@ npfem_status npfem_batch_create(int32_t n_cells, npfem_celltype* const* type_of_
     return bail(fail(NPFEM_E_NOMEM, "device offsets"));
   {
     std::vector<int32_t> type_of(b->type_of.begin(), b->type_of.end());
-    if (hipMalloc((void**)&b->d_type_of, std::max<size_t>(type_of.size(), 1) * sizeof(int32_t)) != hipSuccess ||
-        (n_cells > 0 && hipMemcpy(b->d_type_of, type_of.data(), type_of.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice) != hipSuccess))
+    std::vector<int32_t> by_type;
+    by_type.reserve(n_cells);
+    for (int ti = 0; ti < nt; ++ti) {
+      b->type_first.push_back((int)by_type.size());
+      for (int c = 0; c < n_cells; ++c)
+        if (b->type_of[c] == ti) by_type.push_back(c);
+      b->type_count.push_back((int)by_type.size() - b->type_first.back());
+    }
+    const size_t cb = std::max<size_t>(n_cells, 1) * sizeof(int32_t);
+    if (hipMalloc((void**)&b->d_type_of, cb) != hipSuccess ||
+        hipMalloc((void**)&b->d_cells_by_type, cb) != hipSuccess ||
+        (n_cells > 0 && (hipMemcpy(b->d_type_of, type_of.data(), type_of.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice) != hipSuccess ||
+                         hipMemcpy(b->d_cells_by_type, by_type.data(),
+                                   by_type.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)))
       return bail(fail(NPFEM_E_NOMEM, "device cell types"));
   }
   {
@@ -630,6 +673,7 @@ npfem_status step_fused(npfem_batch* b, const FusedGroup* groups, const int* cou
                                    b->d_offsets, b->offsets.back(), (float*)x, (float*)v,
                                    (const float*)f, (const float*)cp, (const float*)cw, n_pd_iters,
                                    cell_volume_area, b->d_flag, b->lds_bytes, b->fused_extras,
+                                   b->fused_skalak,
                                    stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
   return NPFEM_OK;
@@ -1000,6 +1044,43 @@ npfem_status npfem_detect_contacts_noalloc(npfem_batch* b, const void* x, double
       b->precision, b->d_types, b->d_offsets, b->n_cells, b->d_type_of, V, x, radius, separation,
       weight, contact_p, contact_w, stream);
   if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("contact detection: ") + hipGetErrorString(e));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_global_solve(npfem_batch* b, int32_t solve, const void* rhs, void* out,
+                                void* stream) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch is null");
+  if (solve != NPFEM_SOLVE_DENSE && solve != NPFEM_SOLVE_BANDED)
+    return fail(NPFEM_E_INVALID, "unknown global-step variant");
+  if (b->n_cells == 0) return NPFEM_OK;
+  if (!rhs || !out) return fail(NPFEM_E_INVALID, "null buffer");
+  DeviceGuard guard(b->device);
+  const int64_t V = b->offsets.back();
+  const int nt = (int)b->types.size();
+  if (solve == NPFEM_SOLVE_DENSE) {
+    if (b->form != NPFEM_FORM_FUSED)
+      return fail(NPFEM_E_UNSUPPORTED, "the dense global step needs a fused-form batch (FP32 L^-1)");
+    size_t lds = 0;
+    for (int ti = 0; ti < nt; ++ti) {
+      const npfem_celltype* t = b->types[ti];
+      lds = std::max(lds, (size_t)kFusedWaves * t->layouts[b->layout_of[ti]].gw * t->cs * sizeof(float));
+    }
+    const hipError_t e = launch_global_dense(b->d_types, b->d_groups, b->d_count_all, b->n_groups,
+                                             b->d_offsets, V, static_cast<const float*>(rhs),
+                                             static_cast<float*>(out), lds, stream);
+    if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("dense global step: ") + hipGetErrorString(e));
+    return NPFEM_OK;
+  }
+  for (int ti = 0; ti < nt; ++ti)
+    if (b->dev_types[ti]->p.band_w == 0)
+      return fail(NPFEM_E_UNSUPPORTED, "the banded global step handles band widths up to 65");
+  for (int ti = 0; ti < nt; ++ti) {
+    const hipError_t e = launch_global_banded(b->precision, b->dev_types[ti]->p.n,
+                                              b->dev_types[ti]->p.band_w,
+                                              b->d_types + ti, b->d_cells_by_type + b->type_first[ti],
+                                              b->type_count[ti], b->d_offsets, V, rhs, out, stream);
+    if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("banded global step: ") + hipGetErrorString(e));
+  }
   return NPFEM_OK;
 }
 

@@ -51,42 +51,77 @@ typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 // Schedule records are read with loads of exactly the words a pass uses: a load whose result
 // words are partly unused lets the register allocator reuse those words' registers, which
 // then forces a wait for the load to land before the reuse. Records are loaded two rounds
-// ahead of their use.
-struct TriHead {   // first 16 bytes of a TriRec
-  uint32_t ab, c;
-  float area, orient;
+// ahead of their use. A round's records start at a uniform address (scalar registers) and a
+// lane's record sits at its slot's byte offset from there, so the loads take no vector
+// address arithmetic.
+struct TriHead {   // words 0-3 of a TriRec
+  uint32_t a, b, c;
+  float orient;
 };
-struct TriElem {   // words 0-2 and 4-6 of a TriRec
-  uint32_t ab, c;
+struct TriElem {   // words 0-2 and 4-7 of a TriRec
+  uint32_t a, b, c;
   float area, gb0, gb1, gc1;
 };
-struct HingeElem { // first 24 bytes of a HingeRec
-  uint32_t ij, kl;
+struct HingeElem { // a whole HingeRec
+  uint32_t i, j, k, l;
   float a1, a2, a3, rest;
 };
 
-template <typename V>
-__device__ __forceinline__ V load_words(const void* base, int rec, int word) {
+// Buffer resource over a per-type schedule (raw byte addressing, no range limit of note):
+// a record load then takes the round's byte offset in a scalar register and the lane's slot
+// offset in a vector register, with no address arithmetic in the vector ALU.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t sched_rsrc(const void* sched) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(sched), (short)0, 0x7fffffff,
+                                           0x00020000);
+}
+__device__ __forceinline__ TriHead load_tri_head(__amdgpu_buffer_rsrc_t rs, int round, int S,
+                                                 uint32_t slot_off) {
   static_assert(sizeof(TriRec) == 32 && sizeof(HingeRec) == 32, "32-byte records");
-  typedef const __attribute__((address_space(1))) uint32_t gword;
-  typedef const __attribute__((address_space(1))) V gvec;
-  return *(gvec*)((gword*)base + 8 * rec + word);
+  const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, slot_off, round * S * 32, 0);
+  return {v.x, v.y, v.z, __uint_as_float(v.w)};
 }
-__device__ __forceinline__ TriHead load_tri_head(const TriRec* base, int i) {
-  const u4 v = load_words<u4>(base, i, 0);
-  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(v.w)};
+__device__ __forceinline__ TriElem load_tri_elem(__amdgpu_buffer_rsrc_t rs, int round, int S,
+                                                 uint32_t slot_off) {
+  // a, b, c (orient unused here), then area, gb0, gb1, gc1
+  const u3 v = __builtin_amdgcn_raw_buffer_load_b96(rs, slot_off, round * S * 32, 0);
+  const u4 w = __builtin_amdgcn_raw_buffer_load_b128(rs, slot_off + 16u, round * S * 32, 0);
+  return {v.x, v.y, v.z, __uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z),
+          __uint_as_float(w.w)};
 }
-__device__ __forceinline__ TriElem load_tri_elem(const TriRec* base, int i) {
-  const u3 v = load_words<u3>(base, i, 0);   // ab, c, area (orient is not used here)
-  const u3 w = load_words<u3>(base, i, 4);   // gb0, gb1, gc1
-  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(w.x), __uint_as_float(w.y),
-          __uint_as_float(w.z)};
+__device__ __forceinline__ HingeElem load_hinge(__amdgpu_buffer_rsrc_t rs, int round, int S,
+                                                uint32_t slot_off) {
+  const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, slot_off, round * S * 32, 0);
+  const u4 w = __builtin_amdgcn_raw_buffer_load_b128(rs, slot_off + 16u, round * S * 32, 0);
+  return {v.x, v.y, v.z, v.w, __uint_as_float(w.x), __uint_as_float(w.y),
+          __uint_as_float(w.z), __uint_as_float(w.w)};
 }
-__device__ __forceinline__ HingeElem load_hinge(const HingeRec* base, int i) {
-  const u4 v = load_words<u4>(base, i, 0);
-  const u2 w = load_words<u2>(base, i, 4);
-  return {v.x, v.y, __uint_as_float(v.z), __uint_as_float(v.w), __uint_as_float(w.x),
-          __uint_as_float(w.y)};
+
+// Split record loads for the rounds' two-stage pipeline: the vertex offsets of a round are
+// loaded two rounds ahead of its arithmetic (its positions one round ahead), its
+// coefficients one round ahead.
+__device__ __forceinline__ u3 load_tri_offs(__amdgpu_buffer_rsrc_t rs, int round, int S,
+                                            uint32_t slot_off) {
+  return __builtin_amdgcn_raw_buffer_load_b96(rs, slot_off, round * S * 32, 0);
+}
+__device__ __forceinline__ float load_tri_orient(__amdgpu_buffer_rsrc_t rs, int round, int S,
+                                                 uint32_t slot_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, slot_off + 12u, round * S * 32, 0));
+}
+__device__ __forceinline__ u4 load_rec_hi(__amdgpu_buffer_rsrc_t rs, int round, int S,
+                                          uint32_t slot_off) {   // words 4-7
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, slot_off + 16u, round * S * 32, 0);
+}
+__device__ __forceinline__ u4 load_hinge_offs(__amdgpu_buffer_rsrc_t rs, int round, int S,
+                                              uint32_t slot_off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, slot_off, round * S * 32, 0);
+}
+
+// A vertex's xyz in a cell block, from the block's base and the vertex's byte offset.
+__device__ __forceinline__ float* vat(float* base, uint32_t byte_off) {
+  return (float*)((char*)base + byte_off);
+}
+__device__ __forceinline__ const float* vat(const float* base, uint32_t byte_off) {
+  return (const float*)((const char*)base + byte_off);
 }
 
 // Makes the packed owner-item codes opaque to the optimiser so that the per-item LDS
@@ -209,7 +244,7 @@ __device__ __forceinline__ void write_tile(float* R, f4 acc, int rt, int ct, int
 // EXTRAS: some type of the batch has position-based damping, a velocity cap or Rayleigh
 // damping with beta > 0, or the step has contacts (cp, cw: collision points [3][V] and
 // weights [V]); without them the kernel is built without those code paths.
-template <int NQ, bool EXTRAS>
+template <int NQ, bool EXTRAS, bool SKALAK>
 __global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
              const int* __restrict__ n_groups_dev, const int64_t* __restrict__ offsets, int64_t vt,
@@ -219,6 +254,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
   extern __shared__ float lds[];
   __shared__ float lam_lds[kMaxGroupCells];
   __shared__ int64_t off_lds[kMaxGroupCells];
+  // Skalak line search, per cell: step length, accepted flag, g(x^k) and grad g . d
+  __shared__ float ls_a[SKALAK ? kMaxGroupCells : 1];
+  __shared__ int ls_done[SKALAK ? kMaxGroupCells : 1];
+  __shared__ double ls_e0[SKALAK ? kMaxGroupCells : 1], ls_slope[SKALAK ? kMaxGroupCells : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   const int n_groups = *n_groups_dev;
@@ -230,7 +269,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const int G4 = kFusedWaves * gw;
     const int CS = T.p.cs;                   // words per cell block (3 npad + pad)
     float* X = lds;
-    float* R = lds + G4 * CS;
+    float* R = lds + kFusedRWords;   // fixed offset: one address per vertex serves X and R
 
     __syncthreads();   // the previous group's last reads of LDS are done
     for (int i = tid; i < G4 * CS; i += kFusedThreads) R[i] = 0.0f;
@@ -258,6 +297,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     const int e_cw = lane / S, e_s = lane - e_cw * S;
     const int e_gc = wave * gw + e_cw;
     const bool e_ok = e_gc < count;
+    const uint32_t e_soff = 32u * (uint32_t)e_s;   // the lane's record within a round
+    const __amdgpu_buffer_rsrc_t tri_rs = sched_rsrc(T.tri_sched);
+    const __amdgpu_buffer_rsrc_t hinge_rs = sched_rsrc(T.hinge_sched);
     // e = delta - delta^0 is the only per-vertex state kept in registers; delta^0 is
     // recomputed from v and F when the step is written back. With position-based damping
     // each cell's centre of mass x_cm, its velocity v_cm, angular velocity w and first vertex
@@ -273,7 +315,11 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     // subtracts ray_c e (both the plain values for other types)
     const float gmass = EXTRAS ? (float)T.p.grad_mass : ih2m;
     const float ray_c = (float)T.p.ray_c;
-    float* Dm = R + G4 * CS;
+    // Skalak types: a third block per cell after R holds grad g (for grad g . d), then the
+    // line search's trial positions
+    const bool sk = SKALAK && T.p.skalak;
+    float* Gt = R + G4 * CS;
+    float* Dm = (SKALAK && sk) ? Gt + G4 * CS : R + G4 * CS;
     float e[NQ][3];
 #pragma unroll
     for (int it = 0; it < NQ; ++it) {
@@ -481,47 +527,54 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       // so that R_i = 6 grad_i V, and x_a . N_t (= 6 x its signed volume) to the lane's sum.
       double v6 = 0.0;
       {
-        // software-pipelined rounds: while round r computes, the positions of round r + 1
-        // and the record of round r + 2 are in flight, and round r's residual reads were
-        // issued before its arithmetic. Reads of empty slots (vertex 0) and of cells past the
-        // group's count stay inside the LDS blocks; only their writes are skipped. The loop is
-        // unrolled by two so that the two register sets swap roles instead of being copied.
+        // Two-stage pipeline over the rounds, unrolled by two so that the A and B register
+        // sets swap roles: while round r computes, the positions of round r + 1 (from its
+        // offsets, loaded during round r - 1), its orientation and the offsets of round r + 2
+        // are in flight, and round r's residual reads were issued before its arithmetic.
+        // Reads of empty slots (vertex 0) and of cells past the group's count stay inside the
+        // LDS blocks; only their writes are skipped.
         const int NR = T.p.tri_rounds;
-        TriHead recA = load_tri_head(T.tri_sched, e_s);
-        TriHead recB = load_tri_head(T.tri_sched, min(1, NR - 1) * S + e_s);
+        u3 o = load_tri_offs(tri_rs, 0, S, e_soff);
+        float orA = load_tri_orient(tri_rs, 0, S, e_soff), orB;
+        float *rA0, *rA1, *rA2, *rB0, *rB1, *rB2;
         Vec3<float> xA0, xA1, xA2, xB0, xB1, xB2;
-        auto positions = [&](const TriHead& rc, Vec3<float>& p0, Vec3<float>& p1, Vec3<float>& p2) {
-          p0 = ld3(Xe + 3 * (int)(rc.ab & 0xffffu));
-          p1 = ld3(Xe + 3 * (int)(rc.ab >> 16));
-          p2 = ld3(Xe + 3 * (int)rc.c);
+        auto place = [&](int rr, float*& q0, float*& q1, float*& q2, Vec3<float>& p0,
+                         Vec3<float>& p1, Vec3<float>& p2) {
+          p0 = ld3(vat(Xe, o.x));
+          p1 = ld3(vat(Xe, o.y));
+          p2 = ld3(vat(Xe, o.z));
+          q0 = vat(Re, o.x);
+          q1 = vat(Re, o.y);
+          q2 = vat(Re, o.z);
+          __builtin_amdgcn_sched_barrier(0);   // o is consumed before it is reloaded
+          o = load_tri_offs(tri_rs, min(rr + 1, NR - 1), S, e_soff);
         };
-        auto round = [&](TriHead& rc, const Vec3<float>& xa, const Vec3<float>& xb,
-                         const Vec3<float>& xc, int r_next2) {
-          const TriHead rnn = load_tri_head(T.tri_sched, min(r_next2, NR - 1) * S + e_s);
-          const int a = (int)(rc.ab & 0xffffu), b = (int)(rc.ab >> 16), c = (int)rc.c;
-          const Vec3<float> oa = ld3(Re + 3 * a), ob = ld3(Re + 3 * b), oc = ld3(Re + 3 * c);
+        auto work = [&](float orient, float* q0, float* q1, float* q2, const Vec3<float>& xa,
+                        const Vec3<float>& xb, const Vec3<float>& xc) {
+          const Vec3<float> oa = ld3(q0), ob = ld3(q1), oc = ld3(q2);
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
           // N_t and x_a . N_t in FP64 from the FP32 positions (differences of FP32 values are
           // exact in FP64); N_t enters the FP32 residual rounded once
           const Vec3<double> da = to_d(xa);
-          const Vec3<double> ntd = cross3(to_d(xb) - da, to_d(xc) - da) * (double)rc.orient;
+          const Vec3<double> ntd = cross3(to_d(xb) - da, to_d(xc) - da) * (double)orient;
           const Vec3<float> nt = v3<float>((float)ntd.x, (float)ntd.y, (float)ntd.z);
-          if (e_ok && rc.area > 0.0f) {
-            st3(Re + 3 * a, oa + nt);
-            st3(Re + 3 * b, ob + nt);
-            st3(Re + 3 * c, oc + nt);
+          if (e_ok && orient != 0.0f) {
+            st3(q0, oa + nt);
+            st3(q1, ob + nt);
+            st3(q2, oc + nt);
             v6 += dot3(da, ntd);
           }
           __builtin_amdgcn_wave_barrier();
-          rc = rnn;
         };
-        positions(recA, xA0, xA1, xA2);
+        place(0, rA0, rA1, rA2, xA0, xA1, xA2);
         for (int r = 0; r < NR; r += 2) {
-          positions(recB, xB0, xB1, xB2);          // round r + 1 (re-reads round r at the end)
-          round(recA, xA0, xA1, xA2, r + 2);
+          place(r + 1, rB0, rB1, rB2, xB0, xB1, xB2);
+          orB = load_tri_orient(tri_rs, min(r + 1, NR - 1), S, e_soff);
+          work(orA, rA0, rA1, rA2, xA0, xA1, xA2);
           if (r + 1 < NR) {
-            positions(recA, xA0, xA1, xA2);        // round r + 2
-            round(recB, xB0, xB1, xB2, r + 3);
+            place(r + 2, rA0, rA1, rA2, xA0, xA1, xA2);
+            orA = load_tri_orient(tri_rs, min(r + 2, NR - 1), S, e_soff);
+            work(orB, rB0, rB1, rB2, xB0, xB1, xB2);
           }
         }
       }
@@ -569,86 +622,115 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
       {
-        // pipelined and unrolled as the volume rounds
+        // pipelined and unrolled as the hinge rounds below
         const int NR = T.p.tri_rounds;
-        TriElem recA = load_tri_elem(T.tri_sched, e_s);
-        TriElem recB = load_tri_elem(T.tri_sched, min(1, NR - 1) * S + e_s);
+        u3 o = load_tri_offs(tri_rs, 0, S, e_soff);
+        u4 cA = load_rec_hi(tri_rs, 0, S, e_soff), cB;     // area, gb0, gb1, gc1
+        float *rA0, *rA1, *rA2, *rB0, *rB1, *rB2;
         Vec3<float> xA0, xA1, xA2, xB0, xB1, xB2;
-        auto positions = [&](const TriElem& rc, Vec3<float>& p0, Vec3<float>& p1, Vec3<float>& p2) {
-          p0 = ld3(Xe + 3 * (int)(rc.ab & 0xffffu));
-          p1 = ld3(Xe + 3 * (int)(rc.ab >> 16));
-          p2 = ld3(Xe + 3 * (int)rc.c);
+        auto place = [&](int rr, float*& q0, float*& q1, float*& q2, Vec3<float>& p0,
+                         Vec3<float>& p1, Vec3<float>& p2) {
+          p0 = ld3(vat(Xe, o.x));
+          p1 = ld3(vat(Xe, o.y));
+          p2 = ld3(vat(Xe, o.z));
+          q0 = vat(Re, o.x);
+          q1 = vat(Re, o.y);
+          q2 = vat(Re, o.z);
+          __builtin_amdgcn_sched_barrier(0);   // o is consumed before it is reloaded
+          o = load_tri_offs(tri_rs, min(rr + 1, NR - 1), S, e_soff);
         };
-        auto round = [&](TriElem& rc, const Vec3<float>& xa, const Vec3<float>& xb,
-                         const Vec3<float>& xc, int r_next2) {
-          const TriElem rnn = load_tri_elem(T.tri_sched, min(r_next2, NR - 1) * S + e_s);
+        auto work = [&](const u4& c, float* q0, float* q1, float* q2, const Vec3<float>& xa,
+                        const Vec3<float>& xb, const Vec3<float>& xc) {
           __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the arithmetic
-          if (e_ok && rc.area > 0.0f) {
-            float* pa = Re + 3 * (int)(rc.ab & 0xffffu);
-            float* pb = Re + 3 * (int)(rc.ab >> 16);
-            float* pc = Re + 3 * (int)rc.c;
-            Vec3<float> ra = ld3(pa), rb = ld3(pb), rcv = ld3(pc);
-            triangle_residual<float>(xa, xb, xc, rc.gb0, rc.gb1, 0.0f, rc.gc1, rc.area, w_s,
-                                     w_a, s_min, s_max, ra, rb, rcv);
-            st3(pa, ra);
-            st3(pb, rb);
-            st3(pc, rcv);
+          const float area = __uint_as_float(c.x);
+          if (e_ok && area > 0.0f) {
+            Vec3<float> ra = ld3(q0), rb = ld3(q1), rcv = ld3(q2);
+            if (SKALAK && sk)   // Skalak strain energy (B = w_s, C = w_a per unit rest area)
+              (void)skalak_residual<float>(xa, xb, xc, __uint_as_float(c.y), __uint_as_float(c.z),
+                                           0.0f, __uint_as_float(c.w), area, w_s, w_a, ra, rb, rcv);
+            else
+              triangle_residual<float>(xa, xb, xc, __uint_as_float(c.y), __uint_as_float(c.z), 0.0f,
+                                       __uint_as_float(c.w), area, w_s, w_a, s_min, s_max, ra, rb,
+                                       rcv);
+            st3(q0, ra);
+            st3(q1, rb);
+            st3(q2, rcv);
           }
           __builtin_amdgcn_wave_barrier();
-          rc = rnn;
         };
-        positions(recA, xA0, xA1, xA2);
+        place(0, rA0, rA1, rA2, xA0, xA1, xA2);
         for (int r = 0; r < NR; r += 2) {
-          positions(recB, xB0, xB1, xB2);
-          round(recA, xA0, xA1, xA2, r + 2);
+          place(r + 1, rB0, rB1, rB2, xB0, xB1, xB2);
+          cB = load_rec_hi(tri_rs, min(r + 1, NR - 1), S, e_soff);
+          work(cA, rA0, rA1, rA2, xA0, xA1, xA2);
           if (r + 1 < NR) {
-            positions(recA, xA0, xA1, xA2);
-            round(recB, xB0, xB1, xB2, r + 3);
+            place(r + 2, rA0, rA1, rA2, xA0, xA1, xA2);
+            cA = load_rec_hi(tri_rs, min(r + 2, NR - 1), S, e_soff);
+            work(cB, rB0, rB1, rB2, xB0, xB1, xB2);
           }
         }
       }
       // ---- edge bending constraints
       {
-        // pipelined and unrolled as the volume rounds
+        // Two-stage pipeline over the rounds, unrolled by two so that the A and B register
+        // sets swap roles: while round r computes, the positions of round r + 1 (from its
+        // offsets, loaded during round r - 1), its coefficients and the offsets of round r + 2
+        // are in flight, and round r's residual reads were issued before its arithmetic.
         const int NR = T.p.hinge_rounds;
-        HingeElem recA = load_hinge(T.hinge_sched, e_s);
-        HingeElem recB = load_hinge(T.hinge_sched, min(1, NR - 1) * S + e_s);
+        u4 o = load_hinge_offs(hinge_rs, 0, S, e_soff);      // offsets of the round to place
+        u4 cA = load_rec_hi(hinge_rs, 0, S, e_soff), cB;     // a1, a2, a3, rest
+        float *rA0, *rA1, *rA2, *rA3, *rB0, *rB1, *rB2, *rB3;   // R addresses
         Vec3<float> xA0, xA1, xA2, xA3, xB0, xB1, xB2, xB3;
-        auto positions = [&](const HingeElem& rc, Vec3<float>& p0, Vec3<float>& p1,
-                             Vec3<float>& p2, Vec3<float>& p3) {
-          p0 = ld3(Xe + 3 * (int)(rc.ij & 0xffffu));
-          p1 = ld3(Xe + 3 * (int)(rc.ij >> 16));
-          p2 = ld3(Xe + 3 * (int)(rc.kl & 0xffffu));
-          p3 = ld3(Xe + 3 * (int)(rc.kl >> 16));
+        // place round rr: positions and R addresses from o, then the offsets of round rr + 1
+        auto place = [&](int rr, float*& q0, float*& q1, float*& q2, float*& q3, Vec3<float>& p0,
+                         Vec3<float>& p1, Vec3<float>& p2, Vec3<float>& p3) {
+          p0 = ld3(vat(Xe, o.x));
+          p1 = ld3(vat(Xe, o.y));
+          p2 = ld3(vat(Xe, o.z));
+          p3 = ld3(vat(Xe, o.w));
+          q0 = vat(Re, o.x);
+          q1 = vat(Re, o.y);
+          q2 = vat(Re, o.z);
+          q3 = vat(Re, o.w);
+          __builtin_amdgcn_sched_barrier(0);   // o is consumed before it is reloaded
+          o = load_hinge_offs(hinge_rs, min(rr + 1, NR - 1), S, e_soff);
         };
-        auto round = [&](HingeElem& rc, const Vec3<float>& xi, const Vec3<float>& xj,
-                         const Vec3<float>& xk, const Vec3<float>& xl, int r_next2) {
-          const HingeElem rnn = load_hinge(T.hinge_sched, min(r_next2, NR - 1) * S + e_s);
-          const int i = (int)(rc.ij & 0xffffu), j = (int)(rc.ij >> 16);
-          const int kk = (int)(rc.kl & 0xffffu), l = (int)(rc.kl >> 16);
-          Vec3<float> ri = ld3(Re + 3 * i), rj = ld3(Re + 3 * j), rk = ld3(Re + 3 * kk),
-                      rl = ld3(Re + 3 * l);
+        auto work = [&](const u4& c, float* q0, float* q1, float* q2, float* q3,
+                        const Vec3<float>& xi, const Vec3<float>& xj, const Vec3<float>& xk,
+                        const Vec3<float>& xl) {
+          Vec3<float> ri = ld3(q0), rj = ld3(q1), rk = ld3(q2), rl = ld3(q3);
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
-          hinge_residual<float>(xi, xj, xk, xl, rc.a1, rc.a2, rc.a3, rc.rest, w_b, ri, rj, rk,
-                                rl);
-          if (e_ok && rc.rest >= 0.0f) {
-            st3(Re + 3 * i, ri);
-            st3(Re + 3 * j, rj);
-            st3(Re + 3 * kk, rk);
-            st3(Re + 3 * l, rl);
+          const float a1 = __uint_as_float(c.x), a2 = __uint_as_float(c.y);
+          const float a3 = __uint_as_float(c.z), rest = __uint_as_float(c.w);
+          hinge_residual<float>(xi, xj, xk, xl, a1, a2, a3, rest, w_b, ri, rj, rk, rl);
+          if (e_ok && rest >= 0.0f) {
+            st3(q0, ri);
+            st3(q1, rj);
+            st3(q2, rk);
+            st3(q3, rl);
           }
           __builtin_amdgcn_wave_barrier();
-          rc = rnn;
         };
-        positions(recA, xA0, xA1, xA2, xA3);
+        place(0, rA0, rA1, rA2, rA3, xA0, xA1, xA2, xA3);
         for (int r = 0; r < NR; r += 2) {
-          positions(recB, xB0, xB1, xB2, xB3);
-          round(recA, xA0, xA1, xA2, xA3, r + 2);
+          place(r + 1, rB0, rB1, rB2, rB3, xB0, xB1, xB2, xB3);   // round r + 1 (clamped)
+          cB = load_rec_hi(hinge_rs, min(r + 1, NR - 1), S, e_soff);
+          work(cA, rA0, rA1, rA2, rA3, xA0, xA1, xA2, xA3);
           if (r + 1 < NR) {
-            positions(recA, xA0, xA1, xA2, xA3);
-            round(recB, xB0, xB1, xB2, xB3, r + 3);
+            place(r + 2, rA0, rA1, rA2, rA3, xA0, xA1, xA2, xA3);
+            cA = load_rec_hi(hinge_rs, min(r + 2, NR - 1), S, e_soff);
+            work(cB, rB0, rB1, rB2, rB3, xB0, xB1, xB2, xB3);
           }
         }
+      }
+      if (SKALAK && sk) {   // keep grad g for grad g . d (each owner copies its vertices)
+        refresh_items(item);
+#pragma unroll
+        for (int it = 0; it < NQ; ++it)
+          if (ITEM_OK(it)) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Gt[ITEM_W(it) + c] = R[ITEM_W(it) + c];
+          }
       }
       __syncthreads();
       // ---- global step: D = -L^-1 R on the matrix cores (the product of global_product,
@@ -713,16 +795,187 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       }
       __syncthreads();
-      // ---- update: delta += D (registers), x^{k+1} = x^k + D (LDS)
+      if (SKALAK && sk) {
+        // ---- line search along d = D (R), per cell and wave-local: the first step length a
+        //      of 1, 1/2, ..., 2^-kMaxHalvings with g(x + a d) <= g(x) + kArmijoC a grad g . d
+        //      (the last one when none qualifies), every sum in FP64
+        const int lc0 = wave * gw;   // the wave's first cell in the group
+        // per-cell sums over the owner items of the wave (every lane gets all of its cells')
+        auto owner_sum = [&](double (&v)[kSkalakMaxGw]) {
+#pragma unroll
+          for (int q = 0; q < kSkalakMaxGw; ++q)
+            for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+        };
+        // g at positions P (cell-local, [cell][vertex][xyz] blocks like X) with delta - delta^0
+        // = e + a D (a = 0 at x^k); returns the total of the lane's element cell
+        auto energy = [&](const float* P, bool trial) -> double {
+          double g2[kSkalakMaxGw], vx[kSkalakMaxGw], em[kSkalakMaxGw], ec[kSkalakMaxGw];
+#pragma unroll
+          for (int q = 0; q < kSkalakMaxGw; ++q) g2[q] = vx[q] = em[q] = ec[q] = 0.0;
+          refresh_items(item);
+#pragma unroll
+          for (int it = 0; it < NQ; ++it)
+            if (ITEM_OK(it)) {
+              const int lc = ITEM_C(it) - lc0, vi = ITEM_V(it);
+              const float* Pc = P + ITEM_C(it) * CS;
+              const Vec3<float> pi = ld3(Pc + 3 * vi);
+              // 6 grad_i V = sum over the triangles (i, b, c) around i of (p_b - p_i) x (p_c - p_i)
+              const uint32_t info = T.ring_info[vi];
+              const int roff = (int)(info >> 8), deg = (int)(info & 255u);
+              const Vec3<double> dpi = to_d(pi);
+              Vec3<double> gi = v3<double>(0.0, 0.0, 0.0);
+              for (int q = 0; q < deg; ++q) {
+                const uint32_t pr = T.ring_pairs[roff + q];
+                const Vec3<double> pb = to_d(ld3(Pc + 3 * (int)(pr & 0xffffu))) - dpi;
+                const Vec3<double> pc = to_d(ld3(Pc + 3 * (int)(pr >> 16))) - dpi;
+                gi = gi + cross3(pb, pc);
+              }
+              const float a = trial ? ls_a[ITEM_C(it)] : 0.0f;
+              const float* Dv = R + ITEM_W(it);
+              double g2i = dot3(gi, gi), vxi = dot3(dpi, gi), emi = 0.0, eci = 0.0;
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                const float el = trial ? e[it][c] + a * Dv[c] : e[it][c];
+                emi += (double)el * (double)el;
+              }
+              if (EXTRAS && cw != nullptr) {
+                const int64_t off = off_lds[ITEM_C(it)];
+                const float wc = cw[off + vi];
+                if (wc != 0.0f) {
+                  const float pic[3] = {pi.x, pi.y, pi.z};
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) {
+                    const float gd = (x[c * vt + off] - cp[c * vt + off + vi]) + pic[c];
+                    eci += 0.5 * (double)wc * (double)gd * (double)gd;
+                  }
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < kSkalakMaxGw; ++q)
+                if (q == lc) {
+                  g2[q] += g2i;
+                  vx[q] += vxi;
+                  em[q] += emi;
+                  ec[q] += eci;
+                }
+            }
+          owner_sum(g2);
+          owner_sum(vx);
+          owner_sum(em);
+          owner_sum(ec);
+          // element energies of the lane's cell: Skalak triangles and bending hinges
+          double el = 0.0;
+          if (e_ok) {
+            const float* Pe = P + e_gc * CS;
+            for (int r = 0; r < T.p.tri_rounds; ++r) {
+              const u3 o = load_tri_offs(tri_rs, r, S, e_soff);
+              const u4 c = load_rec_hi(tri_rs, r, S, e_soff);
+              const float area = __uint_as_float(c.x);
+              if (area > 0.0f)
+                el += (double)skalak_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
+                                                   ld3(vat(Pe, o.z)), __uint_as_float(c.y),
+                                                   __uint_as_float(c.z), 0.0f,
+                                                   __uint_as_float(c.w), area, w_s, w_a);
+            }
+            for (int r = 0; r < T.p.hinge_rounds; ++r) {
+              const u4 o = load_hinge_offs(hinge_rs, r, S, e_soff);
+              const u4 c = load_rec_hi(hinge_rs, r, S, e_soff);
+              const float rest = __uint_as_float(c.w);
+              if (rest >= 0.0f)
+                el += (double)hinge_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
+                                                  ld3(vat(Pe, o.z)), ld3(vat(Pe, o.w)),
+                                                  __uint_as_float(c.x), __uint_as_float(c.y),
+                                                  __uint_as_float(c.z), rest, w_b);
+            }
+          }
+          for (int o = S >> 1; o > 0; o >>= 1) el += __shfl_xor(el, o, 64);
+          // the lane's cell: volume energy (w_v/2)(V0 - V)^2 / |grad V|^2 with
+          // V = sum p_i . grad_i V / 3 (homogeneity) and grad V = (6 grad V) / 6, inertia,
+          // contacts
+          double G2 = 0.0, V6 = 0.0, EM = 0.0, EC = 0.0;
+#pragma unroll
+          for (int q = 0; q < kSkalakMaxGw; ++q)
+            if (q == e_cw) {
+              G2 = g2[q];
+              V6 = vx[q];
+              EM = em[q];
+              EC = ec[q];
+            }
+          const double V = V6 / 18.0, gv2 = G2 / 36.0;
+          const double ev = gv2 > 0.0 ? 0.5 * T.p.w_v * (T.p.V0 - V) * (T.p.V0 - V) / gv2 : 0.0;
+          return el + 0.5 * T.p.inv_h2m * EM + ev + EC;
+        };
+        // grad g . d per cell from the owner items (grad g in Gt, d in R)
+        {
+          double sl[kSkalakMaxGw];
+#pragma unroll
+          for (int q = 0; q < kSkalakMaxGw; ++q) sl[q] = 0.0;
+          refresh_items(item);
+#pragma unroll
+          for (int it = 0; it < NQ; ++it)
+            if (ITEM_OK(it)) {
+              const int lc = ITEM_C(it) - lc0;
+              double d = 0.0;
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                d += (double)Gt[ITEM_W(it) + c] * (double)R[ITEM_W(it) + c];
+#pragma unroll
+              for (int q = 0; q < kSkalakMaxGw; ++q)
+                if (q == lc) sl[q] += d;
+            }
+          owner_sum(sl);
+          double e0 = energy(X, false);
+          double mine = 0.0;
+#pragma unroll
+          for (int q = 0; q < kSkalakMaxGw; ++q)
+            if (q == e_cw) mine = sl[q];
+          if (e_ok && e_s == 0) {
+            ls_a[e_gc] = 1.0f;
+            ls_done[e_gc] = 0;
+            ls_e0[e_gc] = e0;
+            ls_slope[e_gc] = mine;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int h = 0; h <= kMaxHalvings; ++h) {
+          // trial positions x + a d of the wave's cells (over grad g, no longer needed)
+          refresh_items(item);
+#pragma unroll
+          for (int it = 0; it < NQ; ++it)
+            if (ITEM_OK(it)) {
+              const float a = ls_a[ITEM_C(it)];
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                Gt[ITEM_W(it) + c] = X[ITEM_W(it) + c] + a * R[ITEM_W(it) + c];
+            }
+          __builtin_amdgcn_wave_barrier();
+          const double et = energy(Gt, true);
+          if (e_ok && e_s == 0 && !ls_done[e_gc]) {
+            const float a = ls_a[e_gc];
+            if (et <= ls_e0[e_gc] + kArmijoC * (double)a * ls_slope[e_gc])
+              ls_done[e_gc] = 1;
+            else if (h < kMaxHalvings)
+              ls_a[e_gc] = 0.5f * a;
+          }
+          __builtin_amdgcn_wave_barrier();
+          int open = 0;
+          for (int q = 0; q < gw; ++q)
+            if (lc0 + q < count) open |= !ls_done[lc0 + q];
+          if (!open) break;
+        }
+      }
+      // ---- update: delta += D (registers), x^{k+1} = x^k + D (LDS); Skalak: a D
       refresh_items(item);
 #pragma unroll
       for (int it = 0; it < NQ; ++it)
         if (ITEM_OK(it)) {
           float* Rv = R + ITEM_W(it);
           float* Xv = X + ITEM_W(it);
+          const float a_ls = (SKALAK && sk) ? ls_a[ITEM_C(it)] : 1.0f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float dd = EXTRAS ? Rv[c] - ray_c * e[it][c] : Rv[c];
+            const float dd = (SKALAK && sk) ? a_ls * Rv[c]
+                                            : (EXTRAS ? Rv[c] - ray_c * e[it][c] : Rv[c]);
             e[it][c] += dd;
             Xv[c] += dd;
             Rv[c] = 0.0f;   // R starts the next iteration at zero
@@ -738,11 +991,11 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       double vs = 0.0, as = 0.0;
       if (e_ok)
         for (int r = 0; r < T.p.tri_rounds; ++r) {
-          const TriHead rc = load_tri_head(T.tri_sched, r * S + e_s);
-          if (rc.area > 0.0f) {
-            const Vec3<double> da = to_d(ld3(Xe + 3 * (int)(rc.ab & 0xffffu)));
-            const Vec3<double> db = to_d(ld3(Xe + 3 * (int)(rc.ab >> 16)));
-            const Vec3<double> dc = to_d(ld3(Xe + 3 * (int)rc.c));
+          const TriHead rc = load_tri_head(tri_rs, r, S, e_soff);
+          if (rc.orient != 0.0f) {
+            const Vec3<double> da = to_d(ld3(vat(Xe, rc.a)));
+            const Vec3<double> db = to_d(ld3(vat(Xe, rc.b)));
+            const Vec3<double> dc = to_d(ld3(vat(Xe, rc.c)));
             const Vec3<double> ntd = cross3(db - da, dc - da);
             vs += (double)rc.orient * dot3(da, ntd);
             as += __builtin_sqrt(dot3(ntd, ntd));
@@ -807,26 +1060,142 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
   }
 }
 
+
+// Global step alone, dense form: out = L^-1 r for every cell of the listed groups (FP32), the
+// product of the fused kernel's global step on the matrix cores with the right-hand sides
+// staged from HBM (one workgroup per group of same-type cells, as in the fused step). r and
+// out are [3][V] SoA; they may be the same buffer (a group is staged before it is written).
+__global__ void __launch_bounds__(kFusedThreads)
+k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
+               const int* __restrict__ n_groups_dev, const int64_t* __restrict__ offsets,
+               int64_t vt, const float* r, float* out) {
+  extern __shared__ float lds[];
+  __shared__ int64_t off_lds[kMaxGroupCells];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n_groups = *n_groups_dev;
+  for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    const FusedGroup& grp = groups[g];
+    const int count = grp.count;
+    const DevType& T = types[grp.type];
+    const int n = T.p.n, npad = T.p.npad, CS = T.p.cs;
+    float* R = lds;
+    __syncthreads();   // the previous group's reads of LDS are done
+    if (tid < count) off_lds[tid] = offsets[grp.cells[tid]];
+    __syncthreads();
+    // R = -r in [cell][vertex][xyz] blocks, rows n..npad-1 zero (the product writes -A B);
+    // vertex-fastest order for coalesced reads
+    for (int i = tid; i < count * 3 * npad; i += kFusedThreads) {
+      const int cc = i / npad, v = i - cc * npad, cell = cc / 3, c = cc - 3 * cell;
+      R[cell * CS + 3 * v + c] = v < n ? -r[c * vt + off_lds[cell] + v] : 0.0f;
+    }
+    __syncthreads();
+    const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
+    const int ncols = 3 * count, CT = (ncols + 15) / 16;
+    const int n_units = RT * CT;
+    const int u0 = (n_units * wave) / kFusedWaves, u1 = (n_units * (wave + 1)) / kFusedWaves;
+    f4 acc[kMaxTilesPerWave];
+#pragma unroll
+    for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+    int n_items = 0;
+    {
+      const gfloat* Lt = gptr(T.linv_tiles) + lane;
+      const int kq = lane >> 4;
+      for (int u = u0; u < u1;) {
+        f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
+        if (CT >= 2) {
+          const int rt = u / CT, ct = u - rt * CT;
+          const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
+          if (ct + 1 < CT && u + 1 < u1) {
+            const lfloat* RbB =
+                (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
+            mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
+            u += 2;
+          } else {
+            mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
+            u += 1;
+          }
+        } else {
+          const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
+          mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
+          if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
+          u += (u + 1 < u1) ? 2 : 1;
+        }
+        // keep the item's tiles at the end of the held set (indices stay compile-time)
+#pragma unroll
+        for (int i = 0; i + 2 < kMaxTilesPerWave; ++i) acc[i] = acc[i + 2];
+        acc[kMaxTilesPerWave - 2] = d0;
+        acc[kMaxTilesPerWave - 1] = d1;
+        ++n_items;
+      }
+    }
+    __syncthreads();
+    {
+      // replay the item sequence to place the held tiles
+      int u = u0;
+#pragma unroll
+      for (int q = 0; q < kMaxTilesPerWave / 2; ++q) {
+        if (q >= kMaxTilesPerWave / 2 - n_items) {
+          if (CT >= 2) {
+            const int rt = u / CT, ct = u - rt * CT;
+            write_tile(R, acc[2 * q], rt, ct, lane, n, ncols, CS);
+            if (ct + 1 < CT && u + 1 < u1) {
+              write_tile(R, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS);
+              u += 2;
+            } else {
+              u += 1;
+            }
+          } else {
+            write_tile(R, acc[2 * q], u, 0, lane, n, ncols, CS);
+            if (u + 1 < u1) write_tile(R, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS);
+            u += (u + 1 < u1) ? 2 : 1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < count * 3 * n; i += kFusedThreads) {
+      const int cc = i / n, v = i - cc * n, cell = cc / 3, c = cc - 3 * cell;
+      out[c * vt + off_lds[cell] + v] = R[cell * CS + 3 * v + c];
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedGroup* groups,
                              const int* n_groups_dev, int max_groups, const int64_t* offsets,
                              int64_t vtot, float* x, float* v, const float* f, const float* cp,
                              const float* cw, int K, double* vol_area, int* flag, size_t lds_bytes,
-                             bool extras, void* stream) {
+                             bool extras, bool skalak, void* stream) {
   (void)n_types;
   if (max_groups == 0) return hipSuccess;
   // one workgroup per group up to a few waves of the chip; beyond that workgroups loop
   const int grid = max_groups < kMaxFusedGrid ? max_groups : kMaxFusedGrid;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (extras || cw != nullptr)
-    hipLaunchKernelGGL((k_fused_step<kMaxItems, true>), dim3(grid), dim3(kFusedThreads), lds_bytes,
-                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, cp, cw, K,
-                       vol_area, flag);
+  if (skalak)
+    hipLaunchKernelGGL((k_fused_step<kMaxItems, true, true>), dim3(grid), dim3(kFusedThreads),
+                       lds_bytes, s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, cp,
+                       cw, K, vol_area, flag);
+  else if (extras || cw != nullptr)
+    hipLaunchKernelGGL((k_fused_step<kMaxItems, true, false>), dim3(grid), dim3(kFusedThreads),
+                       lds_bytes, s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, cp,
+                       cw, K, vol_area, flag);
   else
-    hipLaunchKernelGGL((k_fused_step<kMaxItems, false>), dim3(grid), dim3(kFusedThreads), lds_bytes,
-                       s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f, nullptr, nullptr,
-                       K, vol_area, flag);
+    hipLaunchKernelGGL((k_fused_step<kMaxItems, false, false>), dim3(grid), dim3(kFusedThreads),
+                       lds_bytes, s, types_dev, groups, n_groups_dev, offsets, vtot, x, v, f,
+                       nullptr, nullptr, K, vol_area, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_global_dense(const DevType* types_dev, const FusedGroup* groups,
+                               const int* n_groups_dev, int max_groups, const int64_t* offsets,
+                               int64_t vtot, const float* r, float* out, size_t lds_bytes,
+                               void* stream) {
+  if (max_groups == 0) return hipSuccess;
+  const int grid = max_groups < kMaxFusedGrid ? max_groups : kMaxFusedGrid;
+  hipLaunchKernelGGL(k_global_dense, dim3(grid), dim3(kFusedThreads), lds_bytes,
+                     reinterpret_cast<hipStream_t>(stream), types_dev, groups, n_groups_dev,
+                     offsets, vtot, r, out);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 // cell's first vertex, which leaves every difference, and the enclosed volume, unchanged.
 #include <hip/hip_runtime.h>
 
+#include "banded.h"
 #include "npfem_internal.h"
 #include "filters.h"
 #include "projections.h"
@@ -311,6 +312,41 @@ k_plain_solve(const DevType* __restrict__ dtp, void* work, int mode) {
   }
 }
 
+// The same solves (kSolveUpdate, kSolveDirection) by the register-window substitution of
+// banded.h: one wave, lanes 0-2 take the three coordinates (the factor through scalar loads,
+// pending row sums in registers), then the whole wave applies the result.
+template <typename T, int BW>
+__global__ void __launch_bounds__(64)
+k_plain_solve_band(const DevType* __restrict__ dtp, void* work, int mode) {
+  const DevType& dt = *dtp;
+  const int n = dt.p.n;
+  PlainWork<T> w = plain_layout<T>(work, n, dt.p.m, dt.p.e);
+  const int lane = threadIdx.x;
+  if (lane < 3) band_solve_column<T, BW>(dt, w.r + lane * n, w.dir + lane * n);
+  __threadfence_block();
+  __syncthreads();
+  if (mode == kSolveDirection) {
+    for (int i = lane; i < 3 * n; i += 64) w.dir[i] = -w.dir[i];
+  } else {
+    for (int i = lane; i < 3 * n; i += 64) w.d[i] -= w.dir[i];
+  }
+}
+
+template <typename T>
+void launch_plain_solve(const DevType* dt_dev, const TypeParams& p, void* work, int mode,
+                        hipStream_t s) {
+  switch (p.band_w) {
+#define NPFEM_CASE(W)                                                                            \
+  case W:                                                                                        \
+    hipLaunchKernelGGL((k_plain_solve_band<T, W>), dim3(1), dim3(64), 0, s, dt_dev, work, mode); \
+    return;
+    NPFEM_BAND_WINDOWS(NPFEM_CASE)
+#undef NPFEM_CASE
+    default:   // wider bands: the wave-reduction form
+      hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, mode);
+  }
+}
+
 // Skalak membrane: backtracking line search along dir from delta, one cell. g at step length
 // a (positions x_n + delta + a dir): Skalak energies of the triangles, bending energies of the
 // hinges (projections at that point), the volume energy (w_v/2)(V0 - V)^2/|grad V|^2, the
@@ -459,12 +495,11 @@ hipError_t plain_step_t(const DevType* dt_dev, const TypeParams& p, T* x, T* v, 
     hipLaunchKernelGGL(k_plain_local<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt, off,
                        work, cp, cw);
     if (p.skalak) {
-      hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work,
-                         (int)kSolveDirection);
+      launch_plain_solve<T>(dt_dev, p, work, (int)kSolveDirection, s);
       hipLaunchKernelGGL(k_plain_linesearch<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, vt,
                          off, work, cp, cw);
     } else {
-      hipLaunchKernelGGL(k_plain_solve<T>, dim3(1), dim3(192), 0, s, dt_dev, work, (int)kSolveUpdate);
+      launch_plain_solve<T>(dt_dev, p, work, (int)kSolveUpdate, s);
     }
   }
   hipLaunchKernelGGL(k_plain_finalize<T>, dim3(1), dim3(kPlainThreads), 0, s, dt_dev, x, v, vt,

@@ -23,29 +23,27 @@ constexpr uint16_t kPadNeg = 0, kPadPos = 1, kNbBias = 2;
 // Device-side records (plain structs, identical layout on host and device).
 // ------------------------------------------------------------------------------------------
 
-// One triangle slot of the per-wave round schedule (32 bytes). A slot with area == 0 is
+// One triangle slot of the per-wave round schedule (32 bytes). The vertex fields hold byte
+// offsets (12 x vertex index) into a cell's LDS block of [vertex][xyz] floats, so that a lane
+// adds its cell's base address and nothing else. A slot with orient == 0 (and area == 0) is
 // empty. g_b, g_c are the rest-frame gradient vectors (g_a = -g_b - g_c); the rest frame makes
-// D_m upper triangular, so g_c0 is always zero. The fields a pass reads come first: the volume
-// pass reads the first 16 bytes, the strain/area pass the first 28.
+// D_m upper triangular, so g_c0 is always zero and not stored. The volume pass reads the first
+// 16 bytes, the strain/area pass words 0-2 and 4-7.
 struct TriRec {
-  uint32_t ab;        // a | b << 16
-  uint32_t c;         // c
+  uint32_t a, b, c;   // 12 x vertex index
+  float orient;       // +1 if (a, b, c) is a rotation of the mesh's (outward) order, -1 if
+                      // not, 0 for an empty slot
   float area;
-  float orient;       // +1 if (a, b, c) is a rotation of the mesh's (outward) order, else -1
   float gb0, gb1, gc1;
-  float gc0;          // 0
 };
 
-// One hinge slot (32 bytes): edge (i, j), opposite vertices k, l, stencil a_e, rest norm.
-// A slot with rest < 0 is empty. The kernel reads the first 24 bytes (a_0 = -(a_1 + a_2 + a_3)
-// is implied by the stencil summing to zero).
+// One hinge slot (32 bytes): edge (i, j), opposite vertices k, l (byte offsets as in TriRec),
+// stencil a_e without a_i (a_i = -(a_j + a_k + a_l): the stencil sums to zero), rest norm.
+// A slot with rest < 0 is empty.
 struct HingeRec {
-  uint32_t ij;        // i | j << 16
-  uint32_t kl;        // k | l << 16
+  uint32_t i, j, k, l;   // 12 x vertex index
   float a1, a2, a3;
   float rest;
-  float a0;
-  float pad;
 };
 
 // Element schedules of the fused form for one number of cells per wave (gw): slots = 64 / gw
@@ -68,6 +66,8 @@ struct TypeParams {
   int32_t k_steps;              // MFMA k steps stored per L^-1 row tile: npad / 4 rounded
                                 // up to whole kMfmaChunk chunks plus two chunks (zeros)
   int32_t skalak;               // membrane: 0 = PD constraints, 1 = Skalak energy
+  int32_t band_w;               // window of the standalone banded substitution: the smallest
+                                // 8 k + 1 >= bw (0: bw > 64, unsupported)
   double h, mass, inv_h2m;      // h, m, m / h^2
   double h2_over_m;             // h^2 / m
   double w_s, w_a, w_b, w_v;
@@ -110,6 +110,10 @@ struct DevType {
   double* cband64 = nullptr; float* cband32 = nullptr;   // [n][bw+1]: C[i][i-k]
   double* mband64 = nullptr; float* mband32 = nullptr;   // [n][bw+1]: factor of M~ (Rayleigh)
   double* kband64 = nullptr; float* kband32 = nullptr;   // [n][bw+1]: K[i][i-k] (Rayleigh)
+  // standalone global step (npfem_global_solve), banded factor padded to band_w:
+  double* sband_rows64 = nullptr; float* sband_rows32 = nullptr;   // [n][band_w+1]: C[i][i-k]
+  double* sband_cols64 = nullptr; float* sband_cols32 = nullptr;   // [n][band_w+1]: C[i+k][i],
+                                                                   // k = 0: 1 / C[i][i]
 };
 
 }  // namespace npfem
@@ -174,6 +178,11 @@ constexpr int kFusedThreads = 256;          // 4 waves per workgroup
 constexpr int kFusedWaves = 4;
 constexpr int kMaxItems = 9;                // owner items per lane (cells x vertices / 64)
 constexpr int kFusedLdsBudget = 52224;      // bytes of LDS per fused workgroup
+// The fused kernel's residual blocks R start at this fixed word offset from the position
+// blocks X (half the budget), so that one address per vertex serves both arrays (the offset
+// goes into the LDS instruction's immediate field). X, and R with its damping words, must
+// each fit in half the budget.
+constexpr int kFusedRWords = kFusedLdsBudget / 8;
 constexpr int kMaxGroupCells = 64;
 constexpr int kMaxFusedGrid = 4096;         // workgroups of one fused launch (then they loop)
 
@@ -187,6 +196,7 @@ struct FusedGroup {
 constexpr int kMfmaChunk = 8;               // k steps per prefetched L^-1 chunk
 constexpr double kArmijoC = 1e-4;           // Skalak line search: sufficient decrease
 constexpr int kMaxHalvings = 8;             //   and step lengths 1, 1/2, ..., 1/256
+constexpr int kSkalakMaxGw = 2;             // fused Skalak types: at most 2 cells per wave
 constexpr int kDampWords = 12;              // LDS floats per cell for position-based damping
 constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
 
@@ -246,7 +256,16 @@ hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedG
                              const int* n_groups_dev, int max_groups, const int64_t* offsets,
                              int64_t vtot, float* x, float* v, const float* f, const float* cp,
                              const float* cw, int K, double* vol_area, int* flag, size_t lds_bytes,
-                             bool extras, void* stream);
+                             bool extras, bool skalak, void* stream);
+// Global step alone (npfem_global_solve): dense L^-1 on the matrix cores over the fused work
+// list's groups (FP32), or the banded substitution over one type's cells (either precision).
+hipError_t launch_global_dense(const DevType* types_dev, const FusedGroup* groups,
+                               const int* n_groups_dev, int max_groups, const int64_t* offsets,
+                               int64_t vtot, const float* r, float* out, size_t lds_bytes,
+                               void* stream);
+hipError_t launch_global_banded(int precision, int n, int band_w, const DevType* dt, const int32_t* cells,
+                                int n_cells, const int64_t* offsets, int64_t vt, const void* r,
+                                void* out, void* stream);
 hipError_t launch_median_filter(int precision, int net_keys, const DevType* types,
                                 const FilterBlock* blocks, int n_blocks, int64_t vt,
                                 const void* f, void* out, size_t lds_bytes, void* stream);

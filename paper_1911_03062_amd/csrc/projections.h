@@ -256,6 +256,19 @@ __host__ __device__ __forceinline__ T skalak_residual(Vec3<T> pa, Vec3<T> pb, Ve
   return area * W;
 }
 
+// Skalak energy A W of one triangle alone (the value skalak_residual returns).
+template <typename T>
+__host__ __device__ __forceinline__ T skalak_energy(Vec3<T> pa, Vec3<T> pb, Vec3<T> pc, T gb0, T gb1,
+                                                    T gc0, T gc1, T area, T B, T Cm) {
+  const Vec3<T> e1 = pb - pa, e2 = pc - pa;
+  const Vec3<T> f0 = e1 * gb0 + e2 * gc0, f1 = e1 * gb1 + e2 * gc1;
+  const T c00 = dot3(f0, f0), c01 = dot3(f0, f1), c11 = dot3(f1, f1);
+  const T I1 = (c00 - T(1)) + (c11 - T(1));
+  const T I2 = c00 * c11 - c01 * c01 - T(1);
+  const T W = T(0.25) * B * (I1 * I1 + T(2) * I1 - T(2) * I2) + T(0.25) * Cm * I2 * I2;
+  return area * W;
+}
+
 // Position-based damping (Mueller et al. 2007): the angular velocity of a cell's rigid motion
 // solves I w = L with the inertia tensor I = sum (|r|^2 1 - r r^T) and angular momentum
 // L = sum r x v about the centre of mass (equal masses cancel). Isym = (xx, yy, zz, xy, xz, yz).

@@ -602,11 +602,15 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   const int npad = std::max((n + 3) / 4 * 4, 4 * kMfmaChunk);
   ct->npad = npad;
   ct->cs = 3 * npad + (((3 - 3 * npad) % 16) + 16) % 16;
-  // X and R blocks (FP32), plus the per-cell damping data when the type is damped
-  const int per_cell = 2 * ct->cs * 4 + (ct->kappa > 0.0 ? kDampWords * 4 : 0);
+  // X blocks in the first half of the LDS budget; R blocks (plus, for the Skalak membrane, the
+  // blocks of grad g / trial positions of its line search), plus the per-cell damping data
+  // when the type is damped, in the second (FP32)
+  const bool skalak = ct->membrane == NPFEM_MEMBRANE_SKALAK;
+  const int per_cell = (skalak ? 2 : 1) * ct->cs * 4 + (ct->kappa > 0.0 ? kDampWords * 4 : 0);
   std::vector<int> feasible;
   for (int cand : {16, 8, 4, 2, 1}) {
-    if (kFusedWaves * cand * per_cell > kFusedLdsBudget) continue;
+    if (kFusedWaves * cand * per_cell > 4 * kFusedRWords) continue;
+    if (skalak && cand > kSkalakMaxGw) continue;
     if ((cand * n + 63) / 64 > kMaxItems) continue;
     if (kFusedWaves * cand > kMaxGroupCells) continue;
     // every wave's share of the global step's output tiles, for every group size, must form
@@ -626,9 +630,9 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     ct->fused_reason = "mesh too large for the fused kernel's LDS layout (n <= 576)";
     return NPFEM_OK;
   }
-  if (ct->membrane == NPFEM_MEMBRANE_SKALAK) {
+  if (skalak && ct->beta > 0.0) {
     ct->fused_ok = false;
-    ct->fused_reason = "the Skalak membrane runs in the plain form";
+    ct->fused_reason = "the Skalak membrane with Rayleigh beta runs in neither form";
     return NPFEM_OK;
   }
 
@@ -647,8 +651,7 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     const Schedule hr = best_schedule(hel, n, gw, lay.slots, ct->cs, kHingeRoundValu);
     lay.tri_rounds = (int)tr.rounds.size();
     lay.hinge_rounds = (int)hr.rounds.size();
-    TriRec empty_tri{};
-    empty_tri.area = 0.0f;
+    TriRec empty_tri{};   // orient 0, area 0
     lay.tri_sched.assign((size_t)lay.tri_rounds * lay.slots, empty_tri);
     HingeRec empty_hinge{};
     empty_hinge.rest = -1.0f;
@@ -660,10 +663,11 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
         const int t = tr.ids[r][s];
         const auto fr = rest_frame(P(v[0]), P(v[1]), P(v[2]));
         TriRec rec;
-        rec.ab = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-        rec.c = (uint32_t)v[2];
+        rec.a = 12u * (uint32_t)v[0];
+        rec.b = 12u * (uint32_t)v[1];
+        rec.c = 12u * (uint32_t)v[2];
         rec.gb0 = (float)fr[0]; rec.gb1 = (float)fr[1];
-        rec.gc0 = (float)fr[2]; rec.gc1 = (float)fr[3];
+        rec.gc1 = (float)fr[3];   // fr[2] = g_c0 = 0 in this rest frame
         rec.area = (float)ct->A[t];
         // the roles may reverse the triangle's orientation, which the volume terms see
         int k0 = 0;
@@ -681,12 +685,12 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
           for (int p = 0; p < 4; ++p)
             if (ct->hinge[4 * h + p] == v[q]) a[q] = ct->coef[4 * h + p];
         HingeRec rec;
-        rec.ij = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-        rec.kl = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-        rec.a0 = (float)a[0]; rec.a1 = (float)a[1];
-        rec.a2 = (float)a[2]; rec.a3 = (float)a[3];
+        rec.i = 12u * (uint32_t)v[0];
+        rec.j = 12u * (uint32_t)v[1];
+        rec.k = 12u * (uint32_t)v[2];
+        rec.l = 12u * (uint32_t)v[3];
+        rec.a1 = (float)a[1]; rec.a2 = (float)a[2]; rec.a3 = (float)a[3];
         rec.rest = (float)ct->rest_norm[h];
-        rec.pad = 0;
         lay.hinge_sched[(size_t)r * lay.slots + s] = rec;
       }
     ct->layouts.push_back(std::move(lay));

@@ -21,6 +21,7 @@ STATUS = {0: "NPFEM_OK", -1: "NPFEM_E_INVALID", -2: "NPFEM_E_MESH", -3: "NPFEM_E
           -4: "NPFEM_E_DT", -5: "NPFEM_E_NOMEM", -6: "NPFEM_E_HIP", -7: "NPFEM_E_NONFINITE",
           -8: "NPFEM_E_UNSUPPORTED"}
 FORMS = {"plain": 0, "fused": 1}
+SOLVES = {"dense": 0, "banded": 1}
 
 
 class NpfemError(RuntimeError):
@@ -98,6 +99,8 @@ def lib() -> ctypes.CDLL:
     L.npfem_detect_contacts_noalloc.argtypes = [c_void_p, c_void_p, c_double, c_double, c_double,
                                                 c_void_p, c_void_p, c_void_p]
     L.npfem_detect_contacts_noalloc.restype = c_int32
+    L.npfem_global_solve.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+    L.npfem_global_solve.restype = c_int32
     L.npfem_batch_check.restype = c_int32
     L.npfem_celltype_cells_per_wave.argtypes = [c_void_p, POINTER(c_int32), c_int32]
     L.npfem_celltype_cells_per_wave.restype = c_int32
@@ -277,6 +280,25 @@ class Batch:
                                            float(weight), contact_p.data_ptr(),
                                            contact_w.data_ptr(), c_void_p(s.cuda_stream)))
         return contact_p, contact_w
+
+    def global_solve(self, rhs, out=None, solve: str = "dense", stream=None):
+        """out = L^-1 rhs for every cell's 3 coordinate columns ([3][V_total] device tensors in
+        the batch precision), with the dense L^-1 on the matrix cores ("dense", fused batches)
+        or the banded Cholesky substitution ("banded")."""
+        import torch
+        dtype = torch.float64 if self.precision == 64 else torch.float32
+        if out is None:
+            out = torch.empty_like(rhs)
+        for name, t in (("rhs", rhs), ("out", out)):
+            if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()
+                    and tuple(t.shape) == (3, self.vertex_count)):
+                raise ValueError(f"{name} must be a contiguous device tensor [3][{self.vertex_count}] of {dtype}")
+        if solve not in SOLVES:
+            raise ValueError(f"solve must be one of {sorted(SOLVES)}")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().npfem_global_solve(self._h, SOLVES[solve], rhs.data_ptr(), out.data_ptr(),
+                                        c_void_p(s.cuda_stream)))
+        return out
 
     def detect_contacts_noalloc(self, x, radius: float, separation: float, weight: float,
                                 contact_p, contact_w, stream=None):

@@ -1,0 +1,116 @@
+"""The global step alone (npfem_global_solve): the dense L^-1 product on the matrix cores and
+the banded Cholesky substitution against the FP64 oracle's prefactored solve (cho_solve with
+the same L), on mixed batches and on sampled cells of the full 24 000-cell workload."""
+import sys
+
+import numpy as np
+import pytest
+
+import npfem_inputs as I
+import oracle as O
+from _runners import lib_types, oracle_types
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_solve(ot, types, offsets, rhs, cells):
+    """L^-1 rhs per listed cell, FP64, as [3][n] blocks keyed by cell."""
+    out = {}
+    for c in cells:
+        ct = ot[int(types[c])]
+        s = slice(int(offsets[c]), int(offsets[c + 1]))
+        b = np.transpose(rhs[:, s])[None, :, :]              # [1][n][3]
+        out[int(c)] = np.transpose(O.solve(ct, b)[0])        # [3][n]
+    return out
+
+
+def _rel_err(xg, ref, offsets, cells):
+    worst = 0.0
+    for c in cells:
+        s = slice(int(offsets[c]), int(offsets[c + 1]))
+        for k in range(3):
+            r = ref[int(c)][k]
+            worst = max(worst, np.linalg.norm(xg[k, s] - r) / np.linalg.norm(r))
+    return worst
+
+
+def _run(batch, rhs_np, solve, precision, inplace=False):
+    import torch
+    dt = torch.float64 if precision == 64 else torch.float32
+    rhs = torch.tensor(rhs_np, dtype=dt, device="cuda").contiguous()
+    out = rhs if inplace else torch.full_like(rhs, float("nan"))
+    batch.global_solve(rhs, out, solve=solve)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("solve,precision,form,tol", [("dense", 32, "fused", 2e-6),
+                                                      ("banded", 32, "fused", 2e-6),
+                                                      ("banded", 32, "plain", 2e-6),
+                                                      ("banded", 64, "plain", 1e-13)])
+def test_global_solve_matches_oracle(solve, precision, form, tol):
+    """11 RBC + 9 PLT interleaved; right-hand sides N(0, 1) rounded to the batch precision;
+    relative error per column against the oracle's FP64 solve with the same L."""
+    from paper_1911_03062_amd import npfem as N
+    tids = np.array([I.RBC] * 11 + [I.PLT] * 9, dtype=np.int32)
+    tids = tids[np.random.default_rng(501).permutation(len(tids))]
+    b = I.make_batch(tids, seed=502)
+    rng = np.random.default_rng(503)
+    rhs = rng.normal(size=(3, b.v_total))
+    if precision == 32:
+        rhs = rhs.astype(np.float32).astype(np.float64)
+    lt = lib_types()
+    batch = N.Batch([lt[int(t)] for t in tids], precision=precision, form=form)
+    _say(f"case: global solve {solve} FP{precision} {form}, {len(tids)} cells")
+    ref = _oracle_solve(oracle_types(), tids, b.offsets, rhs, range(len(tids)))
+    for inplace in (False, True):
+        xg = _run(batch, rhs, solve, precision, inplace)
+        err = _rel_err(xg, ref, b.offsets, range(len(tids)))
+        _say(f"  in place {inplace}: max relative error per column {err:.3e}")
+        assert err <= tol, err
+
+
+def test_global_solve_dense_and_banded_agree_on_the_large_workload():
+    """The 24 000-cell workload's layout (20 000 RBC + 4 000 PLT interleaved, the benchmark's
+    cells per wave): both variants over the whole batch, 48 sampled cells against the oracle
+    (all three coordinate columns of each), and the two variants against each other on every
+    vertex."""
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    w = I.WORKLOADS["large_24000"]
+    b = w.batch()
+    lt = lib_types()
+    batch = N.Batch([lt[int(t)] for t in b.types], precision=32, form="fused")
+    batch.set_cells_per_wave(lt[I.RBC], 2)
+    batch.set_cells_per_wave(lt[I.PLT], 4)
+    rhs = np.random.default_rng(504).normal(size=(3, b.v_total)).astype(np.float32).astype(np.float64)
+    _say(f"case: global solve, large_24000 ({b.n_cells} cells, {b.v_total} vertices)")
+    xd = _run(batch, rhs, "dense", 32)
+    xb = _run(batch, rhs, "banded", 32)
+    cells = np.random.default_rng(505).choice(b.n_cells, 48, replace=False)
+    ref = _oracle_solve(oracle_types(), b.types, b.offsets, rhs, cells)
+    ed = _rel_err(xd, ref, b.offsets, cells)
+    eb = _rel_err(xb, ref, b.offsets, cells)
+    scale = np.abs(xd).max()
+    diff = np.abs(xd - xb).max() / scale
+    _say(f"  dense {ed:.3e}, banded {eb:.3e} (relative, sampled); dense vs banded {diff:.3e} of max")
+    assert ed <= 2e-6 and eb <= 2e-6
+    assert diff <= 1e-5
+
+
+def test_global_solve_errors():
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    lt = lib_types()
+    plain = N.Batch([lt[I.RBC], lt[I.PLT]], precision=64, form="plain")
+    rhs = torch.zeros((3, plain.vertex_count), dtype=torch.float64, device="cuda")
+    with pytest.raises(N.NpfemError) as e:
+        plain.global_solve(rhs, solve="dense")
+    assert e.value.name == "NPFEM_E_UNSUPPORTED"
+    with pytest.raises(ValueError):
+        plain.global_solve(rhs, solve="lu")

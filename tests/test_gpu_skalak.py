@@ -1,6 +1,6 @@
-"""The Skalak membrane with its line-searched quasi-Newton step (plain form) on the GPU against
-the FP64 oracle: loads where the full step is accepted, and an inflated cell where the line
-search halves the step."""
+"""The Skalak membrane with its line-searched quasi-Newton step on the GPU (plain form in FP64
+and FP32, fused form in FP32) against the FP64 oracle: loads where the full step is accepted,
+and an inflated cell where the line search halves the step."""
 import sys
 
 import numpy as np
@@ -26,28 +26,31 @@ def _types():
     return lt, ot
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_skalak_plain_mixed_batch(precision):
+FORMS = [("plain", 64), ("plain", 32), ("fused", 32)]
+
+
+@pytest.mark.parametrize("form,precision", FORMS)
+def test_skalak_mixed_batch(form, precision):
     lt, ot = _types()
     tids = np.array([I.RBC] * 2 + [I.PLT] * 3, dtype=np.int32)
     b = I.make_batch(tids, seed=190)
     rng = np.random.default_rng(191)
     v0 = rng.normal(0, 0.05, size=b.x0.shape).astype(np.float32).astype(np.float64)
     forces = list(I.force_stream(b, seed=192, sigma=20.0, n_steps=3))
-    _say(f"case: Skalak plain FP{precision}, 2 RBC + 3 PLT, 3 steps x K = 10")
+    _say(f"case: Skalak {form} FP{precision}, 2 RBC + 3 PLT, 3 steps x K = 10")
     xo, vo = run_oracle(ot, b.types, b.offsets, b.x0, v0, forces, 10)
-    xg, vg = run_gpu(lt, b.types, b.x0, v0, forces, 10, form="plain", precision=precision)
+    xg, vg = run_gpu(lt, b.types, b.x0, v0, forces, 10, form=form, precision=precision)
     err = cell_errors(b.types, b.offsets, xg, xo)
     xp, _ = run_oracle({k: O.CellType(x, t, m, I.DT) for k, (x, t, m) in I.cell_type_inputs().items()},
                        b.types, b.offsets, b.x0, v0, forces, 10)
     sep = cell_errors(b.types, b.offsets, xp, xo)
-    _say(f"Skalak plain FP{precision}: max err/diam {err.max():.3e}, Skalak vs PD {sep.min():.3e}")
+    _say(f"Skalak {form} FP{precision}: max err/diam {err.max():.3e}, Skalak vs PD {sep.min():.3e}")
     assert err.max() <= (1e-10 if precision == 64 else 1e-5)
     assert sep.min() > 100 * err.max()
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_skalak_inflated_cell_halves_the_step(precision):
+@pytest.mark.parametrize("form,precision", FORMS)
+def test_skalak_inflated_cell_halves_the_step(form, precision):
     """Cells inflated by 40 % (area strain ~ 1.8): the full quasi-Newton step overshoots and the
     line search halves it (step lengths 1/2 to 1/8); K = 4 iterates against the oracle's."""
     lt, ot = _types()
@@ -59,9 +62,9 @@ def test_skalak_inflated_cell_halves_the_step(precision):
     x0 = x0.astype(np.float32).astype(np.float64)
     v0 = np.zeros_like(x0)
     forces = [np.zeros_like(x0)]
-    _say(f"case: Skalak plain FP{precision}, RBC + PLT inflated by 40 %, 1 step x K = 4")
+    _say(f"case: Skalak {form} FP{precision}, RBC + PLT inflated by 40 %, 1 step x K = 4")
     xo, _ = run_oracle(ot, b.types, b.offsets, x0, v0, forces, 4)
-    xg, _ = run_gpu(lt, b.types, x0, v0, forces, 4, form="plain", precision=precision)
+    xg, _ = run_gpu(lt, b.types, x0, v0, forces, 4, form=form, precision=precision)
     err = cell_errors(b.types, b.offsets, xg, xo)
     # step lengths the oracle's line search takes, per cell and iteration, read off its
     # updates: each is a multiple of the full quasi-Newton step -L^-1 grad g
@@ -77,14 +80,66 @@ def test_skalak_inflated_cell_halves_the_step(precision):
             steps.append(float(np.sum((xn - xk) * d) / np.sum(d * d)))
             xk = xn
     halved = min(steps) < 1.0
-    _say(f"Skalak inflated FP{precision}: max err/diam {err.max():.3e}; step lengths {steps}")
+    _say(f"Skalak inflated {form} FP{precision}: max err/diam {err.max():.3e}; step lengths {steps}")
     assert halved
     assert err.max() <= (1e-10 if precision == 64 else 1e-5)
 
 
-def test_skalak_fused_is_unsupported():
+def test_skalak_fused_mixed_with_pd_types_and_contacts():
+    """One fused batch holding Skalak red cells, PD platelets (the same kernel variant runs both)
+    and collision energies on 10 % of the vertices, 3 steps x K = 10, against the oracle."""
     from paper_1911_03062_amd import npfem as N
-    lt, _ = _types()
-    with pytest.raises(N.NpfemError) as ei:
-        N.Batch([lt[I.RBC]], precision=32, form="fused")
-    assert ei.value.name == "NPFEM_E_UNSUPPORTED"
+    import torch
+    inp = I.cell_type_inputs()
+    lt = {I.RBC: N.CellType(*inp[I.RBC][:2], inp[I.RBC][2].with_membrane("skalak"), I.DT),
+          I.PLT: N.CellType(*inp[I.PLT][:2], inp[I.PLT][2], I.DT)}
+    ot = {I.RBC: O.CellType(*inp[I.RBC][:2], inp[I.RBC][2].with_membrane("skalak"), I.DT),
+          I.PLT: O.CellType(*inp[I.PLT][:2], inp[I.PLT][2], I.DT)}
+    tids = np.array([I.RBC, I.PLT, I.RBC, I.PLT, I.PLT, I.RBC], dtype=np.int32)
+    b = I.make_batch(tids, seed=194)
+    rng = np.random.default_rng(195)
+    cw = np.where(rng.random(b.v_total) < 0.1, 400.0, 0.0)
+    cpt = (b.x0 + rng.normal(0, 0.1, size=b.x0.shape)).astype(np.float32).astype(np.float64)
+    forces = [np.where(cw > 0, 0.0, f) for f in I.force_stream(b, seed=196, sigma=20.0, n_steps=3)]
+    _say("case: fused, Skalak RBC + PD platelets with contacts, 3 steps x K = 10")
+    xo, vo = b.x0.copy(), b.v0.copy()
+    for f in forces:
+        xo, vo = O.step_batch(ot, tids, b.offsets, xo, vo, f, 10, contact_p=cpt, contact_w=cw)
+    batch = N.Batch([lt[int(t)] for t in tids], precision=32, form="fused")
+    x = torch.tensor(b.x0, dtype=torch.float32, device="cuda")
+    v = torch.tensor(b.v0, dtype=torch.float32, device="cuda")
+    cpd = torch.tensor(cpt, dtype=torch.float32, device="cuda")
+    cwd = torch.tensor(cw, dtype=torch.float32, device="cuda")
+    for f in forces:
+        batch.step(x, v, torch.tensor(f, dtype=torch.float32, device="cuda"), I.DT, 10,
+                   contacts=(cpd, cwd))
+    batch.check()
+    err = cell_errors(tids, b.offsets, x.double().cpu().numpy(), xo)
+    _say(f"fused Skalak + PD + contacts: max err/diam {err.max():.3e}")
+    assert err.max() <= 1e-5
+
+
+def test_skalak_fused_full_size_sampled():
+    """Every cell of the 24 000-cell workload with the Skalak membrane, fused form, 2 steps x
+    K = 20 with the workload's forces; 12 sampled cells (4 of them strongly forced) against
+    the oracle."""
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    lt, ot = _types()
+    w = I.WORKLOADS["large_24000"]
+    b = w.batch()
+    forces = list(w.forces(b, n_steps=2))
+    strong = I.strong_cells(b, w.seed, w.strong_fraction)
+    cells = np.unique(np.concatenate([np.random.default_rng(197).choice(b.n_cells, 8, replace=False),
+                                      strong[:4]]))
+    _say(f"case: fused Skalak, large_24000, 2 steps x K = {w.n_pd_iters}, {len(cells)} sampled cells")
+    batch = N.Batch([lt[int(t)] for t in b.types], precision=32, form="fused")
+    x = torch.tensor(b.x0, dtype=torch.float32, device="cuda")
+    v = torch.tensor(b.v0, dtype=torch.float32, device="cuda")
+    for f in forces:
+        batch.step(x, v, torch.tensor(f, dtype=torch.float32, device="cuda"), I.DT, w.n_pd_iters)
+    batch.check()
+    xo, _ = run_oracle(ot, b.types, b.offsets, b.x0, b.v0, forces, w.n_pd_iters, cells=cells)
+    err = cell_errors(b.types, b.offsets, x.double().cpu().numpy(), xo, cells)
+    _say(f"fused Skalak full size: max err/diam {err.max():.3e}, median {np.median(err):.3e}")
+    assert err.max() <= 2e-5

@@ -113,10 +113,14 @@ def test_rayleigh_system_matrix_matches_oracle(alpha, beta):
     assert ct.cells_per_wave() != []
 
 
-def test_skalak_membrane_is_plain_form_only_and_excludes_rayleigh_beta():
+def test_skalak_membrane_layouts_and_rayleigh_beta_excluded():
+    """The fused form's Skalak types keep a third LDS block per cell (grad g, trial positions)
+    in the residual half, which leaves one red cell or two platelets per wave."""
     x, t, m = I.cell_type_inputs()[I.RBC]
     ct = N.CellType(x, t, m.with_membrane("skalak"), I.DT)
-    assert ct.cells_per_wave() == []
+    assert ct.cells_per_wave() == [1]
+    xp, tp, mp = I.cell_type_inputs()[I.PLT]
+    assert N.CellType(xp, tp, mp.with_membrane("skalak"), I.DT).cells_per_wave() == [2, 1]
     oc = O.CellType(x, t, m.with_membrane("skalak"), I.DT)
     assert np.abs(ct.matrix() - oc.L).max() <= 1e-13 * np.abs(oc.L).max()
     _expect("NPFEM_E_UNSUPPORTED", lambda: N.CellType(x, t, m.with_membrane("skalak").with_rayleigh(0.0, 0.01), I.DT))
