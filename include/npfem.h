@@ -213,7 +213,10 @@ npfem_status npfem_batch_set_cells_per_wave(npfem_batch* batch, const npfem_cell
 /* Time every feasible layout of every type of the batch (warm-up step, then `reps` steps of
  * n_pd_iters iterations on `stream`, with only that type's cells active, on library-allocated
  * scratch state: each cell at its rest shape under small pseudo-random forces) and keep the
- * fastest per cell. Synchronises the device; the caller's state buffers are not touched. The
+ * fastest per cell. Then, with those layouts, time the two variants of the global step alone
+ * (npfem_global_solve, `reps` calls each over the whole batch) and keep the faster for
+ * NPFEM_SOLVE_AUTO. The fused step itself always applies L^-1 as the dense product on the
+ * matrix cores. Synchronises the device; the caller's state buffers are not touched. The
  * all-cells list is current afterwards. Errors: NPFEM_E_INVALID (n_pd_iters or reps < 1),
  * NPFEM_E_UNSUPPORTED (plain form), NPFEM_E_NOMEM, NPFEM_E_HIP. */
 npfem_status npfem_batch_autotune(npfem_batch* batch, int32_t n_pd_iters, int32_t reps,
@@ -299,15 +302,20 @@ npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double rad
  *                       cores, as the fused step does; fused-form (FP32) batches only;
  *   NPFEM_SOLVE_BANDED  forward and back substitution with the banded Cholesky factor
  *                       (FP64-computed, used in the batch precision), one lane per column;
- *                       either form and precision, band widths up to 65.
+ *                       either form and precision, band widths up to 65;
+ *   NPFEM_SOLVE_AUTO    the faster of the two as npfem_batch_autotune last timed them on this
+ *                       batch (before any autotune: dense for fused, banded for plain batches).
  *   rhs, out  device, [3][V_total] in the batch precision (may be the same buffer);
  * every cell takes part, whatever npfem_batch_set_active selected. Asynchronous on `stream`.
  * Errors: NPFEM_E_INVALID (null batch or buffer, unknown variant), NPFEM_E_UNSUPPORTED (dense on
  * a plain-form batch; a band wider than 65), NPFEM_E_HIP.
  */
-enum { NPFEM_SOLVE_DENSE = 0, NPFEM_SOLVE_BANDED = 1 };
+enum { NPFEM_SOLVE_DENSE = 0, NPFEM_SOLVE_BANDED = 1, NPFEM_SOLVE_AUTO = 2 };
 npfem_status npfem_global_solve(npfem_batch* batch, int32_t solve, const void* rhs, void* out,
                                 void* stream);
+/* The variant NPFEM_SOLVE_AUTO uses for `batch` (NPFEM_SOLVE_DENSE or NPFEM_SOLVE_BANDED) into
+ * *solve. Errors: NPFEM_E_INVALID (null argument). */
+npfem_status npfem_batch_get_global_solve(const npfem_batch* batch, int32_t* solve);
 
 /*
  * Allocation-free variant of npfem_detect_contacts, for callers that cannot allocate device

@@ -320,6 +320,7 @@ struct npfem_batch {
   size_t lds_bytes = 0;
   bool fused_extras = false;                // a type damps or caps velocities (kernel variant)
   bool fused_skalak = false;                // a type has the Skalak membrane (kernel variant)
+  int solve_choice = -1;                    // NPFEM_SOLVE_AUTO's variant (-1: by form)
   void* work = nullptr;                     // plain-form workspace
   int* d_flag = nullptr;
   npfem::ContactWork contacts;              // contact detection workspace (first use)
@@ -950,10 +951,28 @@ npfem_status npfem_batch_autotune(npfem_batch* b, int32_t n_pd_iters, int32_t re
     b->layout_of[ti] = best;
   }
   (void)hipStreamSynchronize(s);
-  cleanup();
   // the scratch steps may have set the non-finite flag: clear it, then restore all cells
   (void)hipMemset(b->d_flag, 0, sizeof(int));
-  const npfem_status st2 = relayout(b);
+  npfem_status st2 = relayout(b);
+  // the global step alone (npfem_global_solve with NPFEM_SOLVE_AUTO): time both variants on
+  // the whole batch with the chosen layouts, the scratch forces as right-hand sides
+  if (st == NPFEM_OK && st2 == NPFEM_OK) {
+    float t_solve[2] = {0.0f, 0.0f};
+    for (int variant = NPFEM_SOLVE_DENSE; variant <= NPFEM_SOLVE_BANDED && st == NPFEM_OK; ++variant) {
+      st = npfem_global_solve(b, variant, f, v, stream);   // warm-up
+      if (st == NPFEM_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(NPFEM_E_HIP, "event");
+      for (int r = 0; r < reps && st == NPFEM_OK; ++r) st = npfem_global_solve(b, variant, f, v, stream);
+      if (st == NPFEM_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&t_solve[variant], e0, e1) != hipSuccess))
+        st = fail(NPFEM_E_HIP, "autotune timing");
+    }
+    if (st == NPFEM_OK)
+      b->solve_choice = t_solve[NPFEM_SOLVE_BANDED] < t_solve[NPFEM_SOLVE_DENSE] ? NPFEM_SOLVE_BANDED
+                                                                                : NPFEM_SOLVE_DENSE;
+  }
+  (void)hipStreamSynchronize(s);
+  cleanup();
   if (st != NPFEM_OK) return st;
   if (st2 == NPFEM_OK) g_last_error.clear();
   return st2;
@@ -1050,8 +1069,11 @@ npfem_status npfem_detect_contacts_noalloc(npfem_batch* b, const void* x, double
 npfem_status npfem_global_solve(npfem_batch* b, int32_t solve, const void* rhs, void* out,
                                 void* stream) {
   if (!b) return fail(NPFEM_E_INVALID, "batch is null");
-  if (solve != NPFEM_SOLVE_DENSE && solve != NPFEM_SOLVE_BANDED)
+  if (solve != NPFEM_SOLVE_DENSE && solve != NPFEM_SOLVE_BANDED && solve != NPFEM_SOLVE_AUTO)
     return fail(NPFEM_E_INVALID, "unknown global-step variant");
+  if (solve == NPFEM_SOLVE_AUTO)
+    solve = b->solve_choice >= 0 ? b->solve_choice
+                                 : (b->form == NPFEM_FORM_FUSED ? NPFEM_SOLVE_DENSE : NPFEM_SOLVE_BANDED);
   if (b->n_cells == 0) return NPFEM_OK;
   if (!rhs || !out) return fail(NPFEM_E_INVALID, "null buffer");
   DeviceGuard guard(b->device);
@@ -1081,6 +1103,13 @@ npfem_status npfem_global_solve(npfem_batch* b, int32_t solve, const void* rhs, 
                                               b->type_count[ti], b->d_offsets, V, rhs, out, stream);
     if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("banded global step: ") + hipGetErrorString(e));
   }
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_get_global_solve(const npfem_batch* b, int32_t* solve) {
+  if (!b || !solve) return fail(NPFEM_E_INVALID, "null argument");
+  *solve = b->solve_choice >= 0 ? b->solve_choice
+                                : (b->form == NPFEM_FORM_FUSED ? NPFEM_SOLVE_DENSE : NPFEM_SOLVE_BANDED);
   return NPFEM_OK;
 }
 

@@ -21,7 +21,7 @@ STATUS = {0: "NPFEM_OK", -1: "NPFEM_E_INVALID", -2: "NPFEM_E_MESH", -3: "NPFEM_E
           -4: "NPFEM_E_DT", -5: "NPFEM_E_NOMEM", -6: "NPFEM_E_HIP", -7: "NPFEM_E_NONFINITE",
           -8: "NPFEM_E_UNSUPPORTED"}
 FORMS = {"plain": 0, "fused": 1}
-SOLVES = {"dense": 0, "banded": 1}
+SOLVES = {"dense": 0, "banded": 1, "auto": 2}
 
 
 class NpfemError(RuntimeError):
@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
     L.npfem_detect_contacts_noalloc.restype = c_int32
     L.npfem_global_solve.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
     L.npfem_global_solve.restype = c_int32
+    L.npfem_batch_get_global_solve.argtypes = [c_void_p, POINTER(c_int32)]
+    L.npfem_batch_get_global_solve.restype = c_int32
     L.npfem_batch_check.restype = c_int32
     L.npfem_celltype_cells_per_wave.argtypes = [c_void_p, POINTER(c_int32), c_int32]
     L.npfem_celltype_cells_per_wave.restype = c_int32
@@ -299,6 +301,12 @@ class Batch:
         _check(lib().npfem_global_solve(self._h, SOLVES[solve], rhs.data_ptr(), out.data_ptr(),
                                         c_void_p(s.cuda_stream)))
         return out
+
+    def global_solve_choice(self) -> str:
+        """The variant global_solve(solve="auto") takes ("dense" or "banded")."""
+        out = c_int32(0)
+        _check(lib().npfem_batch_get_global_solve(self._h, ctypes.byref(out)))
+        return {v: k for k, v in SOLVES.items()}[out.value]
 
     def detect_contacts_noalloc(self, x, radius: float, separation: float, weight: float,
                                 contact_p, contact_w, stream=None):

@@ -153,6 +153,8 @@ class StepServer:
         self.sessions: dict[int, Session] = {}
         self.track: set = set()          # session ids whose final state is kept
         self.finals: dict = {}           # sid -> (x, v) host copies at release / end of run
+        self.resident = 0                # cells of the admitted sessions
+        self.peak_resident = 0
 
     def _admit(self, sess: Session) -> bool:
         if sess.initialised:
@@ -167,6 +169,8 @@ class StepServer:
         sess.rbc, sess.plt = r, p
         init_session_state(self.pool, sess, sess.sid)
         sess.initialised = True
+        self.resident += sess.n_rbc + sess.n_plt
+        self.peak_resident = max(self.peak_resident, self.resident)
         return True
 
     def _snapshot(self, sess: Session):
@@ -185,6 +189,7 @@ class StepServer:
         self.pool.alloc[PLT].release(sess.plt)
         sess.rbc = sess.plt = (0, 0)
         sess.initialised = False
+        self.resident -= sess.n_rbc + sess.n_plt
 
     def warmup(self):
         """Run one tick of the whole request path (state set-up, seeded forces, active list,
@@ -209,6 +214,8 @@ class StepServer:
         self.finals.pop(tmp.sid, None)
         self.pool.alloc[RBC].release(tmp.rbc)
         self.pool.alloc[PLT].release(tmp.plt)
+        self.resident -= tmp.n_rbc + tmp.n_plt
+        self.peak_resident = 0
         self.pool.batch.set_active(None)
         self.pool.batch.check()
 
@@ -244,6 +251,7 @@ class StepServer:
         t0 = time.perf_counter()
         busy_ms = 0.0
         n_cells_stepped = 0
+        waited: set = set()              # requests held back at least once for want of slots
         while pending or waiting or in_flight:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
@@ -260,10 +268,6 @@ class StepServer:
                     if s.remaining <= 0:
                         self._release(s)
             # admit: one request per idle session, in arrival order
-            def pending_admissible(ws):
-                # with nothing in flight every session is idle; only slot shortage blocks
-                return any(self.sessions[r.session].initialised for r in ws)
-
             batch_reqs = []
             if len(in_flight) < self.max_in_flight:
                 still = []
@@ -273,9 +277,13 @@ class StepServer:
                         s.busy = True
                         batch_reqs.append(rq)
                     else:
+                        if not s.busy:
+                            waited.add(rq.rid)
                         still.append(rq)
                 waiting = still
-            if not batch_reqs and not in_flight and waiting and not pending_admissible(waiting):
+            # slots held by live sessions come free when their last requests (still to arrive
+            # or waiting) are done; only with no session resident can a wait last forever
+            if not batch_reqs and not in_flight and waiting and self.resident == 0:
                 raise RuntimeError("slot pool too small: waiting requests can never be admitted")
             if batch_reqs:
                 ids = []
@@ -313,7 +321,8 @@ class StepServer:
             busy_ms += tk.start.elapsed_time(tk.event)
         self.pool.batch.set_active(None)
         return {"ticks": ticks, "wall_s": total, "busy_ms": busy_ms,
-                "cells_stepped": n_cells_stepped}
+                "cells_stepped": n_cells_stepped, "admission_waits": len(waited),
+                "peak_cells_resident": self.peak_resident}
 
 
 def poisson_workload(duration_s: float, rate: float, seed: int, n_min=50, n_max=10_000,

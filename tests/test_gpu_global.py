@@ -101,6 +101,13 @@ def test_global_solve_dense_and_banded_agree_on_the_large_workload():
     _say(f"  dense {ed:.3e}, banded {eb:.3e} (relative, sampled); dense vs banded {diff:.3e} of max")
     assert ed <= 2e-6 and eb <= 2e-6
     assert diff <= 1e-5
+    # the autotuner times both and NPFEM_SOLVE_AUTO takes the faster
+    assert batch.global_solve_choice() == "dense"          # the default of a fused batch
+    batch.autotune(2, reps=2)
+    choice = batch.global_solve_choice()
+    xa = _run(batch, rhs, "auto", 32)
+    _say(f"  autotuner's global-step choice: {choice}")
+    assert np.array_equal(xa, _run(batch, rhs, choice, 32))
 
 
 def test_global_solve_errors():
