@@ -735,6 +735,7 @@ def main():
                 "gpu_busy_frac": st["busy_ms"] * 1e-3 / st["wall_s"],
                 "hbm_budget_bytes": mb << 20, "slot_capacity_cells": spool.cap,
                 "admission_waits": st["admission_waits"],
+                "moved_to_host": st["evictions"], "moved_back": st["restores"],
                 "peak_cells_resident": st["peak_cells_resident"],
                 "mean_cells_per_tick": float(np.mean([tk.n_cells for tk in st["ticks"]])),
             }

@@ -116,6 +116,13 @@ __device__ __forceinline__ u4 load_hinge_offs(__amdgpu_buffer_rsrc_t rs, int rou
   return __builtin_amdgcn_raw_buffer_load_b128(rs, slot_off, round * S * 32, 0);
 }
 
+// x + a d with the product rounded on its own (no fused multiply-add): the Skalak line
+// search's trial positions and the update that takes a trial must form the same values.
+__device__ __forceinline__ float add_scaled(float x, float a, float d) {
+#pragma clang fp contract(off)
+  return x + a * d;
+}
+
 // A vertex's xyz in a cell block, from the block's base and the vertex's byte offset.
 __device__ __forceinline__ float* vat(float* base, uint32_t byte_off) {
   return (float*)((char*)base + byte_off);
@@ -258,6 +265,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
   __shared__ float ls_a[SKALAK ? kMaxGroupCells : 1];
   __shared__ int ls_done[SKALAK ? kMaxGroupCells : 1];
   __shared__ double ls_e0[SKALAK ? kMaxGroupCells : 1], ls_slope[SKALAK ? kMaxGroupCells : 1];
+  __shared__ double ls_enext[SKALAK ? kMaxGroupCells : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   const int n_groups = *n_groups_dev;
@@ -835,7 +843,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               double g2i = dot3(gi, gi), vxi = dot3(dpi, gi), emi = 0.0, eci = 0.0;
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                const float el = trial ? e[it][c] + a * Dv[c] : e[it][c];
+                // e + a d rounded as the update forms it (a d, then the sum)
+                const float el = trial ? add_scaled(e[it][c], a, Dv[c]) : e[it][c];
                 emi += (double)el * (double)el;
               }
               if (EXTRAS && cw != nullptr) {
@@ -863,29 +872,46 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           owner_sum(vx);
           owner_sum(em);
           owner_sum(ec);
-          // element energies of the lane's cell: Skalak triangles and bending hinges
+          // element energies of the lane's cell: Skalak triangles and bending hinges, each
+          // round's record loaded one round ahead
           double el = 0.0;
           if (e_ok) {
             const float* Pe = P + e_gc * CS;
-            for (int r = 0; r < T.p.tri_rounds; ++r) {
-              const u3 o = load_tri_offs(tri_rs, r, S, e_soff);
-              const u4 c = load_rec_hi(tri_rs, r, S, e_soff);
-              const float area = __uint_as_float(c.x);
-              if (area > 0.0f)
-                el += (double)skalak_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
-                                                   ld3(vat(Pe, o.z)), __uint_as_float(c.y),
-                                                   __uint_as_float(c.z), 0.0f,
-                                                   __uint_as_float(c.w), area, w_s, w_a);
+            {
+              const int NR = T.p.tri_rounds;
+              u3 o = load_tri_offs(tri_rs, 0, S, e_soff);
+              u4 c = load_rec_hi(tri_rs, 0, S, e_soff);
+              for (int r = 0; r < NR; ++r) {
+                const int rn = min(r + 1, NR - 1);
+                const u3 on = load_tri_offs(tri_rs, rn, S, e_soff);
+                const u4 cn = load_rec_hi(tri_rs, rn, S, e_soff);
+                const float area = __uint_as_float(c.x);
+                if (area > 0.0f)
+                  el += (double)skalak_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
+                                                     ld3(vat(Pe, o.z)), __uint_as_float(c.y),
+                                                     __uint_as_float(c.z), 0.0f,
+                                                     __uint_as_float(c.w), area, w_s, w_a);
+                o = on;
+                c = cn;
+              }
             }
-            for (int r = 0; r < T.p.hinge_rounds; ++r) {
-              const u4 o = load_hinge_offs(hinge_rs, r, S, e_soff);
-              const u4 c = load_rec_hi(hinge_rs, r, S, e_soff);
-              const float rest = __uint_as_float(c.w);
-              if (rest >= 0.0f)
-                el += (double)hinge_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
-                                                  ld3(vat(Pe, o.z)), ld3(vat(Pe, o.w)),
-                                                  __uint_as_float(c.x), __uint_as_float(c.y),
-                                                  __uint_as_float(c.z), rest, w_b);
+            {
+              const int NR = T.p.hinge_rounds;
+              u4 o = load_hinge_offs(hinge_rs, 0, S, e_soff);
+              u4 c = load_rec_hi(hinge_rs, 0, S, e_soff);
+              for (int r = 0; r < NR; ++r) {
+                const int rn = min(r + 1, NR - 1);
+                const u4 on = load_hinge_offs(hinge_rs, rn, S, e_soff);
+                const u4 cn = load_rec_hi(hinge_rs, rn, S, e_soff);
+                const float rest = __uint_as_float(c.w);
+                if (rest >= 0.0f)
+                  el += (double)hinge_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
+                                                    ld3(vat(Pe, o.z)), ld3(vat(Pe, o.w)),
+                                                    __uint_as_float(c.x), __uint_as_float(c.y),
+                                                    __uint_as_float(c.z), rest, w_b);
+                o = on;
+                c = cn;
+              }
             }
           }
           for (int o = S >> 1; o > 0; o >>= 1) el += __shfl_xor(el, o, 64);
@@ -924,7 +950,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
                 if (q == lc) sl[q] += d;
             }
           owner_sum(sl);
-          double e0 = energy(X, false);
+          // g(x^k): computed at the first iteration; afterwards it is the energy of the trial
+          // the previous iteration accepted (the update forms the same positions and e)
+          const double e0 = k == 0 ? energy(X, false) : 0.0;
           double mine = 0.0;
 #pragma unroll
           for (int q = 0; q < kSkalakMaxGw; ++q)
@@ -932,7 +960,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           if (e_ok && e_s == 0) {
             ls_a[e_gc] = 1.0f;
             ls_done[e_gc] = 0;
-            ls_e0[e_gc] = e0;
+            if (k == 0) ls_e0[e_gc] = e0;
             ls_slope[e_gc] = mine;
           }
         }
@@ -945,17 +973,19 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
             if (ITEM_OK(it)) {
               const float a = ls_a[ITEM_C(it)];
 #pragma unroll
-              for (int c = 0; c < 3; ++c)
-                Gt[ITEM_W(it) + c] = X[ITEM_W(it) + c] + a * R[ITEM_W(it) + c];
+              for (int c = 0; c < 3; ++c)   // rounded as the update forms x + a d
+                Gt[ITEM_W(it) + c] = add_scaled(X[ITEM_W(it) + c], a, R[ITEM_W(it) + c]);
             }
           __builtin_amdgcn_wave_barrier();
           const double et = energy(Gt, true);
           if (e_ok && e_s == 0 && !ls_done[e_gc]) {
             const float a = ls_a[e_gc];
-            if (et <= ls_e0[e_gc] + kArmijoC * (double)a * ls_slope[e_gc])
+            if (et <= ls_e0[e_gc] + kArmijoC * (double)a * ls_slope[e_gc] || h == kMaxHalvings) {
               ls_done[e_gc] = 1;
-            else if (h < kMaxHalvings)
+              ls_enext[e_gc] = et;   // g(x^{k+1})
+            } else {
               ls_a[e_gc] = 0.5f * a;
+            }
           }
           __builtin_amdgcn_wave_barrier();
           int open = 0;
@@ -963,6 +993,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
             if (lc0 + q < count) open |= !ls_done[lc0 + q];
           if (!open) break;
         }
+        if (e_ok && e_s == 0) ls_e0[e_gc] = ls_enext[e_gc];
       }
       // ---- update: delta += D (registers), x^{k+1} = x^k + D (LDS); Skalak: a D
       refresh_items(item);
@@ -974,10 +1005,14 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const float a_ls = (SKALAK && sk) ? ls_a[ITEM_C(it)] : 1.0f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float dd = (SKALAK && sk) ? a_ls * Rv[c]
-                                            : (EXTRAS ? Rv[c] - ray_c * e[it][c] : Rv[c]);
-            e[it][c] += dd;
-            Xv[c] += dd;
+            if (SKALAK && sk) {
+              e[it][c] = add_scaled(e[it][c], a_ls, Rv[c]);
+              Xv[c] = add_scaled(Xv[c], a_ls, Rv[c]);
+            } else {
+              const float dd = EXTRAS ? Rv[c] - ray_c * e[it][c] : Rv[c];
+              e[it][c] += dd;
+              Xv[c] += dd;
+            }
             Rv[c] = 0.0f;   // R starts the next iteration at zero
           }
         }

@@ -4,10 +4,15 @@ Cell state lives on the device in a slot pool sized by an HBM budget (x, v, F: 3
 per vertex). A request asks for one time step of a session's cells; a session owns a
 contiguous range of red-cell slots and one of platelet slots and keeps its state resident
 between requests. The server loop admits arrived requests whenever their session is idle
-and, for a new session, slots are free; every tick advances the union of all admitted
-requests' cells with ONE fused launch (the library's active-cell work list), so requests
-that arrive while earlier ticks run join the next tick and share its launch. Up to two
-ticks are in flight on the stream; completion times come from events on that stream.
+and its cells have slots; every tick advances the union of all admitted requests' cells with
+ONE fused launch (the library's active-cell work list), so requests that arrive while
+earlier ticks run join the next tick and share its launch. Up to two ticks are in flight on
+the stream; completion times come from events on that stream.
+
+When a session needs slots that are taken, idle sessions (resident, no request in flight)
+are moved out to pinned host memory, least recently stepped first, and moved back when their
+next request is admitted: the copies (x and v, 24 bytes per vertex) run on the stream in
+order with the steps, so a session's results do not depend on whether it was moved.
 """
 from __future__ import annotations
 
@@ -65,7 +70,10 @@ class Session:
     plt: tuple = (0, 0)
     remaining: int = 10          # requests left before the session is freed
     busy: bool = False
-    initialised: bool = False
+    initialised: bool = False    # resident in slots
+    saved: object = None         # (x, v) pinned host copies while moved out
+    last_tick: int = -1          # last tick that stepped it (eviction order)
+    moved: int = 0               # times moved out to host memory
 
 
 @dataclass
@@ -155,10 +163,11 @@ class StepServer:
         self.finals: dict = {}           # sid -> (x, v) host copies at release / end of run
         self.resident = 0                # cells of the admitted sessions
         self.peak_resident = 0
+        self.evictions = 0               # sessions moved out to host memory
+        self.restores = 0                # ... and back
+        self.protect: set = set()        # sessions of the tick being built (never moved out)
 
-    def _admit(self, sess: Session) -> bool:
-        if sess.initialised:
-            return True
+    def _try_slots(self, sess: Session) -> bool:
         r = self.pool.alloc[RBC].alloc(sess.n_rbc)
         if r is None:
             return False
@@ -167,24 +176,80 @@ class StepServer:
             self.pool.alloc[RBC].release(r)
             return False
         sess.rbc, sess.plt = r, p
-        init_session_state(self.pool, sess, sess.sid)
+        return True
+
+    def _evict(self, sess: Session):
+        """Move an idle resident session's x and v to pinned host memory and free its slots."""
+        import torch
+        saved = []
+        for kind, rng in ((RBC, sess.rbc), (PLT, sess.plt)):
+            if rng[1]:
+                sl = self.pool.vertex_range(kind, rng)
+                hx = torch.empty((2, 3, sl.stop - sl.start), dtype=torch.float32, pin_memory=True)
+                hx[0].copy_(self.pool.x[:, sl], non_blocking=True)
+                hx[1].copy_(self.pool.v[:, sl], non_blocking=True)
+                saved.append(hx)
+            else:
+                saved.append(None)
+        sess.saved = saved
+        self.pool.alloc[RBC].release(sess.rbc)
+        self.pool.alloc[PLT].release(sess.plt)
+        sess.rbc = sess.plt = (0, 0)
+        sess.initialised = False
+        sess.moved += 1
+        self.resident -= sess.n_rbc + sess.n_plt
+        self.evictions += 1
+
+    def _admit(self, sess: Session) -> bool:
+        if sess.initialised:
+            return True
+        if not self._try_slots(sess):
+            # move idle sessions out, least recently stepped first, until the slots fit
+            idle = sorted((s for s in self.sessions.values()
+                           if s.initialised and not s.busy and s.sid not in self.protect),
+                          key=lambda s: s.last_tick)
+            for s in idle:
+                self._evict(s)
+                if self._try_slots(sess):
+                    break
+            else:
+                return False
+        if sess.saved is not None:   # back from host memory, in stream order
+            for (kind, rng), hx in zip(((RBC, sess.rbc), (PLT, sess.plt)), sess.saved):
+                if rng[1]:
+                    sl = self.pool.vertex_range(kind, rng)
+                    self.pool.x[:, sl].copy_(hx[0], non_blocking=True)
+                    self.pool.v[:, sl].copy_(hx[1], non_blocking=True)
+            sess.saved = None
+            self.restores += 1
+        else:
+            init_session_state(self.pool, sess, sess.sid)
         sess.initialised = True
         self.resident += sess.n_rbc + sess.n_plt
         self.peak_resident = max(self.peak_resident, self.resident)
         return True
 
     def _snapshot(self, sess: Session):
+        import torch
         xs, vs = [], []
-        for kind, rng in ((RBC, sess.rbc), (PLT, sess.plt)):
-            if rng[1]:
-                sl = self.pool.vertex_range(kind, rng)
-                xs.append(self.pool.x[:, sl].double().cpu().numpy())
-                vs.append(self.pool.v[:, sl].double().cpu().numpy())
+        if sess.saved is not None:   # moved out: the host copies (after their copies finish)
+            torch.cuda.current_stream().synchronize()
+            for hx in sess.saved:
+                if hx is not None:
+                    xs.append(hx[0].double().numpy())
+                    vs.append(hx[1].double().numpy())
+        else:
+            for kind, rng in ((RBC, sess.rbc), (PLT, sess.plt)):
+                if rng[1]:
+                    sl = self.pool.vertex_range(kind, rng)
+                    xs.append(self.pool.x[:, sl].double().cpu().numpy())
+                    vs.append(self.pool.v[:, sl].double().cpu().numpy())
         self.finals[sess.sid] = (np.concatenate(xs, axis=1), np.concatenate(vs, axis=1))
 
     def _release(self, sess: Session):
         if sess.sid in self.track:
             self._snapshot(sess)
+        sess.saved = None
         self.pool.alloc[RBC].release(sess.rbc)
         self.pool.alloc[PLT].release(sess.plt)
         sess.rbc = sess.plt = (0, 0)
@@ -271,10 +336,12 @@ class StepServer:
             batch_reqs = []
             if len(in_flight) < self.max_in_flight:
                 still = []
+                self.protect = set()
                 for rq in waiting:
                     s = self.sessions[rq.session]
                     if not s.busy and self._admit(s):
                         s.busy = True
+                        self.protect.add(s.sid)
                         batch_reqs.append(rq)
                     else:
                         if not s.busy:
@@ -304,6 +371,7 @@ class StepServer:
                 tk.n_cells = len(cells)
                 for rq in batch_reqs:
                     rq.tick = tk.index
+                    self.sessions[rq.session].last_tick = tk.index
                 ticks.append(tk)
                 in_flight.append(tk)
                 n_cells_stepped += len(cells)
@@ -315,14 +383,15 @@ class StepServer:
         total = time.perf_counter() - t0
         for sid in self.track:
             s = self.sessions[sid]
-            if s.initialised and sid not in self.finals:
+            if (s.initialised or s.saved is not None) and sid not in self.finals:
                 self._snapshot(s)
         for tk in ticks:
             busy_ms += tk.start.elapsed_time(tk.event)
         self.pool.batch.set_active(None)
         return {"ticks": ticks, "wall_s": total, "busy_ms": busy_ms,
                 "cells_stepped": n_cells_stepped, "admission_waits": len(waited),
-                "peak_cells_resident": self.peak_resident}
+                "peak_cells_resident": self.peak_resident, "evictions": self.evictions,
+                "restores": self.restores}
 
 
 def poisson_workload(duration_s: float, rate: float, seed: int, n_min=50, n_max=10_000,
