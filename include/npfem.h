@@ -297,9 +297,11 @@ npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double rad
  * of its 3 coordinate columns, L the cell type's constant system matrix (supplementary
  * material, npFEM subsection: the prefactored Hessian approximation H~ of the quasi-Newton
  * update x - H~ grad g, shared by every cell of a type). Two ways of applying it:
- *   NPFEM_SOLVE_DENSE   the dense precomputed L^-1 (FP64-derived, stored FP32) times the
- *                       right-hand sides of each group of same-type cells on the FP32 matrix
- *                       cores, as the fused step does; fused-form (FP32) batches only;
+ *   NPFEM_SOLVE_DENSE   the dense precomputed L^-1 (FP64-derived) times the right-hand sides
+ *                       of each group of same-type cells on the fp16 matrix cores with split
+ *                       operands (each FP32 value as a hi + lo pair of fp16 values, 22
+ *                       significant bits; FP32 accumulation), as the fused step does;
+ *                       fused-form (FP32) batches only;
  *   NPFEM_SOLVE_BANDED  forward and back substitution with the banded Cholesky factor
  *                       (FP64-computed, used in the batch precision), one lane per column;
  *                       either form and precision, band widths up to 65;

@@ -182,33 +182,54 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   chk(upload(&d->ring_nb16, ct->ring_nb16));
   if (ct->fused_ok) {
     chk(layout_schedules_locked(ct, dev, 0, &d->tri_sched, &d->hinge_sched));
-    // L^-1 in MFMA A-operand order: row tile rt, chunk c, step j, lane l -> (row rt*16 + l%16,
-    // k row kr). Chunk c covers the 32 k rows from 4 s0(c), s0(c) = min(c C, KR - C) (C =
-    // kMfmaChunk, KR = npad / 4 >= C), in the order that keeps the global step's LDS reads free
-    // of bank conflicts: lane group g = l/16 reads kr = 4 s0 + k_row_in_chunk(g, j). The last chunk
-    // ends at the last row and overlaps the one before it, so its rows below 4 c C are stored as
-    // zeros; the two chunks after the last one are zero too (the kernel's look-ahead loads read
-    // them).
+    // L^-1 as the split fp16 A operand of v_mfma_f32_16x16x32_f16: entries times 2^exp (exp
+    // puts the largest magnitude in [2^13, 2^14)) as hi = fp16(a) and lo = fp16(a - hi), so
+    // that hi + lo holds a to 22 significant bits (to 2^-25 absolute where lo is subnormal).
+    // Row tile rt, chunk c (32 k rows), lane l, element i -> (row rt*16 + l%16, k row kr =
+    // 4 s0 + k_row_in_chunk(l/16, i)), s0(c) = min(c C, KR - C) (C = kMfmaChunk, KR = npad / 4
+    // >= C): each lane group reads its B rows in the order that keeps the global step's LDS
+    // reads free of bank conflicts. A chunk is 512 words at word (rt KS + c C) 64: lane l's 8
+    // hi values in words 4l..4l+3 (element i in half i % 2 of word 4l + i/2), then the lo
+    // values in words 256 + 4l... The last chunk ends at the last row and overlaps the one
+    // before it, so its rows below 4 c C are stored as zeros; the two chunks after the last
+    // one are zero too (the kernel's look-ahead loads read them).
     const int RT = p.row_tiles, KS = p.k_steps, n = ct->n;
     const int KR = ct->npad / 4, C = kMfmaChunk, nch = (KR + C - 1) / C;
-    auto tiles = [&](const std::vector<double>& dense) {
-      std::vector<float> lt((size_t)RT * KS * 64, 0.0f);
+    auto tiles = [&](const std::vector<double>& dense, int32_t* exp_out) {
+      double amax = 0.0;
+      for (double a : dense) amax = std::max(amax, std::fabs(a));
+      int ex = 0;
+      if (amax > 0.0) std::frexp(amax, &ex);   // amax in [2^(ex-1), 2^ex)
+      const int sh = amax > 0.0 ? 14 - ex : 0;
+      *exp_out = sh;
+      std::vector<uint16_t> halves((size_t)RT * KS * 64 * 2, 0);
       for (int rt = 0; rt < RT; ++rt)
         for (int c = 0; c < nch; ++c) {
           const int s0 = std::min(c * C, KR - C);
-          for (int j = 0; j < C; ++j)
-            for (int l = 0; l < 64; ++l) {
-              const int row = rt * 16 + (l & 15), kr = 4 * s0 + k_row_in_chunk(l >> 4, j);
+          uint16_t* chunk = halves.data() + ((size_t)rt * KS + (size_t)c * C) * 128;
+          for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < C; ++i) {
+              const int row = rt * 16 + (l & 15), kr = 4 * s0 + k_row_in_chunk(l >> 4, i);
               if (kr < 4 * c * C) continue;   // covered by the previous chunk
-              if (row < n && kr < n)
-                lt[((size_t)rt * KS + c * C + j) * 64 + l] = (float)dense[(size_t)row * n + kr];
+              if (row >= n || kr >= n) continue;
+              const double a = std::ldexp(dense[(size_t)row * n + kr], sh);
+              const _Float16 hi = (_Float16)a;
+              const _Float16 lo = (_Float16)(a - (double)hi);
+              std::memcpy(&chunk[8 * l + i], &hi, 2);
+              std::memcpy(&chunk[512 + 8 * l + i], &lo, 2);
             }
         }
-      return lt;
+      return halves;
     };
-    chk(upload(&d->linv_tiles, tiles(ct->Linv)));
-    // Rayleigh damping with beta > 0: m M~^-1 in the same order, for the prediction
-    if (!ct->pinv.empty()) chk(upload(&d->pinv_tiles, tiles(ct->pinv)));
+    {
+      const std::vector<uint16_t> t = tiles(ct->Linv, &p.linv_exp);
+      chk(upload_raw(&d->linv_tiles, reinterpret_cast<const float*>(t.data()), t.size() / 2));
+    }
+    // Rayleigh damping with beta > 0: m M~^-1 in the same form, for the prediction
+    if (!ct->pinv.empty()) {
+      const std::vector<uint16_t> t = tiles(ct->pinv, &p.pinv_exp);
+      chk(upload_raw(&d->pinv_tiles, reinterpret_cast<const float*>(t.data()), t.size() / 2));
+    }
   }
   if (st != NPFEM_OK) {
     free_devtype(d);

@@ -16,10 +16,11 @@
 //                   and hinge adds its constraint residual; the schedule packs vertex-disjoint
 //                   elements into rounds, so one wave updates R without atomics or barriers
 //                   and the summation order is fixed (bitwise reproducible);
-//   global step     D = -L^-1 R for all 3 * cells columns of the group at once as an FP32
-//                   MFMA product (v_mfma_f32_16x16x4_f32), A = L^-1 tiles streamed from L2,
-//                   B = R from LDS, both double-buffered; the 4 waves split the output tiles
-//                   in pairs that share A;
+//   global step     D = -L^-1 R for all 3 * cells columns of the group at once as a product
+//                   on the fp16 matrix cores (v_mfma_f32_16x16x32_f16) with split operands
+//                   (hi + lo fp16 pairs, 22 significant bits, FP32 accumulation), A = L^-1
+//                   tiles streamed from L2, B = R from LDS (split in place), both
+//                   double-buffered; the 4 waves split the output tiles in pairs that share A;
 //   update          delta += D (quasi-Newton step of the fourth displayed equation).
 // Three workgroup barriers per iteration; everything else is wave-local.
 #include <hip/hip_runtime.h>
@@ -165,55 +166,84 @@ __device__ __forceinline__ int col_base(int col, int ncols, int CS) {
   return cell * CS + (col - 3 * cell);
 }
 
-// One k chunk of A fragments (kMfmaChunk k steps, 64 lane-ordered values each) from L2. A row
-// tile stores its chunks plus two zero chunks, so every chunk load below is in bounds.
-__device__ __forceinline__ void load_a(float (&a)[kMfmaChunk], gfloat* La, int c) {
-#pragma unroll
-  for (int j = 0; j < kMfmaChunk; ++j) a[j] = La[(c * kMfmaChunk + j) * 64];
+// The global step's product runs on the fp16 matrix cores with split operands: each FP32
+// value x (scaled by a power of two) is carried as hi = fp16(x) and lo = fp16(x - hi), and
+// A B = A_hi B_hi + A_hi B_lo + A_lo B_hi up to the dropped A_lo B_lo (2^-22 relative); the
+// products of fp16 values are exact in the FP32 accumulator. Per 32 k rows and output tile,
+// three v_mfma_f32_16x16x32_f16 issue in about 60 cycles (two accumulator chains; measured on
+// gfx950) where eight v_mfma_f32_16x16x4_f32 take 256.
+// Dynamic LDS of the fused kernels (cell blocks).
+extern __shared__ float lds[];
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef const __attribute__((address_space(1))) u4 gu4;
+
+// One k chunk (kMfmaChunk k steps = 32 k rows) of the split A operand from L2: the lane's 8 hi
+// and 8 lo values (La: the row tile's first chunk plus the lane, in 16-byte units). A row tile
+// stores its chunks plus two zero chunks, so every chunk load below is in bounds.
+struct AChunk {
+  u4 hi, lo;
+};
+__device__ __forceinline__ void load_a(AChunk& a, gu4* La, int c) {
+  a.hi = La[c * 128];
+  a.lo = La[c * 128 + 64];
 }
 
-// B values of chunk c: k row 4 s0 + k_row_in_chunk(lane / 16, j) of the lane's column at step
-// j, read at Rb[12 s0 + 6 j] (Rb includes the lane group's row offset). Chunks start at
-// s0 = min(c kMfmaChunk, KR - kMfmaChunk): the last chunk is shifted back to end at the last
-// row and overlaps its predecessor, whose rows hold zero A fragments in that chunk (as do the
-// zero chunks after it).
+// B words of chunk c: the lane's column at k rows 4 s0 + k_row_in_chunk(lane / 16, j), read
+// at Rb[12 s0 + 6 j] (Rb includes the lane group's row offset). Chunks start at s0 =
+// min(c kMfmaChunk, KR - kMfmaChunk): the last chunk is shifted back to end at the last row
+// and overlaps its predecessor, whose rows hold zero A values in that chunk (as do the zero
+// chunks after it). A lane's rows for j and j + 1 (j even) are rows r and r + 2 with r mod 4
+// in {0, 1}, whose words hold the two hi values and the two lo values (split_b): the even
+// words are the lane's 8 hi values, the odd words its 8 lo values, already in MFMA order.
 template <bool TWO>
-__device__ __forceinline__ void load_b(float (&b0)[kMfmaChunk], float (&b1)[kMfmaChunk],
-                                       const lfloat* RbA, const lfloat* RbB, int c, int KR) {
+__device__ __forceinline__ void load_b(u4 (&b0)[2], u4 (&b1)[2], const lfloat* RbA, const lfloat* RbB,
+                                       int c, int KR) {
   const int s0 = min(c * kMfmaChunk, KR - kMfmaChunk);
   const lfloat* pa = RbA + 12 * s0;
   const lfloat* pb = RbB + 12 * s0;
 #pragma unroll
   for (int j = 0; j < kMfmaChunk; ++j) {
-    b0[j] = pa[3 * k_row_in_chunk(0, j)];
-    if (TWO) b1[j] = pb[3 * k_row_in_chunk(0, j)];
+    b0[j & 1][j >> 1] = __float_as_uint(pa[3 * k_row_in_chunk(0, j)]);
+    if (TWO) b1[j & 1][j >> 1] = __float_as_uint(pb[3 * k_row_in_chunk(0, j)]);
   }
 }
 
+// acc0 (and acc1 with TWO) += A B over one chunk, the small terms first.
 template <bool TWO>
-__device__ __forceinline__ void mma_chunk(const float (&a)[kMfmaChunk], const float (&b0)[kMfmaChunk],
-                                          const float (&b1)[kMfmaChunk], f4& acc0, f4& acc1) {
-#pragma unroll
-  for (int j = 0; j < kMfmaChunk; ++j) {
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b0[j], acc0, 0, 0, 0);
-    if (TWO) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b1[j], acc1, 0, 0, 0);
+__device__ __forceinline__ void mma_chunk(const AChunk& a, const u4 (&b0)[2], const u4 (&b1)[2],
+                                          f4& acc0, f4& acc1) {
+  const h8 ah = __builtin_bit_cast(h8, a.hi), al = __builtin_bit_cast(h8, a.lo);
+  const h8 b0h = __builtin_bit_cast(h8, b0[0]), b0l = __builtin_bit_cast(h8, b0[1]);
+  if (TWO) {
+    const h8 b1h = __builtin_bit_cast(h8, b1[0]), b1l = __builtin_bit_cast(h8, b1[1]);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, b0h, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, b1h, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, b0l, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, b1l, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, b0h, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, b1h, acc1, 0, 0, 0);
+  } else {
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, b0h, acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, b0l, acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, b0h, acc0, 0, 0, 0);
   }
 }
 
-// D tiles of one L^-1 row tile: acc0 (and acc1 with TWO) += A x B over the chunks covering
-// the k steps s < KR (KR >= kMfmaChunk). Two register sets alternate: while one chunk's MFMAs run, the next
-// chunk's A fragments (from L2) and B values (from LDS) are in flight. The loads are the same
-// on every pass (the last pass fetches a zero chunk), so each chunk waits only for its own
-// operands.
+// D tiles of one A row tile: acc0 (and acc1 with TWO) += A x B over the chunks covering the k
+// steps s < KR (KR >= kMfmaChunk). Two register sets alternate: while one chunk's MFMAs run,
+// the next chunk's A values (from L2) and B words (from LDS) are in flight. The loads are the
+// same on every pass (the last pass fetches a zero chunk), so each chunk waits only for its
+// own operands.
 template <bool TWO>
-__device__ __forceinline__ void mfma_rows(gfloat* La, const lfloat* RbA, const lfloat* RbB,
-                                          int KR, f4& acc0, f4& acc1) {
+__device__ __forceinline__ void mfma_rows(gu4* La, const lfloat* RbA, const lfloat* RbB, int KR,
+                                          f4& acc0, f4& acc1) {
   const int nch = (KR + kMfmaChunk - 1) / kMfmaChunk;
   // raised wave priority while the matrix cores work: the CU's other workgroups are in their
   // VALU-bound element rounds, and issuing this wave's loads and MFMAs first keeps both busy
   __builtin_amdgcn_s_setprio(1);
-  float aP[kMfmaChunk], aQ[kMfmaChunk], bP0[kMfmaChunk], bP1[kMfmaChunk], bQ0[kMfmaChunk],
-      bQ1[kMfmaChunk];
+  AChunk aP, aQ;
+  u4 bP0[2], bP1[2], bQ0[2], bQ1[2];
   load_a(aP, La, 0);
   load_b<TWO>(bP0, bP1, RbA, RbB, 0, KR);
   int c = 0;
@@ -233,18 +263,63 @@ __device__ __forceinline__ void mfma_rows(gfloat* La, const lfloat* RbA, const l
   __builtin_amdgcn_s_setprio(0);
 }
 
-// D = -acc for output tile (rt, ct) into R: lane holds rows rt*16 + 4 (lane/16) + r of
-// column ct*16 + lane%16.
-__device__ __forceinline__ void write_tile(float* R, f4 acc, int rt, int ct, int lane, int n,
-                                           int ncols, int CS) {
+// D = -acc usc[cell] for output tile (rt, ct) into R (usc: the power of two that undoes the
+// operands' scaling): lane holds rows rt*16 + 4 (lane/16) + r of column ct*16 + lane%16.
+// R is the block at word r_off of the dynamic LDS (addressed from the array itself: a pointer
+// held across the iteration would be a 64-bit generic one).
+__device__ __forceinline__ void write_tile(int r_off, f4 acc, int rt, int ct, int lane, int n,
+                                           int ncols, int CS, const float* usc) {
   const int col = ct * 16 + (lane & 15);
   const int row0 = rt * 16 + 4 * (lane >> 4);
   if (col < ncols) {
     const int cell = col / 3;
-    float* Rw = R + cell * CS + (col - 3 * cell);
+    const float u = -usc[cell];
+    lfloat* Rl = (lfloat*)lds + r_off;
+    const int w = cell * CS + (col - 3 * cell) + 3 * row0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (row0 + r < n) Rw[3 * (row0 + r)] = -acc[r];
+      if (row0 + r < n) Rl[w + 3 * r] = acc[r] * u;
+  }
+}
+
+// The product's B operand in place: x = R 2^sc (sc per cell putting the cell's largest |R| in
+// [2^13, 2^14)) as hi = fp16(x) and lo = fp16(x - hi) (the difference is exact in FP32). Rows
+// r and r + 2 with r mod 4 in {0, 1} are paired: word (r, coord) holds their hi values (r in
+// the low half), word (r + 2, coord) their lo values, which is the order of the MFMA's B
+// operand (load_b). Rows n..npad-1 count as zero (their words are not read as values).
+// *usc = 2^-(sc + a_exp) undoes both operands' scaling. Lane mapping of the element phase:
+// cell block Rc, S lanes per cell from slot s (all cells of the wave at once).
+__device__ __forceinline__ void split_b(float* Rc, int n, int npad, int S, int s, bool ok, int a_exp,
+                                        float* usc) {
+  float m = 0.0f;
+  if (ok)
+    for (int vv = s; vv < n; vv += S) {
+      const Vec3<float> r = ld3(Rc + 3 * vv);
+      m = fmaxf(m, fmaxf(fabsf(r.x), fmaxf(fabsf(r.y), fabsf(r.z))));
+    }
+  for (int o = S >> 1; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  int ex = 0;
+  (void)frexpf(m, &ex);   // m in [2^(ex-1), 2^ex)
+  const int sc = m > 0.0f ? min(max(14 - ex, -100), 100) : 0;
+  const float f = ldexpf(1.0f, sc);
+  if (ok) {
+    for (int p = s; p < npad / 2; p += S) {
+      const int r = 4 * (p >> 1) + (p & 1);
+      float* w0 = Rc + 3 * r;
+      float* w1 = w0 + 6;   // row r + 2
+      const bool ok0 = r < n, ok1 = r + 2 < n;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float x0 = ok0 ? w0[c] * f : 0.0f, x1 = ok1 ? w1[c] * f : 0.0f;
+        const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
+        const _Float16 l0 = (_Float16)(x0 - (float)h0), l1 = (_Float16)(x1 - (float)h1);
+        w0[c] = __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                                ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16));
+        w1[c] = __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, l0) |
+                                ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16));
+      }
+    }
+    if (s == 0) *usc = ldexpf(1.0f, -(sc + a_exp));
   }
 }
 
@@ -258,9 +333,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
              float* __restrict__ x, float* __restrict__ v, const float* __restrict__ f,
              const float* __restrict__ cp, const float* __restrict__ cw, int K,
              double* __restrict__ vol_area, int* __restrict__ flag) {
-  extern __shared__ float lds[];
   __shared__ float lam_lds[kMaxGroupCells];
   __shared__ int64_t off_lds[kMaxGroupCells];
+  __shared__ float usc_lds[kMaxGroupCells];   // per cell: undoes the product's operand scaling
   // Skalak line search, per cell: step length, accepted flag, g(x^k) and grad g . d
   __shared__ float ls_a[SKALAK ? kMaxGroupCells : 1];
   __shared__ int ls_done[SKALAK ? kMaxGroupCells : 1];
@@ -450,7 +525,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
       int n_items = 0;
       {
-        const gfloat* Lt = gptr(tiles) + lane;
+        gu4* Lt = reinterpret_cast<gu4*>(gptr(tiles)) + lane;
         const int kq = lane >> 4;
         for (int u = u0; u < u1;) {
           f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
@@ -460,16 +535,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
             if (ct + 1 < CT && u + 1 < u1) {
               const lfloat* RbB =
                   (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-              mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
+              mfma_rows<true>(Lt + (size_t)rt * KS * 16, RbA, RbB, KR, d0, d1);
               u += 2;
             } else {
-              mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
+              mfma_rows<false>(Lt + (size_t)rt * KS * 16, RbA, RbA, KR, d0, d1);
               u += 1;
             }
           } else {
             const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-            mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
-            if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
+            mfma_rows<false>(Lt + (size_t)u * KS * 16, Rb, Rb, KR, d0, d1);
+            if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 16, Rb, Rb, KR, d1, d0);
             u += (u + 1 < u1) ? 2 : 1;
           }
           // keep the item's tiles at the end of the held set (indices stay compile-time)
@@ -489,16 +564,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           if (q >= kMaxTilesPerWave / 2 - n_items) {
             if (CT >= 2) {
               const int rt = u / CT, ct = u - rt * CT;
-              write_tile(R, acc[2 * q], rt, ct, lane, n, ncols, CS);
+              write_tile(kFusedRWords, acc[2 * q], rt, ct, lane, n, ncols, CS, usc_lds);
               if (ct + 1 < CT && u + 1 < u1) {
-                write_tile(R, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS);
+                write_tile(kFusedRWords, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS, usc_lds);
                 u += 2;
               } else {
                 u += 1;
               }
             } else {
-              write_tile(R, acc[2 * q], u, 0, lane, n, ncols, CS);
-              if (u + 1 < u1) write_tile(R, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS);
+              write_tile(kFusedRWords, acc[2 * q], u, 0, lane, n, ncols, CS, usc_lds);
+              if (u + 1 < u1) write_tile(kFusedRWords, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS, usc_lds);
               u += (u + 1 < u1) ? 2 : 1;
             }
           }
@@ -507,6 +582,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     };
 
     if (ray) {   // delta^0 = m M~^-1 (h v + h^2 F/m): R holds its negated right-hand side
+      split_b(Re, n, npad, S, e_s, e_ok, T.p.pinv_exp, &usc_lds[e_gc]);
+      __syncthreads();
       global_product(T.pinv_tiles);
       __syncthreads();
       refresh_items(item);
@@ -739,7 +816,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #pragma unroll
             for (int c = 0; c < 3; ++c) Gt[ITEM_W(it) + c] = R[ITEM_W(it) + c];
           }
+        __builtin_amdgcn_wave_barrier();
       }
+      split_b(Re, n, npad, S, e_s, e_ok, T.p.linv_exp, &usc_lds[e_gc]);
       __syncthreads();
       // ---- global step: D = -L^-1 R on the matrix cores (the product of global_product,
       //      written out here: through the lambda the loop spills one more register)
@@ -748,7 +827,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
       for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
       int n_items = 0;
       {
-        const gfloat* Lt = gptr(T.linv_tiles) + lane;
+        gu4* Lt = reinterpret_cast<gu4*>(gptr(T.linv_tiles)) + lane;
         const int kq = lane >> 4;
         for (int u = u0; u < u1;) {
           f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
@@ -758,16 +837,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
             if (ct + 1 < CT && u + 1 < u1) {
               const lfloat* RbB =
                   (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-              mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
+              mfma_rows<true>(Lt + (size_t)rt * KS * 16, RbA, RbB, KR, d0, d1);
               u += 2;
             } else {
-              mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
+              mfma_rows<false>(Lt + (size_t)rt * KS * 16, RbA, RbA, KR, d0, d1);
               u += 1;
             }
           } else {
             const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-            mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
-            if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
+            mfma_rows<false>(Lt + (size_t)u * KS * 16, Rb, Rb, KR, d0, d1);
+            if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 16, Rb, Rb, KR, d1, d0);
             u += (u + 1 < u1) ? 2 : 1;
           }
           // keep the item's tiles at the end of the held set (indices stay compile-time)
@@ -787,16 +866,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           if (q >= kMaxTilesPerWave / 2 - n_items) {
             if (CT >= 2) {
               const int rt = u / CT, ct = u - rt * CT;
-              write_tile(R, acc[2 * q], rt, ct, lane, n, ncols, CS);
+              write_tile(kFusedRWords, acc[2 * q], rt, ct, lane, n, ncols, CS, usc_lds);
               if (ct + 1 < CT && u + 1 < u1) {
-                write_tile(R, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS);
+                write_tile(kFusedRWords, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS, usc_lds);
                 u += 2;
               } else {
                 u += 1;
               }
             } else {
-              write_tile(R, acc[2 * q], u, 0, lane, n, ncols, CS);
-              if (u + 1 < u1) write_tile(R, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS);
+              write_tile(kFusedRWords, acc[2 * q], u, 0, lane, n, ncols, CS, usc_lds);
+              if (u + 1 < u1) write_tile(kFusedRWords, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS, usc_lds);
               u += (u + 1 < u1) ? 2 : 1;
             }
           }
@@ -1104,8 +1183,8 @@ __global__ void __launch_bounds__(kFusedThreads)
 k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
                const int* __restrict__ n_groups_dev, const int64_t* __restrict__ offsets,
                int64_t vt, const float* r, float* out) {
-  extern __shared__ float lds[];
   __shared__ int64_t off_lds[kMaxGroupCells];
+  __shared__ float usc_lds[kMaxGroupCells];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n_groups = *n_groups_dev;
   for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
@@ -1124,6 +1203,13 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
       R[cell * CS + 3 * v + c] = v < n ? -r[c * vt + off_lds[cell] + v] : 0.0f;
     }
     __syncthreads();
+    {
+      // split fp16 B operand, per cell over the lanes of its wave (as in the fused step)
+      const int gw = T.p.gw, S = T.p.slots;
+      const int e_cw = lane / S, e_s = lane - e_cw * S, e_gc = wave * gw + e_cw;
+      split_b(R + e_gc * CS, n, npad, S, e_s, e_gc < count, T.p.linv_exp, &usc_lds[e_gc]);
+    }
+    __syncthreads();
     const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
     const int ncols = 3 * count, CT = (ncols + 15) / 16;
     const int n_units = RT * CT;
@@ -1133,7 +1219,7 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
     for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
     int n_items = 0;
     {
-      const gfloat* Lt = gptr(T.linv_tiles) + lane;
+      gu4* Lt = reinterpret_cast<gu4*>(gptr(T.linv_tiles)) + lane;
       const int kq = lane >> 4;
       for (int u = u0; u < u1;) {
         f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
@@ -1143,16 +1229,16 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
           if (ct + 1 < CT && u + 1 < u1) {
             const lfloat* RbB =
                 (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-            mfma_rows<true>(Lt + (size_t)rt * KS * 64, RbA, RbB, KR, d0, d1);
+            mfma_rows<true>(Lt + (size_t)rt * KS * 16, RbA, RbB, KR, d0, d1);
             u += 2;
           } else {
-            mfma_rows<false>(Lt + (size_t)rt * KS * 64, RbA, RbA, KR, d0, d1);
+            mfma_rows<false>(Lt + (size_t)rt * KS * 16, RbA, RbA, KR, d0, d1);
             u += 1;
           }
         } else {
           const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-          mfma_rows<false>(Lt + (size_t)u * KS * 64, Rb, Rb, KR, d0, d1);
-          if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 64, Rb, Rb, KR, d1, d0);
+          mfma_rows<false>(Lt + (size_t)u * KS * 16, Rb, Rb, KR, d0, d1);
+          if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 16, Rb, Rb, KR, d1, d0);
           u += (u + 1 < u1) ? 2 : 1;
         }
         // keep the item's tiles at the end of the held set (indices stay compile-time)
@@ -1172,16 +1258,16 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
         if (q >= kMaxTilesPerWave / 2 - n_items) {
           if (CT >= 2) {
             const int rt = u / CT, ct = u - rt * CT;
-            write_tile(R, acc[2 * q], rt, ct, lane, n, ncols, CS);
+            write_tile(0, acc[2 * q], rt, ct, lane, n, ncols, CS, usc_lds);
             if (ct + 1 < CT && u + 1 < u1) {
-              write_tile(R, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS);
+              write_tile(0, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS, usc_lds);
               u += 2;
             } else {
               u += 1;
             }
           } else {
-            write_tile(R, acc[2 * q], u, 0, lane, n, ncols, CS);
-            if (u + 1 < u1) write_tile(R, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS);
+            write_tile(0, acc[2 * q], u, 0, lane, n, ncols, CS, usc_lds);
+            if (u + 1 < u1) write_tile(0, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS, usc_lds);
             u += (u + 1 < u1) ? 2 : 1;
           }
         }

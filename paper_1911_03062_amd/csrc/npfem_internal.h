@@ -68,6 +68,8 @@ struct TypeParams {
   int32_t skalak;               // membrane: 0 = PD constraints, 1 = Skalak energy
   int32_t band_w;               // window of the standalone banded substitution: the smallest
                                 // 8 k + 1 >= bw (0: bw > 64, unsupported)
+  int32_t linv_exp, pinv_exp;   // the fused global step's A tiles hold L^-1 (m M~^-1) times
+                                // 2^exp
   double h, mass, inv_h2m;      // h, m, m / h^2
   double h2_over_m;             // h^2 / m
   double w_s, w_a, w_b, w_v;
@@ -94,8 +96,9 @@ struct DevType {
   // fused form
   TriRec* tri_sched = nullptr;       // [tri_rounds][slots]
   HingeRec* hinge_sched = nullptr;   // [hinge_rounds][slots]
-  float* linv_tiles = nullptr;       // [row_tiles][k_steps][64] MFMA A-operand order
-  float* pinv_tiles = nullptr;       // m M~^-1 in the same order (Rayleigh beta > 0)
+  float* linv_tiles = nullptr;       // [row_tiles][k_steps / kMfmaChunk][512 words]: split
+                                     // fp16 MFMA A operand of L^-1 2^linv_exp
+  float* pinv_tiles = nullptr;       // m M~^-1 2^pinv_exp in the same form (Rayleigh beta > 0)
   // plain form (both precisions)
   int32_t* tri = nullptr;            // [m][3]
   int32_t* hinge = nullptr;          // [e][4]
