@@ -425,10 +425,8 @@ npfem_status relayout(npfem_batch* b) {
     if (st != NPFEM_OK) return st;
     HIP_TRY(hipMemcpy(b->d_types + ti, &v, sizeof(DevType), hipMemcpyHostToDevice));
     const int cap = kFusedWaves * t->layouts[b->layout_of[ti]].gw;
-    // X blocks below kFusedRWords, R blocks from there (for a Skalak type followed by its
-    // grad g / trial blocks), then the damping words
-    const int blocks = t->membrane == NPFEM_MEMBRANE_SKALAK ? 2 : 1;
-    const size_t per_cell = (blocks * (size_t)t->cs + (t->kappa > 0.0 ? kDampWords : 0)) * sizeof(float);
+    // X blocks below kFusedRWords, R blocks from there, then the damping words
+    const size_t per_cell = ((size_t)t->cs + (t->kappa > 0.0 ? kDampWords : 0)) * sizeof(float);
     b->lds_bytes = std::max(b->lds_bytes, kFusedRWords * sizeof(float) + (size_t)cap * per_cell);
   }
   std::vector<FusedGroup> groups;

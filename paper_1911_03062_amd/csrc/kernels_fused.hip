@@ -264,21 +264,44 @@ __device__ __forceinline__ void mfma_rows(gu4* La, const lfloat* RbA, const lflo
 }
 
 // D = -acc usc[cell] for output tile (rt, ct) into R (usc: the power of two that undoes the
-// operands' scaling): lane holds rows rt*16 + 4 (lane/16) + r of column ct*16 + lane%16.
-// R is the block at word r_off of the dynamic LDS (addressed from the array itself: a pointer
-// held across the iteration would be a 64-bit generic one).
+// operands' scaling): lane holds rows rt*16 + 4 (lane/16) + r of column ct*16 + lane%16. R is
+// the block at word r_off of the dynamic LDS (addressed from the array itself: a pointer held
+// across the iteration would be a 64-bit generic one). With SL and slp (the Skalak line
+// search), grad g . D of the tile's columns is added to slp[col] first: grad g is R's split
+// B operand at these rows (a lane's rows row0..row0+3 hold the pairs (row0, row0 + 2) and
+// (row0 + 1, row0 + 3) in their four words), times 2^-sc = usc 2^a_exp; the four lane
+// groups of a column are summed in a fixed order, so the sums are reproducible.
+template <bool SL = false>
 __device__ __forceinline__ void write_tile(int r_off, f4 acc, int rt, int ct, int lane, int n,
-                                           int ncols, int CS, const float* usc) {
+                                           int ncols, int CS, const float* usc,
+                                           double* slp = nullptr, int a_exp = 0) {
   const int col = ct * 16 + (lane & 15);
   const int row0 = rt * 16 + 4 * (lane >> 4);
+  double part = 0.0;
   if (col < ncols) {
     const int cell = col / 3;
     const float u = -usc[cell];
     lfloat* Rl = (lfloat*)lds + r_off;
     const int w = cell * CS + (col - 3 * cell) + 3 * row0;
+    if (SL && slp != nullptr && row0 < n) {
+      const uint32_t w0 = __float_as_uint(Rl[w]), w1 = __float_as_uint(Rl[w + 3]);
+      const uint32_t w2 = __float_as_uint(Rl[w + 6]), w3 = __float_as_uint(Rl[w + 9]);
+      auto hf = [](uint32_t bits) { return (float)__builtin_bit_cast(_Float16, (uint16_t)bits); };
+      const float gs = ldexpf(usc[cell], a_exp);
+      const float g[4] = {(hf(w0) + hf(w2)) * gs, (hf(w1) + hf(w3)) * gs,
+                          (hf(w0 >> 16) + hf(w2 >> 16)) * gs, (hf(w1 >> 16) + hf(w3 >> 16)) * gs};
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < n) part += (double)g[r] * (double)(acc[r] * u);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       if (row0 + r < n) Rl[w + 3 * r] = acc[r] * u;
+  }
+  if (SL && slp != nullptr) {
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (lane < 16 && col < ncols) slp[col] += part;
   }
 }
 
@@ -337,10 +360,12 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
   __shared__ int64_t off_lds[kMaxGroupCells];
   __shared__ float usc_lds[kMaxGroupCells];   // per cell: undoes the product's operand scaling
   // Skalak line search, per cell: step length, accepted flag, g(x^k) and grad g . d
-  __shared__ float ls_a[SKALAK ? kMaxGroupCells : 1];
-  __shared__ int ls_done[SKALAK ? kMaxGroupCells : 1];
-  __shared__ double ls_e0[SKALAK ? kMaxGroupCells : 1], ls_slope[SKALAK ? kMaxGroupCells : 1];
-  __shared__ double ls_enext[SKALAK ? kMaxGroupCells : 1];
+  __shared__ float ls_a[SKALAK ? kSkalakMaxCells : 1];
+  __shared__ int ls_done[SKALAK ? kSkalakMaxCells : 1];
+  __shared__ double ls_e0[SKALAK ? kSkalakMaxCells : 1], ls_slope[SKALAK ? kSkalakMaxCells : 1];
+  __shared__ double ls_enext[SKALAK ? kSkalakMaxCells : 1];
+  // grad g . d per wave and MFMA column (3 cell + coord), summed in the product's write-back
+  __shared__ double sl_part[SKALAK ? kFusedWaves : 1][SKALAK ? 3 * kSkalakMaxCells : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   const int n_groups = *n_groups_dev;
@@ -398,11 +423,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
     // subtracts ray_c e (both the plain values for other types)
     const float gmass = EXTRAS ? (float)T.p.grad_mass : ih2m;
     const float ray_c = (float)T.p.ray_c;
-    // Skalak types: a third block per cell after R holds grad g (for grad g . d), then the
-    // line search's trial positions
+    // Skalak types: the line search's slope grad g . d comes from the product's write-back
+    // (grad g is R's split words there), its trial positions x + a d from X and R = d
     const bool sk = SKALAK && T.p.skalak;
-    float* Gt = R + G4 * CS;
-    float* Dm = (SKALAK && sk) ? Gt + G4 * CS : R + G4 * CS;
+    float* Dm = R + G4 * CS;
     float e[NQ][3];
 #pragma unroll
     for (int it = 0; it < NQ; ++it) {
@@ -808,16 +832,6 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           }
         }
       }
-      if (SKALAK && sk) {   // keep grad g for grad g . d (each owner copies its vertices)
-        refresh_items(item);
-#pragma unroll
-        for (int it = 0; it < NQ; ++it)
-          if (ITEM_OK(it)) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Gt[ITEM_W(it) + c] = R[ITEM_W(it) + c];
-          }
-        __builtin_amdgcn_wave_barrier();
-      }
       split_b(Re, n, npad, S, e_s, e_ok, T.p.linv_exp, &usc_lds[e_gc]);
       __syncthreads();
       // ---- global step: D = -L^-1 R on the matrix cores (the product of global_product,
@@ -858,6 +872,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         }
       }
       __syncthreads();
+      // Skalak: this wave's grad g . d sums per column, filled by the write-back below
+      double* slp = (SKALAK && sk) ? sl_part[wave] : nullptr;
+      if (SKALAK && sk && lane < 3 * kSkalakMaxCells) sl_part[wave][lane] = 0.0;
       {
         // replay the item sequence to place the held tiles
         int u = u0;
@@ -866,16 +883,19 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           if (q >= kMaxTilesPerWave / 2 - n_items) {
             if (CT >= 2) {
               const int rt = u / CT, ct = u - rt * CT;
-              write_tile(kFusedRWords, acc[2 * q], rt, ct, lane, n, ncols, CS, usc_lds);
+              write_tile<SKALAK>(kFusedRWords, acc[2 * q], rt, ct, lane, n, ncols, CS, usc_lds, slp, T.p.linv_exp);
               if (ct + 1 < CT && u + 1 < u1) {
-                write_tile(kFusedRWords, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS, usc_lds);
+                write_tile<SKALAK>(kFusedRWords, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS, usc_lds, slp,
+                                   T.p.linv_exp);
                 u += 2;
               } else {
                 u += 1;
               }
             } else {
-              write_tile(kFusedRWords, acc[2 * q], u, 0, lane, n, ncols, CS, usc_lds);
-              if (u + 1 < u1) write_tile(kFusedRWords, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS, usc_lds);
+              write_tile<SKALAK>(kFusedRWords, acc[2 * q], u, 0, lane, n, ncols, CS, usc_lds, slp, T.p.linv_exp);
+              if (u + 1 < u1)
+                write_tile<SKALAK>(kFusedRWords, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS, usc_lds, slp,
+                                   T.p.linv_exp);
               u += (u + 1 < u1) ? 2 : 1;
             }
           }
@@ -893,9 +913,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           for (int q = 0; q < kSkalakMaxGw; ++q)
             for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
         };
-        // g at positions P (cell-local, [cell][vertex][xyz] blocks like X) with delta - delta^0
-        // = e + a D (a = 0 at x^k); returns the total of the lane's element cell
-        auto energy = [&](const float* P, bool trial) -> double {
+        // g at x^k (trial false) or at the trial positions x + a d formed from X and R = d as
+        // the update forms them (add_scaled), with delta - delta^0 = e + a d; returns the total
+        // of the lane's element cell
+        auto pos = [&](const float* xp, float a, bool trial) -> Vec3<float> {
+          const Vec3<float> p = ld3(xp);
+          if (!trial) return p;
+          const Vec3<float> d = ld3(xp + kFusedRWords);
+          return v3<float>(add_scaled(p.x, a, d.x), add_scaled(p.y, a, d.y), add_scaled(p.z, a, d.z));
+        };
+        auto energy = [&](bool trial) -> double {
           double g2[kSkalakMaxGw], vx[kSkalakMaxGw], em[kSkalakMaxGw], ec[kSkalakMaxGw];
 #pragma unroll
           for (int q = 0; q < kSkalakMaxGw; ++q) g2[q] = vx[q] = em[q] = ec[q] = 0.0;
@@ -904,8 +931,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           for (int it = 0; it < NQ; ++it)
             if (ITEM_OK(it)) {
               const int lc = ITEM_C(it) - lc0, vi = ITEM_V(it);
-              const float* Pc = P + ITEM_C(it) * CS;
-              const Vec3<float> pi = ld3(Pc + 3 * vi);
+              const float* Pc = X + ITEM_C(it) * CS;
+              const float a = trial ? ls_a[ITEM_C(it)] : 0.0f;
+              const Vec3<float> pi = pos(Pc + 3 * vi, a, trial);
               // 6 grad_i V = sum over the triangles (i, b, c) around i of (p_b - p_i) x (p_c - p_i)
               const uint32_t info = T.ring_info[vi];
               const int roff = (int)(info >> 8), deg = (int)(info & 255u);
@@ -913,11 +941,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               Vec3<double> gi = v3<double>(0.0, 0.0, 0.0);
               for (int q = 0; q < deg; ++q) {
                 const uint32_t pr = T.ring_pairs[roff + q];
-                const Vec3<double> pb = to_d(ld3(Pc + 3 * (int)(pr & 0xffffu))) - dpi;
-                const Vec3<double> pc = to_d(ld3(Pc + 3 * (int)(pr >> 16))) - dpi;
+                const Vec3<double> pb = to_d(pos(Pc + 3 * (int)(pr & 0xffffu), a, trial)) - dpi;
+                const Vec3<double> pc = to_d(pos(Pc + 3 * (int)(pr >> 16), a, trial)) - dpi;
                 gi = gi + cross3(pb, pc);
               }
-              const float a = trial ? ls_a[ITEM_C(it)] : 0.0f;
               const float* Dv = R + ITEM_W(it);
               double g2i = dot3(gi, gi), vxi = dot3(dpi, gi), emi = 0.0, eci = 0.0;
 #pragma unroll
@@ -955,7 +982,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           // round's record loaded one round ahead
           double el = 0.0;
           if (e_ok) {
-            const float* Pe = P + e_gc * CS;
+            const float* Pe = X + e_gc * CS;
+            const float ae = trial ? ls_a[e_gc] : 0.0f;
             {
               const int NR = T.p.tri_rounds;
               u3 o = load_tri_offs(tri_rs, 0, S, e_soff);
@@ -966,8 +994,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
                 const u4 cn = load_rec_hi(tri_rs, rn, S, e_soff);
                 const float area = __uint_as_float(c.x);
                 if (area > 0.0f)
-                  el += (double)skalak_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
-                                                     ld3(vat(Pe, o.z)), __uint_as_float(c.y),
+                  el += (double)skalak_energy<float>(pos(vat(Pe, o.x), ae, trial), pos(vat(Pe, o.y), ae, trial),
+                                                     pos(vat(Pe, o.z), ae, trial), __uint_as_float(c.y),
                                                      __uint_as_float(c.z), 0.0f,
                                                      __uint_as_float(c.w), area, w_s, w_a);
                 o = on;
@@ -984,8 +1012,8 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
                 const u4 cn = load_rec_hi(hinge_rs, rn, S, e_soff);
                 const float rest = __uint_as_float(c.w);
                 if (rest >= 0.0f)
-                  el += (double)hinge_energy<float>(ld3(vat(Pe, o.x)), ld3(vat(Pe, o.y)),
-                                                    ld3(vat(Pe, o.z)), ld3(vat(Pe, o.w)),
+                  el += (double)hinge_energy<float>(pos(vat(Pe, o.x), ae, trial), pos(vat(Pe, o.y), ae, trial),
+                                                    pos(vat(Pe, o.z), ae, trial), pos(vat(Pe, o.w), ae, trial),
                                                     __uint_as_float(c.x), __uint_as_float(c.y),
                                                     __uint_as_float(c.z), rest, w_b);
                 o = on;
@@ -1010,53 +1038,25 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const double ev = gv2 > 0.0 ? 0.5 * T.p.w_v * (T.p.V0 - V) * (T.p.V0 - V) / gv2 : 0.0;
           return el + 0.5 * T.p.inv_h2m * EM + ev + EC;
         };
-        // grad g . d per cell from the owner items (grad g in Gt, d in R)
         {
-          double sl[kSkalakMaxGw];
-#pragma unroll
-          for (int q = 0; q < kSkalakMaxGw; ++q) sl[q] = 0.0;
-          refresh_items(item);
-#pragma unroll
-          for (int it = 0; it < NQ; ++it)
-            if (ITEM_OK(it)) {
-              const int lc = ITEM_C(it) - lc0;
-              double d = 0.0;
-#pragma unroll
-              for (int c = 0; c < 3; ++c)
-                d += (double)Gt[ITEM_W(it) + c] * (double)R[ITEM_W(it) + c];
-#pragma unroll
-              for (int q = 0; q < kSkalakMaxGw; ++q)
-                if (q == lc) sl[q] += d;
-            }
-          owner_sum(sl);
           // g(x^k): computed at the first iteration; afterwards it is the energy of the trial
           // the previous iteration accepted (the update forms the same positions and e)
-          const double e0 = k == 0 ? energy(X, false) : 0.0;
-          double mine = 0.0;
-#pragma unroll
-          for (int q = 0; q < kSkalakMaxGw; ++q)
-            if (q == e_cw) mine = sl[q];
+          const double e0 = k == 0 ? energy(false) : 0.0;
           if (e_ok && e_s == 0) {
+            // grad g . d of the cell: the waves' column sums in a fixed order
+            double sl = 0.0;
+            for (int w = 0; w < kFusedWaves; ++w)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) sl += sl_part[w][3 * e_gc + c];
             ls_a[e_gc] = 1.0f;
             ls_done[e_gc] = 0;
             if (k == 0) ls_e0[e_gc] = e0;
-            ls_slope[e_gc] = mine;
+            ls_slope[e_gc] = sl;
           }
         }
         __builtin_amdgcn_wave_barrier();
         for (int h = 0; h <= kMaxHalvings; ++h) {
-          // trial positions x + a d of the wave's cells (over grad g, no longer needed)
-          refresh_items(item);
-#pragma unroll
-          for (int it = 0; it < NQ; ++it)
-            if (ITEM_OK(it)) {
-              const float a = ls_a[ITEM_C(it)];
-#pragma unroll
-              for (int c = 0; c < 3; ++c)   // rounded as the update forms x + a d
-                Gt[ITEM_W(it) + c] = add_scaled(X[ITEM_W(it) + c], a, R[ITEM_W(it) + c]);
-            }
-          __builtin_amdgcn_wave_barrier();
-          const double et = energy(Gt, true);
+          const double et = energy(true);
           if (e_ok && e_s == 0 && !ls_done[e_gc]) {
             const float a = ls_a[e_gc];
             if (et <= ls_e0[e_gc] + kArmijoC * (double)a * ls_slope[e_gc] || h == kMaxHalvings) {

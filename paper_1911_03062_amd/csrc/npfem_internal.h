@@ -200,6 +200,7 @@ constexpr int kMfmaChunk = 8;               // k steps per prefetched L^-1 chunk
 constexpr double kArmijoC = 1e-4;           // Skalak line search: sufficient decrease
 constexpr int kMaxHalvings = 8;             //   and step lengths 1, 1/2, ..., 1/256
 constexpr int kSkalakMaxGw = 2;             // fused Skalak types: at most 2 cells per wave
+constexpr int kSkalakMaxCells = kFusedWaves * kSkalakMaxGw;   // and per group
 constexpr int kDampWords = 12;              // LDS floats per cell for position-based damping
 constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
 

@@ -602,11 +602,10 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
   const int npad = std::max((n + 3) / 4 * 4, 4 * kMfmaChunk);
   ct->npad = npad;
   ct->cs = 3 * npad + (((3 - 3 * npad) % 16) + 16) % 16;
-  // X blocks in the first half of the LDS budget; R blocks (plus, for the Skalak membrane, the
-  // blocks of grad g / trial positions of its line search), plus the per-cell damping data
+  // X blocks in the first half of the LDS budget; R blocks, plus the per-cell damping data
   // when the type is damped, in the second (FP32)
   const bool skalak = ct->membrane == NPFEM_MEMBRANE_SKALAK;
-  const int per_cell = (skalak ? 2 : 1) * ct->cs * 4 + (ct->kappa > 0.0 ? kDampWords * 4 : 0);
+  const int per_cell = ct->cs * 4 + (ct->kappa > 0.0 ? kDampWords * 4 : 0);
   std::vector<int> feasible;
   for (int cand : {16, 8, 4, 2, 1}) {
     if (kFusedWaves * cand * per_cell > 4 * kFusedRWords) continue;

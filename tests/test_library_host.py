@@ -114,11 +114,12 @@ def test_rayleigh_system_matrix_matches_oracle(alpha, beta):
 
 
 def test_skalak_membrane_layouts_and_rayleigh_beta_excluded():
-    """The fused form's Skalak types keep a third LDS block per cell (grad g, trial positions)
-    in the residual half, which leaves one red cell or two platelets per wave."""
+    """The fused form's Skalak types use the PD types' LDS layout (the line search forms its
+    trial positions from X and R and its slope in the global step's write-back); the line
+    search's per-cell state caps them at two cells per wave."""
     x, t, m = I.cell_type_inputs()[I.RBC]
     ct = N.CellType(x, t, m.with_membrane("skalak"), I.DT)
-    assert ct.cells_per_wave() == [1]
+    assert ct.cells_per_wave() == [2, 1]
     xp, tp, mp = I.cell_type_inputs()[I.PLT]
     assert N.CellType(xp, tp, mp.with_membrane("skalak"), I.DT).cells_per_wave() == [2, 1]
     oc = O.CellType(x, t, m.with_membrane("skalak"), I.DT)
