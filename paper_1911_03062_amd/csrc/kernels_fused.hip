@@ -363,7 +363,6 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
   __shared__ float ls_a[SKALAK ? kSkalakMaxCells : 1];
   __shared__ int ls_done[SKALAK ? kSkalakMaxCells : 1];
   __shared__ double ls_e0[SKALAK ? kSkalakMaxCells : 1], ls_slope[SKALAK ? kSkalakMaxCells : 1];
-  __shared__ double ls_enext[SKALAK ? kSkalakMaxCells : 1];
   // grad g . d per wave and MFMA column (3 cell + coord), summed in the product's write-back
   __shared__ double sl_part[SKALAK ? kFusedWaves : 1][SKALAK ? 3 * kSkalakMaxCells : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -913,14 +912,16 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           for (int q = 0; q < kSkalakMaxGw; ++q)
             for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
         };
-        // g at x^k (trial false) or at the trial positions x + a d formed from X and R = d as
-        // the update forms them (add_scaled), with delta - delta^0 = e + a d; returns the total
-        // of the lane's element cell
-        auto pos = [&](const float* xp, float a, bool trial) -> Vec3<float> {
-          const Vec3<float> p = ld3(xp);
+        // g at x^k (trial false) or at x^k + a d, everything in FP64: the positions x + a d
+        // from X and R = d (exact in FP64 up to its rounding: a is a power of two), delta -
+        // delta^0 = e + a d, the element energies. Near convergence a d falls below the FP32
+        // spacing of x, and a test on FP32 trial positions (which then equal x^k) could never
+        // show the decrease it asks for; in FP64 the test resolves it as the paper's
+        // formulation does. Returns the total of the lane's element cell.
+        auto pos = [&](const float* xp, float a, bool trial) -> Vec3<double> {
+          const Vec3<double> p = to_d(ld3(xp));
           if (!trial) return p;
-          const Vec3<float> d = ld3(xp + kFusedRWords);
-          return v3<float>(add_scaled(p.x, a, d.x), add_scaled(p.y, a, d.y), add_scaled(p.z, a, d.z));
+          return p + to_d(ld3(xp + kFusedRWords)) * (double)a;
         };
         auto energy = [&](bool trial) -> double {
           double g2[kSkalakMaxGw], vx[kSkalakMaxGw], em[kSkalakMaxGw], ec[kSkalakMaxGw];
@@ -933,35 +934,33 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               const int lc = ITEM_C(it) - lc0, vi = ITEM_V(it);
               const float* Pc = X + ITEM_C(it) * CS;
               const float a = trial ? ls_a[ITEM_C(it)] : 0.0f;
-              const Vec3<float> pi = pos(Pc + 3 * vi, a, trial);
+              const Vec3<double> dpi = pos(Pc + 3 * vi, a, trial);
               // 6 grad_i V = sum over the triangles (i, b, c) around i of (p_b - p_i) x (p_c - p_i)
               const uint32_t info = T.ring_info[vi];
               const int roff = (int)(info >> 8), deg = (int)(info & 255u);
-              const Vec3<double> dpi = to_d(pi);
               Vec3<double> gi = v3<double>(0.0, 0.0, 0.0);
               for (int q = 0; q < deg; ++q) {
                 const uint32_t pr = T.ring_pairs[roff + q];
-                const Vec3<double> pb = to_d(pos(Pc + 3 * (int)(pr & 0xffffu), a, trial)) - dpi;
-                const Vec3<double> pc = to_d(pos(Pc + 3 * (int)(pr >> 16), a, trial)) - dpi;
+                const Vec3<double> pb = pos(Pc + 3 * (int)(pr & 0xffffu), a, trial) - dpi;
+                const Vec3<double> pc = pos(Pc + 3 * (int)(pr >> 16), a, trial) - dpi;
                 gi = gi + cross3(pb, pc);
               }
               const float* Dv = R + ITEM_W(it);
               double g2i = dot3(gi, gi), vxi = dot3(dpi, gi), emi = 0.0, eci = 0.0;
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                // e + a d rounded as the update forms it (a d, then the sum)
-                const float el = trial ? add_scaled(e[it][c], a, Dv[c]) : e[it][c];
-                emi += (double)el * (double)el;
+                const double el = trial ? (double)e[it][c] + (double)a * (double)Dv[c] : (double)e[it][c];
+                emi += el * el;
               }
               if (EXTRAS && cw != nullptr) {
                 const int64_t off = off_lds[ITEM_C(it)];
                 const float wc = cw[off + vi];
                 if (wc != 0.0f) {
-                  const float pic[3] = {pi.x, pi.y, pi.z};
+                  const double pic[3] = {dpi.x, dpi.y, dpi.z};
 #pragma unroll
                   for (int c = 0; c < 3; ++c) {
-                    const float gd = (x[c * vt + off] - cp[c * vt + off + vi]) + pic[c];
-                    eci += 0.5 * (double)wc * (double)gd * (double)gd;
+                    const double gd = ((double)x[c * vt + off] - (double)cp[c * vt + off + vi]) + pic[c];
+                    eci += 0.5 * (double)wc * gd * gd;
                   }
                 }
               }
@@ -994,10 +993,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
                 const u4 cn = load_rec_hi(tri_rs, rn, S, e_soff);
                 const float area = __uint_as_float(c.x);
                 if (area > 0.0f)
-                  el += (double)skalak_energy<float>(pos(vat(Pe, o.x), ae, trial), pos(vat(Pe, o.y), ae, trial),
-                                                     pos(vat(Pe, o.z), ae, trial), __uint_as_float(c.y),
-                                                     __uint_as_float(c.z), 0.0f,
-                                                     __uint_as_float(c.w), area, w_s, w_a);
+                  el += skalak_energy<double>(pos(vat(Pe, o.x), ae, trial), pos(vat(Pe, o.y), ae, trial),
+                                              pos(vat(Pe, o.z), ae, trial), (double)__uint_as_float(c.y),
+                                              (double)__uint_as_float(c.z), 0.0,
+                                              (double)__uint_as_float(c.w), (double)area, T.p.w_s, T.p.w_a);
                 o = on;
                 c = cn;
               }
@@ -1012,10 +1011,10 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
                 const u4 cn = load_rec_hi(hinge_rs, rn, S, e_soff);
                 const float rest = __uint_as_float(c.w);
                 if (rest >= 0.0f)
-                  el += (double)hinge_energy<float>(pos(vat(Pe, o.x), ae, trial), pos(vat(Pe, o.y), ae, trial),
-                                                    pos(vat(Pe, o.z), ae, trial), pos(vat(Pe, o.w), ae, trial),
-                                                    __uint_as_float(c.x), __uint_as_float(c.y),
-                                                    __uint_as_float(c.z), rest, w_b);
+                  el += hinge_energy<double>(pos(vat(Pe, o.x), ae, trial), pos(vat(Pe, o.y), ae, trial),
+                                             pos(vat(Pe, o.z), ae, trial), pos(vat(Pe, o.w), ae, trial),
+                                             (double)__uint_as_float(c.x), (double)__uint_as_float(c.y),
+                                             (double)__uint_as_float(c.z), (double)rest, T.p.w_b);
                 o = on;
                 c = cn;
               }
@@ -1039,9 +1038,9 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           return el + 0.5 * T.p.inv_h2m * EM + ev + EC;
         };
         {
-          // g(x^k): computed at the first iteration; afterwards it is the energy of the trial
-          // the previous iteration accepted (the update forms the same positions and e)
-          const double e0 = k == 0 ? energy(false) : 0.0;
+          // g(x^k) at the stored (FP32) iterate: the accepted trial's FP64 positions were
+          // rounded by the update
+          const double e0 = energy(false);
           if (e_ok && e_s == 0) {
             // grad g . d of the cell: the waves' column sums in a fixed order
             double sl = 0.0;
@@ -1050,7 +1049,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               for (int c = 0; c < 3; ++c) sl += sl_part[w][3 * e_gc + c];
             ls_a[e_gc] = 1.0f;
             ls_done[e_gc] = 0;
-            if (k == 0) ls_e0[e_gc] = e0;
+            ls_e0[e_gc] = e0;
             ls_slope[e_gc] = sl;
           }
         }
@@ -1061,7 +1060,6 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
             const float a = ls_a[e_gc];
             if (et <= ls_e0[e_gc] + kArmijoC * (double)a * ls_slope[e_gc] || h == kMaxHalvings) {
               ls_done[e_gc] = 1;
-              ls_enext[e_gc] = et;   // g(x^{k+1})
             } else {
               ls_a[e_gc] = 0.5f * a;
             }
@@ -1072,7 +1070,6 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
             if (lc0 + q < count) open |= !ls_done[lc0 + q];
           if (!open) break;
         }
-        if (e_ok && e_s == 0) ls_e0[e_gc] = ls_enext[e_gc];
       }
       // ---- update: delta += D (registers), x^{k+1} = x^k + D (LDS); Skalak: a D
       refresh_items(item);
