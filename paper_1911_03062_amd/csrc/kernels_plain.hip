@@ -351,7 +351,7 @@ void launch_plain_solve(const DevType* dt_dev, const TypeParams& p, void* work, 
 // a (positions x_n + delta + a dir): Skalak energies of the triangles, bending energies of the
 // hinges (projections at that point), the volume energy (w_v/2)(V0 - V)^2/|grad V|^2, the
 // inertia term (1 + h alpha)(m/2h^2)|delta + a dir - delta^0|^2 and the contact energies,
-// summed in FP64. The first a of 1, 1/2, ..., 2^-kMaxHalvings with
+// all in FP64. The first a of 1, 1/2, ..., 2^-kMaxHalvings with
 // g(a) <= g(0) + kArmijoC a grad g . dir is taken (the last one when none qualifies).
 template <typename T>
 __global__ void __launch_bounds__(kPlainThreads)
@@ -370,47 +370,54 @@ k_plain_linesearch(const DevType* __restrict__ dtp, const T* __restrict__ x, int
   for (int i = threadIdx.x; i < n; i += blockDim.x)
     for (int c = 0; c < 3; ++c) sl += (double)w.r[c * n + i] * (double)w.dir[c * n + i];
   const double slope = block_sum(sl, sh);
+  // positions x + a dir of the trial, cell-local, in FP64 from the stored values (exact up to
+  // FP64 rounding: a is a power of two): near convergence a dir falls below the spacing of x
+  // in FP32, and FP32 trial positions would equal x^k so that no halving could show the
+  // decrease the test asks for
   auto pos = [&](int i, T a) {
-    return v3<T>((x[off + i] - x[off]) + (w.d[i] + a * w.dir[i]),
-                 (x[vt + off + i] - x[vt + off]) + (w.d[n + i] + a * w.dir[n + i]),
-                 (x[2 * vt + off + i] - x[2 * vt + off]) + (w.d[2 * n + i] + a * w.dir[2 * n + i]));
+    const double ad = (double)a;
+    return v3<double>(((double)x[off + i] - (double)x[off]) + ((double)w.d[i] + ad * (double)w.dir[i]),
+                      ((double)x[vt + off + i] - (double)x[vt + off]) +
+                          ((double)w.d[n + i] + ad * (double)w.dir[n + i]),
+                      ((double)x[2 * vt + off + i] - (double)x[2 * vt + off]) +
+                          ((double)w.d[2 * n + i] + ad * (double)w.dir[2 * n + i]));
   };
+  // g at step length a, every term in FP64
   auto energy = [&](T a) {
+    const double ad = (double)a;
     double ee = 0;
-    for (int t = threadIdx.x; t < m; t += blockDim.x) {
-      const Vec3<T> pa = pos(dt.tri[3 * t], a), pb = pos(dt.tri[3 * t + 1], a);
-      const Vec3<T> pc = pos(dt.tri[3 * t + 2], a);
-      Vec3<T> ra = v3<T>(0, 0, 0), rb = ra, rc = ra;
-      ee += (double)skalak_residual<T>(pa, pb, pc, G[6 * t + 2], G[6 * t + 3], G[6 * t + 4],
-                                       G[6 * t + 5], A[t], T(p.w_s), T(p.w_a), ra, rb, rc);
-      const Vec3<T> nt = cross3(pb - pa, pc - pa);
-      w.tn[3 * t] = nt.x; w.tn[3 * t + 1] = nt.y; w.tn[3 * t + 2] = nt.z;
-    }
+    for (int t = threadIdx.x; t < m; t += blockDim.x)
+      ee += skalak_energy<double>(pos(dt.tri[3 * t], a), pos(dt.tri[3 * t + 1], a), pos(dt.tri[3 * t + 2], a),
+                                  (double)G[6 * t + 2], (double)G[6 * t + 3], (double)G[6 * t + 4],
+                                  (double)G[6 * t + 5], (double)A[t], p.w_s, p.w_a);
     for (int h = threadIdx.x; h < e; h += blockDim.x) {
       const int* hv = dt.hinge + 4 * h;
-      ee += (double)hinge_energy<T>(pos(hv[0], a), pos(hv[1], a), pos(hv[2], a), pos(hv[3], a),
-                                    coef[4 * h + 1], coef[4 * h + 2], coef[4 * h + 3], rest[h],
-                                    T(p.w_b));
+      ee += hinge_energy<double>(pos(hv[0], a), pos(hv[1], a), pos(hv[2], a), pos(hv[3], a),
+                                 (double)coef[4 * h + 1], (double)coef[4 * h + 2], (double)coef[4 * h + 3],
+                                 (double)rest[h], p.w_b);
     }
-    __syncthreads();
     double vp = 0, gp = 0, em = 0, ec = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      T gx = 0, gy = 0, gz = 0;
+      // grad_i V = 1/6 sum of the doubled area vectors of the triangles around i
+      Vec3<double> g = v3<double>(0.0, 0.0, 0.0);
       for (int s = dt.vt_off[i]; s < dt.vt_off[i + 1]; ++s) {
         const int t = dt.vt_list[s] / 3;
-        gx += w.tn[3 * t]; gy += w.tn[3 * t + 1]; gz += w.tn[3 * t + 2];
+        const Vec3<double> pa = pos(dt.tri[3 * t], a), pb = pos(dt.tri[3 * t + 1], a);
+        const Vec3<double> pc = pos(dt.tri[3 * t + 2], a);
+        g = g + cross3(pb - pa, pc - pa);
       }
-      gx *= T(1.0 / 6.0); gy *= T(1.0 / 6.0); gz *= T(1.0 / 6.0);
-      const Vec3<T> pi = pos(i, a);
-      vp += (double)pi.x * (double)gx + (double)pi.y * (double)gy + (double)pi.z * (double)gz;
-      gp += (double)gx * (double)gx + (double)gy * (double)gy + (double)gz * (double)gz;
+      g = g * (1.0 / 6.0);
+      const Vec3<double> pi = pos(i, a);
+      vp += dot3(pi, g);
+      gp += dot3(g, g);
       const T wc = cw != nullptr ? cw[off + i] : T(0);
       for (int c = 0; c < 3; ++c) {
-        const T dl = (w.d[c * n + i] + a * w.dir[c * n + i]) - w.d0[c * n + i];
-        em += (double)dl * (double)dl;
+        const double dd = (double)w.d[c * n + i] + ad * (double)w.dir[c * n + i];
+        const double dl = dd - (double)w.d0[c * n + i];
+        em += dl * dl;
         if (wc != T(0)) {
-          const T g = (x[c * vt + off + i] - cp[c * vt + off + i]) + (w.d[c * n + i] + a * w.dir[c * n + i]);
-          ec += 0.5 * (double)wc * (double)g * (double)g;
+          const double gd = ((double)x[c * vt + off + i] - (double)cp[c * vt + off + i]) + dd;
+          ec += 0.5 * (double)wc * gd * gd;
         }
       }
     }
@@ -419,7 +426,6 @@ k_plain_linesearch(const DevType* __restrict__ dtp, const T* __restrict__ x, int
     const double E_m = 0.5 * p.inv_h2m * block_sum(em, sh);
     const double E_c = block_sum(ec, sh);
     const double E_v = G2 > 0 ? 0.5 * p.w_v * (p.V0 - V) * (p.V0 - V) / G2 : 0.0;
-    __syncthreads();   // w.tn is rewritten by the next evaluation
     return E_el + E_m + E_v + E_c;
   };
   const double e0 = energy(T(0));
