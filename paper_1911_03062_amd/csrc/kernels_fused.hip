@@ -936,14 +936,23 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               const float a = trial ? ls_a[ITEM_C(it)] : 0.0f;
               const Vec3<double> dpi = pos(Pc + 3 * vi, a, trial);
               // 6 grad_i V = sum over the triangles (i, b, c) around i of (p_b - p_i) x (p_c - p_i)
+              // = sum of p_b x p_c: the remainder (sum of p_c - p_b) x p_i vanishes on a closed
+              // star, where every neighbour is once a b and once a c. The ring is stored in
+              // cyclic order (c of one pair is b of the next), so the walk reads each neighbour
+              // once and loads b only where a star has several cycles.
               const uint32_t info = T.ring_info[vi];
               const int roff = (int)(info >> 8), deg = (int)(info & 255u);
               Vec3<double> gi = v3<double>(0.0, 0.0, 0.0);
+              uint32_t prev_c = 0xffffffffu;
+              Vec3<double> pprev = v3<double>(0.0, 0.0, 0.0);
               for (int q = 0; q < deg; ++q) {
                 const uint32_t pr = T.ring_pairs[roff + q];
-                const Vec3<double> pb = pos(Pc + 3 * (int)(pr & 0xffffu), a, trial) - dpi;
-                const Vec3<double> pc = pos(Pc + 3 * (int)(pr >> 16), a, trial) - dpi;
+                const uint32_t b = pr & 0xffffu, c = pr >> 16;
+                const Vec3<double> pb = b == prev_c ? pprev : pos(Pc + 3 * (int)b, a, trial);
+                const Vec3<double> pc = pos(Pc + 3 * (int)c, a, trial);
                 gi = gi + cross3(pb, pc);
+                prev_c = c;
+                pprev = pc;
               }
               const float* Dv = R + ITEM_W(it);
               double g2i = dot3(gi, gi), vxi = dot3(dpi, gi), emi = 0.0, eci = 0.0;

@@ -573,6 +573,21 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     }
   }
   if (max_deg > 255) return fail(NPFEM_E_UNSUPPORTED, "vertex degree above 255");
+  // each ring in cyclic order where the triangles chain (pair q + 1 starts where pair q ends,
+  // c_q = b_{q+1}: the consecutive triangles around i share an edge), so that a walk around
+  // the ring reads each neighbour once; a star of several cycles keeps them one after another
+  for (int i = 0; i < n; ++i) {
+    uint32_t* r = &ct->ring_pairs[ct->vt_off[i]];
+    const int deg = ct->vt_off[i + 1] - ct->vt_off[i];
+    for (int q = 0; q + 1 < deg; ++q) {
+      const uint32_t c = r[q] >> 16;
+      for (int u = q + 1; u < deg; ++u)
+        if ((r[u] & 0xffffu) == c) {
+          std::swap(r[q + 1], r[u]);
+          break;
+        }
+    }
+  }
   for (int i = 0; i < n; ++i)
     ct->ring_info[i] = ((uint32_t)ct->vt_off[i] << 8) | (uint32_t)(ct->vt_off[i + 1] - ct->vt_off[i]);
   // median-filter neighbour tables: the second vertex of each ring triangle (i, b, c) is every
