@@ -177,7 +177,11 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   }
   // vertex rings: the fused form's volume gradient and the median filter (both forms)
   chk(upload(&d->ring_info, ct->ring_info));
-  chk(upload(&d->ring_pairs, ct->ring_pairs));
+  {
+    std::vector<uint32_t> padded(ct->ring_pairs);
+    padded.resize(padded.size() + kRingBatch, 0u);   // batched ring loads read past the last ring
+    chk(upload(&d->ring_pairs, padded));
+  }
   chk(upload(&d->ring_nb8, ct->ring_nb8));
   chk(upload(&d->ring_nb16, ct->ring_nb16));
   if (ct->fused_ok) {

@@ -940,19 +940,27 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               // star, where every neighbour is once a b and once a c. The ring is stored in
               // cyclic order (c of one pair is b of the next), so the walk reads each neighbour
               // once and loads b only where a star has several cycles.
+              // The ring words come in batches of kRingBatch independent loads (the array is
+              // padded by kRingBatch words, so a batch past the last ring stays in bounds).
               const uint32_t info = T.ring_info[vi];
               const int roff = (int)(info >> 8), deg = (int)(info & 255u);
               Vec3<double> gi = v3<double>(0.0, 0.0, 0.0);
               uint32_t prev_c = 0xffffffffu;
               Vec3<double> pprev = v3<double>(0.0, 0.0, 0.0);
-              for (int q = 0; q < deg; ++q) {
-                const uint32_t pr = T.ring_pairs[roff + q];
-                const uint32_t b = pr & 0xffffu, c = pr >> 16;
-                const Vec3<double> pb = b == prev_c ? pprev : pos(Pc + 3 * (int)b, a, trial);
-                const Vec3<double> pc = pos(Pc + 3 * (int)c, a, trial);
-                gi = gi + cross3(pb, pc);
-                prev_c = c;
-                pprev = pc;
+              for (int q0 = 0; q0 < deg; q0 += kRingBatch) {
+                uint32_t prs[kRingBatch];
+#pragma unroll
+                for (int j = 0; j < kRingBatch; ++j) prs[j] = T.ring_pairs[roff + q0 + j];
+#pragma unroll
+                for (int j = 0; j < kRingBatch; ++j)
+                  if (q0 + j < deg) {
+                    const uint32_t b = prs[j] & 0xffffu, c = prs[j] >> 16;
+                    const Vec3<double> pb = b == prev_c ? pprev : pos(Pc + 3 * (int)b, a, trial);
+                    const Vec3<double> pc = pos(Pc + 3 * (int)c, a, trial);
+                    gi = gi + cross3(pb, pc);
+                    prev_c = c;
+                    pprev = pc;
+                  }
               }
               const float* Dv = R + ITEM_W(it);
               double g2i = dot3(gi, gi), vxi = dot3(dpi, gi), emi = 0.0, eci = 0.0;

@@ -90,7 +90,7 @@ struct DevType {
   TypeParams p;
   // vertex rings (fused form and median filter): the triangles (i, b, c) around each vertex i
   uint32_t* ring_info = nullptr;     // [n]: offset << 8 | degree
-  uint32_t* ring_pairs = nullptr;    // [sum deg]: b | c << 16
+  uint32_t* ring_pairs = nullptr;    // [sum deg + kRingBatch]: b | c << 16 (then zero padding)
   uint16_t* ring_nb8 = nullptr;      // [n][8]: median-filter neighbour table, 8 keys
   uint16_t* ring_nb16 = nullptr;     // [n][16]: the same for 16 keys
   // fused form
@@ -202,6 +202,7 @@ constexpr int kMaxHalvings = 8;             //   and step lengths 1, 1/2, ..., 1
 constexpr int kSkalakMaxGw = 2;             // fused Skalak types: at most 2 cells per wave
 constexpr int kSkalakMaxCells = kFusedWaves * kSkalakMaxGw;   // and per group
 constexpr int kDampWords = 12;              // LDS floats per cell for position-based damping
+constexpr int kRingBatch = 8;               // ring words loaded together (device copy padded by as many)
 constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
 
 // MFMA output tiles of the global step: each wave takes an equal share of the
