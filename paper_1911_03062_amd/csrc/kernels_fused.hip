@@ -1004,6 +1004,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               const int NR = T.p.tri_rounds;
               u3 o = load_tri_offs(tri_rs, 0, S, e_soff);
               u4 c = load_rec_hi(tri_rs, 0, S, e_soff);
+#pragma unroll 2
               for (int r = 0; r < NR; ++r) {
                 const int rn = min(r + 1, NR - 1);
                 const u3 on = load_tri_offs(tri_rs, rn, S, e_soff);
@@ -1022,6 +1023,7 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
               const int NR = T.p.hinge_rounds;
               u4 o = load_hinge_offs(hinge_rs, 0, S, e_soff);
               u4 c = load_rec_hi(hinge_rs, 0, S, e_soff);
+#pragma unroll 2
               for (int r = 0; r < NR; ++r) {
                 const int rn = min(r + 1, NR - 1);
                 const u4 on = load_hinge_offs(hinge_rs, rn, S, e_soff);
