@@ -465,8 +465,9 @@ def main():
 
     if want("global"):
         # the global step alone over every cell (3 right-hand sides each): the dense L^-1 product
-        # on the matrix cores against the banded Cholesky substitution, on seeded N(0, 1)
-        # right-hand sides; sampled cells checked against the oracle's FP64 solve
+        # on the matrix cores, the dense L^-1 on the vector ALU and the banded Cholesky
+        # substitution, on seeded N(0, 1) right-hand sides; sampled cells checked against the
+        # oracle's FP64 solve
         import oracle as O
         g = torch.Generator(device="cuda").manual_seed(21)
         grhs = torch.randn((3, b.v_total), generator=g, device="cuda", dtype=torch.float32)
@@ -500,7 +501,7 @@ def main():
                 mfma_flop += 3 * 2 * (16 * rt) * (32 * nch) * (16 * ct_cols)
         band_flop = sum(3 * 4 * nnz[int(t)] for t in b.types)
         gres = {}
-        for solve in ("dense", "banded"):
+        for solve in ("dense", "banded", "gemv"):
             batch.global_solve(grhs, gout, solve=solve)
             torch.cuda.synchronize()
             xg = gout.double().cpu().numpy()
@@ -518,7 +519,7 @@ def main():
             ge1.record(stream)
             torch.cuda.synchronize()
             us = ge0.elapsed_time(ge1) / g_reps * 1e3
-            flop = dense_flop if solve == "dense" else band_flop
+            flop = band_flop if solve == "banded" else dense_flop
             gres[solve] = {"avg_launch_us": us, "algorithmic_flop": flop,
                            "achieved_TFLOPs": flop / (us * 1e-6) / 1e12,
                            "max_rel_err_vs_oracle": err}
@@ -532,6 +533,9 @@ def main():
         gres["banded"].update({"kernel": "k_global_banded", "bound": "alu", "peak": PEAK_FP32_VECTOR_TFLOPS,
                                "frac": gres["banded"]["achieved_TFLOPs"] / PEAK_FP32_VECTOR_TFLOPS,
                                "flop_note": "4 nnz(C) per column (forward and back substitution)"})
+        gres["gemv"].update({"kernel": "k_global_gemv", "bound": "alu", "peak": PEAK_FP32_VECTOR_TFLOPS,
+                             "frac": gres["gemv"]["achieved_TFLOPs"] / PEAK_FP32_VECTOR_TFLOPS,
+                             "flop_note": "2 n^2 per column (dense L^-1 times one right-hand side, FP32 FMAs)"})
         out["global_step"] = {
             "config": f"every cell of {w.name}: {3 * n_rbc} RBC columns against the 258 x 258 "
                       f"inverse, {3 * n_plt} platelet columns against the 66 x 66 one; FP32, "
@@ -543,7 +547,7 @@ def main():
             "autotune_choice": batch.global_solve_choice(),
         }
         log(f"global step: dense {gres['dense']['avg_launch_us']:.1f} us, banded "
-            f"{gres['banded']['avg_launch_us']:.1f} us")
+            f"{gres['banded']['avg_launch_us']:.1f} us, gemv {gres['gemv']['avg_launch_us']:.1f} us")
         del grhs, gout
 
     if want("visco"):

@@ -213,9 +213,9 @@ npfem_status npfem_batch_set_cells_per_wave(npfem_batch* batch, const npfem_cell
 /* Time every feasible layout of every type of the batch (warm-up step, then `reps` steps of
  * n_pd_iters iterations on `stream`, with only that type's cells active, on library-allocated
  * scratch state: each cell at its rest shape under small pseudo-random forces) and keep the
- * fastest per cell. Then, with those layouts, time the two variants of the global step alone
- * (npfem_global_solve, `reps` calls each over the whole batch) and keep the faster for
- * NPFEM_SOLVE_AUTO. The fused step itself always applies L^-1 as the dense product on the
+ * fastest per cell. Then, with those layouts, time the variants of the global step alone the
+ * batch supports (npfem_global_solve, `reps` calls each over the whole batch) and keep the
+ * fastest for NPFEM_SOLVE_AUTO. The fused step itself always applies L^-1 as the dense product on the
  * matrix cores. Synchronises the device; the caller's state buffers are not touched. The
  * all-cells list is current afterwards. Errors: NPFEM_E_INVALID (n_pd_iters or reps < 1),
  * NPFEM_E_UNSUPPORTED (plain form), NPFEM_E_NOMEM, NPFEM_E_HIP. */
@@ -296,7 +296,7 @@ npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double rad
  * The global step alone: out[:, cell] = L^-1 rhs[:, cell] for every cell of the batch and each
  * of its 3 coordinate columns, L the cell type's constant system matrix (supplementary
  * material, npFEM subsection: the prefactored Hessian approximation H~ of the quasi-Newton
- * update x - H~ grad g, shared by every cell of a type). Two ways of applying it:
+ * update x - H~ grad g, shared by every cell of a type). Three ways of applying it:
  *   NPFEM_SOLVE_DENSE   the dense precomputed L^-1 (FP64-derived) times the right-hand sides
  *                       of each group of same-type cells on the fp16 matrix cores with split
  *                       operands (each FP32 value as a hi + lo pair of fp16 values, 22
@@ -305,17 +305,22 @@ npfem_status npfem_detect_contacts(npfem_batch* batch, const void* x, double rad
  *   NPFEM_SOLVE_BANDED  forward and back substitution with the banded Cholesky factor
  *                       (FP64-computed, used in the batch precision), one lane per column;
  *                       either form and precision, band widths up to 65;
- *   NPFEM_SOLVE_AUTO    the faster of the two as npfem_batch_autotune last timed them on this
- *                       batch (before any autotune: dense for fused, banded for plain batches).
+ *   NPFEM_SOLVE_GEMV    the dense L^-1 (FP64-derived, in the batch precision) times each
+ *                       cell's right-hand sides on the vector ALU, a few cells per
+ *                       workgroup; either form and precision, meshes whose staged
+ *                       right-hand sides fit 64 KiB of LDS (n <= 1365 in FP32, 682 in FP64);
+ *   NPFEM_SOLVE_AUTO    the fastest variant the batch supports as npfem_batch_autotune last
+ *                       timed them on this batch (before any autotune: dense for fused,
+ *                       banded for plain batches).
  *   rhs, out  device, [3][V_total] in the batch precision (may be the same buffer);
  * every cell takes part, whatever npfem_batch_set_active selected. Asynchronous on `stream`.
  * Errors: NPFEM_E_INVALID (null batch or buffer, unknown variant), NPFEM_E_UNSUPPORTED (dense on
- * a plain-form batch; a band wider than 65), NPFEM_E_HIP.
+ * a plain-form batch; a band wider than 65; GEMV staging above 64 KiB), NPFEM_E_HIP.
  */
-enum { NPFEM_SOLVE_DENSE = 0, NPFEM_SOLVE_BANDED = 1, NPFEM_SOLVE_AUTO = 2 };
+enum { NPFEM_SOLVE_DENSE = 0, NPFEM_SOLVE_BANDED = 1, NPFEM_SOLVE_AUTO = 2, NPFEM_SOLVE_GEMV = 3 };
 npfem_status npfem_global_solve(npfem_batch* batch, int32_t solve, const void* rhs, void* out,
                                 void* stream);
-/* The variant NPFEM_SOLVE_AUTO uses for `batch` (NPFEM_SOLVE_DENSE or NPFEM_SOLVE_BANDED) into
+/* The variant NPFEM_SOLVE_AUTO uses for `batch` (NPFEM_SOLVE_DENSE, _BANDED or _GEMV) into
  * *solve. Errors: NPFEM_E_INVALID (null argument). */
 npfem_status npfem_batch_get_global_solve(const npfem_batch* batch, int32_t* solve);
 

@@ -62,7 +62,8 @@ void free_devtype(DevType* d) {
                   d->vh_list,   d->G64,         d->G32,       d->A64,        d->A32,
                   d->coef64,    d->coef32,      d->rest64,    d->rest32,     d->cband64,
                   d->cband32,   d->mband64,     d->mband32,   d->kband64,    d->kband32,
-                  d->sband_rows64, d->sband_rows32, d->sband_cols64, d->sband_cols32};
+                  d->sband_rows64, d->sband_rows32, d->sband_cols64, d->sband_cols32,
+                  d->linv64,    d->linv32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete d;
@@ -175,6 +176,8 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
     chk(upload(&d->mband64, ct->mband)); chk(upload(&d->mband32, ct->mband));
     chk(upload(&d->kband64, ct->kband)); chk(upload(&d->kband32, ct->kband));
   }
+  // dense L^-1 for the standalone global step's vector form (both precisions)
+  chk(upload(&d->linv64, ct->Linv)); chk(upload(&d->linv32, ct->Linv));
   // vertex rings: the fused form's volume gradient and the median filter (both forms)
   chk(upload(&d->ring_info, ct->ring_info));
   {
@@ -980,19 +983,32 @@ npfem_status npfem_batch_autotune(npfem_batch* b, int32_t n_pd_iters, int32_t re
   // the global step alone (npfem_global_solve with NPFEM_SOLVE_AUTO): time both variants on
   // the whole batch with the chosen layouts, the scratch forces as right-hand sides
   if (st == NPFEM_OK && st2 == NPFEM_OK) {
-    float t_solve[2] = {0.0f, 0.0f};
-    for (int variant = NPFEM_SOLVE_DENSE; variant <= NPFEM_SOLVE_BANDED && st == NPFEM_OK; ++variant) {
-      st = npfem_global_solve(b, variant, f, v, stream);   // warm-up
+    // every variant the batch supports (the matrix-core form needs a fused batch, the banded
+    // one band widths up to 65); the fastest becomes NPFEM_SOLVE_AUTO's
+    int best = -1;
+    float best_ms = 0.0f;
+    for (int variant : {NPFEM_SOLVE_DENSE, NPFEM_SOLVE_BANDED, NPFEM_SOLVE_GEMV}) {
+      if (st != NPFEM_OK) break;
+      if (variant == NPFEM_SOLVE_DENSE && b->form != NPFEM_FORM_FUSED) continue;
+      npfem_status sv = npfem_global_solve(b, variant, f, v, stream);   // warm-up
+      if (sv == NPFEM_E_UNSUPPORTED) {
+        g_last_error.clear();
+        continue;
+      }
+      st = sv;
+      float ms = 0.0f;
       if (st == NPFEM_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(NPFEM_E_HIP, "event");
       for (int r = 0; r < reps && st == NPFEM_OK; ++r) st = npfem_global_solve(b, variant, f, v, stream);
       if (st == NPFEM_OK && (hipEventRecord(e1, s) != hipSuccess ||
                              hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&t_solve[variant], e0, e1) != hipSuccess))
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
         st = fail(NPFEM_E_HIP, "autotune timing");
+      if (st == NPFEM_OK && (best < 0 || ms < best_ms)) {
+        best = variant;
+        best_ms = ms;
+      }
     }
-    if (st == NPFEM_OK)
-      b->solve_choice = t_solve[NPFEM_SOLVE_BANDED] < t_solve[NPFEM_SOLVE_DENSE] ? NPFEM_SOLVE_BANDED
-                                                                                : NPFEM_SOLVE_DENSE;
+    if (st == NPFEM_OK && best >= 0) b->solve_choice = best;
   }
   (void)hipStreamSynchronize(s);
   cleanup();
@@ -1092,7 +1108,8 @@ npfem_status npfem_detect_contacts_noalloc(npfem_batch* b, const void* x, double
 npfem_status npfem_global_solve(npfem_batch* b, int32_t solve, const void* rhs, void* out,
                                 void* stream) {
   if (!b) return fail(NPFEM_E_INVALID, "batch is null");
-  if (solve != NPFEM_SOLVE_DENSE && solve != NPFEM_SOLVE_BANDED && solve != NPFEM_SOLVE_AUTO)
+  if (solve != NPFEM_SOLVE_DENSE && solve != NPFEM_SOLVE_BANDED && solve != NPFEM_SOLVE_AUTO &&
+      solve != NPFEM_SOLVE_GEMV)
     return fail(NPFEM_E_INVALID, "unknown global-step variant");
   if (solve == NPFEM_SOLVE_AUTO)
     solve = b->solve_choice >= 0 ? b->solve_choice
@@ -1114,6 +1131,17 @@ npfem_status npfem_global_solve(npfem_batch* b, int32_t solve, const void* rhs, 
                                              b->d_offsets, V, static_cast<const float*>(rhs),
                                              static_cast<float*>(out), lds, stream);
     if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("dense global step: ") + hipGetErrorString(e));
+    return NPFEM_OK;
+  }
+  if (solve == NPFEM_SOLVE_GEMV) {
+    for (int ti = 0; ti < nt; ++ti) {
+      const hipError_t e = launch_global_gemv(b->precision, b->dev_types[ti]->p.n, b->d_types + ti,
+                                              b->d_cells_by_type + b->type_first[ti], b->type_count[ti],
+                                              b->d_offsets, V, rhs, out, stream);
+      if (e == hipErrorInvalidValue)
+        return fail(NPFEM_E_UNSUPPORTED, "the dense vector global step stages at most 64 KiB per workgroup");
+      if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("dense vector global step: ") + hipGetErrorString(e));
+    }
     return NPFEM_OK;
   }
   for (int ti = 0; ti < nt; ++ti)

@@ -117,6 +117,8 @@ struct DevType {
   double* sband_rows64 = nullptr; float* sband_rows32 = nullptr;   // [n][band_w+1]: C[i][i-k]
   double* sband_cols64 = nullptr; float* sband_cols32 = nullptr;   // [n][band_w+1]: C[i+k][i],
                                                                    // k = 0: 1 / C[i][i]
+  // standalone global step, dense vector form: L^-1 [n][n] (symmetric) in either precision
+  double* linv64 = nullptr; float* linv32 = nullptr;
 };
 
 }  // namespace npfem
@@ -263,11 +265,14 @@ hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedG
                              const float* cw, int K, double* vol_area, int* flag, size_t lds_bytes,
                              bool extras, bool skalak, void* stream);
 // Global step alone (npfem_global_solve): dense L^-1 on the matrix cores over the fused work
-// list's groups (FP32), or the banded substitution over one type's cells (either precision).
+// list's groups (FP32), the dense L^-1 on the vector ALU or the banded substitution over one
+// type's cells (either precision).
 hipError_t launch_global_dense(const DevType* types_dev, const FusedGroup* groups,
                                const int* n_groups_dev, int max_groups, const int64_t* offsets,
                                int64_t vtot, const float* r, float* out, size_t lds_bytes,
                                void* stream);
+hipError_t launch_global_gemv(int precision, int n, const DevType* dt, const int32_t* cells, int n_cells,
+                              const int64_t* offsets, int64_t vt, const void* r, void* out, void* stream);
 hipError_t launch_global_banded(int precision, int n, int band_w, const DevType* dt, const int32_t* cells,
                                 int n_cells, const int64_t* offsets, int64_t vt, const void* r,
                                 void* out, void* stream);

@@ -21,7 +21,7 @@ STATUS = {0: "NPFEM_OK", -1: "NPFEM_E_INVALID", -2: "NPFEM_E_MESH", -3: "NPFEM_E
           -4: "NPFEM_E_DT", -5: "NPFEM_E_NOMEM", -6: "NPFEM_E_HIP", -7: "NPFEM_E_NONFINITE",
           -8: "NPFEM_E_UNSUPPORTED"}
 FORMS = {"plain": 0, "fused": 1}
-SOLVES = {"dense": 0, "banded": 1, "auto": 2}
+SOLVES = {"dense": 0, "banded": 1, "auto": 2, "gemv": 3}
 
 
 class NpfemError(RuntimeError):
@@ -285,8 +285,9 @@ class Batch:
 
     def global_solve(self, rhs, out=None, solve: str = "dense", stream=None):
         """out = L^-1 rhs for every cell's 3 coordinate columns ([3][V_total] device tensors in
-        the batch precision), with the dense L^-1 on the matrix cores ("dense", fused batches)
-        or the banded Cholesky substitution ("banded")."""
+        the batch precision), with the dense L^-1 on the matrix cores ("dense", fused batches),
+        the dense L^-1 on the vector ALU ("gemv") or the banded Cholesky substitution
+        ("banded"); "auto" takes the variant the autotuner timed fastest."""
         import torch
         dtype = torch.float64 if self.precision == 64 else torch.float32
         if out is None:
@@ -303,7 +304,7 @@ class Batch:
         return out
 
     def global_solve_choice(self) -> str:
-        """The variant global_solve(solve="auto") takes ("dense" or "banded")."""
+        """The variant global_solve(solve="auto") takes ("dense", "banded" or "gemv")."""
         out = c_int32(0)
         _check(lib().npfem_batch_get_global_solve(self._h, ctypes.byref(out)))
         return {v: k for k, v in SOLVES.items()}[out.value]

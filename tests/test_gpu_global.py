@@ -1,6 +1,7 @@
-"""The global step alone (npfem_global_solve): the dense L^-1 product on the matrix cores and
-the banded Cholesky substitution against the FP64 oracle's prefactored solve (cho_solve with
-the same L), on mixed batches and on sampled cells of the full 24 000-cell workload."""
+"""The global step alone (npfem_global_solve): the dense L^-1 product on the matrix cores, the
+dense L^-1 on the vector ALU and the banded Cholesky substitution against the FP64 oracle's
+prefactored solve (cho_solve with the same L), on mixed batches and on sampled cells of the
+full 24 000-cell workload."""
 import sys
 
 import numpy as np
@@ -52,7 +53,9 @@ def _run(batch, rhs_np, solve, precision, inplace=False):
 @pytest.mark.parametrize("solve,precision,form,tol", [("dense", 32, "fused", 2e-6),
                                                       ("banded", 32, "fused", 2e-6),
                                                       ("banded", 32, "plain", 2e-6),
-                                                      ("banded", 64, "plain", 1e-13)])
+                                                      ("banded", 64, "plain", 1e-13),
+                                                      ("gemv", 32, "fused", 2e-6),
+                                                      ("gemv", 64, "plain", 1e-13)])
 def test_global_solve_matches_oracle(solve, precision, form, tol):
     """11 RBC + 9 PLT interleaved; right-hand sides N(0, 1) rounded to the batch precision;
     relative error per column against the oracle's FP64 solve with the same L."""
@@ -92,16 +95,20 @@ def test_global_solve_dense_and_banded_agree_on_the_large_workload():
     _say(f"case: global solve, large_24000 ({b.n_cells} cells, {b.v_total} vertices)")
     xd = _run(batch, rhs, "dense", 32)
     xb = _run(batch, rhs, "banded", 32)
+    xg = _run(batch, rhs, "gemv", 32)
     cells = np.random.default_rng(505).choice(b.n_cells, 48, replace=False)
     ref = _oracle_solve(oracle_types(), b.types, b.offsets, rhs, cells)
     ed = _rel_err(xd, ref, b.offsets, cells)
     eb = _rel_err(xb, ref, b.offsets, cells)
+    eg = _rel_err(xg, ref, b.offsets, cells)
     scale = np.abs(xd).max()
     diff = np.abs(xd - xb).max() / scale
-    _say(f"  dense {ed:.3e}, banded {eb:.3e} (relative, sampled); dense vs banded {diff:.3e} of max")
-    assert ed <= 2e-6 and eb <= 2e-6
-    assert diff <= 1e-5
-    # the autotuner times both and NPFEM_SOLVE_AUTO takes the faster
+    diffg = np.abs(xd - xg).max() / scale
+    _say(f"  dense {ed:.3e}, banded {eb:.3e}, gemv {eg:.3e} (relative, sampled); dense vs banded "
+         f"{diff:.3e}, dense vs gemv {diffg:.3e} of max")
+    assert ed <= 2e-6 and eb <= 2e-6 and eg <= 2e-6
+    assert diff <= 1e-5 and diffg <= 1e-5
+    # the autotuner times every variant and NPFEM_SOLVE_AUTO takes the fastest
     assert batch.global_solve_choice() == "dense"          # the default of a fused batch
     batch.autotune(2, reps=2)
     choice = batch.global_solve_choice()
