@@ -47,7 +47,6 @@ __device__ __forceinline__ const __attribute__((address_space(1))) P* gptr(const
 
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u3 __attribute__((ext_vector_type(3)));
-typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 // Schedule records are read with loads of exactly the words a pass uses: a load whose result
 // words are partly unused lets the register allocator reuse those words' registers, which
@@ -148,13 +147,7 @@ __device__ __forceinline__ void st3(float* p, Vec3<float> v) {
   p[1] = v.y;
   p[2] = v.z;
 }
-__device__ __forceinline__ void add3(float* p, Vec3<float> v) {
-  p[0] += v.x;
-  p[1] += v.y;
-  p[2] += v.z;
-}
 
-typedef const __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(3))) float lfloat;
 
 // Word offset of MFMA column col (3 cell + coord) of row 0; columns past the group's last
