@@ -268,8 +268,12 @@ template <bool SL = false>
 __device__ __forceinline__ void write_tile(int r_off, f4 acc, int rt, int ct, int lane, int n,
                                            int ncols, int CS, const float* usc,
                                            double* slp = nullptr, int a_exp = 0) {
-  const int col = ct * 16 + (lane & 15);
-  const int row0 = rt * 16 + 4 * (lane >> 4);
+  // the lane index made opaque: the tile's addresses are recomputed here (a few VALU
+  // instructions) instead of being hoisted out of the iteration loop and spilled
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
+  const int col = ct * 16 + (ln & 15);
+  const int row0 = rt * 16 + 4 * (ln >> 4);
   double part = 0.0;
   if (col < ncols) {
     const int cell = col / 3;
@@ -287,9 +291,14 @@ __device__ __forceinline__ void write_tile(int r_off, f4 acc, int rt, int ct, in
       for (int r = 0; r < 4; ++r)
         if (row0 + r < n) part += (double)g[r] * (double)(acc[r] * u);
     }
+    if (row0 + 3 < n) {   // every row but those of the last row tile
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (row0 + r < n) Rl[w + 3 * r] = acc[r] * u;
+      for (int r = 0; r < 4; ++r) Rl[w + 3 * r] = acc[r] * u;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < n) Rl[w + 3 * r] = acc[r] * u;
+    }
   }
   if (SL && slp != nullptr) {
     part += __shfl_xor(part, 16, 64);
