@@ -104,8 +104,9 @@ enum {
   NPFEM_FORM_PLAIN = 0,  /* one cell at a time: predict, K x (local, global), finalise are
                             separate kernel launches per cell; FP64 or FP32                 */
   NPFEM_FORM_FUSED = 1   /* every cell of the batch in one launch per step: local + global
-                            iterations fused in LDS, global step as a dense-inverse FP32
-                            MFMA product; FP32 state, FP64 volume/area reductions           */
+                            iterations fused in LDS, global step as a dense-inverse product
+                            on the matrix cores (split fp16 operands, FP32 accumulation);
+                            FP32 state, FP64 volume/area reductions                         */
 };
 
 /*
