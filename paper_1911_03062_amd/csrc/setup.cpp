@@ -11,7 +11,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
+#include <random>
 #include <set>
 #include <utility>
 
@@ -205,50 +207,160 @@ int lds_access_cycles(const int* words) {
   return total;
 }
 
+// Rows the empty slots of a round read, per role: the empty lanes of a role all read one row
+// of their cell (the same word within a cell), the row of the first n with the fewest modelled
+// LDS cycles for that role's access. Their writes are skipped, so any row of the cell serves.
+// Returns the round's LDS cycles for one coordinate of every role.
+int empty_rows(const std::vector<std::vector<int>>& rr, int arity, int gw, int slots,
+               int cell_words, int n, std::vector<int>* rows) {
+  int words[64], total = 0;
+  if (rows) rows->assign(arity, 0);
+  for (int q = 0; q < arity; ++q) {
+    int best = -1, best_row = 0;
+    const bool any_empty = (int)rr.size() < slots;
+    for (int e = 0; e < (any_empty ? std::min(n, 96) : 1); ++e) {
+      for (int lane = 0; lane < 64; ++lane) {
+        const int cw = lane / slots, sl = lane % slots;
+        words[lane] = cw >= gw ? -1 : cw * cell_words + 3 * (sl < (int)rr.size() ? rr[sl][q] : e);
+      }
+      const int c = lds_access_cycles(words);
+      if (best < 0 || c < best) {
+        best = c;
+        best_row = e;
+      }
+    }
+    total += best;
+    if (rows) (*rows)[q] = best_row;
+  }
+  return total;
+}
+
 // Modelled cost of a schedule: per round, the larger of the LDS cycles of its accesses and its
 // VALU instructions, plus a quarter of the smaller (the waves sharing a CU overlap the two only
 // in part). Each role costs a position read, a residual read and a residual write per coordinate.
 double schedule_cost(const std::vector<std::vector<std::vector<int>>>& rounds, int gw,
-                     int slots, int cell_words, double valu_per_round) {
+                     int slots, int cell_words, int n, double valu_per_round) {
   double cost = 0.0;
-  int words[64];
   for (auto& rr : rounds) {
     if (rr.empty()) continue;
-    const int arity = (int)rr[0].size();
-    int lds = 0;
-    for (int q = 0; q < arity; ++q) {
-      for (int lane = 0; lane < 64; ++lane) {
-        const int cw = lane / slots, s = lane % slots;
-        words[lane] = (cw < gw && s < (int)rr.size()) ? cw * cell_words + 3 * rr[s][q] : -1;
-      }
-      lds += 3 * 3 * lds_access_cycles(words);
-    }
+    const int lds = 3 * 3 * empty_rows(rr, (int)rr[0].size(), gw, slots, cell_words, n, nullptr);
     cost += std::max((double)lds, valu_per_round) + 0.25 * std::min((double)lds, valu_per_round);
   }
   return cost;
 }
 
-Schedule best_schedule(const std::vector<std::vector<int>>& elems, int n, int gw, int slots,
-                       int cell_words, double valu_per_round) {
+int arity_of(const std::vector<std::vector<int>>& elems) {
+  return elems.empty() ? 1 : (int)elems[0].size();
+}
+
+// Steps of the packing refinement per schedule (about 0.1 s for the 258-vertex RBC mesh).
+constexpr long kRefineSteps = 1000000;
+
+// Local search over the packing of one schedule. A step moves an element to another round
+// that has a free slot, or swaps two elements of different rounds, keeping every round
+// vertex-disjoint; the objective is the number of vertices beyond the arity per residue class
+// mod M and round (with none beyond, the role assignment gives every role access distinct
+// classes). Simulated annealing with a fixed seed and step count, so the result is the same on
+// every run.
+std::vector<std::vector<int>> refine_rounds(const std::vector<std::vector<int>>& elems, int n,
+                                            int slots, int M, std::vector<std::vector<int>> rounds,
+                                            long steps) {
+  const int E = (int)elems.size(), R = (int)rounds.size();
+  if (E == 0 || R < 2) return rounds;
+  const int arity = (int)elems[0].size();
+  std::vector<int> rnd(E), pos(E);
+  std::vector<std::vector<int>> mem(R);
+  std::vector<unsigned char> used((size_t)R * n, 0);
+  std::vector<int> cnt((size_t)R * M, 0);
+  long total = 0;
+  auto add = [&](int e, int r, int sign) {
+    for (int v : elems[e]) {
+      int& c = cnt[(size_t)r * M + v % M];
+      total -= std::max(0, c - arity);
+      c += sign;
+      total += std::max(0, c - arity);
+      used[(size_t)r * n + v] = sign > 0;
+    }
+    if (sign > 0) {
+      rnd[e] = r;
+      pos[e] = (int)mem[r].size();
+      mem[r].push_back(e);
+    } else {
+      const int last = mem[r].back();
+      mem[r][pos[e]] = last;
+      pos[last] = pos[e];
+      mem[r].pop_back();
+    }
+  };
+  for (int r = 0; r < R; ++r)
+    for (int e : rounds[r]) add(e, r, 1);
+  auto has = [&](int e, int v) {
+    if (e < 0) return false;
+    for (int x : elems[e])
+      if (x == v) return true;
+    return false;
+  };
+  std::mt19937_64 rng(0x6e70'6665'6d5fULL);
+  const double t0 = 0.3;
+  for (long it = 0; it < steps && total > 0; ++it) {
+    const int e1 = (int)(rng() % (unsigned)E), r1 = rnd[e1];
+    const int r2 = (int)(rng() % (unsigned)R);
+    if (r2 == r1) continue;
+    int e2 = -1;
+    if ((int)mem[r2].size() >= slots || (!mem[r2].empty() && (rng() & 1))) e2 = mem[r2][rng() % mem[r2].size()];
+    bool ok = true;
+    for (int v : elems[e1])
+      if (used[(size_t)r2 * n + v] && !has(e2, v)) ok = false;
+    if (ok && e2 >= 0)
+      for (int v : elems[e2])
+        if (used[(size_t)r1 * n + v] && !has(e1, v)) ok = false;
+    if (!ok) continue;
+    const long before = total;
+    add(e1, r1, -1);
+    if (e2 >= 0) add(e2, r2, -1);
+    add(e1, r2, 1);
+    if (e2 >= 0) add(e2, r1, 1);
+    const long d = total - before;
+    const double temp = t0 * (1.0 - (double)it / (double)steps) + 0.02;
+    if (d > 0 && (double)(rng() >> 11) * 0x1.0p-53 >= std::exp(-(double)d / temp)) {
+      add(e1, r2, -1);
+      if (e2 >= 0) add(e2, r1, -1);
+      add(e1, r1, 1);
+      if (e2 >= 0) add(e2, r2, 1);
+    }
+  }
+  std::vector<std::vector<int>> out;   // rounds left empty by the moves are dropped
+  for (int r = 0; r < R; ++r)
+    if (!mem[r].empty()) {
+      out.push_back(mem[r]);
+      std::sort(out.back().begin(), out.back().end());
+    }
+  return out;
+}
+
+Schedule best_schedule_uncached(const std::vector<std::vector<int>>& elems, int n, int gw,
+                                int slots, int cell_words, double valu_per_round) {
   Schedule best;
   bool have = false;
-  const int arity = elems.empty() ? 1 : (int)elems[0].size();
   const int m_role = std::min(slots, 32);
+  auto make = [&](const std::vector<std::vector<int>>& packed) {
+    Schedule s;
+    for (auto& r : packed) {
+      std::vector<std::vector<int>> els;
+      for (int id : r) els.push_back(elems[id]);
+      s.rounds.push_back(assign_roles(els, m_role));
+      s.ids.push_back(r);
+    }
+    s.cost = schedule_cost(s.rounds, gw, slots, cell_words, n, valu_per_round);
+    return s;
+  };
   for (int M : {1, 2, 4, 8, 16, 32}) {
     if (M > m_role) break;
     for (int capf : {1, 2})
       for (int hard : {0, 1}) {
         if (M == 1 && (capf > 1 || hard)) continue;
-        const auto packed = pack_rounds(elems, n, slots, M, M == 1 ? 1 << 30 : capf * arity,
-                                        hard != 0);
-        Schedule s;
-        for (auto& r : packed) {
-          std::vector<std::vector<int>> els;
-          for (int id : r) els.push_back(elems[id]);
-          s.rounds.push_back(assign_roles(els, m_role));
-          s.ids.push_back(r);
-        }
-        s.cost = schedule_cost(s.rounds, gw, slots, cell_words, valu_per_round);
+        Schedule s = make(pack_rounds(elems, n, slots, M, M == 1 ? 1 << 30 : capf * arity_of(elems),
+                                      hard != 0));
         if (!have || s.cost < best.cost ||
             (s.cost == best.cost && s.rounds.size() < best.rounds.size())) {
           best = std::move(s);
@@ -256,7 +368,36 @@ Schedule best_schedule(const std::vector<std::vector<int>>& elems, int n, int gw
         }
       }
   }
+  // the greedy packings leave residue classes crowded in most rounds: refine the best one
+  if (have) {
+    Schedule s = make(refine_rounds(elems, n, slots, m_role, best.ids, kRefineSteps));
+    if (s.cost <= best.cost) best = std::move(s);
+  }
   return best;
+}
+
+// Schedules depend only on the element lists and the layout, and their search takes a fraction
+// of a second per schedule: the process keeps every schedule it built, keyed by all of its
+// inputs, so types built again from the same mesh reuse it.
+Schedule best_schedule(const std::vector<std::vector<int>>& elems, int n, int gw, int slots,
+                       int cell_words, double valu_per_round) {
+  static std::mutex mu;
+  static std::map<std::vector<int64_t>, Schedule> cache;
+  std::vector<int64_t> key{n, gw, slots, cell_words, (int64_t)std::llround(valu_per_round * 1024.0),
+                           (int64_t)elems.size()};
+  for (auto& el : elems) {
+    key.push_back((int64_t)el.size());
+    key.insert(key.end(), el.begin(), el.end());
+  }
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  Schedule s = best_schedule_uncached(elems, n, gw, slots, cell_words, valu_per_round);
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(std::move(key), s);
+  return s;
 }
 
 // D_m^-1 of the triangle (a, b, c): F = [x_b - x_a, x_c - x_a] D_m^-1 with D_m upper triangular
@@ -665,11 +806,33 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
     const Schedule hr = best_schedule(hel, n, gw, lay.slots, ct->cs, kHingeRoundValu);
     lay.tri_rounds = (int)tr.rounds.size();
     lay.hinge_rounds = (int)hr.rounds.size();
-    TriRec empty_tri{};   // orient 0, area 0
+    // empty slots (orient 0 and area 0, or rest < 0: their writes are skipped) read the rows
+    // that empty_rows chose for their round and role
+    TriRec empty_tri{};
     lay.tri_sched.assign((size_t)lay.tri_rounds * lay.slots, empty_tri);
     HingeRec empty_hinge{};
     empty_hinge.rest = -1.0f;
     lay.hinge_sched.assign((size_t)lay.hinge_rounds * lay.slots, empty_hinge);
+    std::vector<int> er;
+    for (int r = 0; r < lay.tri_rounds; ++r) {
+      empty_rows(tr.rounds[r], 3, gw, lay.slots, ct->cs, n, &er);
+      for (size_t s = tr.rounds[r].size(); s < (size_t)lay.slots; ++s) {
+        TriRec& rec = lay.tri_sched[(size_t)r * lay.slots + s];
+        rec.a = 12u * (uint32_t)er[0];
+        rec.b = 12u * (uint32_t)er[1];
+        rec.c = 12u * (uint32_t)er[2];
+      }
+    }
+    for (int r = 0; r < lay.hinge_rounds; ++r) {
+      empty_rows(hr.rounds[r], 4, gw, lay.slots, ct->cs, n, &er);
+      for (size_t s = hr.rounds[r].size(); s < (size_t)lay.slots; ++s) {
+        HingeRec& rec = lay.hinge_sched[(size_t)r * lay.slots + s];
+        rec.i = 12u * (uint32_t)er[0];
+        rec.j = 12u * (uint32_t)er[1];
+        rec.k = 12u * (uint32_t)er[2];
+        rec.l = 12u * (uint32_t)er[3];
+      }
+    }
     for (int r = 0; r < lay.tri_rounds; ++r)
       for (size_t s = 0; s < tr.rounds[r].size(); ++s) {
         // roles (a, b, c) in the order the schedule chose; the rest frame follows it
