@@ -68,6 +68,18 @@ __host__ __device__ __forceinline__ float kRootTol<float>() { return 2e-7f; }
 template <>
 __host__ __device__ __forceinline__ double kRootTol<double>() { return 4e-16; }
 
+// The area root's Halley start is kept without the safeguarded iteration when its step is at
+// most this times (1 + eps) and both singular values lie within 0.3 of one: there the error
+// after the step falls as the cube of the step (relative error below 1.3e-9 for steps up to
+// 1e-3, measured against a bisected FP64 root over that square of singular values), well
+// under the FP32 iteration's tolerance. Negative: never (FP64 keeps the iteration).
+template <typename T>
+__host__ __device__ __forceinline__ T kHalleyAccept();
+template <>
+__host__ __device__ __forceinline__ float kHalleyAccept<float>() { return 1e-3f; }
+template <>
+__host__ __device__ __forceinline__ double kHalleyAccept<double>() { return -1.0; }
+
 template <typename T>
 __host__ __device__ __forceinline__ T clamp_dev(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -160,6 +172,7 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
   const T k0 = b - a, k1 = T(2) - T(3) * a + b, k2 = T(3) - T(3) * a, k3 = T(3) - a;
   T lo = T(0), hi = T(1) + (a > T(0) ? a : T(0));
   T eps = T(0.5) * hi;
+  bool settled = false;
   if (rs > T(0)) {
     const T e0 = s1 * rs - T(1);
     const T f0 = k0 + e0 * (k1 + e0 * (k2 + e0 * (k3 + e0)));
@@ -167,9 +180,13 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
     const T f2 = T(2) * k2 + e0 * (T(6) * k3 + T(12) * e0);
     const T den = T(2) * f1 * f1 - f0 * f2;
     eps = (den > T(0)) ? e0 - T(2) * f0 * f1 * drcp(den) : e0;
+    const T st = eps - e0;
+    settled = den > T(0) && (st < T(0) ? -st : st) <= kHalleyAccept<T>() * (T(1) + e0) &&
+              a < T(0.3) && b > T(-0.3);   // b <= a: both within 0.3 of zero
   }
+  settled = settled && eps >= lo && eps <= hi;
   eps = (eps >= lo && eps <= hi) ? eps : T(0.5) * (lo + hi);
-  for (int it = 0; it < 40; ++it) {
+  for (int it = 0; !settled && it < 40; ++it) {
     const T fv = k0 + eps * (k1 + eps * (k2 + eps * (k3 + eps)));
     if (fv == T(0)) break;
     const T fp = k1 + eps * (T(2) * k2 + eps * (T(3) * k3 + T(4) * eps));
