@@ -188,8 +188,11 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
   eps = (eps >= lo && eps <= hi) ? eps : T(0.5) * (lo + hi);
   for (int it = 0; !settled && it < 40; ++it) {
     const T fv = k0 + eps * (k1 + eps * (k2 + eps * (k3 + eps)));
-    if (fv == T(0)) break;
     const T fp = k1 + eps * (T(2) * k2 + eps * (T(3) * k3 + T(4) * eps));
+    // an exact zero ends the iteration only where the quartic increases: for s1 = s2 > 2 the
+    // start (eps = 0, t = 1) is a root where it decreases, a stationary point of the distance
+    // that is not its minimiser, and the bisection goes on to the larger root
+    if (fv == T(0) && fp > T(0)) break;
     if (fv > T(0)) hi = eps;
     else lo = eps;
     T nx = (fp > T(0)) ? eps - fv * drcp(fp) : T(-1);

@@ -93,6 +93,30 @@ def test_area_root_extreme_stretches(lib):
         assert np.abs(out.reshape(3, 3) - ref).max() <= 1e-9 * np.abs(ref).max(), (s1, s2)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("s", [0.6, 1.5, 2.5, 4.0])
+def test_area_projection_of_isotropic_stretch_is_nearest(lib, prec, s):
+    """An isotropic stretch s (sigma1 = sigma2, where the SVD basis is arbitrary and for s > 2
+    two area-preserving stretches (d, 1/d) and (1/d, d) are equally near): with w_s = 0 and
+    unit area the residual contributions are (F - p_a) g_j, so ||F - p_a|| recovered from
+    them must equal the distance to the nearest (d, 1/d), d the minimiser of
+    (t - s)^2 + (1/t - s)^2 (t = 1 for s <= 2, else the larger root of t^2 - s t + 1)."""
+    X = np.array([[0, 0, 0], [1.0, 0, 0], [0.3, 0.8, 0]])
+    G, _ = O.triangle_rest_frames(X, np.array([[0, 1, 2]]))
+    xs = X * s
+    p = np.ascontiguousarray(xs.ravel())
+    g = np.ascontiguousarray([G[0, 1, 0], G[0, 1, 1], G[0, 2, 0], G[0, 2, 1]])
+    out = np.zeros(9)
+    lib.npfem_check_triangle(_ptr(p), _ptr(g), 1.0, 0.0, 1.0, 1.0, 1.0, _ptr(out), prec)
+    # contributions of vertices b, c are M g_b, M g_c with M = F - p_a (3 x 2)
+    cb, cc = out.reshape(3, 3)[1], out.reshape(3, 3)[2]
+    M = np.stack([cb, cc], axis=1) @ np.linalg.inv(np.stack([G[0, 1], G[0, 2]], axis=1))
+    d = 1.0 if s <= 2.0 else 0.5 * (s + np.sqrt(s * s - 4.0))
+    dist = np.hypot(s - d, s - 1.0 / d)
+    tol = 1e-10 if prec == 64 else 2e-5
+    assert abs(np.linalg.norm(M) - dist) <= tol * s, (s, np.linalg.norm(M), dist)
+
+
 @pytest.mark.parametrize("kind", [I.RBC, I.PLT])
 def test_vertex_roles_are_interchangeable(lib, kind):
     """The fused schedules may list an element's vertices in any order (chosen to spread LDS
