@@ -68,6 +68,16 @@ __host__ __device__ __forceinline__ float kRootTol<float>() { return 2e-7f; }
 template <>
 __host__ __device__ __forceinline__ double kRootTol<double>() { return 4e-16; }
 
+// F is taken as rank-deficient when s1 s2 <= this times s1^2 + s2^2 (about s2/s1): below it
+// the computed s2 is dominated by the rounding of det C (noise near sqrt(eps) s1), so F S^-1
+// would follow that noise, and s2 = 0 is the nearer value.
+template <typename T>
+__host__ __device__ __forceinline__ T kRankTol();
+template <>
+__host__ __device__ __forceinline__ float kRankTol<float>() { return 1e-3f; }
+template <>
+__host__ __device__ __forceinline__ double kRankTol<double>() { return 1e-7; }
+
 // The area root's Halley start is kept without the safeguarded iteration when its step is at
 // most this times (1 + eps) and both singular values lie within 0.3 of one: there the error
 // after the step falls as the cube of the step (relative error below 1.3e-9 for steps up to
@@ -110,7 +120,7 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
   const T disc = dsqrt(dl * dl + of * of);         // s1^2 - s2^2
   Vec3<T> P0, P1;
   T A00, A01, A11, a, b, rs;
-  if (s > T(1e-30) * (tr + T(1e-30))) {
+  if (s > kRankTol<T>() * tr) {
     const T inv = drcp(s * tt);                    // 1 / (s t)
     P0 = F0;
     P1 = F1;
@@ -125,18 +135,25 @@ __host__ __device__ __forceinline__ void triangle_residual(Vec3<T> pa, Vec3<T> p
     b = T(0.5) * tm2 - half_diff;
     rs = drsqrt(s);                                // sqrt(s1 / s2) = s1 / sqrt(s)
   } else {
-    // rank-deficient F: Gram-Schmidt frame of F's columns (any orthonormal completion)
-    T n0 = dsqrt(c00);
-    if (n0 > T(0)) P0 = F0 * drcp(n0);
-    else P0 = v3<T>(1, 0, 0);
-    Vec3<T> w = F1 - P0 * dot3(P0, F1);
-    T nw = dsqrt(dot3(w, w));
-    if (nw > T(1e-30)) P1 = w * drcp(nw);
-    else {
-      Vec3<T> ax = (P0.x * P0.x < T(0.5)) ? v3<T>(1, 0, 0) : v3<T>(0, 1, 0);
-      w = ax - P0 * dot3(P0, ax);
-      P1 = w * drsqrt(dot3(w, w));
+    // rank-deficient F = s1 u1 v1^T: the polar factor R = u1 v1^T + u2 v2^T with v1 the unit
+    // eigenvector of C for its larger eigenvalue, u1 = F v1 / |F v1| and u2 any unit vector
+    // orthogonal to u1 (the SVD's free completion); P holds R's columns R e1, R e2, and
+    // F = 0 takes v1 = e1, u1 = e_x
+    T ch = T(1), sh = T(0);   // v1 = (cos, sin) of half the angle of (dl, of)
+    if (disc > T(0)) {
+      const T qc = dl * drcp(disc);
+      ch = dsqrt(clamp_dev(T(0.5) * (T(1) + qc), T(0), T(1)));
+      sh = dsqrt(clamp_dev(T(0.5) * (T(1) - qc), T(0), T(1)));
+      if (of < T(0)) sh = -sh;
     }
+    Vec3<T> u1 = F0 * ch + F1 * sh;
+    const T n1 = dsqrt(dot3(u1, u1));
+    u1 = n1 > T(0) ? u1 * drcp(n1) : v3<T>(1, 0, 0);
+    const Vec3<T> ax = (u1.x * u1.x < T(0.5)) ? v3<T>(1, 0, 0) : v3<T>(0, 1, 0);
+    const Vec3<T> w = ax - u1 * dot3(u1, ax);
+    const Vec3<T> u2 = w * drsqrt(dot3(w, w));
+    P0 = u1 * ch - u2 * sh;   // v2 = (-sin, cos)
+    P1 = u1 * sh + u2 * ch;
     A00 = T(1);
     A01 = T(0);
     A11 = T(1);

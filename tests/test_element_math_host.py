@@ -117,6 +117,47 @@ def test_area_projection_of_isotropic_stretch_is_nearest(lib, prec, s):
     assert abs(np.linalg.norm(M) - dist) <= tol * s, (s, np.linalg.norm(M), dist)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("s1", [0.5, 1.0, 2.0])
+def test_projections_of_a_collinear_triangle(lib, prec, s1):
+    """A triangle collapsed onto a line (F of rank one, sigma2 = 0), where the SVD's second
+    left vector is any unit vector orthogonal to the first: the strain projection (polar
+    factor) must have orthonormal columns, map F's right singular vector v1 to u1, and lie at
+    distance sqrt((s1 - 1)^2 + 1) from F; the area projection must have singular values
+    (d, 1/d) with d the largest root of t^4 - s1 t^3 - 1 and lie at distance
+    sqrt((s1 - d)^2 + 1/d^2). Both projections are recovered from the residual contributions
+    (F - p) g_j with one weight set to zero."""
+    X = np.array([[0, 0, 0], [1.0, 0, 0], [0.3, 0.8, 0]])
+    G, _ = O.triangle_rest_frames(X, np.array([[0, 1, 2]]))
+    Gm = np.stack([G[0, 1], G[0, 2]], axis=1)
+    # deformed positions on the x axis: F = [x_b - x_a, x_c - x_a] G has rank one
+    v = np.array([0.6, 0.8])                       # unit right singular vector in the frame
+    F = np.zeros((3, 2))
+    F[0] = s1 * v                                  # F = s1 e_x v^T
+    E = F @ np.linalg.inv(Gm.T)                    # edge vectors: F = [x_b - x_a, x_c - x_a] Gm^T
+    xs = np.array([[0.2, 0.0, 0.0], [0.2, 0.0, 0.0] + E[:, 0], [0.2, 0.0, 0.0] + E[:, 1]])
+    p = np.ascontiguousarray(xs.ravel())
+    g = np.ascontiguousarray([G[0, 1, 0], G[0, 1, 1], G[0, 2, 0], G[0, 2, 1]])
+    tol = 1e-10 if prec == 64 else 3e-5
+
+    def proj(w_s, w_a):
+        out = np.zeros(9)
+        lib.npfem_check_triangle(_ptr(p), _ptr(g), 1.0, w_s, w_a, 1.0, 1.0, _ptr(out), prec)
+        M = np.stack([out.reshape(3, 3)[1], out.reshape(3, 3)[2]], axis=1) @ np.linalg.inv(Gm)
+        return F - M
+
+    ps = proj(1.0, 0.0)
+    assert np.abs(ps.T @ ps - np.eye(2)).max() <= tol, ps
+    assert np.abs(ps @ v - np.array([1.0, 0.0, 0.0])).max() <= tol, ps @ v
+    assert abs(np.linalg.norm(F - ps) - np.hypot(s1 - 1.0, 1.0)) <= tol
+    r = np.roots([1.0, -s1, 0.0, 0.0, -1.0])
+    d = max(x.real for x in r if abs(x.imag) < 1e-9 and x.real > 0)
+    pa = proj(0.0, 1.0)
+    sv = np.linalg.svd(pa, compute_uv=False)
+    assert np.abs(sv - np.array([d, 1.0 / d])).max() <= tol * d, (sv, d)
+    assert abs(np.linalg.norm(F - pa) - np.hypot(s1 - d, 1.0 / d)) <= tol * d
+
+
 @pytest.mark.parametrize("kind", [I.RBC, I.PLT])
 def test_vertex_roles_are_interchangeable(lib, kind):
     """The fused schedules may list an element's vertices in any order (chosen to spread LDS
