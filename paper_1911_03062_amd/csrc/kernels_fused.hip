@@ -1193,6 +1193,63 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 }
 
 
+// mfma_rows with the A values of a chunk requested two chunks ahead (three register sets in
+// turn; B one chunk ahead, two sets), for the global step alone, where no element state
+// competes for registers. Past the last chunk the loads fetch zero chunks (A; a row tile
+// stores two) or repeat the last one (B) and are never used.
+template <bool TWO>
+__device__ __forceinline__ void mfma_rows_deep(gu4* La, const lfloat* RbA, const lfloat* RbB, int KR,
+                                               f4& acc0, f4& acc1) {
+  const int nch = (KR + kMfmaChunk - 1) / kMfmaChunk;
+  AChunk a0, a1, a2;
+  u4 bP0[2], bP1[2], bQ0[2], bQ1[2];
+  load_a(a0, La, 0);
+  load_a(a1, La, 1);
+  load_b<TWO>(bP0, bP1, RbA, RbB, 0, KR);
+  // chunk c: A set c mod 3, B set c mod 2; the loads refill the sets chunk c - 1 used
+  auto step = [&](const AChunk& ac, const u4 (&bc0)[2], const u4 (&bc1)[2], AChunk& an,
+                  u4 (&bn0)[2], u4 (&bn1)[2], int c) {
+    load_a(an, La, c + 2);
+    load_b<TWO>(bn0, bn1, RbA, RbB, c + 1, KR);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_chunk<TWO>(ac, bc0, bc1, acc0, acc1);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int c = 0;; c += 6) {
+    step(a0, bP0, bP1, a2, bQ0, bQ1, c);
+    if (c + 1 >= nch) break;
+    step(a1, bQ0, bQ1, a0, bP0, bP1, c + 1);
+    if (c + 2 >= nch) break;
+    step(a2, bP0, bP1, a1, bQ0, bQ1, c + 2);
+    if (c + 3 >= nch) break;
+    step(a0, bQ0, bQ1, a2, bP0, bP1, c + 3);
+    if (c + 4 >= nch) break;
+    step(a1, bP0, bP1, a0, bQ0, bQ1, c + 4);
+    if (c + 5 >= nch) break;
+    step(a2, bQ0, bQ1, a1, bP0, bP1, c + 5);
+    if (c + 6 >= nch) break;
+  }
+}
+
+// D = -acc usc[cell] of output tile (rt, ct) straight to out ([3][V] SoA): the lane's four
+// rows row0..row0+3 of column col = 3 cell + coord are consecutive words of that plane.
+__device__ __forceinline__ void store_tile(float* out, int64_t vt, f4 acc, int rt, int ct, int lane,
+                                           int n, int ncols, const float* usc, const int64_t* off) {
+  const int col = ct * 16 + (lane & 15);
+  const int row0 = rt * 16 + 4 * (lane >> 4);
+  if (col < ncols) {
+    const int cell = col / 3;
+    const float u = -usc[cell];
+    float* o = out + (col - 3 * cell) * vt + off[cell] + row0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (row0 + r < n) o[r] = acc[r] * u;
+  }
+}
+
+constexpr int kStageLoads = 26;   // right-hand-side loads per thread in flight (global step alone):
+                                  // an RBC group of 8 cells in one batch
+
 // Global step alone, dense form: out = L^-1 r for every cell of the listed groups (FP32), the
 // product of the fused kernel's global step on the matrix cores with the right-hand sides
 // staged from HBM (one workgroup per group of same-type cells, as in the fused step). r and
@@ -1215,10 +1272,30 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
     if (tid < count) off_lds[tid] = offsets[grp.cells[tid]];
     __syncthreads();
     // R = -r in [cell][vertex][xyz] blocks, rows n..npad-1 zero (the product writes -A B);
-    // vertex-fastest order for coalesced reads
-    for (int i = tid; i < count * 3 * npad; i += kFusedThreads) {
-      const int cc = i / npad, v = i - cc * npad, cell = cc / 3, c = cc - 3 * cell;
-      R[cell * CS + 3 * v + c] = v < n ? -r[c * vt + off_lds[cell] + v] : 0.0f;
+    // vertex-fastest order for coalesced reads, kStageLoads independent loads per thread in
+    // flight before their LDS stores (one HBM round trip per batch, not per element)
+    // i / npad as a float product: i < 2^24, so the product's rounding (below 1e-5 here) never
+    // crosses an integer, which (i + 1/2) / npad stays at least 1/(2 npad) away from
+    const int total = count * 3 * npad;
+    const float inv_npad = 1.0f / (float)npad;
+    for (int i0 = tid; i0 < total; i0 += kFusedThreads * kStageLoads) {
+      float val[kStageLoads];
+      int dst[kStageLoads];
+#pragma unroll
+      for (int j = 0; j < kStageLoads; ++j) {
+        const int i = i0 + j * kFusedThreads;
+        const int ii = i < total ? i : 0;   // past the end: decoded in range, not stored
+        const int cc = (int)(((float)ii + 0.5f) * inv_npad);
+        const int v = ii - cc * npad, cell = cc / 3, c = cc - 3 * cell;
+        dst[j] = i < total ? cell * CS + 3 * v + c : -1;
+        // an unconditional load of an in-range word (padding rows read row n - 1), selected
+        // afterwards: a load under a branch is waited for at once, one round trip per element
+        const float x = r[c * vt + off_lds[cell] + min(v, n - 1)];
+        val[j] = (i < total && v < n) ? -x : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < kStageLoads; ++j)
+        if (dst[j] >= 0) R[dst[j]] = val[j];
     }
     __syncthreads();
     {
@@ -1228,73 +1305,37 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
       split_b(R + e_gc * CS, n, npad, S, e_s, e_gc < count, T.p.linv_exp, &usc_lds[e_gc]);
     }
     __syncthreads();
+    // each wave's share of the output tiles, as in the fused step; every tile goes straight to
+    // out (the group's right-hand sides are all in LDS already, so out may alias r)
     const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
     const int ncols = 3 * count, CT = (ncols + 15) / 16;
     const int n_units = RT * CT;
     const int u0 = (n_units * wave) / kFusedWaves, u1 = (n_units * (wave + 1)) / kFusedWaves;
-    f4 acc[kMaxTilesPerWave];
-#pragma unroll
-    for (int i = 0; i < kMaxTilesPerWave; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-    int n_items = 0;
-    {
-      gu4* Lt = reinterpret_cast<gu4*>(gptr(T.linv_tiles)) + lane;
-      const int kq = lane >> 4;
-      for (int u = u0; u < u1;) {
-        f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
-        if (CT >= 2) {
-          const int rt = u / CT, ct = u - rt * CT;
-          const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-          if (ct + 1 < CT && u + 1 < u1) {
-            const lfloat* RbB =
-                (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-            mfma_rows<true>(Lt + (size_t)rt * KS * 16, RbA, RbB, KR, d0, d1);
-            u += 2;
-          } else {
-            mfma_rows<false>(Lt + (size_t)rt * KS * 16, RbA, RbA, KR, d0, d1);
-            u += 1;
-          }
+    gu4* Lt = reinterpret_cast<gu4*>(gptr(T.linv_tiles)) + lane;
+    const int kq = lane >> 4;
+    for (int u = u0; u < u1;) {
+      f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
+      if (CT >= 2) {
+        const int rt = u / CT, ct = u - rt * CT;
+        const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
+        if (ct + 1 < CT && u + 1 < u1) {
+          const lfloat* RbB =
+              (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
+          mfma_rows_deep<true>(Lt + (size_t)rt * KS * 16, RbA, RbB, KR, d0, d1);
+          store_tile(out, vt, d0, rt, ct, lane, n, ncols, usc_lds, off_lds);
+          store_tile(out, vt, d1, rt, ct + 1, lane, n, ncols, usc_lds, off_lds);
+          u += 2;
         } else {
-          const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-          mfma_rows<false>(Lt + (size_t)u * KS * 16, Rb, Rb, KR, d0, d1);
-          if (u + 1 < u1) mfma_rows<false>(Lt + (size_t)(u + 1) * KS * 16, Rb, Rb, KR, d1, d0);
-          u += (u + 1 < u1) ? 2 : 1;
+          mfma_rows_deep<false>(Lt + (size_t)rt * KS * 16, RbA, RbA, KR, d0, d1);
+          store_tile(out, vt, d0, rt, ct, lane, n, ncols, usc_lds, off_lds);
+          u += 1;
         }
-        // keep the item's tiles at the end of the held set (indices stay compile-time)
-#pragma unroll
-        for (int i = 0; i + 2 < kMaxTilesPerWave; ++i) acc[i] = acc[i + 2];
-        acc[kMaxTilesPerWave - 2] = d0;
-        acc[kMaxTilesPerWave - 1] = d1;
-        ++n_items;
+      } else {
+        const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
+        mfma_rows_deep<false>(Lt + (size_t)u * KS * 16, Rb, Rb, KR, d0, d1);
+        store_tile(out, vt, d0, u, 0, lane, n, ncols, usc_lds, off_lds);
+        u += 1;
       }
-    }
-    __syncthreads();
-    {
-      // replay the item sequence to place the held tiles
-      int u = u0;
-#pragma unroll
-      for (int q = 0; q < kMaxTilesPerWave / 2; ++q) {
-        if (q >= kMaxTilesPerWave / 2 - n_items) {
-          if (CT >= 2) {
-            const int rt = u / CT, ct = u - rt * CT;
-            write_tile(0, acc[2 * q], rt, ct, lane, n, ncols, CS, usc_lds);
-            if (ct + 1 < CT && u + 1 < u1) {
-              write_tile(0, acc[2 * q + 1], rt, ct + 1, lane, n, ncols, CS, usc_lds);
-              u += 2;
-            } else {
-              u += 1;
-            }
-          } else {
-            write_tile(0, acc[2 * q], u, 0, lane, n, ncols, CS, usc_lds);
-            if (u + 1 < u1) write_tile(0, acc[2 * q + 1], u + 1, 0, lane, n, ncols, CS, usc_lds);
-            u += (u + 1 < u1) ? 2 : 1;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < count * 3 * n; i += kFusedThreads) {
-      const int cc = i / n, v = i - cc * n, cell = cc / 3, c = cc - 3 * cell;
-      out[c * vt + off_lds[cell] + v] = R[cell * CS + 3 * v + c];
     }
   }
 }
