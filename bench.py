@@ -483,22 +483,21 @@ def main():
         for k_, ct_ in ot_g.items():
             nnz[k_] = int(np.count_nonzero(np.abs(np.linalg.cholesky(ct_.L)) > 0))
         dense_flop = sum(3 * 2 * ot_g[int(t)].n ** 2 for t in b.types)
-        # matrix-core work the dense form issues: per group of same-type cells, 16-row tiles of
-        # L^-1 times 16-column tiles of right-hand sides over 32-row k chunks, three fp16
+        # matrix-core work the dense form issues: per block of up to 16 same-type cells (as many
+        # as fit 64 KB of LDS), pairs of 16-row tiles of L^-1 (the odd last one twice) times
+        # every 16-column tile of the block's right-hand sides over 32-row k chunks, three fp16
         # products (split operands) each
         mfma_flop = 0
-        name_of = {k_: name for name, k_ in present.items()}
         for k_, ct_ in ot_g.items():
-            if k_ not in name_of:
-                continue
             n_t = ct_.n
             npad = max(32, -(-n_t // 4) * 4)
+            cs = 3 * npad + (3 - 3 * npad) % 16   # the cell-block stride (3 mod 16)
+            bc = min(16, max(1, 65536 // (4 * cs)))
             rt, nch = -(-n_t // 16), -(-(npad // 4) // 8)
+            cols = -(-3 * bc // 16)
             cells_t = int(np.count_nonzero(b.types == k_))
-            gsize = 4 * layouts[name_of[k_]]
-            for g0 in range(0, cells_t, gsize):
-                ct_cols = -(-3 * min(gsize, cells_t - g0) // 16)
-                mfma_flop += 3 * 2 * (16 * rt) * (32 * nch) * (16 * ct_cols)
+            blocks = -(-cells_t // bc)
+            mfma_flop += blocks * 3 * 2 * (16 * 2 * (-(-rt // 2))) * (32 * nch) * (16 * cols)
         band_flop = sum(3 * 4 * nnz[int(t)] for t in b.types)
         gres = {}
         for solve in ("dense", "banded", "gemv"):
@@ -524,7 +523,7 @@ def main():
                            "achieved_TFLOPs": flop / (us * 1e-6) / 1e12,
                            "max_rel_err_vs_oracle": err}
         mfma_tflops = mfma_flop / (gres["dense"]["avg_launch_us"] * 1e-6) / 1e12
-        gres["dense"].update({"kernel": "k_global_dense", "bound": "mfma",
+        gres["dense"].update({"kernel": "k_global_dense_wide", "bound": "mfma",
                               "mfma_dtype": "fp16 split operands (hi + lo, three products), FP32 accumulation",
                               "mfma_flop_issued": mfma_flop, "mfma_TFLOPs": mfma_tflops,
                               "peak": PEAK_FP16_MFMA_TFLOPS, "frac": mfma_tflops / PEAK_FP16_MFMA_TFLOPS,

@@ -1122,15 +1122,13 @@ npfem_status npfem_global_solve(npfem_batch* b, int32_t solve, const void* rhs, 
   if (solve == NPFEM_SOLVE_DENSE) {
     if (b->form != NPFEM_FORM_FUSED)
       return fail(NPFEM_E_UNSUPPORTED, "the dense global step needs a fused-form batch (FP32 L^-1)");
-    size_t lds = 0;
     for (int ti = 0; ti < nt; ++ti) {
-      const npfem_celltype* t = b->types[ti];
-      lds = std::max(lds, (size_t)kFusedWaves * t->layouts[b->layout_of[ti]].gw * t->cs * sizeof(float));
+      const hipError_t e = launch_global_dense_wide(b->d_types + ti, b->types[ti]->cs,
+                                                    b->d_cells_by_type + b->type_first[ti], b->type_count[ti],
+                                                    b->d_offsets, V, static_cast<const float*>(rhs),
+                                                    static_cast<float*>(out), stream);
+      if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("dense global step: ") + hipGetErrorString(e));
     }
-    const hipError_t e = launch_global_dense(b->d_types, b->d_groups, b->d_count_all, b->n_groups,
-                                             b->d_offsets, V, static_cast<const float*>(rhs),
-                                             static_cast<float*>(out), lds, stream);
-    if (e != hipSuccess) return fail(NPFEM_E_HIP, std::string("dense global step: ") + hipGetErrorString(e));
     return NPFEM_OK;
   }
   if (solve == NPFEM_SOLVE_GEMV) {

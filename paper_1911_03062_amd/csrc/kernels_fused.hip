@@ -1193,44 +1193,6 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 }
 
 
-// mfma_rows with the A values of a chunk requested two chunks ahead (three register sets in
-// turn; B one chunk ahead, two sets), for the global step alone, where no element state
-// competes for registers. Past the last chunk the loads fetch zero chunks (A; a row tile
-// stores two) or repeat the last one (B) and are never used.
-template <bool TWO>
-__device__ __forceinline__ void mfma_rows_deep(gu4* La, const lfloat* RbA, const lfloat* RbB, int KR,
-                                               f4& acc0, f4& acc1) {
-  const int nch = (KR + kMfmaChunk - 1) / kMfmaChunk;
-  AChunk a0, a1, a2;
-  u4 bP0[2], bP1[2], bQ0[2], bQ1[2];
-  load_a(a0, La, 0);
-  load_a(a1, La, 1);
-  load_b<TWO>(bP0, bP1, RbA, RbB, 0, KR);
-  // chunk c: A set c mod 3, B set c mod 2; the loads refill the sets chunk c - 1 used
-  auto step = [&](const AChunk& ac, const u4 (&bc0)[2], const u4 (&bc1)[2], AChunk& an,
-                  u4 (&bn0)[2], u4 (&bn1)[2], int c) {
-    load_a(an, La, c + 2);
-    load_b<TWO>(bn0, bn1, RbA, RbB, c + 1, KR);
-    __builtin_amdgcn_sched_barrier(0);
-    mma_chunk<TWO>(ac, bc0, bc1, acc0, acc1);
-    __builtin_amdgcn_sched_barrier(0);
-  };
-  for (int c = 0;; c += 6) {
-    step(a0, bP0, bP1, a2, bQ0, bQ1, c);
-    if (c + 1 >= nch) break;
-    step(a1, bQ0, bQ1, a0, bP0, bP1, c + 1);
-    if (c + 2 >= nch) break;
-    step(a2, bP0, bP1, a1, bQ0, bQ1, c + 2);
-    if (c + 3 >= nch) break;
-    step(a0, bQ0, bQ1, a2, bP0, bP1, c + 3);
-    if (c + 4 >= nch) break;
-    step(a1, bP0, bP1, a0, bQ0, bQ1, c + 4);
-    if (c + 5 >= nch) break;
-    step(a2, bQ0, bQ1, a1, bP0, bP1, c + 5);
-    if (c + 6 >= nch) break;
-  }
-}
-
 // D = -acc usc[cell] of output tile (rt, ct) straight to out ([3][V] SoA): the lane's four
 // rows row0..row0+3 of column col = 3 cell + coord are consecutive words of that plane.
 __device__ __forceinline__ void store_tile(float* out, int64_t vt, f4 acc, int rt, int ct, int lane,
@@ -1250,32 +1212,35 @@ __device__ __forceinline__ void store_tile(float* out, int64_t vt, f4 acc, int r
 constexpr int kStageLoads = 26;   // right-hand-side loads per thread in flight (global step alone):
                                   // an RBC group of 8 cells in one batch
 
-// Global step alone, dense form: out = L^-1 r for every cell of the listed groups (FP32), the
-// product of the fused kernel's global step on the matrix cores with the right-hand sides
-// staged from HBM (one workgroup per group of same-type cells, as in the fused step). r and
-// out are [3][V] SoA; they may be the same buffer (a group is staged before it is written).
+// Global step alone, wide form: out = L^-1 r for the cells of one type, up to kWideMaxCells
+// per workgroup (bc, chosen per type so that bc cell blocks fit 64 KB of LDS), 3 bc columns in
+// COLS column tiles. The right-hand sides are staged into the cell-block layout in LDS (rows
+// n..npad-1 zero) and split as in the fused step (16 lanes per cell, four cells per wave); the
+// staging issues kStageLoads loads per thread before any LDS store, every load unconditional
+// from an in-range word (padding rows read row n - 1) and selected afterwards (a load under a
+// branch is waited for at once), the element's (cell, coordinate, row) from a float-reciprocal
+// division that is exact for every index and npad here. A work item is two row tiles times all COLS column tiles: each A chunk from L2 then
+// feeds 6 COLS MFMAs and each B word read from LDS two row tiles, which keeps the operand
+// traffic per MFMA within what a CU's L2 path and LDS deliver. The products of an
+// accumulator run in the order of mma_chunk (the small terms first), as in the fused step.
+// Every finished tile goes straight to HBM (its four rows are consecutive words of one
+// coordinate plane); the block's right-hand sides are all in LDS by then, so out may alias r. The odd last row tile pairs with itself (computed twice,
+// stored once).
+template <int COLS>
 __global__ void __launch_bounds__(kFusedThreads)
-k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__ groups,
-               const int* __restrict__ n_groups_dev, const int64_t* __restrict__ offsets,
-               int64_t vt, const float* r, float* out) {
-  __shared__ int64_t off_lds[kMaxGroupCells];
-  __shared__ float usc_lds[kMaxGroupCells];
+k_global_dense_wide(const DevType* __restrict__ tp, const int32_t* __restrict__ cells, int n_cells,
+                    int bc, const int64_t* __restrict__ offsets, int64_t vt, const float* r, float* out) {
+  __shared__ int64_t off_lds[kWideMaxCells];
+  __shared__ float usc_lds[kWideMaxCells];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n_groups = *n_groups_dev;
-  for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
-    const FusedGroup& grp = groups[g];
-    const int count = grp.count;
-    const DevType& T = types[grp.type];
-    const int n = T.p.n, npad = T.p.npad, CS = T.p.cs;
-    float* R = lds;
-    __syncthreads();   // the previous group's reads of LDS are done
-    if (tid < count) off_lds[tid] = offsets[grp.cells[tid]];
-    __syncthreads();
-    // R = -r in [cell][vertex][xyz] blocks, rows n..npad-1 zero (the product writes -A B);
-    // vertex-fastest order for coalesced reads, kStageLoads independent loads per thread in
-    // flight before their LDS stores (one HBM round trip per batch, not per element)
-    // i / npad as a float product: i < 2^24, so the product's rounding (below 1e-5 here) never
-    // crosses an integer, which (i + 1/2) / npad stays at least 1/(2 npad) away from
+  const DevType& T = *tp;
+  const int n = T.p.n, npad = T.p.npad, CS = T.p.cs;
+  const int c0 = blockIdx.x * bc;
+  const int count = min(bc, n_cells - c0);
+  float* R = lds;
+  if (tid < count) off_lds[tid] = offsets[cells[c0 + tid]];
+  __syncthreads();
+  {
     const int total = count * 3 * npad;
     const float inv_npad = 1.0f / (float)npad;
     for (int i0 = tid; i0 < total; i0 += kFusedThreads * kStageLoads) {
@@ -1284,12 +1249,10 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
 #pragma unroll
       for (int j = 0; j < kStageLoads; ++j) {
         const int i = i0 + j * kFusedThreads;
-        const int ii = i < total ? i : 0;   // past the end: decoded in range, not stored
+        const int ii = i < total ? i : 0;
         const int cc = (int)(((float)ii + 0.5f) * inv_npad);
         const int v = ii - cc * npad, cell = cc / 3, c = cc - 3 * cell;
         dst[j] = i < total ? cell * CS + 3 * v + c : -1;
-        // an unconditional load of an in-range word (padding rows read row n - 1), selected
-        // afterwards: a load under a branch is waited for at once, one round trip per element
         const float x = r[c * vt + off_lds[cell] + min(v, n - 1)];
         val[j] = (i < total && v < n) ? -x : 0.0f;
       }
@@ -1297,45 +1260,80 @@ k_global_dense(const DevType* __restrict__ types, const FusedGroup* __restrict__
       for (int j = 0; j < kStageLoads; ++j)
         if (dst[j] >= 0) R[dst[j]] = val[j];
     }
-    __syncthreads();
-    {
-      // split fp16 B operand, per cell over the lanes of its wave (as in the fused step)
-      const int gw = T.p.gw, S = T.p.slots;
-      const int e_cw = lane / S, e_s = lane - e_cw * S, e_gc = wave * gw + e_cw;
-      split_b(R + e_gc * CS, n, npad, S, e_s, e_gc < count, T.p.linv_exp, &usc_lds[e_gc]);
-    }
-    __syncthreads();
-    // each wave's share of the output tiles, as in the fused step; every tile goes straight to
-    // out (the group's right-hand sides are all in LDS already, so out may alias r)
-    const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
-    const int ncols = 3 * count, CT = (ncols + 15) / 16;
-    const int n_units = RT * CT;
-    const int u0 = (n_units * wave) / kFusedWaves, u1 = (n_units * (wave + 1)) / kFusedWaves;
-    gu4* Lt = reinterpret_cast<gu4*>(gptr(T.linv_tiles)) + lane;
-    const int kq = lane >> 4;
-    for (int u = u0; u < u1;) {
-      f4 d0 = f4{0.f, 0.f, 0.f, 0.f}, d1 = f4{0.f, 0.f, 0.f, 0.f};
-      if (CT >= 2) {
-        const int rt = u / CT, ct = u - rt * CT;
-        const lfloat* RbA = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-        if (ct + 1 < CT && u + 1 < u1) {
-          const lfloat* RbB =
-              (const lfloat*)(R + col_base(ct * 16 + 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-          mfma_rows_deep<true>(Lt + (size_t)rt * KS * 16, RbA, RbB, KR, d0, d1);
-          store_tile(out, vt, d0, rt, ct, lane, n, ncols, usc_lds, off_lds);
-          store_tile(out, vt, d1, rt, ct + 1, lane, n, ncols, usc_lds, off_lds);
-          u += 2;
-        } else {
-          mfma_rows_deep<false>(Lt + (size_t)rt * KS * 16, RbA, RbA, KR, d0, d1);
-          store_tile(out, vt, d0, rt, ct, lane, n, ncols, usc_lds, off_lds);
-          u += 1;
-        }
-      } else {
-        const lfloat* Rb = (const lfloat*)(R + col_base(lane & 15, ncols, CS) + 3 * k_row_in_chunk(kq, 0));
-        mfma_rows_deep<false>(Lt + (size_t)u * KS * 16, Rb, Rb, KR, d0, d1);
-        store_tile(out, vt, d0, u, 0, lane, n, ncols, usc_lds, off_lds);
-        u += 1;
+  }
+  __syncthreads();
+  {
+    const int e_cw = lane >> 4, e_s = lane & 15, e_gc = wave * 4 + e_cw;
+    split_b(R + e_gc * CS, n, npad, 16, e_s, e_gc < count, T.p.linv_exp, &usc_lds[e_gc]);
+  }
+  __syncthreads();
+  const int RT = T.p.row_tiles, KS = T.p.k_steps, KR = npad / 4;
+  const int ncols = 3 * count;
+  const int nch = (KR + kMfmaChunk - 1) / kMfmaChunk;
+  gu4* Lt = reinterpret_cast<gu4*>(gptr(T.linv_tiles)) + lane;
+  const int kq = lane >> 4;
+  const lfloat* Rb[COLS];
+#pragma unroll
+  for (int ct = 0; ct < COLS; ++ct)
+    Rb[ct] = (const lfloat*)(R + col_base(ct * 16 + (lane & 15), ncols, CS) + 3 * k_row_in_chunk(kq, 0));
+  for (int ip = wave; 2 * ip < RT; ip += kFusedWaves) {
+    const int rt0 = 2 * ip, rt1 = min(rt0 + 1, RT - 1);
+    gu4* La0 = Lt + (size_t)rt0 * KS * 16;
+    gu4* La1 = Lt + (size_t)rt1 * KS * 16;
+    f4 acc[2][COLS];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int ct = 0; ct < COLS; ++ct) acc[q][ct] = f4{0.f, 0.f, 0.f, 0.f};
+    AChunk aP0, aP1, aQ0, aQ1;
+    u4 bP[COLS][2], bQ[COLS][2];
+    auto loads = [&](AChunk& a0, AChunk& a1, u4 (&b)[COLS][2], int c) {
+      load_a(a0, La0, c);
+      load_a(a1, La1, c);
+#pragma unroll
+      for (int ct = 0; ct < COLS; ++ct) load_b<false>(b[ct], b[ct], Rb[ct], Rb[ct], c, KR);
+    };
+    auto mmas = [&](const AChunk& a0, const AChunk& a1, const u4 (&b)[COLS][2]) {
+      const h8 a0h = __builtin_bit_cast(h8, a0.hi), a0l = __builtin_bit_cast(h8, a0.lo);
+      const h8 a1h = __builtin_bit_cast(h8, a1.hi), a1l = __builtin_bit_cast(h8, a1.lo);
+#pragma unroll
+      for (int ct = 0; ct < COLS; ++ct) {
+        const h8 bh = __builtin_bit_cast(h8, b[ct][0]);
+        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0l, bh, acc[0][ct], 0, 0, 0);
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1l, bh, acc[1][ct], 0, 0, 0);
       }
+#pragma unroll
+      for (int ct = 0; ct < COLS; ++ct) {
+        const h8 bl = __builtin_bit_cast(h8, b[ct][1]);
+        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0h, bl, acc[0][ct], 0, 0, 0);
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1h, bl, acc[1][ct], 0, 0, 0);
+      }
+#pragma unroll
+      for (int ct = 0; ct < COLS; ++ct) {
+        const h8 bh = __builtin_bit_cast(h8, b[ct][0]);
+        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0h, bh, acc[0][ct], 0, 0, 0);
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1h, bh, acc[1][ct], 0, 0, 0);
+      }
+    };
+    // two register sets alternate: while one chunk's MFMAs run, the next chunk's operands are
+    // in flight; the loads past the last chunk fetch a zero chunk (A) or repeat the last (B)
+    loads(aP0, aP1, bP, 0);
+    int c = 0;
+    for (; c + 1 < nch; c += 2) {
+      loads(aQ0, aQ1, bQ, c + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mmas(aP0, aP1, bP);
+      __builtin_amdgcn_sched_barrier(0);
+      loads(aP0, aP1, bP, c + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      mmas(aQ0, aQ1, bQ);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (c < nch) mmas(aP0, aP1, bP);
+#pragma unroll
+    for (int ct = 0; ct < COLS; ++ct) {
+      store_tile(out, vt, acc[0][ct], rt0, ct, lane, n, ncols, usc_lds, off_lds);
+      if (rt1 != rt0) store_tile(out, vt, acc[1][ct], rt1, ct, lane, n, ncols, usc_lds, off_lds);
     }
   }
 }
@@ -1367,15 +1365,24 @@ hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedG
   return hipGetLastError();
 }
 
-hipError_t launch_global_dense(const DevType* types_dev, const FusedGroup* groups,
-                               const int* n_groups_dev, int max_groups, const int64_t* offsets,
-                               int64_t vtot, const float* r, float* out, size_t lds_bytes,
-                               void* stream) {
-  if (max_groups == 0) return hipSuccess;
-  const int grid = max_groups < kMaxFusedGrid ? max_groups : kMaxFusedGrid;
-  hipLaunchKernelGGL(k_global_dense, dim3(grid), dim3(kFusedThreads), lds_bytes,
-                     reinterpret_cast<hipStream_t>(stream), types_dev, groups, n_groups_dev,
-                     offsets, vtot, r, out);
+hipError_t launch_global_dense_wide(const DevType* dt, int cs, const int32_t* cells, int n_cells,
+                                    const int64_t* offsets, int64_t vtot, const float* r, float* out,
+                                    void* stream) {
+  if (n_cells == 0) return hipSuccess;
+  const int bc = wide_cells_per_block(cs);
+  const int cols = (3 * bc + 15) / 16;
+  const int grid = (n_cells + bc - 1) / bc;
+  const size_t lds = (size_t)bc * cs * sizeof(float);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (cols >= 3)
+    hipLaunchKernelGGL(k_global_dense_wide<3>, dim3(grid), dim3(kFusedThreads), lds, s, dt, cells, n_cells, bc,
+                       offsets, vtot, r, out);
+  else if (cols == 2)
+    hipLaunchKernelGGL(k_global_dense_wide<2>, dim3(grid), dim3(kFusedThreads), lds, s, dt, cells, n_cells, bc,
+                       offsets, vtot, r, out);
+  else
+    hipLaunchKernelGGL(k_global_dense_wide<1>, dim3(grid), dim3(kFusedThreads), lds, s, dt, cells, n_cells, bc,
+                       offsets, vtot, r, out);
   return hipGetLastError();
 }
 

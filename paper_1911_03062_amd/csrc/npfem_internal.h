@@ -264,13 +264,18 @@ hipError_t launch_fused_step(const DevType* types_dev, int n_types, const FusedG
                              int64_t vtot, float* x, float* v, const float* f, const float* cp,
                              const float* cw, int K, double* vol_area, int* flag, size_t lds_bytes,
                              bool extras, bool skalak, void* stream);
-// Global step alone (npfem_global_solve): dense L^-1 on the matrix cores over the fused work
-// list's groups (FP32), the dense L^-1 on the vector ALU or the banded substitution over one
-// type's cells (either precision).
-hipError_t launch_global_dense(const DevType* types_dev, const FusedGroup* groups,
-                               const int* n_groups_dev, int max_groups, const int64_t* offsets,
-                               int64_t vtot, const float* r, float* out, size_t lds_bytes,
-                               void* stream);
+// Global step alone (npfem_global_solve), over one type's cells: dense L^-1 on the matrix cores
+// (FP32), the dense L^-1 on the vector ALU or the banded substitution (either precision).
+// Wide form of the dense global step over one type's cells: kWideMaxCells cells per workgroup
+// unless their LDS cell blocks exceed 64 KB.
+constexpr int kWideMaxCells = 16;
+inline int wide_cells_per_block(int cs) {
+  const int fit = (int)(65536 / ((size_t)cs * sizeof(float)));
+  return fit < kWideMaxCells ? (fit < 1 ? 1 : fit) : kWideMaxCells;
+}
+hipError_t launch_global_dense_wide(const DevType* dt, int cs, const int32_t* cells, int n_cells,
+                                    const int64_t* offsets, int64_t vtot, const float* r, float* out,
+                                    void* stream);
 hipError_t launch_global_gemv(int precision, int n, const DevType* dt, const int32_t* cells, int n_cells,
                               const int64_t* offsets, int64_t vt, const void* r, void* out, void* stream);
 hipError_t launch_global_banded(int precision, int n, int band_w, const DevType* dt, const int32_t* cells,
