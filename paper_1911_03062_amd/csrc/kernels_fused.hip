@@ -438,19 +438,29 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
         const int vi = ITEM_V(it);
         float* Xv = X + ITEM_W(it);
         float* Rv = R + ITEM_W(it);
+        // every input word loaded before the type's branches (a load whose value is used past a
+        // branch is waited for there, one HBM round trip per item otherwise)
+        float xi[3], x0[3], vv[3], ff[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xi[c] = x[c * vt + off + vi];
+          x0[c] = x[c * vt + off];
+          vv[c] = v[c * vt + off + vi];
+          ff[c] = f[c * vt + off + vi];
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           // cell-local coordinates: positions relative to the cell's first vertex
-          const float xl = x[c * vt + off + vi] - x[c * vt + off];
+          const float xl = xi[c] - x0[c];
           if (damp) {
             Xv[c] = xl;                       // x_n and v_n staged for the reductions
-            Rv[c] = v[c * vt + off + vi];
-            if (vi == 0) Dm[kDampWords * ITEM_C(it) + 9 + c] = x[c * vt + off];
+            Rv[c] = vv[c];
+            if (vi == 0) Dm[kDampWords * ITEM_C(it) + 9 + c] = x0[c];
           } else if (ray) {
             Xv[c] = xl;
-            Rv[c] = -(h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi]);
+            Rv[c] = -(h * vv[c] + h2m * ff[c]);
           } else {
-            Xv[c] = xl + (h * v[c * vt + off + vi] + h2m * f[c * vt + off + vi]);
+            Xv[c] = xl + (h * vv[c] + h2m * ff[c]);
           }
         }
       }
@@ -717,18 +727,40 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           const float lw = w_v * lam_lds[ITEM_C(it)];   // w_v lambda / 6
 #pragma unroll
           for (int c = 0; c < 3; ++c) Rv[c] = gmass * e[it][c] - lw * Rv[c];
-          if (EXTRAS && cw != nullptr) {   // collision energy: w (x - p), x = x_n[0] + X
-            const int64_t off = off_lds[ITEM_C(it)];
-            const int vi = ITEM_V(it);
-            const float wc = cw[off + vi];
-            if (wc != 0.0f) {
-              const float* Xv = X + ITEM_W(it);
-#pragma unroll
-              for (int c = 0; c < 3; ++c)
-                Rv[c] += wc * ((x[c * vt + off] - cp[c * vt + off + vi]) + Xv[c]);
-            }
-          }
         }
+      if (EXTRAS && cw != nullptr) {
+        // collision energy w (x - p), x = x_n[0] + X. The weight, x_n[0] and p of three items
+        // are loaded before any is used, every load unconditional (empty items read the first
+        // vertex), and a zero weight selects no contribution: a load that a branch depends on
+        // is waited for at once, which made every item an HBM round trip
+#pragma unroll
+        for (int i0 = 0; i0 < NQ; i0 += 3) {
+          float wl[3], dl[3][3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            if (i0 + d < NQ) {
+              const int it = i0 + d;
+              const int64_t off = ITEM_OK(it) ? off_lds[ITEM_C(it)] : 0;
+              const int64_t o = off + (ITEM_OK(it) ? ITEM_V(it) : 0);
+              wl[d] = cw[o];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) dl[d][c] = x[c * vt + off] - cp[c * vt + o];
+            }
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            if (i0 + d < NQ && ITEM_OK(i0 + d)) {
+              const int it = i0 + d;
+              float* Rv = R + ITEM_W(it);
+              const float* Xv = X + ITEM_W(it);
+              const float w = wl[d];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                const float t = w * (dl[d][c] + Xv[c]);
+                Rv[c] += w != 0.0f ? t : 0.0f;
+              }
+            }
+        }
+      }
       __builtin_amdgcn_wave_barrier();
       // ---- triangle strain + area constraints
       {
