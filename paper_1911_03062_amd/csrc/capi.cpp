@@ -70,25 +70,24 @@ void free_devtype(DevType* d) {
 }
 
 // Device copies of layout li's schedules on device dev (uploaded once). Caller holds ct->mu.
-npfem_status layout_schedules_locked(npfem_celltype* ct, int dev, int li, TriRec** tri,
-                                     HingeRec** hinge) {
+npfem_status layout_schedules_locked(npfem_celltype* ct, int dev, int li, LayoutDev* out) {
   auto& v = ct->dev_sched[dev];
-  if (v.empty()) v.assign(ct->layouts.size(), {nullptr, nullptr});
-  if (!v[li].first) {
+  if (v.empty()) v.assign(ct->layouts.size(), LayoutDev{});
+  if (!v[li].tri) {
     const FusedLayout& lay = ct->layouts[li];
-    TriRec* t = nullptr;
-    HingeRec* h = nullptr;
-    npfem_status st = upload_raw(&t, lay.tri_sched.data(), lay.tri_sched.size());
-    if (st == NPFEM_OK) st = upload_raw(&h, lay.hinge_sched.data(), lay.hinge_sched.size());
+    LayoutDev d;
+    npfem_status st = upload_raw(&d.tri, lay.tri_sched.data(), lay.tri_sched.size());
+    if (st == NPFEM_OK) st = upload_raw(&d.hinge, lay.hinge_sched.data(), lay.hinge_sched.size());
+    if (st == NPFEM_OK) st = upload_raw(&d.gather, lay.gather_sched.data(), lay.gather_sched.size());
     if (st != NPFEM_OK) {
-      if (t) (void)hipFree(t);
-      if (h) (void)hipFree(h);
+      if (d.tri) (void)hipFree(d.tri);
+      if (d.hinge) (void)hipFree(d.hinge);
+      if (d.gather) (void)hipFree(d.gather);
       return st;
     }
-    v[li] = {t, h};
+    v[li] = d;
   }
-  *tri = v[li].first;
-  *hinge = v[li].second;
+  *out = v[li];
   return NPFEM_OK;
 }
 
@@ -108,6 +107,7 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   p.n = ct->n; p.m = ct->m; p.e = ct->e; p.bw = ct->bw;
   p.npad = ct->npad; p.cs = ct->cs; p.gw = ct->gw; p.slots = ct->slots;
   p.tri_rounds = ct->tri_rounds; p.hinge_rounds = ct->hinge_rounds;
+  p.gather_slots = ct->fused_ok ? ct->layouts[0].gather_slots : 0;
   p.row_tiles = (ct->n + 15) / 16;
   // whole chunks plus two zero chunks read by the global step's look-ahead loads
   p.k_steps = ((ct->npad / 4 + kMfmaChunk - 1) / kMfmaChunk + 2) * kMfmaChunk;
@@ -188,7 +188,11 @@ npfem_status upload_celltype(npfem_celltype* ct, DevType** out) {
   chk(upload(&d->ring_nb8, ct->ring_nb8));
   chk(upload(&d->ring_nb16, ct->ring_nb16));
   if (ct->fused_ok) {
-    chk(layout_schedules_locked(ct, dev, 0, &d->tri_sched, &d->hinge_sched));
+    LayoutDev ld;
+    chk(layout_schedules_locked(ct, dev, 0, &ld));
+    d->tri_sched = ld.tri;
+    d->hinge_sched = ld.hinge;
+    d->gather_sched = ld.gather;
     // L^-1 as the split fp16 A operand of v_mfma_f32_16x16x32_f16: entries times 2^exp (exp
     // puts the largest magnitude in [2^13, 2^14)) as hi = fp16(a) and lo = fp16(a - hi), so
     // that hi + lo holds a to 22 significant bits (to 2^-25 absolute where lo is subnormal).
@@ -257,13 +261,18 @@ npfem_status devtype_value(npfem_celltype* ct, int li, DevType* out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(ct->mu);
-  st = layout_schedules_locked(ct, dev, li, &out->tri_sched, &out->hinge_sched);
+  LayoutDev ld;
+  st = layout_schedules_locked(ct, dev, li, &ld);
   if (st != NPFEM_OK) return st;
+  out->tri_sched = ld.tri;
+  out->hinge_sched = ld.hinge;
+  out->gather_sched = ld.gather;
   const FusedLayout& lay = ct->layouts[li];
   out->p.gw = lay.gw;
   out->p.slots = lay.slots;
   out->p.tri_rounds = lay.tri_rounds;
   out->p.hinge_rounds = lay.hinge_rounds;
+  out->p.gather_slots = lay.gather_slots;
   return NPFEM_OK;
 }
 
@@ -281,8 +290,9 @@ npfem_celltype::~npfem_celltype() {
   for (auto& kv : dev_sched) {
     (void)hipSetDevice(kv.first);
     for (auto& p : kv.second) {
-      if (p.first) (void)hipFree(p.first);
-      if (p.second) (void)hipFree(p.second);
+      if (p.tri) (void)hipFree(p.tri);
+      if (p.hinge) (void)hipFree(p.hinge);
+      if (p.gather) (void)hipFree(p.gather);
     }
   }
   (void)hipSetDevice(cur);

@@ -961,52 +961,78 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
           double g2[kSkalakMaxGw], vx[kSkalakMaxGw], em[kSkalakMaxGw], ec[kSkalakMaxGw];
 #pragma unroll
           for (int q = 0; q < kSkalakMaxGw; ++q) g2[q] = vx[q] = em[q] = ec[q] = 0.0;
+          // volume terms over the gather schedule (the wave's vertices by ring length, 64 to a
+          // slot): 6 grad_i V = sum over the triangles (i, b, c) around i of
+          // (p_b - p_i) x (p_c - p_i) = sum of p_b x p_c (the remainder (sum of p_c - p_b) x p_i
+          // vanishes on a closed star, where every neighbour is once a b and once a c). The ring
+          // is stored in cyclic order (c of one pair is b of the next), so the walk reads each
+          // neighbour once and loads b only where a star has several cycles. A lane's codes and
+          // ring descriptors are loaded before any is used (a load that a branch depends on is
+          // waited for at once); ring words come in batches of kRingBatch independent loads
+          // (the array is padded by kRingBatch words, so a batch past the last ring stays in
+          // bounds).
+          {
+            uint32_t code[NQ], info[NQ];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) code[j] = T.gather_sched[j * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) info[j] = T.ring_info[code[j] == kGatherEmpty ? 0 : (code[j] & 0xfffu)];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+              const int lc = (int)(code[j] >> 12), vi = (int)(code[j] & 0xfffu);
+              if (code[j] != kGatherEmpty && lc0 + lc < count) {
+                const float* Pc = X + (lc0 + lc) * CS;
+                const float a = trial ? ls_a[lc0 + lc] : 0.0f;
+                const Vec3<double> dpi = pos(Pc + 3 * vi, a, trial);
+                const int roff = (int)(info[j] >> 8), deg = (int)(info[j] & 255u);
+                Vec3<double> gi = v3<double>(0.0, 0.0, 0.0);
+                uint32_t prev_c = 0xffffffffu;
+                Vec3<double> pprev = v3<double>(0.0, 0.0, 0.0);
+                for (int q0 = 0; q0 < deg; q0 += kRingBatch) {
+                  uint32_t prs[kRingBatch];
+#pragma unroll
+                  for (int jj = 0; jj < kRingBatch; ++jj) prs[jj] = T.ring_pairs[roff + q0 + jj];
+#pragma unroll
+                  for (int jj = 0; jj < kRingBatch; ++jj)
+                    if (q0 + jj < deg) {
+                      const uint32_t bb = prs[jj] & 0xffffu, cc = prs[jj] >> 16;
+                      const Vec3<double> pb = bb == prev_c ? pprev : pos(Pc + 3 * (int)bb, a, trial);
+                      const Vec3<double> pc = pos(Pc + 3 * (int)cc, a, trial);
+                      gi = gi + cross3(pb, pc);
+                      prev_c = cc;
+                      pprev = pc;
+                    }
+                }
+                const double g2i = dot3(gi, gi), vxi = dot3(dpi, gi);
+#pragma unroll
+                for (int q = 0; q < kSkalakMaxGw; ++q)
+                  if (q == lc) {
+                    g2[q] += g2i;
+                    vx[q] += vxi;
+                  }
+              }
+            }
+          }
+          // inertia and collision terms over the owner items
           refresh_items(item);
 #pragma unroll
           for (int it = 0; it < NQ; ++it)
             if (ITEM_OK(it)) {
               const int lc = ITEM_C(it) - lc0, vi = ITEM_V(it);
-              const float* Pc = X + ITEM_C(it) * CS;
-              const float a = trial ? ls_a[ITEM_C(it)] : 0.0f;
-              const Vec3<double> dpi = pos(Pc + 3 * vi, a, trial);
-              // 6 grad_i V = sum over the triangles (i, b, c) around i of (p_b - p_i) x (p_c - p_i)
-              // = sum of p_b x p_c: the remainder (sum of p_c - p_b) x p_i vanishes on a closed
-              // star, where every neighbour is once a b and once a c. The ring is stored in
-              // cyclic order (c of one pair is b of the next), so the walk reads each neighbour
-              // once and loads b only where a star has several cycles.
-              // The ring words come in batches of kRingBatch independent loads (the array is
-              // padded by kRingBatch words, so a batch past the last ring stays in bounds).
-              const uint32_t info = T.ring_info[vi];
-              const int roff = (int)(info >> 8), deg = (int)(info & 255u);
-              Vec3<double> gi = v3<double>(0.0, 0.0, 0.0);
-              uint32_t prev_c = 0xffffffffu;
-              Vec3<double> pprev = v3<double>(0.0, 0.0, 0.0);
-              for (int q0 = 0; q0 < deg; q0 += kRingBatch) {
-                uint32_t prs[kRingBatch];
-#pragma unroll
-                for (int j = 0; j < kRingBatch; ++j) prs[j] = T.ring_pairs[roff + q0 + j];
-#pragma unroll
-                for (int j = 0; j < kRingBatch; ++j)
-                  if (q0 + j < deg) {
-                    const uint32_t b = prs[j] & 0xffffu, c = prs[j] >> 16;
-                    const Vec3<double> pb = b == prev_c ? pprev : pos(Pc + 3 * (int)b, a, trial);
-                    const Vec3<double> pc = pos(Pc + 3 * (int)c, a, trial);
-                    gi = gi + cross3(pb, pc);
-                    prev_c = c;
-                    pprev = pc;
-                  }
-              }
               const float* Dv = R + ITEM_W(it);
-              double g2i = dot3(gi, gi), vxi = dot3(dpi, gi), emi = 0.0, eci = 0.0;
+              double emi = 0.0, eci = 0.0;
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                const double el = trial ? (double)e[it][c] + (double)a * (double)Dv[c] : (double)e[it][c];
+                const double el = trial ? (double)e[it][c] + (double)ls_a[ITEM_C(it)] * (double)Dv[c] : (double)e[it][c];
                 emi += el * el;
               }
               if (EXTRAS && cw != nullptr) {
                 const int64_t off = off_lds[ITEM_C(it)];
                 const float wc = cw[off + vi];
                 if (wc != 0.0f) {
+                  const float* Pc = X + ITEM_C(it) * CS;
+                  const float a = trial ? ls_a[ITEM_C(it)] : 0.0f;
+                  const Vec3<double> dpi = pos(Pc + 3 * vi, a, trial);
                   const double pic[3] = {dpi.x, dpi.y, dpi.z};
 #pragma unroll
                   for (int c = 0; c < 3; ++c) {
@@ -1018,8 +1044,6 @@ k_fused_step(const DevType* __restrict__ types, const FusedGroup* __restrict__ g
 #pragma unroll
               for (int q = 0; q < kSkalakMaxGw; ++q)
                 if (q == lc) {
-                  g2[q] += g2i;
-                  vx[q] += vxi;
                   em[q] += emi;
                   ec[q] += eci;
                 }

@@ -52,7 +52,18 @@ struct FusedLayout {
   int gw = 0, slots = 0, tri_rounds = 0, hinge_rounds = 0;
   std::vector<TriRec> tri_sched;      // [tri_rounds][slots]
   std::vector<HingeRec> hinge_sched;  // [hinge_rounds][slots]
+  int gather_slots = 0;
+  std::vector<uint16_t> gather_sched; // [kMaxItems][64]: cell of the wave << 12 | vertex, or
+                                      // kGatherEmpty; vertices by ring length, longest first
 };
+
+// Device copies of one fused layout's schedules.
+struct LayoutDev {
+  TriRec* tri = nullptr;
+  HingeRec* hinge = nullptr;
+  uint16_t* gather = nullptr;
+};
+constexpr uint16_t kGatherEmpty = 0xffff;
 
 // Scalar parameters of a cell type as seen by the kernels.
 struct TypeParams {
@@ -62,6 +73,7 @@ struct TypeParams {
   int32_t gw;                   // cells owned by one wave in a fused group
   int32_t slots;                // element slots per cell in a wave (64 / gw)
   int32_t tri_rounds, hinge_rounds;
+  int32_t gather_slots;         // slots of the fused Skalak energy's ring gather (per lane)
   int32_t row_tiles;            // ceil(n / 16): MFMA row tiles of L^-1
   int32_t k_steps;              // MFMA k steps stored per L^-1 row tile: npad / 4 rounded
                                 // up to whole kMfmaChunk chunks plus two chunks (zeros)
@@ -96,6 +108,7 @@ struct DevType {
   // fused form
   TriRec* tri_sched = nullptr;       // [tri_rounds][slots]
   HingeRec* hinge_sched = nullptr;   // [hinge_rounds][slots]
+  uint16_t* gather_sched = nullptr;  // [kMaxItems][64] (fused Skalak energy)
   float* linv_tiles = nullptr;       // [row_tiles][k_steps / kMfmaChunk][512 words]: split
                                      // fp16 MFMA A operand of L^-1 2^linv_exp
   float* pinv_tiles = nullptr;       // m M~^-1 2^pinv_exp in the same form (Rayleigh beta > 0)
@@ -162,7 +175,7 @@ struct npfem_celltype {
   std::mutex mu;
   std::map<int, npfem::DevType*> dev;   // per HIP device: shared device data, layouts[0]
   // per HIP device, per layout: device copies of that layout's schedules
-  std::map<int, std::vector<std::pair<npfem::TriRec*, npfem::HingeRec*>>> dev_sched;
+  std::map<int, std::vector<npfem::LayoutDev>> dev_sched;
   ~npfem_celltype();
 };
 
@@ -204,7 +217,7 @@ constexpr int kMaxHalvings = 8;             //   and step lengths 1, 1/2, ..., 1
 constexpr int kSkalakMaxGw = 2;             // fused Skalak types: at most 2 cells per wave
 constexpr int kSkalakMaxCells = kFusedWaves * kSkalakMaxGw;   // and per group
 constexpr int kDampWords = 12;              // LDS floats per cell for position-based damping
-constexpr int kRingBatch = 8;               // ring words loaded together (device copy padded by as many)
+constexpr int kRingBatch = 6;               // ring words loaded together (device copy padded by as many)
 constexpr int kMaxTilesPerWave = 10;        // MFMA 16x16 output tiles held per wave (even)
 
 // MFMA output tiles of the global step: each wave takes an equal share of the

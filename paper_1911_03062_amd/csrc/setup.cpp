@@ -870,6 +870,19 @@ npfem_status build_celltype(const npfem_mesh* mesh, const npfem_material* mat, d
         rec.rest = (float)ct->rest_norm[h];
         lay.hinge_sched[(size_t)r * lay.slots + s] = rec;
       }
+    // ring gather of the fused Skalak energy: the wave's gw n vertices by ring length (longest
+    // first, then cell and vertex), 64 to a slot, so that the long rings of a mesh (the poles
+    // of a UV sphere) share one slot and the wave walks each slot's longest ring once
+    {
+      std::vector<std::pair<int, int>> vs;   // (-ring length, code)
+      for (int cw = 0; cw < gw; ++cw)
+        for (int v = 0; v < n; ++v) vs.push_back({-(ct->vt_off[v + 1] - ct->vt_off[v]), (cw << 12) | v});
+      std::stable_sort(vs.begin(), vs.end(),
+                       [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.first < y.first; });
+      lay.gather_slots = (int)((vs.size() + 63) / 64);
+      lay.gather_sched.assign((size_t)kMaxItems * 64, kGatherEmpty);
+      for (size_t k = 0; k < vs.size(); ++k) lay.gather_sched[k] = (uint16_t)vs[k].second;
+    }
     ct->layouts.push_back(std::move(lay));
   }
   ct->gw = ct->layouts[0].gw;
