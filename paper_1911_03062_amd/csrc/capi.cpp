@@ -394,11 +394,18 @@ struct npfem_batch {
 
 namespace {
 
-// Groups of up to 4*gw same-type cells, types in order, cells in the given order.
+// Groups of up to 4*gw same-type cells, cells in the given order. Workgroups are dispatched
+// in list order, so the types with the most vertices per cell (the longest groups) come first
+// and the shorter groups fill the last, partial round of workgroups; equal sizes keep the
+// types' order.
 void build_groups(const npfem_batch* b, const int32_t* ids, int n, std::vector<FusedGroup>& out) {
   out.clear();
   const int nt = (int)b->types.size();
-  for (int ti = 0; ti < nt; ++ti) {
+  std::vector<int> type_order(nt);
+  for (int ti = 0; ti < nt; ++ti) type_order[ti] = ti;
+  std::stable_sort(type_order.begin(), type_order.end(),
+                   [&](int p, int q) { return b->types[p]->n > b->types[q]->n; });
+  for (int ti : type_order) {
     const int cap = kFusedWaves * b->types[ti]->layouts[b->layout_of[ti]].gw;
     FusedGroup gcur{};
     gcur.type = ti;
