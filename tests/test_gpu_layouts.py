@@ -87,3 +87,35 @@ def test_autotune_picks_a_feasible_layout_and_keeps_parity():
     err = cell_errors(b.types, b.offsets, xg, xo)
     _say(f"after autotune: max err/diam {err.max():.3e}")
     assert err.max() <= 1e-5
+
+
+def test_cell_order_does_not_change_results():
+    """The fused work list sends the types with the most vertices per cell first, whatever
+    order the batch lists its cells in; that order only decides when a cell's group runs, so
+    every cell's step is bitwise the same when the batch lists its cells in another order
+    (platelets first here, red cells first in the other batch)."""
+    import torch
+    from paper_1911_03062_amd import npfem as N
+    types = lib_types()
+    b = _mixed(seed=121)
+    forces = list(I.force_stream(b, seed=122, sigma=20.0, n_steps=3))
+    order = np.concatenate([np.where(b.types == I.PLT)[0], np.where(b.types == I.RBC)[0]])
+    idx = np.concatenate([np.arange(b.offsets[c], b.offsets[c + 1]) for c in order])
+    _say(f"case: {len(order)} cells listed platelets first vs the original order, 3 steps x K = 10")
+    results = []
+    for cells, cols in ((np.arange(len(b.types)), np.arange(b.x0.shape[1])), (order, idx)):
+        batch = N.Batch([types[int(b.types[c])] for c in cells], 32, "fused")
+        x = torch.tensor(np.ascontiguousarray(b.x0[:, cols]), dtype=torch.float32, device="cuda")
+        v = torch.tensor(np.ascontiguousarray(b.v0[:, cols]), dtype=torch.float32, device="cuda")
+        for f in forces:
+            ft = torch.tensor(np.ascontiguousarray(np.asarray(f)[:, cols]), dtype=torch.float32,
+                              device="cuda")
+            batch.step(x, v, ft, I.DT, 10)
+        batch.check()
+        xo = np.empty_like(b.x0, dtype=np.float32)
+        vo = np.empty_like(b.v0, dtype=np.float32)
+        xo[:, cols] = x.cpu().numpy()
+        vo[:, cols] = v.cpu().numpy()
+        results.append((xo, vo))
+    assert np.array_equal(results[0][0], results[1][0])
+    assert np.array_equal(results[0][1], results[1][1])
